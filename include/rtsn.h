@@ -1,0 +1,269 @@
+/*
+ * rtsn.h - C ABI of the MI355X (gfx950) matrix-free S_N radiative-transfer
+ * library.
+ *
+ * The library solves the discrete linear radiative-transfer problem of
+ * Benedusi, Riva, Belluzzi and Serra-Capizzano, "Analysis of eigenvalue
+ * clustering leads to optimal scaling in numerical radiative transfer"
+ * (arXiv:2602.21958), written in source-function form:
+ *
+ *     A s = s - (1 - eps) Mhat Lambda_0 s = b,
+ *     b   = (1 - eps) Mhat I_bc + t,
+ *
+ * where Lambda_0 is the formal solution with zero incoming radiation
+ * (Sec. 3.2, eqs. ie_1/ie_2 and eq. lambda_block), Mhat the scattering block
+ * diag(1/(phi_nu + r)) Psi diag(w_o w_nu) shared by all spatial points
+ * (Sec. 3.3, eq. Sigma), I_bc the boundary intensity propagated through the
+ * medium (Sec. 3.1, the I_in vector) and t the thermal source (eq. S).  This
+ * is the system (Id - Lambda Sigma) I = Lambda t + I_in of eq.
+ * RT_sys_algebraic after the substitution I = Lambda_0 s + I_bc; both forms
+ * have the same spectrum (Sec. 3.5).
+ *
+ * Conventions
+ * -----------
+ * Vector layout ("ray-major", the permuted ordering X~ = P X of Sec. 3.1):
+ *   element [k * n_points + i], ray k = o * n_nu + nu (frequency fastest,
+ *   Sec. 3.1 ray ordering), ordinate o (slab: inclination index, mu
+ *   ascending; box: o = m * n_az + b, inclination-major), point i
+ *   (slab: depth index, 0 = top; box: i = (z * ny + y) * nx + x, z = 0 is
+ *   the bottom plane).
+ * Device pointers: every vector argument marked "device" is memory of the
+ *   problem's device (hipMalloc'd or torch CUDA memory); "host" arrays are
+ *   ordinary CPU memory.  The library never frees caller memory and keeps no
+ *   pointer to it after the call returns.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
+ *   Calls are asynchronous on that stream unless stated otherwise.
+ * Errors: every call returns an rt_status; on failure rt_last_error() gives a
+ *   message (thread-local).  No C++ exception and no abort crosses the ABI.
+ *   Invalid arguments are rejected on the host before any kernel launch.
+ * Threading: one problem is used by one host thread at a time.
+ */
+#ifndef RTSN_H
+#define RTSN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTSN_VERSION 1
+
+typedef enum {
+  RT_OK = 0,
+  RT_NOT_CONVERGED = 1,   /* solver hit max_iters; x holds the last iterate */
+  RT_E_INVALID = -1,      /* bad argument (sizes, pointers, enum values)     */
+  RT_E_NOMEM = -2,        /* device allocation failed                        */
+  RT_E_DEVICE = -3,       /* HIP runtime error                               */
+  RT_E_BREAKDOWN = -4,    /* BiCGStab breakdown (rho or omega vanished)      */
+  RT_E_NONFINITE = -5,    /* NaN/Inf in an input or in a residual            */
+  RT_E_BUSY = -6          /* batch: queue full / ticket still pending        */
+} rt_status;
+
+typedef struct rt_problem_s* rt_problem;
+typedef struct rt_batch_s* rt_batch;
+
+enum { RT_GEOM_SLAB = 0, RT_GEOM_BOX = 1 };
+enum { RT_KERNEL_DIPOLE_PRD = 0, RT_KERNEL_EXPLICIT = 1 };
+enum { RT_FORMAL_LINEAR_SC = 0, RT_FORMAL_IMPLICIT_EULER = 1 };
+
+/* Arithmetic of one operator application.
+ *   FP64  : vectors double; Lambda and Sigma in FP64 (Sigma on FP64 MFMA).
+ *   FP32  : vectors float;  Lambda FP32; Sigma FP32 MFMA.
+ *   BF16  : vectors float;  Lambda FP32 emitting bf16; Sigma bf16 MFMA with
+ *           FP32 accumulation; epilogue FP32.
+ *   FP16  : as BF16 with fp16 operands (kernel matrix column-scaled to stay
+ *           in fp16 range, scale undone in FP32).
+ *   BF16X3: as BF16 but the kernel matrix and Lambda output are split into
+ *           hi + lo bf16 parts and three products are accumulated (about
+ *           16 significant bits).                                            */
+enum { RT_PREC_FP64 = 0, RT_PREC_FP32 = 1, RT_PREC_BF16 = 2, RT_PREC_FP16 = 3,
+       RT_PREC_BF16X3 = 4 };
+
+/* Problem description (Sec. 2 model, Sec. 3.1 grids, Sec. 5 set-up).  All
+ * pointers are host pointers; the library copies what it needs at create.   */
+typedef struct {
+  int geom;               /* RT_GEOM_SLAB or RT_GEOM_BOX                          */
+  int nx, ny, nz;         /* spatial nodes; slab: nx = ny = 1, nz >= 2;
+                             box: nx, ny >= 1 (periodic), nz >= 2; the box edge
+                             is 1 in x, y and z: x_i = i/nx, z_k = k/(nz-1)      */
+  const double* depth;    /* slab: nz frequency-integrated line optical depths t,
+                             strictly increasing, index 0 = top; the optical depth
+                             of ray (mu, nu) between nodes is (phi_nu + r) dt/|mu|
+                             (Sec. 5 set-up, tau = phi t / mu)                     */
+  const double* k_line;   /* box: nz*ny*nx line opacity per unit length (> 0),
+                             C order (z, y, x), z = 0 bottom                      */
+  int n_mu;               /* total inclinations (even): n_mu/2 Gauss-Legendre
+                             nodes per hemisphere (Sec. 5 set-up)                  */
+  int n_az;               /* azimuths (box; equidistant, (b+1/2) 2pi/n_az);
+                             slab: 1                                               */
+  int n_nu;               /* frequencies, equispaced on [-x_max, x_max], trapezoid
+                             weights; Doppler profile exp(-x^2) normalised to unit
+                             discrete area; n_nu = 1 is monochromatic (phi = 1)    */
+  double x_max;
+  double r;               /* continuum / line opacity ratio: chi = k (phi + r)     */
+  double eps;             /* photon destruction probability (used if eps_field
+                             is NULL)                                              */
+  const double* eps_field;/* optional n_points per-point eps                       */
+  double planck;          /* thermal source B (used if planck_field is NULL)       */
+  const double* planck_field; /* optional n_points per-point B                     */
+  double i_top, i_bot;    /* incoming intensity at the top (mu < 0) and bottom
+                             (mu > 0) boundaries (eq. bc)                          */
+  int kernel;             /* RT_KERNEL_DIPOLE_PRD or RT_KERNEL_EXPLICIT            */
+  const double* kernel_matrix; /* EXPLICIT: n_rays*n_rays symmetric Psi, row-major
+                             in ray order (Sec. 3.3, the block Psi_[i])            */
+  double coh_frac;        /* DIPOLE_PRD: weight c of the coherent part            */
+  double coh_width2;      /* DIPOLE_PRD: w2 in exp(-(x - x')^2 / w2)               */
+  int formal;             /* RT_FORMAL_LINEAR_SC (box and slab) or
+                             RT_FORMAL_IMPLICIT_EULER (slab only, eqs. ie_1/ie_2)  */
+} rt_problem_desc;
+
+typedef struct {
+  int64_t n_unknowns;     /* n_rays * n_points                                     */
+  int64_t n_rays;         /* n_mu * n_az * n_nu                                    */
+  int64_t n_points;       /* nx * ny * nz                                          */
+  int64_t bytes_problem;  /* device bytes held by the problem itself               */
+  int64_t bytes_solve_fp64;  /* extra device bytes of an FP64 GMRES(restart) solve
+                                with the restart passed to rt_problem_footprint   */
+  int64_t bytes_solve_mixed; /* same for a mixed-precision (FP32 basis) solve      */
+} rt_problem_info;
+
+/* rt_problem_create: build quadratures, the redistribution kernel (dipole x
+ * PRD with a Sinkhorn-scaled coherent part, Sec. 2 normalisation), Mhat, t
+ * and 1 - eps on the host in FP64, and copy them to `device`.
+ * Errors: RT_E_INVALID (sizes, missing arrays, non-increasing depth,
+ * non-positive opacity, odd n_mu, implicit Euler in a box), RT_E_NONFINITE
+ * (NaN/Inf inputs), RT_E_NOMEM, RT_E_DEVICE.  *out is NULL on failure.     */
+rt_status rt_problem_create(const rt_problem_desc* desc, int device, rt_problem* out);
+
+/* Release all device memory of the problem (and of its solver workspace).   */
+rt_status rt_problem_destroy(rt_problem p);
+
+/* Sizes and device footprint of a problem; restart = GMRES restart length
+ * used for the solve estimates.                                             */
+rt_status rt_problem_footprint(rt_problem p, int restart, rt_problem_info* info);
+
+/* Copy the FP64 scattering block Mhat (n_rays x n_rays, row-major) and the
+ * per-ray quadrature data to host arrays (any may be NULL): mu_ray (ray
+ * direction cosine), w_ray (w_o w_nu), phi_ray (profile).  Synchronous.     */
+rt_status rt_problem_tables(rt_problem p, double* mhat, double* mu_ray,
+                            double* w_ray, double* phi_ray);
+
+/* Formal solution (Sec. 3.2, eq. lambda_block; box: plane-to-plane upwind
+ * short characteristics with bilinear interpolation, the short-
+ * characteristics counterpart of the ray partition of Sec. 3.4):
+ *   I = Lambda_0 (scale * s) + (with_bc ? I_bc : 0).
+ * s, I: device, ray-major, n_unknowns elements of the precision's vector
+ * type (double for FP64, float otherwise).  `scale` is an optional device
+ * double (NULL = 1).  I must not alias s.  Errors: RT_E_INVALID.            */
+rt_status rt_apply_lambda(rt_problem p, int precision, const void* s, void* I,
+                          int with_bc, const double* scale, void* stream);
+
+/* Scattering step (Sec. 3.3, eq. Sigma), as a GEMM shared by all points:
+ *   y = x - (1 - eps) * Mhat * L      (x != NULL)
+ *   y = (1 - eps) * Mhat * L          (x == NULL)
+ * L, x, y: device, ray-major, vector type of the precision (for BF16/FP16/
+ * BF16X3 L is float and is rounded to the 16-bit type inside).  y may alias
+ * x.  Errors: RT_E_INVALID.                                                 */
+rt_status rt_apply_sigma(rt_problem p, int precision, const void* L,
+                         const void* x, void* y, void* stream);
+
+/* Operator application y = A x = x - (1 - eps) Mhat Lambda_0 x (Sec. 3.5,
+ * eq. A_N in source-function form).  x, y: device, ray-major, vector type of
+ * the precision; y must not alias x.  Uses an internal device buffer for
+ * Lambda_0 x.  Errors: RT_E_INVALID, RT_E_NOMEM.                            */
+rt_status rt_apply_operator(rt_problem p, int precision, const void* x, void* y,
+                            void* stream);
+
+/* Right-hand side b = (1 - eps) Mhat I_bc + t (FP64, device, ray-major).     */
+rt_status rt_rhs(rt_problem p, double* b, void* stream);
+
+/* Full intensity I = Lambda_0 s + I_bc for a source function s (FP64 device
+ * arrays), e.g. the emergent spectrum of a solution.                         */
+rt_status rt_intensity(rt_problem p, const double* s, double* I, void* stream);
+
+enum { RT_KRYLOV_GMRES = 0, RT_KRYLOV_BICGSTAB = 1 };
+
+typedef struct {
+  int krylov;             /* RT_KRYLOV_GMRES (default) or RT_KRYLOV_BICGSTAB        */
+  int restart;            /* GMRES restart length m (1..200; default 30)            */
+  int max_iters;          /* total inner iterations cap (default 10000)             */
+  double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual,
+                             FP64)                                                   */
+  int precision;          /* RT_PREC_FP64: plain FP64 Krylov; any other value:
+                             FP64 outer iterative refinement around an inner
+                             solve of A_lo d = r in that precision                 */
+  double inner_rtol;      /* mixed: inner relative tolerance (default 1e-3)         */
+  int max_outer;          /* mixed: outer refinement cap (default 50)               */
+  int record_history;     /* keep the per-iteration residual estimates              */
+} rt_solver_opts;
+
+typedef struct {
+  int iters;              /* total Krylov iterations (inner iterations if mixed)    */
+  int outer_iters;        /* refinement steps (mixed) or restart cycles (FP64)      */
+  int converged;          /* 1 if the true relative residual <= rtol                */
+  double relres;          /* final true relative residual, FP64 operator            */
+  double ms;              /* wall time of the call                                  */
+  int history_len;        /* number of entries in history                           */
+  const double* history;  /* relative residual estimates (library-owned, valid until
+                             the next call on this problem)                          */
+} rt_solve_stats;
+
+/* Fill opts with defaults (GMRES(30), rtol 1e-8, FP64).                     */
+void rt_solver_opts_default(rt_solver_opts* opts);
+
+/* Solve A s = b (restarted GMRES, Sec. 5 and Sec. 5.3; or BiCGStab).
+ * b: device FP64 or NULL (then the physical right-hand side rt_rhs is used).
+ * x: device FP64, n_unknowns; on entry the initial guess if x_is_guess,
+ * otherwise ignored (x0 = 0); on exit the solution s.
+ * The Krylov workspace is allocated on first use and kept on the device with
+ * the problem (re-used by later solves).  Synchronises the stream.
+ * Returns RT_OK, RT_NOT_CONVERGED (x valid), RT_E_BREAKDOWN,
+ * RT_E_NONFINITE, RT_E_INVALID or RT_E_NOMEM.                                */
+rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b,
+                   double* x, int x_is_guess, rt_solve_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves and serving (many independent problems on one device).
+ * A batch engine owns a device-memory budget; submitted solves are admitted
+ * when their footprint (rt_problem_footprint) fits and a slot is free,
+ * otherwise queued.  Admitted solves advance together, one Krylov iteration
+ * of every active slot per engine step; a slot freed by a finished solve is
+ * given to the next queued request at the next step boundary.
+ * ------------------------------------------------------------------------- */
+
+/* Create an engine on `device` with a device-memory budget in bytes and at
+ * most max_slots concurrently admitted solves (queue capacity queue_cap).    */
+rt_status rt_batch_create(int device, int64_t hbm_budget, int max_slots,
+                          int queue_cap, rt_batch* out);
+
+/* Submit a solve of problem p (which must stay alive until completion).
+ * x_out: device FP64 n_unknowns of p, caller-owned, written at completion.
+ * Non-blocking; *ticket identifies the request.  RT_E_BUSY if the queue is
+ * full; RT_E_INVALID if the problem can never fit the budget.               */
+rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts,
+                          double* x_out, uint64_t* ticket);
+
+/* Advance every admitted solve by one engine step (admit, iterate, retire).
+ * Returns the number of solves still admitted or queued in *pending.         */
+rt_status rt_batch_step(rt_batch b, int* pending);
+
+/* RT_OK with stats when the ticket has finished, RT_E_BUSY while pending.    */
+rt_status rt_batch_poll(rt_batch b, uint64_t ticket, rt_solve_stats* stats);
+
+/* Step the engine until every submitted request has finished.               */
+rt_status rt_batch_wait_all(rt_batch b);
+
+rt_status rt_batch_destroy(rt_batch b);
+
+/* Thread-local message of the last failed call on this thread.              */
+const char* rt_last_error(void);
+
+int rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTSN_H */

@@ -1,0 +1,479 @@
+// extern "C" entry points of librtsn (declared in include/rtsn.h), problem
+// construction and operator dispatch.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "krylov.h"
+
+namespace rtsn {
+
+static thread_local std::string g_last_error;
+
+void fail(rt_status code, const std::string& msg) { throw RtError{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? RT_E_NOMEM : RT_E_DEVICE,
+         std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+Problem::~Problem() {
+  delete ws;
+  hipFree(d_mhat64);
+  hipFree(d_mhat32);
+  hipFree(d_mhat_bf16);
+  hipFree(d_mhat_bf16_lo);
+  hipFree(d_mhat_f16);
+  hipFree(d_f16_colscale);
+  hipFree(d_albedo);
+  hipFree(d_thermal);
+  hipFree(d_dt);
+  hipFree(d_kline);
+  hipFree(d_ray_mu);
+  hipFree(d_ray_fac);
+  hipFree(d_stencil);
+  hipFree(d_lbuf);
+  hipFree(d_rhs);
+}
+
+size_t lambda_elem_bytes(int precision) {
+  switch (precision) {
+    case RT_PREC_FP64: return 8;
+    case RT_PREC_FP32: return 4;
+    case RT_PREC_BF16:
+    case RT_PREC_FP16: return 2;
+    case RT_PREC_BF16X3: return 4;
+    default: return 8;
+  }
+}
+
+void* problem_lbuf(Problem& p, size_t bytes) {
+  if (bytes > p.lbuf_bytes) {
+    hipFree(p.d_lbuf);
+    p.d_lbuf = nullptr;
+    p.lbuf_bytes = 0;
+    RT_HIP(hipMalloc(&p.d_lbuf, bytes));
+    p.lbuf_bytes = bytes;
+  }
+  return p.d_lbuf;
+}
+
+namespace {
+
+template <typename T>
+T* upload(const T* h, size_t count, int64_t& total) {
+  void* d = nullptr;
+  RT_HIP(hipMalloc(&d, count * sizeof(T)));
+  RT_HIP(hipMemcpy(d, h, count * sizeof(T), hipMemcpyHostToDevice));
+  total += (int64_t)(count * sizeof(T));
+  return static_cast<T*>(d);
+}
+
+bool all_finite(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+void validate(const rt_problem_desc& d) {
+  if (d.geom != RT_GEOM_SLAB && d.geom != RT_GEOM_BOX) fail(RT_E_INVALID, "geom must be SLAB or BOX");
+  if (d.nz < 2) fail(RT_E_INVALID, "nz must be >= 2");
+  if (d.n_mu < 2 || (d.n_mu & 1)) fail(RT_E_INVALID, "n_mu must be even and >= 2");
+  if (d.n_nu < 1) fail(RT_E_INVALID, "n_nu must be >= 1");
+  if (d.n_nu > 1 && !(d.x_max > 0)) fail(RT_E_INVALID, "x_max must be > 0");
+  if (!(d.r >= 0) || !std::isfinite(d.r)) fail(RT_E_INVALID, "continuum ratio r must be >= 0");
+  if (d.geom == RT_GEOM_SLAB) {
+    if (d.nx != 1 || d.ny != 1) fail(RT_E_INVALID, "slab needs nx = ny = 1");
+    if (!d.depth) fail(RT_E_INVALID, "slab needs depth[nz]");
+    if (!all_finite(d.depth, d.nz)) fail(RT_E_NONFINITE, "depth has NaN/Inf");
+    for (int i = 0; i + 1 < d.nz; ++i)
+      if (!(d.depth[i + 1] > d.depth[i])) fail(RT_E_INVALID, "depth must increase strictly");
+    if (d.nz > 64 * 1024) fail(RT_E_INVALID, "nz too large for the slab sweep");
+  } else {
+    if (d.nx < 1 || d.ny < 1) fail(RT_E_INVALID, "box needs nx, ny >= 1");
+    if (d.n_az < 1) fail(RT_E_INVALID, "box needs n_az >= 1");
+    if (!d.k_line) fail(RT_E_INVALID, "box needs k_line[nz*ny*nx]");
+    const size_t ns = (size_t)d.nx * d.ny * d.nz;
+    if (!all_finite(d.k_line, ns)) fail(RT_E_NONFINITE, "k_line has NaN/Inf");
+    for (size_t i = 0; i < ns; ++i)
+      if (!(d.k_line[i] > 0)) fail(RT_E_INVALID, "k_line must be > 0");
+    if ((int64_t)d.nx * d.ny > 4096) fail(RT_E_INVALID, "box plane larger than 4096 points");
+    if (d.formal != RT_FORMAL_LINEAR_SC) fail(RT_E_INVALID, "box supports linear SC only");
+  }
+  if (d.formal != RT_FORMAL_LINEAR_SC && d.formal != RT_FORMAL_IMPLICIT_EULER)
+    fail(RT_E_INVALID, "unknown formal solver");
+  if (d.kernel == RT_KERNEL_EXPLICIT) {
+    if (!d.kernel_matrix) fail(RT_E_INVALID, "explicit kernel needs kernel_matrix");
+  } else if (d.kernel == RT_KERNEL_DIPOLE_PRD) {
+    if (!(d.coh_frac >= 0 && d.coh_frac <= 1)) fail(RT_E_INVALID, "coh_frac must be in [0,1]");
+    if (!(d.coh_width2 > 0)) fail(RT_E_INVALID, "coh_width2 must be > 0");
+  } else {
+    fail(RT_E_INVALID, "unknown kernel");
+  }
+  if (!std::isfinite(d.i_top) || !std::isfinite(d.i_bot) || !std::isfinite(d.eps) ||
+      !std::isfinite(d.planck))
+    fail(RT_E_NONFINITE, "non-finite scalar input");
+}
+
+}  // namespace
+
+void problem_build(Problem& p, const rt_problem_desc& d) {
+  validate(d);
+  p.geom = d.geom;
+  p.nx = d.nx;
+  p.ny = d.ny;
+  p.nz = d.nz;
+  p.n_mu = d.n_mu;
+  p.n_az = d.geom == RT_GEOM_BOX ? d.n_az : 1;
+  p.n_nu = d.n_nu;
+  p.n_omega = p.n_mu * p.n_az;
+  p.n_r = p.n_omega * p.n_nu;
+  p.n_s = (int64_t)p.nx * p.ny * p.nz;
+  p.n = p.n_s * p.n_r;
+  p.formal = d.formal;
+  p.r = d.r;
+  p.i_top = d.i_top;
+  p.i_bot = d.i_bot;
+  if (p.n_r > 16384) fail(RT_E_INVALID, "too many rays (n_mu*n_az*n_nu > 16384)");
+  if (d.kernel == RT_KERNEL_EXPLICIT &&
+      !all_finite(d.kernel_matrix, (size_t)p.n_r * p.n_r))
+    fail(RT_E_NONFINITE, "kernel_matrix has NaN/Inf");
+
+  build_tables(d, p.tab);
+
+  // per-point albedo 1 - eps and thermal source t = (eps phi + r) B / (phi + r)
+  std::vector<double> eps(p.n_s), bpl(p.n_s), alb(p.n_s);
+  for (int64_t i = 0; i < p.n_s; ++i) {
+    eps[i] = d.eps_field ? d.eps_field[i] : d.eps;
+    bpl[i] = d.planck_field ? d.planck_field[i] : d.planck;
+    if (!std::isfinite(eps[i]) || !std::isfinite(bpl[i]))
+      fail(RT_E_NONFINITE, "eps/planck field has NaN/Inf");
+    if (eps[i] < 0 || eps[i] > 1) fail(RT_E_INVALID, "eps must be in [0, 1]");
+    alb[i] = 1.0 - eps[i];
+  }
+  std::vector<double> therm((size_t)p.n);
+  for (int k = 0; k < p.n_r; ++k) {
+    const double ph = p.tab.phi_ray[k], fac = p.tab.fac_ray[k];
+    for (int64_t i = 0; i < p.n_s; ++i)
+      therm[(size_t)k * p.n_s + i] = (eps[i] * ph + d.r) * bpl[i] / fac;
+  }
+
+  int64_t tot = 0;
+  RT_HIP(hipSetDevice(p.device));
+  const size_t nr2 = (size_t)p.n_r * p.n_r;
+  p.d_mhat64 = upload(p.tab.mhat.data(), nr2, tot);
+  {
+    std::vector<float> m32(nr2);
+    for (size_t i = 0; i < nr2; ++i) m32[i] = (float)p.tab.mhat[i];
+    p.d_mhat32 = upload(m32.data(), nr2, tot);
+  }
+  p.d_albedo = upload(alb.data(), alb.size(), tot);
+  p.d_thermal = upload(therm.data(), therm.size(), tot);
+  p.d_ray_mu = upload(p.tab.mu_ray.data(), p.tab.mu_ray.size(), tot);
+  p.d_ray_fac = upload(p.tab.fac_ray.data(), p.tab.fac_ray.size(), tot);
+  if (p.geom == RT_GEOM_SLAB) {
+    std::vector<double> dt(p.nz - 1);
+    for (int i = 0; i + 1 < p.nz; ++i) dt[i] = d.depth[i + 1] - d.depth[i];
+    p.d_dt = upload(dt.data(), dt.size(), tot);
+  } else {
+    p.d_kline = upload(d.k_line, (size_t)p.n_s, tot);
+    p.stencil.resize(p.n_omega);
+    const double dz = 1.0 / (p.nz - 1);
+    for (int o = 0; o < p.n_omega; ++o) {
+      const double mu = p.tab.mu_o[o];
+      const double path = dz / std::fabs(mu);
+      const double sx = -p.tab.om_x[o] * path * p.nx;
+      const double sy = -p.tab.om_y[o] * path * p.ny;
+      const double fx = std::floor(sx), fy = std::floor(sy);
+      BoxStencil s{};
+      s.i0 = (int)(((long long)fx % p.nx + p.nx) % p.nx);
+      s.j0 = (int)(((long long)fy % p.ny + p.ny) % p.ny);
+      s.tx = sx - fx;
+      s.ty = sy - fy;
+      s.path = path;
+      s.up = mu > 0 ? 1 : 0;
+      p.stencil[o] = s;
+    }
+    p.d_stencil = upload(p.stencil.data(), p.stencil.size(), tot);
+  }
+  p.bytes_problem = tot;
+}
+
+void operator_apply(Problem& p, int precision, const void* x, void* y, const double* xscale,
+                    hipStream_t st) {
+  const size_t n = (size_t)p.n;
+  switch (precision) {
+    case RT_PREC_FP64: {
+      double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
+      launch_lambda<double, double>(p, static_cast<const double*>(x), L, false, xscale, st);
+      launch_sigma_f64(p, L, static_cast<const double*>(x), static_cast<double*>(y), xscale, -1.0,
+                       st);
+      break;
+    }
+    case RT_PREC_FP32: {
+      float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
+      launch_lambda<float, float>(p, static_cast<const float*>(x), L, false, xscale, st);
+      launch_sigma_f32(p, L, static_cast<const float*>(x), static_cast<float*>(y), xscale, -1.0,
+                       st);
+      break;
+    }
+    case RT_PREC_BF16: {
+      auto* L = static_cast<__hip_bfloat16*>(problem_lbuf(p, n * 2));
+      launch_lambda<float, __hip_bfloat16>(p, static_cast<const float*>(x), L, false, xscale, st);
+      launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
+                       xscale, -1.0, st);
+      break;
+    }
+    case RT_PREC_FP16: {
+      auto* L = static_cast<__half*>(problem_lbuf(p, n * 2));
+      launch_lambda<float, __half>(p, static_cast<const float*>(x), L, false, xscale, st);
+      launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
+                       xscale, -1.0, st);
+      break;
+    }
+    case RT_PREC_BF16X3: {
+      float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
+      launch_lambda<float, float>(p, static_cast<const float*>(x), L, false, xscale, st);
+      launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
+                       xscale, -1.0, st);
+      break;
+    }
+    default:
+      fail(RT_E_INVALID, "unknown precision");
+  }
+}
+
+const double* physical_rhs(Problem& p, hipStream_t st) {
+  const size_t n = (size_t)p.n;
+  if (!p.d_rhs) RT_HIP(hipMalloc(&p.d_rhs, n * sizeof(double)));
+  double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
+  RT_HIP(hipMemsetAsync(p.d_rhs, 0, n * sizeof(double), st));
+  launch_lambda<double, double>(p, p.d_rhs, L, true, nullptr, st);
+  launch_sigma_f64(p, L, p.d_thermal, p.d_rhs, nullptr, +1.0, st);
+  return p.d_rhs;
+}
+
+}  // namespace rtsn
+
+using namespace rtsn;
+
+namespace {
+
+template <typename F>
+rt_status guarded(F&& f) {
+  try {
+    f();
+    return RT_OK;
+  } catch (const RtError& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return RT_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return RT_E_DEVICE;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return RT_E_DEVICE;
+  }
+}
+
+Problem* as_problem(rt_problem p) {
+  if (!p) fail(RT_E_INVALID, "null problem handle");
+  Problem* q = reinterpret_cast<Problem*>(p);
+  RT_HIP(hipSetDevice(q->device));
+  return q;
+}
+
+void check_prec(int prec) {
+  if (prec < RT_PREC_FP64 || prec > RT_PREC_BF16X3) fail(RT_E_INVALID, "unknown precision");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+int rt_version(void) { return RTSN_VERSION; }
+
+rt_status rt_problem_create(const rt_problem_desc* desc, int device, rt_problem* out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!desc || !out) fail(RT_E_INVALID, "null argument");
+    int ndev = 0;
+    RT_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(RT_E_INVALID, "bad device index");
+    RT_HIP(hipSetDevice(device));
+    Problem* p = new Problem();
+    p->device = device;
+    try {
+      problem_build(*p, *desc);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = reinterpret_cast<rt_problem>(p);
+  });
+}
+
+rt_status rt_problem_destroy(rt_problem p) {
+  return guarded([&] {
+    if (!p) return;
+    Problem* q = reinterpret_cast<Problem*>(p);
+    RT_HIP(hipSetDevice(q->device));
+    RT_HIP(hipDeviceSynchronize());
+    delete q;
+  });
+}
+
+rt_status rt_problem_footprint(rt_problem p, int restart, rt_problem_info* info) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    if (!info) fail(RT_E_INVALID, "null info");
+    if (restart < 1 || restart > kMaxRestart) fail(RT_E_INVALID, "restart out of range");
+    info->n_unknowns = q->n;
+    info->n_rays = q->n_r;
+    info->n_points = q->n_s;
+    info->bytes_problem = q->bytes_problem;
+    info->bytes_solve_fp64 = (int64_t)workspace_bytes(*q, restart, false, false) +
+                             (int64_t)(q->n * sizeof(double));
+    info->bytes_solve_mixed = (int64_t)workspace_bytes(*q, restart, true, false) +
+                              (int64_t)(q->n * sizeof(double));
+  });
+}
+
+rt_status rt_problem_tables(rt_problem p, double* mhat, double* mu_ray, double* w_ray,
+                            double* phi_ray) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    const size_t nr = (size_t)q->n_r;
+    if (mhat) std::memcpy(mhat, q->tab.mhat.data(), nr * nr * sizeof(double));
+    if (mu_ray) std::memcpy(mu_ray, q->tab.mu_ray.data(), nr * sizeof(double));
+    if (w_ray) std::memcpy(w_ray, q->tab.w_ray.data(), nr * sizeof(double));
+    if (phi_ray) std::memcpy(phi_ray, q->tab.phi_ray.data(), nr * sizeof(double));
+  });
+}
+
+rt_status rt_apply_lambda(rt_problem p, int precision, const void* s, void* I, int with_bc,
+                          const double* scale, void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    check_prec(precision);
+    if (!s || !I) fail(RT_E_INVALID, "null vector");
+    if (s == I) fail(RT_E_INVALID, "I must not alias s");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (precision == RT_PREC_FP64)
+      launch_lambda<double, double>(*q, static_cast<const double*>(s), static_cast<double*>(I),
+                                    with_bc != 0, scale, st);
+    else
+      launch_lambda<float, float>(*q, static_cast<const float*>(s), static_cast<float*>(I),
+                                  with_bc != 0, scale, st);
+  });
+}
+
+rt_status rt_apply_sigma(rt_problem p, int precision, const void* L, const void* x, void* y,
+                         void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    check_prec(precision);
+    if (!L || !y) fail(RT_E_INVALID, "null vector");
+    if (L == y) fail(RT_E_INVALID, "y must not alias L");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double sign = x ? -1.0 : +1.0;
+    if (precision == RT_PREC_FP64) {
+      launch_sigma_f64(*q, static_cast<const double*>(L), static_cast<const double*>(x),
+                       static_cast<double*>(y), nullptr, sign, st);
+    } else if (precision == RT_PREC_FP32) {
+      launch_sigma_f32(*q, static_cast<const float*>(L), static_cast<const float*>(x),
+                       static_cast<float*>(y), nullptr, sign, st);
+    } else {
+      // 16-bit operand paths take an FP32 L and round it like the operator does
+      const size_t n = (size_t)q->n;
+      void* lb = problem_lbuf(*q, n * lambda_elem_bytes(precision));
+      if (precision == RT_PREC_BF16X3) {
+        RT_HIP(hipMemcpyAsync(lb, L, n * sizeof(float), hipMemcpyDeviceToDevice, st));
+      } else if (precision == RT_PREC_BF16) {
+        k_convert<float, __hip_bfloat16>(static_cast<const float*>(L),
+                                         static_cast<__hip_bfloat16*>(lb), (int64_t)n, 1.0, st);
+      } else {
+        k_convert<float, __half>(static_cast<const float*>(L), static_cast<__half*>(lb),
+                                 (int64_t)n, 1.0, st);
+      }
+      launch_sigma_b16(*q, precision, lb, static_cast<const float*>(x), static_cast<float*>(y),
+                       nullptr, sign, st);
+    }
+  });
+}
+
+rt_status rt_apply_operator(rt_problem p, int precision, const void* x, void* y, void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    check_prec(precision);
+    if (!x || !y) fail(RT_E_INVALID, "null vector");
+    if (x == y) fail(RT_E_INVALID, "y must not alias x");
+    operator_apply(*q, precision, x, y, nullptr, static_cast<hipStream_t>(stream));
+  });
+}
+
+rt_status rt_rhs(rt_problem p, double* b, void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    if (!b) fail(RT_E_INVALID, "null vector");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* r = physical_rhs(*q, st);
+    RT_HIP(hipMemcpyAsync(b, r, (size_t)q->n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  });
+}
+
+rt_status rt_intensity(rt_problem p, const double* s, double* I, void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    if (!s || !I) fail(RT_E_INVALID, "null vector");
+    if (s == I) fail(RT_E_INVALID, "I must not alias s");
+    launch_lambda<double, double>(*q, s, I, true, nullptr, static_cast<hipStream_t>(stream));
+  });
+}
+
+void rt_solver_opts_default(rt_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->krylov = RT_KRYLOV_GMRES;
+  o->restart = 30;
+  o->max_iters = 10000;
+  o->rtol = 1e-8;
+  o->precision = RT_PREC_FP64;
+  o->inner_rtol = 1e-3;
+  o->max_outer = 50;
+  o->record_history = 1;
+}
+
+rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, double* x,
+                   int x_is_guess, rt_solve_stats* stats, void* stream) {
+  rt_status status = RT_OK;
+  rt_status g = guarded([&] {
+    Problem* q = as_problem(p);
+    if (!x) fail(RT_E_INVALID, "null solution vector");
+    rt_solver_opts o;
+    if (opts) o = *opts; else rt_solver_opts_default(&o);
+    if (o.krylov != RT_KRYLOV_GMRES && o.krylov != RT_KRYLOV_BICGSTAB)
+      fail(RT_E_INVALID, "unknown Krylov method");
+    if (o.restart < 1 || o.restart > kMaxRestart) fail(RT_E_INVALID, "restart out of range");
+    if (o.max_iters < 0) fail(RT_E_INVALID, "max_iters must be >= 0");
+    if (!(o.rtol > 0) || !std::isfinite(o.rtol)) fail(RT_E_INVALID, "rtol must be > 0");
+    check_prec(o.precision);
+    if (o.precision != RT_PREC_FP64 && !(o.inner_rtol > 0 && o.inner_rtol < 1))
+      fail(RT_E_INVALID, "inner_rtol must be in (0, 1)");
+    if (o.max_outer < 1) o.max_outer = 1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* bb = b ? b : physical_rhs(*q, st);
+    status = solve(*q, o, bb, x, x_is_guess, stats, st);
+  });
+  return g != RT_OK ? g : status;
+}
+
+}  // extern "C"

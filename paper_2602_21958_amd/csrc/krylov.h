@@ -1,0 +1,92 @@
+// Device-side Krylov state and the launchers of krylov.hip.
+#pragma once
+
+#include "rt_internal.h"
+
+namespace rtsn {
+
+constexpr int kMaxRestart = 128;
+constexpr int kReduceBlocks = 1024;
+
+// GMRES state kept in device memory.  The first fields are what the host
+// reads back after each step.
+struct GmresState {
+  double resid;        // |g_{j+1}| after the last Givens step
+  double beta;         // norm computed by finish_norm
+  int breakdown;       // h_{j+1,j} vanished (lucky breakdown)
+  int nonfinite;       // NaN/Inf met
+  double h[kMaxRestart + 1];
+  double R[(size_t)kMaxRestart * (kMaxRestart + 1)];  // column j at j*(kMaxRestart+1)
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double y[kMaxRestart];
+  double coef[kMaxRestart + 1];
+  double vscale[kMaxRestart + 1];
+};
+
+struct BicgState {
+  double rho, alpha, omega, beta;
+  double snorm, rnorm;
+  int iter, breakdown;
+};
+
+template <typename TV>
+void k_mdot(const TV* V, int64_t n, int cnt, const TV* w, double* partial, hipStream_t st);
+void k_reduce_rows(const double* partial, int64_t n, int nrows, const double* scale, double* out,
+                   hipStream_t st);
+template <typename TV>
+void k_update(const TV* V, int64_t n, int cnt, const double* h, const double* vscale, TV* w,
+              double* partial, hipStream_t st);
+template <typename TV, typename TX>
+void k_combine(const TV* V, int64_t n, int cnt, const double* coef, TX* x, hipStream_t st);
+template <typename TB, typename TA, typename TR>
+void k_residual(const TB* b, const TA* ax, int64_t n, TR* r, double* partial, hipStream_t st);
+template <typename T>
+void k_norm_partial(const T* x, int64_t n, double* partial, hipStream_t st);
+void k_finish_norm(const double* partial, int64_t n, GmresState* gs, int start_cycle,
+                   hipStream_t st);
+void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStream_t st);
+void k_givens(const double* partial, int64_t n, GmresState* gs, int j, hipStream_t st);
+void k_solve_r(GmresState* gs, int k, hipStream_t st);
+template <typename T>
+void k_dots4(const T* a0, const T* b0, const T* a1, const T* b1, int cnt, int64_t n,
+             double* partial, hipStream_t st);
+template <typename T>
+void k_bicg_p(const T* r, const T* v, T* p, int64_t n, const BicgState* bs, hipStream_t st);
+template <typename T>
+void k_bicg_s(T* r, const T* v, int64_t n, const BicgState* bs, double* partial, hipStream_t st);
+template <typename T>
+void k_bicg_xr(double* x, const T* p, T* r, const T* t, int64_t n, const BicgState* bs,
+               int only_alpha, double* partial, hipStream_t st);
+void k_bicg_scalar(const double* partial, int64_t n, int stage, BicgState* bs, hipStream_t st);
+template <typename TS, typename TD>
+void k_convert(const TS* a, TD* b, int64_t n, double scale, hipStream_t st);
+void k_axpy_f64(double* x, const float* d, int64_t n, const double* scale, hipStream_t st);
+int reduce_blocks(int64_t n);
+
+// Solver workspace, allocated on first use and kept with the problem.
+struct Workspace {
+  int restart = 0;
+  bool mixed = false;
+  size_t bytes = 0;
+  void* V = nullptr;            // (restart + 1) * n basis (double, or float if mixed)
+  double* partial = nullptr;    // (kMaxRestart + 1) * kReduceBlocks
+  GmresState* gs = nullptr;
+  BicgState* bs = nullptr;
+  double* scal = nullptr;       // small device scalars
+  double* r64 = nullptr;        // n FP64: residual / BiCGStab vectors
+  double* ax64 = nullptr;       // n FP64: A x
+  double* bic = nullptr;        // 4 n FP64 for BiCGStab (rhat, p, v, t)
+  float* d32 = nullptr;         // n: inner correction (mixed)
+  float* t32 = nullptr;         // n: scaled residual, inner right-hand side (mixed)
+  float* a32 = nullptr;         // n: inner operator output (mixed)
+  GmresState* host = nullptr;   // pinned status mirror
+  ~Workspace();
+};
+
+size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab);
+
+rt_status solve(Problem& p, const rt_solver_opts& o, const double* b, double* x, int x_is_guess,
+                rt_solve_stats* stats, hipStream_t st);
+
+}  // namespace rtsn

@@ -1,0 +1,518 @@
+// Krylov building blocks on gfx950: Arnoldi (classical Gram-Schmidt) dots
+// and update, Givens rotations of the Hessenberg column, cycle-end update,
+// residuals and BiCGStab vector updates.
+//
+// The paper solves the system with restarted GMRES (Sec. 5.3: restart 30)
+// and BiCGStab (Sec. 5 set-up).  Here every vector pass streams HBM once:
+//  * mdot:   h_i = s_i <W_i, w> for all i <= j in one pass over w (basis
+//            vectors stored unnormalised, W_i = v_i / s_i, with the scale s_i
+//            kept on the device so no separate normalisation pass is needed);
+//  * update: w -= sum_i (h_i s_i) W_i and ||w||^2 in one pass;
+//  * givens: one workgroup turns the new Hessenberg column into a column of
+//            R, updates g and writes |g_{j+1}| and 1/h_{j+1,j} on the device.
+// Reductions are deterministic: a fixed grid writes per-block partial sums
+// that one workgroup adds in a fixed order; accumulation is in FP64 for
+// FP32 and FP64 vectors alike.
+#include "rt_internal.h"
+#include "krylov.h"
+
+namespace rtsn {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block-reduce G accumulators; result valid in thread 0 for each g, written
+// to out[g * stride].
+template <int G>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[G], double* out, int stride,
+                                                   int count) {
+  __shared__ double red[G][kThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    double v = wave_sum(acc[g]);
+    if (lane == 0) red[g][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < G && threadIdx.x < count) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s += red[threadIdx.x][w];
+    out[(size_t)threadIdx.x * stride] = s;
+  }
+  __syncthreads();
+}
+
+// partial[i * nb + b] = sum over block b's elements of W_i[n] * w[n]
+template <typename TV, int G>
+__global__ __launch_bounds__(kThreads) void mdot_kernel(const TV* __restrict__ V, int64_t n,
+                                                        int i0, int cnt,
+                                                        const TV* __restrict__ w,
+                                                        double* __restrict__ partial) {
+  double acc[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const double wv = (double)w[e];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (g < cnt) acc[g] += (double)V[(size_t)(i0 + g) * n + e] * wv;
+  }
+  block_reduce_store<G>(acc, partial + (size_t)i0 * gridDim.x + blockIdx.x, gridDim.x, cnt);
+}
+
+// out[i] = scale_i * sum_b partial[i * nb + b]   (one wave per i)
+__global__ __launch_bounds__(kThreads) void reduce_rows_kernel(const double* __restrict__ partial,
+                                                               int nb, int nrows,
+                                                               const double* __restrict__ scale,
+                                                               double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nrows; i += kThreads / 64) {
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += partial[(size_t)i * nb + b];
+    s = wave_sum(s);
+    if (lane == 0) out[i] = scale ? scale[i] * s : s;
+  }
+}
+
+// w -= sum_i coef_i W_i with coef_i = h_i * s_i; partial norm^2 of new w.
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__ V, int64_t n,
+                                                          int cnt, const double* __restrict__ h,
+                                                          const double* __restrict__ vscale,
+                                                          TV* __restrict__ w,
+                                                          double* __restrict__ partial) {
+  __shared__ double coef[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < cnt; i += kThreads) coef[i] = h[i] * vscale[i];
+  __syncthreads();
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    double v = (double)w[e];
+    for (int i = 0; i < cnt; ++i) v -= coef[i] * (double)V[(size_t)i * n + e];
+    const TV vs = (TV)v;
+    w[e] = vs;
+    nrm += (double)vs * (double)vs;
+  }
+  double a[1] = {nrm};
+  block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
+}
+
+// x += sum_i coef_i W_i (coef on device, cnt <= kMaxRestart+1)
+template <typename TV, typename TX>
+__global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict__ V, int64_t n,
+                                                           int cnt, const double* __restrict__ coef_d,
+                                                           TX* __restrict__ x) {
+  __shared__ double coef[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < cnt; i += kThreads) coef[i] = coef_d[i];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    double v = (double)x[e];
+    for (int i = 0; i < cnt; ++i) v += coef[i] * (double)V[(size_t)i * n + e];
+    x[e] = (TX)v;
+  }
+}
+
+// r = b - ax (into r, type TR), partial norm^2 of r
+template <typename TB, typename TA, typename TR>
+__global__ __launch_bounds__(kThreads) void residual_kernel(const TB* __restrict__ b,
+                                                            const TA* __restrict__ ax, int64_t n,
+                                                            TR* __restrict__ r,
+                                                            double* __restrict__ partial) {
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const double v = (double)b[e] - (double)ax[e];
+    const TR rv = (TR)v;
+    r[e] = rv;
+    nrm += (double)rv * (double)rv;
+  }
+  double a[1] = {nrm};
+  block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
+}
+
+// partial norm^2 of x (and non-finite flag via NaN propagation)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void norm_kernel(const T* __restrict__ x, int64_t n,
+                                                        double* __restrict__ partial) {
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const double v = (double)x[e];
+    nrm += v * v;
+  }
+  double a[1] = {nrm};
+  block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
+}
+
+// Sum partial norms: st->beta = sqrt(sum); optionally start a GMRES cycle:
+// vscale[0] = 1/beta, g[0] = beta.
+__global__ __launch_bounds__(64) void finish_norm_kernel(const double* __restrict__ partial,
+                                                         int nb, GmresState* st, int start_cycle) {
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += partial[b];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const double beta = sqrt(s);
+    st->beta = beta;
+    if (start_cycle) {
+      st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+      st->g[0] = beta;
+      for (int i = 1; i <= kMaxRestart; ++i) st->g[i] = 0.0;
+    }
+  }
+}
+
+// Givens step j: column h[0..j] (already scaled dots), h_{j+1,j} from the
+// update's partial norms.
+__global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ partial, int nb,
+                                                    GmresState* st, int j) {
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += partial[b];
+  s = wave_sum(s);
+  if (lane != 0) return;
+  const double hn = sqrt(s);
+  double* col = st->R + (size_t)j * (kMaxRestart + 1);
+  for (int i = 0; i <= j; ++i) col[i] = st->h[i];
+  const double raw_diag = col[j];
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t1 = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
+    col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
+    col[i] = t1;
+  }
+  double c = 1.0, sn = 0.0;
+  if (col[j + 1] != 0.0) {
+    const double hh = hypot(col[j], col[j + 1]);
+    c = col[j] / hh;
+    sn = col[j + 1] / hh;
+  }
+  st->cs[j] = c;
+  st->sn[j] = sn;
+  col[j] = c * col[j] + sn * col[j + 1];
+  col[j + 1] = 0.0;
+  st->g[j + 1] = -sn * st->g[j];
+  st->g[j] = c * st->g[j];
+  const int breakdown = !(hn > 1e-14 * fabs(raw_diag) + 1e-300);
+  st->vscale[j + 1] = breakdown ? 0.0 : 1.0 / hn;
+  st->resid = fabs(st->g[j + 1]);
+  st->breakdown = breakdown;
+  st->nonfinite = !isfinite(hn) || !isfinite(st->resid);
+}
+
+// Back substitution R y = g (k x k), coef_i = y_i * vscale_i.
+__global__ __launch_bounds__(64) void solve_r_kernel(GmresState* st, int k) {
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double v = st->g[i];
+    for (int l = i + 1; l < k; ++l) v -= st->R[(size_t)l * (kMaxRestart + 1) + i] * st->y[l];
+    st->y[i] = v / st->R[(size_t)i * (kMaxRestart + 1) + i];
+  }
+  for (int i = 0; i < k; ++i) st->coef[i] = st->y[i] * st->vscale[i];
+}
+
+// ------------------------------------------------------------- BiCGStab
+// out[c * nb + b] partials of up to 4 dot products <a_c, b_c>
+template <typename T>
+__global__ __launch_bounds__(kThreads) void dots4_kernel(const T* a0, const T* b0, const T* a1,
+                                                         const T* b1, const T* a2, const T* b2,
+                                                         const T* a3, const T* b3, int cnt,
+                                                         int64_t n, double* __restrict__ partial) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    acc[0] += (double)a0[e] * (double)b0[e];
+    if (cnt > 1) acc[1] += (double)a1[e] * (double)b1[e];
+    if (cnt > 2) acc[2] += (double)a2[e] * (double)b2[e];
+    if (cnt > 3) acc[3] += (double)a3[e] * (double)b3[e];
+  }
+  block_reduce_store<4>(acc, partial + blockIdx.x, gridDim.x, cnt);
+}
+
+// p = r + beta (p - omega v)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bicg_p_kernel(const T* __restrict__ r,
+                                                          const T* __restrict__ v, T* __restrict__ p,
+                                                          int64_t n, const BicgState* st) {
+  const double beta = st->beta, omega = st->omega;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
+    p[e] = (T)((double)r[e] + beta * ((double)p[e] - omega * (double)v[e]));
+}
+
+// s = r - alpha v (written over r), partial ||s||^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bicg_s_kernel(T* __restrict__ r, const T* __restrict__ v,
+                                                          int64_t n, const BicgState* st,
+                                                          double* __restrict__ partial) {
+  const double alpha = st->alpha;
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const T s = (T)((double)r[e] - alpha * (double)v[e]);
+    r[e] = s;
+    nrm += (double)s * (double)s;
+  }
+  double a[1] = {nrm};
+  block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
+}
+
+// x += alpha p + omega s ; r = s - omega t (s stored in r), partial ||r||^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void bicg_xr_kernel(double* __restrict__ x,
+                                                           const T* __restrict__ p,
+                                                           T* __restrict__ r,
+                                                           const T* __restrict__ t, int64_t n,
+                                                           const BicgState* st, int only_alpha,
+                                                           double* __restrict__ partial) {
+  const double alpha = st->alpha, omega = only_alpha ? 0.0 : st->omega;
+  double nrm = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const double s = (double)r[e];
+    x[e] += alpha * (double)p[e] + omega * s;
+    if (!only_alpha) {
+      const T rn = (T)(s - omega * (double)t[e]);
+      r[e] = rn;
+      nrm += (double)rn * (double)rn;
+    }
+  }
+  double a[1] = {nrm};
+  block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
+}
+
+// Scalar stages of BiCGStab on the device.
+// stage 0: rho_new = <rhat, r>; beta = (rho_new/rho)(alpha/omega); rho = rho_new
+// stage 1: alpha = rho / <rhat, v>
+// stage 2: omega = <t, s> / <t, t>
+__global__ __launch_bounds__(64) void bicg_scalar_kernel(const double* __restrict__ partial,
+                                                         int nb, int stage, BicgState* st) {
+  const int lane = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    s0 += partial[b];
+    if (stage == 2) s1 += partial[nb + b];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane != 0) return;
+  if (stage == 0) {
+    const double rho_new = s0;
+    st->beta = (st->iter == 0) ? 0.0 : (rho_new / st->rho) * (st->alpha / st->omega);
+    st->breakdown = (rho_new == 0.0 || !isfinite(rho_new));
+    st->rho = rho_new;
+  } else if (stage == 1) {
+    st->alpha = (s0 != 0.0) ? st->rho / s0 : 0.0;
+    st->breakdown = (s0 == 0.0 || !isfinite(s0));
+  } else {
+    st->omega = (s1 != 0.0) ? s0 / s1 : 0.0;
+    st->breakdown = (s1 == 0.0 || st->omega == 0.0 || !isfinite(st->omega));
+  }
+}
+
+__global__ __launch_bounds__(64) void finish_norm_simple_kernel(const double* __restrict__ partial,
+                                                                int nb, double* out) {
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += partial[b];
+  s = wave_sum(s);
+  if (lane == 0) *out = sqrt(s);
+}
+
+template <typename TD> __device__ __forceinline__ TD cvt_from(double v) { return (TD)v; }
+template <> __device__ __forceinline__ __hip_bfloat16 cvt_from<__hip_bfloat16>(double v) {
+  return __float2bfloat16((float)v);
+}
+template <> __device__ __forceinline__ __half cvt_from<__half>(double v) {
+  return __float2half((float)v);
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kThreads) void convert_kernel(const TS* __restrict__ a,
+                                                           TD* __restrict__ b, int64_t n,
+                                                           double scale) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
+    b[e] = cvt_from<TD>(scale * (double)a[e]);
+}
+
+__global__ __launch_bounds__(kThreads) void axpy_f64_kernel(double* __restrict__ x,
+                                                            const float* __restrict__ d, int64_t n,
+                                                            const double* __restrict__ scale) {
+  const double s = scale ? *scale : 1.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride)
+    x[e] += s * (double)d[e];
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  return (int)(g < kReduceBlocks ? (g < 1 ? 1 : g) : kReduceBlocks);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <typename TV>
+void k_mdot(const TV* V, int64_t n, int cnt, const TV* w, double* partial, hipStream_t st) {
+  const int nb = grid_for(n);
+  for (int i0 = 0; i0 < cnt; i0 += 16) {
+    const int c = cnt - i0 < 16 ? cnt - i0 : 16;
+    hipLaunchKernelGGL((mdot_kernel<TV, 16>), dim3(nb), dim3(kThreads), 0, st, V, n, i0, c, w,
+                       partial);
+  }
+  RT_HIP(hipGetLastError());
+}
+
+void k_reduce_rows(const double* partial, int64_t n, int nrows, const double* scale, double* out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, st, partial, grid_for(n),
+                     nrows, scale, out);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename TV>
+void k_update(const TV* V, int64_t n, int cnt, const double* h, const double* vscale, TV* w,
+              double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((update_kernel<TV>), dim3(grid_for(n)), dim3(kThreads), 0, st, V, n, cnt, h,
+                     vscale, w, partial);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename TV, typename TX>
+void k_combine(const TV* V, int64_t n, int cnt, const double* coef, TX* x, hipStream_t st) {
+  hipLaunchKernelGGL((combine_kernel<TV, TX>), dim3(grid_for(n)), dim3(kThreads), 0, st, V, n,
+                     cnt, coef, x);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename TB, typename TA, typename TR>
+void k_residual(const TB* b, const TA* ax, int64_t n, TR* r, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((residual_kernel<TB, TA, TR>), dim3(grid_for(n)), dim3(kThreads), 0, st, b,
+                     ax, n, r, partial);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void k_norm_partial(const T* x, int64_t n, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((norm_kernel<T>), dim3(grid_for(n)), dim3(kThreads), 0, st, x, n, partial);
+  RT_HIP(hipGetLastError());
+}
+
+void k_finish_norm(const double* partial, int64_t n, GmresState* gs, int start_cycle,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(finish_norm_kernel, dim3(1), dim3(64), 0, st, partial, grid_for(n), gs,
+                     start_cycle);
+  RT_HIP(hipGetLastError());
+}
+
+void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(finish_norm_simple_kernel, dim3(1), dim3(64), 0, st, partial, grid_for(n),
+                     out);
+  RT_HIP(hipGetLastError());
+}
+
+void k_givens(const double* partial, int64_t n, GmresState* gs, int j, hipStream_t st) {
+  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_for(n), gs, j);
+  RT_HIP(hipGetLastError());
+}
+
+void k_solve_r(GmresState* gs, int k, hipStream_t st) {
+  hipLaunchKernelGGL(solve_r_kernel, dim3(1), dim3(64), 0, st, gs, k);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void k_dots4(const T* a0, const T* b0, const T* a1, const T* b1, int cnt, int64_t n,
+             double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((dots4_kernel<T>), dim3(grid_for(n)), dim3(kThreads), 0, st, a0, b0, a1, b1,
+                     a0, b0, a0, b0, cnt, n, partial);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void k_bicg_p(const T* r, const T* v, T* p, int64_t n, const BicgState* bs, hipStream_t st) {
+  hipLaunchKernelGGL((bicg_p_kernel<T>), dim3(grid_for(n)), dim3(kThreads), 0, st, r, v, p, n, bs);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void k_bicg_s(T* r, const T* v, int64_t n, const BicgState* bs, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((bicg_s_kernel<T>), dim3(grid_for(n)), dim3(kThreads), 0, st, r, v, n, bs,
+                     partial);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void k_bicg_xr(double* x, const T* p, T* r, const T* t, int64_t n, const BicgState* bs,
+               int only_alpha, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((bicg_xr_kernel<T>), dim3(grid_for(n)), dim3(kThreads), 0, st, x, p, r, t, n,
+                     bs, only_alpha, partial);
+  RT_HIP(hipGetLastError());
+}
+
+void k_bicg_scalar(const double* partial, int64_t n, int stage, BicgState* bs, hipStream_t st) {
+  hipLaunchKernelGGL(bicg_scalar_kernel, dim3(1), dim3(64), 0, st, partial, grid_for(n), stage,
+                     bs);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename TS, typename TD>
+void k_convert(const TS* a, TD* b, int64_t n, double scale, hipStream_t st) {
+  hipLaunchKernelGGL((convert_kernel<TS, TD>), dim3(grid_for(n)), dim3(kThreads), 0, st, a, b, n,
+                     scale);
+  RT_HIP(hipGetLastError());
+}
+
+void k_axpy_f64(double* x, const float* d, int64_t n, const double* scale, hipStream_t st) {
+  hipLaunchKernelGGL(axpy_f64_kernel, dim3(grid_for(n)), dim3(kThreads), 0, st, x, d, n, scale);
+  RT_HIP(hipGetLastError());
+}
+
+int reduce_blocks(int64_t n) { return grid_for(n); }
+
+// explicit instantiations
+template void k_mdot<double>(const double*, int64_t, int, const double*, double*, hipStream_t);
+template void k_mdot<float>(const float*, int64_t, int, const float*, double*, hipStream_t);
+template void k_update<double>(const double*, int64_t, int, const double*, const double*, double*,
+                               double*, hipStream_t);
+template void k_update<float>(const float*, int64_t, int, const double*, const double*, float*,
+                              double*, hipStream_t);
+template void k_combine<double, double>(const double*, int64_t, int, const double*, double*,
+                                        hipStream_t);
+template void k_combine<float, float>(const float*, int64_t, int, const double*, float*,
+                                      hipStream_t);
+template void k_residual<double, double, double>(const double*, const double*, int64_t, double*,
+                                                 double*, hipStream_t);
+template void k_residual<double, double, float>(const double*, const double*, int64_t, float*,
+                                                double*, hipStream_t);
+template void k_residual<float, float, float>(const float*, const float*, int64_t, float*,
+                                              double*, hipStream_t);
+template void k_norm_partial<double>(const double*, int64_t, double*, hipStream_t);
+template void k_norm_partial<float>(const float*, int64_t, double*, hipStream_t);
+template void k_dots4<double>(const double*, const double*, const double*, const double*, int,
+                              int64_t, double*, hipStream_t);
+template void k_bicg_p<double>(const double*, const double*, double*, int64_t, const BicgState*,
+                               hipStream_t);
+template void k_bicg_s<double>(double*, const double*, int64_t, const BicgState*, double*,
+                               hipStream_t);
+template void k_bicg_xr<double>(double*, const double*, double*, const double*, int64_t,
+                                const BicgState*, int, double*, hipStream_t);
+template void k_convert<double, float>(const double*, float*, int64_t, double, hipStream_t);
+template void k_convert<float, double>(const float*, double*, int64_t, double, hipStream_t);
+template void k_convert<float, __hip_bfloat16>(const float*, __hip_bfloat16*, int64_t, double,
+                                               hipStream_t);
+template void k_convert<float, __half>(const float*, __half*, int64_t, double, hipStream_t);
+
+}  // namespace rtsn

@@ -1,0 +1,111 @@
+// Internal declarations of the rtsn library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rtsn.h"
+
+namespace rtsn {
+
+// --------------------------------------------------------------------------
+// Errors: internal code throws RtError; the ABI layer converts to rt_status.
+struct RtError {
+  rt_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(rt_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define RT_HIP(call) ::rtsn::hip_check((call), #call)
+
+// --------------------------------------------------------------------------
+// Host-side discretisation tables (FP64), built in setup.cpp.
+struct Tables {
+  std::vector<double> mu_o, w_o;        // per ordinate: direction cosine, weight
+  std::vector<double> om_x, om_y;       // per ordinate horizontal components (box)
+  std::vector<double> x_nu, w_nu, phi;  // per frequency
+  std::vector<double> mu_ray, w_ray, phi_ray, fac_ray;  // per ray k = o*n_nu+nu
+  std::vector<double> mhat;             // n_r x n_r row-major
+};
+
+void build_tables(const rt_problem_desc& d, Tables& t);
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Upwind stencil of one box ordinate (plane-to-plane short characteristics).
+struct BoxStencil {
+  int i0, j0;       // upwind cell offsets, reduced mod nx / ny (>= 0)
+  int up;           // 1: sweep bottom -> top (mu > 0), 0: top -> bottom
+  int pad;
+  double tx, ty;    // bilinear fractions
+  double path;      // dz / |mu|
+};
+
+// --------------------------------------------------------------------------
+// Device-resident problem.
+struct Workspace;
+
+struct Problem {
+  int device = 0;
+  int geom = RT_GEOM_SLAB;
+  int nx = 1, ny = 1, nz = 2;
+  int n_mu = 2, n_az = 1, n_nu = 1, n_omega = 2, n_r = 2;
+  int64_t n_s = 0, n = 0;
+  int formal = RT_FORMAL_LINEAR_SC;
+  double r = 0, i_top = 0, i_bot = 0;
+  Tables tab;
+  std::vector<BoxStencil> stencil;      // box: per ordinate
+
+  // device data
+  double* d_mhat64 = nullptr;           // n_r x n_r
+  float* d_mhat32 = nullptr;
+  __hip_bfloat16* d_mhat_bf16 = nullptr;   // hi part
+  __hip_bfloat16* d_mhat_bf16_lo = nullptr;
+  __half* d_mhat_f16 = nullptr;         // column-scaled
+  float* d_f16_colscale = nullptr;      // n_r: undo factor per column k'
+  double* d_albedo = nullptr;           // n_s: 1 - eps_i
+  double* d_thermal = nullptr;          // n: t
+  double* d_dt = nullptr;               // slab: nz-1 depth increments
+  double* d_kline = nullptr;            // box: n_s
+  double* d_ray_mu = nullptr;           // n_r
+  double* d_ray_fac = nullptr;          // n_r: phi_nu + r
+  BoxStencil* d_stencil = nullptr;      // box: n_omega
+  double* d_rhs = nullptr;              // physical right-hand side (lazily built)
+  void* d_lbuf = nullptr;               // scratch for Lambda output (apply_operator)
+  size_t lbuf_bytes = 0;
+  Workspace* ws = nullptr;
+  int64_t bytes_problem = 0;
+  std::vector<double> history;
+
+  ~Problem();
+};
+
+void problem_build(Problem& p, const rt_problem_desc& d);
+void* problem_lbuf(Problem& p, size_t bytes);
+
+// --------------------------------------------------------------------------
+// Kernel launchers.  Vector types: V = double (FP64) or float (others).
+// Lambda output type LT: double, float, __hip_bfloat16 or __half.
+template <typename VT, typename LT>
+void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
+                   const double* scale, hipStream_t st);
+
+// y = xs * x + sign * albedo .* (Mhat L); x may be null (then xs ignored).
+void launch_sigma_f64(const Problem& p, const double* L, const double* x, double* y,
+                      const double* xscale, double sign, hipStream_t st);
+void launch_sigma_f32(const Problem& p, const float* L, const float* x, float* y,
+                      const double* xscale, double sign, hipStream_t st);
+void launch_sigma_b16(const Problem& p, int precision, const void* L, const float* x,
+                      float* y, const double* xscale, double sign, hipStream_t st);
+
+// Operator y = A (xs x) in the given precision, using the problem's L buffer.
+void operator_apply(Problem& p, int precision, const void* x, void* y,
+                    const double* xscale, hipStream_t st);
+size_t lambda_elem_bytes(int precision);
+const double* physical_rhs(Problem& p, hipStream_t st);
+
+}  // namespace rtsn

@@ -1,0 +1,341 @@
+// Krylov solvers driven from the host, all vector work on the device.
+//
+// * Restarted GMRES(m) (Saad-Schultz) with classical Gram-Schmidt Arnoldi,
+//   Givens rotations and a true-residual check at the end of each cycle; the
+//   paper's solver (Sec. 5 set-up; Sec. 5.3 restart 30).  The host reads one
+//   scalar per Arnoldi step (|g_{j+1}|) and one per cycle (true residual).
+// * Mixed precision: FP64 iterative refinement around a low-precision inner
+//   GMRES: r = b - A_64 x in FP64, inner solve of A_lo d = r / ||r|| with an
+//   FP32 basis (FP64 dot accumulation) and the operator in FP32 / BF16 /
+//   FP16 / split-BF16 arithmetic, then x += ||r|| d.
+// * BiCGStab (van der Vorst), FP64, scalars kept on the device.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "krylov.h"
+
+namespace rtsn {
+
+Workspace::~Workspace() {
+  hipFree(V);
+  hipFree(partial);
+  hipFree(gs);
+  hipFree(bs);
+  hipFree(scal);
+  hipFree(r64);
+  hipFree(ax64);
+  hipFree(bic);
+  hipFree(d32);
+  hipFree(t32);
+  hipFree(a32);
+  if (host) hipHostFree(host);
+}
+
+size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab) {
+  const size_t n = (size_t)p.n;
+  size_t b = sizeof(double) * (size_t)(kMaxRestart + 1) * kReduceBlocks + sizeof(GmresState) +
+             sizeof(BicgState) + 64 * sizeof(double);
+  b += (size_t)(restart + 1) * n * (mixed ? sizeof(float) : sizeof(double));
+  b += 2 * n * sizeof(double);  // r64, ax64
+  if (mixed) b += 3 * n * sizeof(float);
+  if (bicgstab) b += 4 * n * sizeof(double);
+  b += n * lambda_elem_bytes(mixed ? RT_PREC_FP32 : RT_PREC_FP64);  // operator L buffer
+  return b;
+}
+
+namespace {
+
+template <typename T>
+T* dalloc(size_t count, size_t& total) {
+  void* ptr = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(RT_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  total += count * sizeof(T);
+  return static_cast<T*>(ptr);
+}
+
+Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab) {
+  Workspace* ws = p.ws;
+  const bool ok = ws && ws->restart >= restart && ws->mixed == mixed &&
+                  (!bicgstab || ws->bic != nullptr);
+  if (ok) return *ws;
+  delete p.ws;
+  p.ws = nullptr;
+  ws = new Workspace();
+  p.ws = ws;
+  const size_t n = (size_t)p.n;
+  size_t tot = 0;
+  ws->restart = restart;
+  ws->mixed = mixed;
+  if (mixed)
+    ws->V = dalloc<float>((size_t)(restart + 1) * n, tot);
+  else
+    ws->V = dalloc<double>((size_t)(restart + 1) * n, tot);
+  ws->partial = dalloc<double>((size_t)(kMaxRestart + 1) * kReduceBlocks, tot);
+  ws->gs = dalloc<GmresState>(1, tot);
+  ws->bs = dalloc<BicgState>(1, tot);
+  ws->scal = dalloc<double>(64, tot);
+  ws->r64 = dalloc<double>(n, tot);
+  ws->ax64 = dalloc<double>(n, tot);
+  if (mixed) {
+    ws->d32 = dalloc<float>(n, tot);
+    ws->t32 = dalloc<float>(n, tot);
+    ws->a32 = dalloc<float>(n, tot);
+  }
+  if (bicgstab) ws->bic = dalloc<double>(4 * n, tot);
+  RT_HIP(hipHostMalloc((void**)&ws->host, sizeof(GmresState), hipHostMallocDefault));
+  RT_HIP(hipMemset(ws->gs, 0, sizeof(GmresState)));
+  ws->bytes = tot;
+  return *ws;
+}
+
+struct Status {
+  double resid, beta;
+  int breakdown, nonfinite;
+};
+
+Status read_status(Workspace& ws, hipStream_t st) {
+  RT_HIP(hipMemcpyAsync(ws.host, ws.gs, offsetof(GmresState, h), hipMemcpyDeviceToHost, st));
+  RT_HIP(hipStreamSynchronize(st));
+  return Status{ws.host->resid, ws.host->beta, ws.host->breakdown, ws.host->nonfinite};
+}
+
+double read_scalar(const double* d, hipStream_t st, Workspace& ws) {
+  double* h = reinterpret_cast<double*>(ws.host);
+  RT_HIP(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st));
+  RT_HIP(hipStreamSynchronize(st));
+  return *h;
+}
+
+template <typename TV>
+double vec_norm(const TV* v, int64_t n, Workspace& ws, hipStream_t st) {
+  k_norm_partial<TV>(v, n, ws.partial, st);
+  k_finish_norm_simple(ws.partial, n, ws.scal, st);
+  return read_scalar(ws.scal, st, ws);
+}
+
+struct CoreResult {
+  int iters = 0;
+  int cycles = 0;
+  double beta = 0;  // last true residual norm (operator of the core's precision)
+};
+
+// GMRES(m) on A_prec x = b with vectors of type TV.  x is overwritten; if
+// x_zero it starts from 0.  Returns RT_OK / RT_NOT_CONVERGED.
+template <typename TV>
+rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int m, double rtol,
+                     int max_iters, double bnorm, Workspace& ws, TV* tmp, hipStream_t st,
+                     std::vector<double>* hist, CoreResult& res) {
+  const int64_t n = p.n;
+  TV* V = static_cast<TV*>(ws.V);
+  GmresState* gs = ws.gs;
+  if (x_zero) {
+    RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(TV), st));
+    RT_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(TV), hipMemcpyDeviceToDevice, st));
+    k_norm_partial<TV>(V, n, ws.partial, st);
+  } else {
+    operator_apply(p, prec, x, tmp, nullptr, st);
+    k_residual<TV, TV, TV>(b, tmp, n, V, ws.partial, st);
+  }
+  k_finish_norm(ws.partial, n, gs, 1, st);
+  Status s = read_status(ws, st);
+  if (!std::isfinite(s.beta)) fail(RT_E_NONFINITE, "non-finite residual");
+  res.beta = s.beta;
+  if (hist) hist->push_back(s.beta / bnorm);
+  while (s.beta > rtol * bnorm && res.iters < max_iters) {
+    res.cycles++;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      TV* vj = V + (size_t)j * n;
+      TV* w = V + (size_t)(j + 1) * n;
+      operator_apply(p, prec, vj, w, gs->vscale + j, st);
+      k_mdot<TV>(V, n, j + 1, w, ws.partial, st);
+      k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
+      k_update<TV>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
+      k_givens(ws.partial, n, gs, j, st);
+      Status g = read_status(ws, st);
+      res.iters++;
+      k = j + 1;
+      if (g.nonfinite) fail(RT_E_NONFINITE, "non-finite value in the Arnoldi process");
+      if (hist) hist->push_back(g.resid / bnorm);
+      if (g.breakdown || g.resid <= rtol * bnorm || res.iters >= max_iters) break;
+    }
+    k_solve_r(gs, k, st);
+    k_combine<TV, TV>(V, n, k, gs->coef, x, st);
+    operator_apply(p, prec, x, tmp, nullptr, st);
+    k_residual<TV, TV, TV>(b, tmp, n, V, ws.partial, st);
+    k_finish_norm(ws.partial, n, gs, 1, st);
+    s = read_status(ws, st);
+    if (!std::isfinite(s.beta)) fail(RT_E_NONFINITE, "non-finite residual");
+    res.beta = s.beta;
+    if (s.beta > rtol * bnorm && res.iters < max_iters && hist) hist->push_back(s.beta / bnorm);
+  }
+  return s.beta <= rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
+}
+
+rt_status bicgstab_fp64(Problem& p, const double* b, double* x, bool x_zero, double rtol,
+                        int max_iters, double bnorm, Workspace& ws, hipStream_t st,
+                        std::vector<double>* hist, CoreResult& res) {
+  const int64_t n = p.n;
+  double* r = ws.r64;
+  double* rhat = ws.bic;
+  double* pv = ws.bic + n;
+  double* v = ws.bic + 2 * n;
+  double* t = ws.bic + 3 * n;
+  BicgState* bs = ws.bs;
+  if (x_zero) {
+    RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+    RT_HIP(hipMemcpyAsync(r, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    operator_apply(p, RT_PREC_FP64, x, ws.ax64, nullptr, st);
+    k_residual<double, double, double>(b, ws.ax64, n, r, ws.partial, st);
+  }
+  RT_HIP(hipMemcpyAsync(rhat, r, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  RT_HIP(hipMemsetAsync(pv, 0, (size_t)n * sizeof(double), st));
+  RT_HIP(hipMemsetAsync(v, 0, (size_t)n * sizeof(double), st));
+  BicgState init{1.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0, 0};
+  RT_HIP(hipMemcpyAsync(bs, &init, sizeof(init), hipMemcpyHostToDevice, st));
+  double rn = vec_norm<double>(r, n, ws, st);
+  res.beta = rn;
+  if (hist) hist->push_back(rn / bnorm);
+  BicgState hs{};
+  auto read_bs = [&]() {
+    RT_HIP(hipMemcpyAsync(ws.host, bs, sizeof(BicgState), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    std::memcpy(&hs, ws.host, sizeof(BicgState));
+  };
+  int it = 0;
+  while (rn > rtol * bnorm && it < max_iters) {
+    k_dots4<double>(rhat, r, nullptr, nullptr, 1, n, ws.partial, st);
+    k_bicg_scalar(ws.partial, n, 0, bs, st);
+    k_bicg_p<double>(r, v, pv, n, bs, st);
+    operator_apply(p, RT_PREC_FP64, pv, v, nullptr, st);
+    k_dots4<double>(rhat, v, nullptr, nullptr, 1, n, ws.partial, st);
+    k_bicg_scalar(ws.partial, n, 1, bs, st);
+    k_bicg_s<double>(r, v, n, bs, ws.partial, st);  // r now holds s
+    k_finish_norm_simple(ws.partial, n, ws.scal, st);
+    const double sn = read_scalar(ws.scal, st, ws);
+    read_bs();
+    it++;
+    if (hs.breakdown) return RT_E_BREAKDOWN;
+    if (sn <= rtol * bnorm) {
+      k_bicg_xr<double>(x, pv, r, t, n, bs, 1, ws.partial, st);
+      rn = sn;
+      if (hist) hist->push_back(rn / bnorm);
+      break;
+    }
+    operator_apply(p, RT_PREC_FP64, r, t, nullptr, st);
+    k_dots4<double>(t, r, t, t, 2, n, ws.partial, st);
+    k_bicg_scalar(ws.partial, n, 2, bs, st);
+    k_bicg_xr<double>(x, pv, r, t, n, bs, 0, ws.partial, st);
+    k_finish_norm_simple(ws.partial, n, ws.scal, st);
+    rn = read_scalar(ws.scal, st, ws);
+    read_bs();
+    if (!std::isfinite(rn)) fail(RT_E_NONFINITE, "non-finite residual");
+    if (hist) hist->push_back(rn / bnorm);
+    if (hs.breakdown) return RT_E_BREAKDOWN;
+    // next iteration's scalar stage uses iter > 0
+    int one = 1;
+    RT_HIP(hipMemcpyAsync(&bs->iter, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  res.iters = it;
+  // true residual
+  operator_apply(p, RT_PREC_FP64, x, ws.ax64, nullptr, st);
+  k_residual<double, double, double>(b, ws.ax64, n, ws.r64, ws.partial, st);
+  k_finish_norm_simple(ws.partial, n, ws.scal, st);
+  res.beta = read_scalar(ws.scal, st, ws);
+  return res.beta <= rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
+}
+
+}  // namespace
+
+rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double* x,
+                int x_is_guess, rt_solve_stats* stats, hipStream_t st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const bool mixed = o.precision != RT_PREC_FP64;
+  const bool bicg = o.krylov == RT_KRYLOV_BICGSTAB;
+  Workspace& ws = ensure_workspace(p, o.restart, mixed, bicg);
+  const int64_t n = p.n;
+  p.history.clear();
+  std::vector<double>* hist = o.record_history ? &p.history : nullptr;
+
+  const double* b = b_in;
+  const double bnorm = vec_norm<double>(b, n, ws, st);
+  rt_status status = RT_OK;
+  CoreResult res;
+  int outer = 0;
+  if (bnorm == 0.0) {
+    RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+    RT_HIP(hipStreamSynchronize(st));
+    if (hist) hist->push_back(0.0);
+  } else if (!mixed && !bicg) {
+    status = gmres_core<double>(p, RT_PREC_FP64, b, x, !x_is_guess, o.restart, o.rtol,
+                                o.max_iters, bnorm, ws, ws.ax64, st, hist, res);
+    outer = res.cycles;
+  } else if (!mixed && bicg) {
+    status = bicgstab_fp64(p, b, x, !x_is_guess, o.rtol, o.max_iters, bnorm, ws, st, hist, res);
+  } else {
+    if (bicg) fail(RT_E_INVALID, "BiCGStab is available in FP64 precision only");
+    // FP64 iterative refinement
+    if (!x_is_guess) RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
+    double rn;
+    if (!x_is_guess) {
+      RT_HIP(hipMemcpyAsync(ws.r64, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      rn = bnorm;
+    } else {
+      operator_apply(p, RT_PREC_FP64, x, ws.ax64, nullptr, st);
+      k_residual<double, double, double>(b, ws.ax64, n, ws.r64, ws.partial, st);
+      k_finish_norm_simple(ws.partial, n, ws.scal, st);
+      rn = read_scalar(ws.scal, st, ws);
+    }
+    if (hist) hist->push_back(rn / bnorm);
+    int total_inner = 0;
+    while (rn > o.rtol * bnorm && outer < o.max_outer && total_inner < o.max_iters) {
+      outer++;
+      // r32 = r / ||r||  (unit norm keeps FP32/16-bit operands in range)
+      float* r32 = ws.t32;
+      k_convert<double, float>(ws.r64, r32, n, 1.0 / rn, st);
+      // inner tolerance: at least inner_rtol, no tighter than needed overall
+      double itol = o.inner_rtol;
+      const double need = o.rtol * bnorm / rn;
+      if (need > itol) itol = need;
+      CoreResult ir;
+      // inner solve of A_lo d = r32 from d = 0
+      gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol,
+                        o.max_iters - total_inner, 1.0, ws, ws.a32, st, nullptr, ir);
+      total_inner += ir.iters;
+      // x += rn * d
+      RT_HIP(hipMemcpyAsync(ws.scal + 1, &rn, sizeof(double), hipMemcpyHostToDevice, st));
+      k_axpy_f64(x, ws.d32, n, ws.scal + 1, st);
+      operator_apply(p, RT_PREC_FP64, x, ws.ax64, nullptr, st);
+      k_residual<double, double, double>(b, ws.ax64, n, ws.r64, ws.partial, st);
+      k_finish_norm_simple(ws.partial, n, ws.scal, st);
+      const double rn_new = read_scalar(ws.scal, st, ws);
+      if (!std::isfinite(rn_new)) fail(RT_E_NONFINITE, "non-finite residual");
+      rn = rn_new;
+      if (hist) hist->push_back(rn / bnorm);
+    }
+    res.iters = total_inner;
+    res.beta = rn;
+    status = rn <= o.rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
+  }
+  RT_HIP(hipStreamSynchronize(st));
+  auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->iters = res.iters;
+    stats->outer_iters = outer;
+    stats->relres = bnorm > 0 ? res.beta / bnorm : 0.0;
+    stats->converged = status == RT_OK;
+    stats->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    stats->history_len = (int)p.history.size();
+    stats->history = p.history.empty() ? nullptr : p.history.data();
+  }
+  return status;
+}
+
+}  // namespace rtsn

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+FP64 tolerances: single applications of Lambda, Sigma and the operator agree
+to 1e-12 of the largest magnitude (rounding order only); solves are checked
+by the oracle-evaluated FP64 residual and against the oracle's own GMRES
+iterate.  FP32 applications agree to a few FP32 ulps (2e-5 relative).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Problem as OProblem, gmres, bicgstab
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rt():
+    from paper_2602_21958_amd import rt
+    return rt
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------ specs
+def slab(nz=64, n_mu=8, n_nu=21, formal="linear_sc", eps=1e-4):
+    s = W.slab64()
+    s.nz, s.n_mu, s.n_nu, s.formal, s.eps = nz, n_mu, n_nu, formal, eps
+    s.depth = W.log_depth_grid(nz, 1e-4, 1e4)
+    return s
+
+
+SLABS = {
+    "slab64": lambda: W.slab64(),
+    "slab_ie": lambda: slab(formal="implicit_euler"),
+    "slab_nz37_mu2_nu1": lambda: slab(nz=37, n_mu=2, n_nu=1),
+    "slab_nz300": lambda: slab(nz=300, n_mu=4, n_nu=7),
+    "slab_eps_field": lambda: slab(nz=20, n_mu=6, n_nu=5, eps=np.linspace(1e-4, 0.5, 20)),
+}
+
+BOXES = {
+    "box8": lambda: W.small_box(8, 4, 8, 5),
+    "box_12x10x9": lambda: W.small_box(12, 4, 4, 3, nz=9, ny=10),
+    "box16_shallow": lambda: W.small_box(16, 8, 8, 3, nz=6),
+    "box_1x1x5": lambda: W.small_box(1, 2, 4, 2, nz=5, ny=1),
+}
+
+ALL = {**SLABS, **BOXES}
+
+
+@pytest.mark.parametrize("name", list(ALL))
+def test_tables_match_oracle(name):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"tables {name}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        t = p.tables()
+    assert relerr(t["mhat"], op.mhat) < 1e-13
+    assert np.allclose(t["mu_ray"], op.mu_ray, rtol=0, atol=1e-15)
+    assert np.allclose(t["w_ray"], op.w_ray, rtol=1e-14, atol=0)
+    assert np.allclose(t["phi_ray"], op.phi_ray, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("with_bc", [False, True])
+@pytest.mark.parametrize("name", list(ALL))
+def test_lambda_fp64(name, with_bc):
+    rt = _rt()
+    spec = ALL[name]()
+    spec.i_top, spec.i_bot = 0.3, 1.0
+    say(f"lambda fp64 {name} bc={with_bc}")
+    op = OProblem(spec)
+    s = W.random_field(op.n, 11)
+    with rt.Problem(spec) as p:
+        out = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        p.apply_lambda(dev(s), out, with_bc=with_bc)
+        got = host(out)
+    ref = op.lam(s.reshape(op.n_r, op.n_s), with_bc=with_bc).ravel()
+    assert relerr(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
+def test_lambda_fp32(name):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"lambda fp32 {name}")
+    op = OProblem(spec)
+    s = W.random_field(op.n, 12, positive=True)
+    with rt.Problem(spec) as p:
+        out = torch.empty(op.n, dtype=torch.float32, device="cuda:0")
+        p.apply_lambda(dev(s, torch.float32), out, precision="fp32")
+        got = host(out)
+    ref = op.lam(s.astype(np.float32).astype(np.float64).reshape(op.n_r, op.n_s),
+                 with_bc=False).ravel()
+    assert relerr(got, ref) < 2e-5
+
+
+@pytest.mark.parametrize("name", list(ALL))
+def test_sigma_fp64(name):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"sigma fp64 {name}")
+    op = OProblem(spec)
+    L = W.random_field(op.n, 13)
+    x = W.random_field(op.n, 14)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        p.apply_sigma(dev(L), dev(x), y)
+        got = host(y)
+        y2 = torch.empty_like(y)
+        p.apply_sigma(dev(L), None, y2)
+        got2 = host(y2)
+    sc = op.scatter(L)
+    assert relerr(got, x - sc.ravel()) < 1e-12
+    assert relerr(got2, sc.ravel()) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
+def test_sigma_fp32(name):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"sigma fp32 {name}")
+    op = OProblem(spec)
+    L = W.random_field(op.n, 15).astype(np.float32)
+    x = W.random_field(op.n, 16).astype(np.float32)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float32, device="cuda:0")
+        p.apply_sigma(dev(L, torch.float32), dev(x, torch.float32), y, precision="fp32")
+        got = host(y)
+    ref = x - op.scatter(L.astype(np.float64)).ravel()
+    assert relerr(got, ref) < 2e-5
+
+
+@pytest.mark.parametrize("name", list(ALL))
+def test_operator_and_rhs_fp64(name):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"operator fp64 {name}")
+    op = OProblem(spec)
+    x = W.random_field(op.n, 17)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        p.apply(dev(x), y)
+        got = host(y)
+        b = torch.empty_like(y)
+        p.rhs(b)
+        got_b = host(b)
+        inten = torch.empty_like(y)
+        p.intensity(dev(x), inten)
+        got_i = host(inten)
+    assert relerr(got, op.apply(x).ravel()) < 1e-12
+    assert relerr(got_b, op.rhs().ravel()) < 1e-12
+    assert relerr(got_i, op.intensity(x).ravel()) < 1e-12
+
+
+def test_box32_operator_full_size():
+    """The 32^3 box workload at full size (2048 rays x 32768 points)."""
+    rt = _rt()
+    spec = W.box32()
+    say("box32 full-size operator")
+    op = OProblem(spec)
+    x = W.random_field(op.n, 18)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        p.apply(dev(x), y)
+        got = host(y)
+    ref = op.apply(x).ravel()
+    assert relerr(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["slab64", "box8"])
+def test_gmres_fp64_matches_oracle(name):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"gmres fp64 {name}")
+    op = OProblem(spec)
+    b = op.rhs().ravel()
+    ref = gmres(op.apply, b, restart=30, tol=1e-8)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, restart=30)
+        s = host(x)
+    assert st["converged"]
+    assert abs(st["iters"] - ref["iters"]) <= 1
+    # residual histories agree over the first 20 steps
+    h = np.array(st["history"][:20])
+    hr = np.array(ref["history"][:20])
+    assert np.max(np.abs(h - hr) / hr) < 1e-8
+    assert op.residual_norm(s) <= 1.0e-8
+    diff = np.linalg.norm(s - ref["x"]) / np.linalg.norm(ref["x"])
+    if st["iters"] == ref["iters"]:
+        # same Krylov step: iterates differ by Gram-Schmidt rounding only
+        assert diff < 1e-9
+    else:
+        # one step apart: both satisfy the 1e-8 residual bound
+        assert diff < 1e-5
+
+
+def test_gmres_tight_solution_matches_oracle():
+    rt = _rt()
+    spec = W.slab64()
+    say("gmres tight slab64")
+    op = OProblem(spec)
+    ref = gmres(op.apply, op.rhs().ravel(), restart=30, tol=1e-13)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-13, restart=30)
+        s = host(x)
+    assert st["converged"]
+    assert np.linalg.norm(s - ref["x"]) / np.linalg.norm(ref["x"]) < 1e-10
+
+
+def test_eps_one_is_one_iteration():
+    rt = _rt()
+    spec = W.slab64()
+    spec.eps = 1.0
+    say("eps=1")
+    with rt.Problem(spec) as p:
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-12)
+        s = host(x)
+    assert st["converged"] and st["iters"] == 1
+    assert np.allclose(s, 1.0, rtol=1e-14)
+
+
+def test_zero_rhs_gives_zero():
+    rt = _rt()
+    spec = W.slab64()
+    say("zero rhs")
+    with rt.Problem(spec) as p:
+        x = torch.ones(p.n, dtype=torch.float64, device="cuda:0")
+        b = torch.zeros(p.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, b=b)
+        assert st["iters"] == 0 and st["converged"]
+        assert not torch.any(x).item()
+
+
+def test_bicgstab_fp64():
+    rt = _rt()
+    spec = W.slab64()
+    say("bicgstab slab64")
+    op = OProblem(spec)
+    ref = bicgstab(op.apply, op.rhs().ravel(), tol=1e-8)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, krylov="bicgstab")
+        s = host(x)
+    assert st["converged"]
+    assert op.residual_norm(s) <= 1e-8
+    assert abs(st["iters"] - ref["iters"]) <= 2
+
+
+def test_invalid_arguments_raise():
+    rt = _rt()
+    spec = W.slab64()
+    spec.depth = spec.depth[::-1].copy()
+    with pytest.raises(rt.RtError) as e:
+        rt.Problem(spec)
+    assert e.value.code == rt.RT_E_INVALID
+    spec = W.slab64()
+    spec.eps = float("nan")
+    with pytest.raises(rt.RtError) as e:
+        rt.Problem(spec)
+    assert e.value.code == rt.RT_E_NONFINITE
+    spec = W.slab64()
+    with rt.Problem(spec) as p:
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(rt.RtError):
+            p.apply(x, x)
+        with pytest.raises(rt.RtError):
+            p.solve(x, restart=0)
