@@ -257,6 +257,19 @@ rt_status rt_batch_wait_all(rt_batch b);
 
 rt_status rt_batch_destroy(rt_batch b);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing.  While enabled, every launch of the formal solver, of the
+ * scattering GEMM and of the Arnoldi vector kernels (dots, update) is
+ * bracketed by HIP events recorded on the stream it is launched on.
+ * rt_profile_read synchronises the recorded events and returns the number of
+ * launches and their summed device time for one kernel class; `reset` clears
+ * that class afterwards.  Process-wide, internally synchronised.
+ * ------------------------------------------------------------------------- */
+enum { RT_KCLASS_LAMBDA = 0, RT_KCLASS_SIGMA = 1, RT_KCLASS_ARNOLDI = 2, RT_KCLASS_COUNT = 3 };
+
+rt_status rt_profile_enable(int on);
+rt_status rt_profile_read(int kclass, int64_t* launches, double* total_ms, int reset);
+
 /* Thread-local message of the last failed call on this thread.              */
 const char* rt_last_error(void);
 

@@ -367,6 +367,7 @@ int grid_for(int64_t n) {
 template <typename TV>
 void k_mdot(const TV* V, int64_t n, int cnt, const TV* w, double* partial, hipStream_t st) {
   const int nb = grid_for(n);
+  ProfScope prof(RT_KCLASS_ARNOLDI, st);
   for (int i0 = 0; i0 < cnt; i0 += 16) {
     const int c = cnt - i0 < 16 ? cnt - i0 : 16;
     hipLaunchKernelGGL((mdot_kernel<TV, 16>), dim3(nb), dim3(kThreads), 0, st, V, n, i0, c, w,
@@ -385,6 +386,7 @@ void k_reduce_rows(const double* partial, int64_t n, int nrows, const double* sc
 template <typename TV>
 void k_update(const TV* V, int64_t n, int cnt, const double* h, const double* vscale, TV* w,
               double* partial, hipStream_t st) {
+  ProfScope prof(RT_KCLASS_ARNOLDI, st);
   hipLaunchKernelGGL((update_kernel<TV>), dim3(grid_for(n)), dim3(kThreads), 0, st, V, n, cnt, h,
                      vscale, w, partial);
   RT_HIP(hipGetLastError());

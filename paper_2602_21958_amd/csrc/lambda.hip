@@ -253,6 +253,7 @@ template <typename VT, typename LT>
 void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
                    const double* scale, hipStream_t st) {
   using C = typename ComputeOf<VT>::type;
+  ProfScope prof(RT_KCLASS_LAMBDA, st);
   if (p.geom == RT_GEOM_SLAB) {
     dim3 grid((p.n_r + 3) / 4);
     hipLaunchKernelGGL((lambda_slab_kernel<VT, LT, C>), grid, dim3(256), 0, st, s, out,

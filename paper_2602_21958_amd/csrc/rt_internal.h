@@ -108,4 +108,17 @@ void operator_apply(Problem& p, int precision, const void* x, void* y,
 size_t lambda_elem_bytes(int precision);
 const double* physical_rhs(Problem& p, hipStream_t st);
 
+// Kernel timing (rt_profile_*): RAII scope recording a start/stop event pair
+// on `st` around the launches it encloses when profiling is enabled.
+class ProfScope {
+ public:
+  ProfScope(int kclass, hipStream_t st);
+  ~ProfScope();
+
+ private:
+  int kclass_;
+  hipStream_t st_;
+  hipEvent_t start_ = nullptr;
+};
+
 }  // namespace rtsn

@@ -59,8 +59,8 @@ __device__ __forceinline__ void tile_of(int bid, int n_tiles_m, int n_tiles, int
 
 template <typename T>
 __global__ __launch_bounds__(256) void sigma_gemm_kernel(
-    const T* __restrict__ A, const T* __restrict__ B, const T* __restrict__ X,
-    T* __restrict__ Y, const double* __restrict__ albedo, const double* __restrict__ xscale,
+    const T* __restrict__ A, const T* __restrict__ B, const T* X,
+    T* Y, const double* __restrict__ albedo, const double* __restrict__ xscale,
     int M, int N, int K, double sign) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
@@ -159,6 +159,7 @@ void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* 
                     const double* xscale, double sign, hipStream_t st) {
   const int M = p.n_r, N = (int)p.n_s, K = p.n_r;
   const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  ProfScope prof(RT_KCLASS_SIGMA, st);
   hipLaunchKernelGGL((sigma_gemm_kernel<T>), dim3(tiles), dim3(256), 0, st, mhat, L, x, y,
                      p.d_albedo, xscale, M, N, K, sign);
   RT_HIP(hipGetLastError());

@@ -93,6 +93,9 @@ _sig = {
     "rt_batch_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(SolveStats)]),
     "rt_batch_wait_all": (C.c_int, [_vp]),
     "rt_batch_destroy": (C.c_int, [_vp]),
+    "rt_profile_enable": (C.c_int, [C.c_int]),
+    "rt_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.c_int]),
     "rt_last_error": (C.c_char_p, []),
     "rt_version": (C.c_int, []),
 }
@@ -281,6 +284,22 @@ class Problem:
 
     def __exit__(self, *a):
         self.close()
+
+
+KCLASS = {"lambda": 0, "sigma": 1, "arnoldi": 2}
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.rt_profile_enable(int(bool(on))), "rt_profile_enable")
+
+
+def profile_read(kclass: str, reset: bool = True):
+    """(launches, total device ms) of one kernel class since the last reset."""
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(_lib.rt_profile_read(KCLASS[kclass], C.byref(n), C.byref(ms), int(reset)),
+           "rt_profile_read")
+    return int(n.value), float(ms.value)
 
 
 def lib_path() -> str:

@@ -289,3 +289,37 @@ def test_invalid_arguments_raise():
             p.apply(x, x)
         with pytest.raises(rt.RtError):
             p.solve(x, restart=0)
+
+
+@pytest.mark.parametrize("name", ["slab64", "box8"])
+def test_mixed_fp32_refinement_reaches_fp64_residual(name):
+    """FP64 iterative refinement around an FP32 inner GMRES: the oracle-evaluated
+    FP64 residual of the result meets 1e-8."""
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"mixed fp32 IR {name}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, precision="fp32")
+        s = host(x)
+    assert st["converged"], st
+    assert st["outer_iters"] >= 2
+    assert op.residual_norm(s) <= 1.05e-8
+
+
+def test_profile_counts_launches():
+    rt = _rt()
+    spec = W.slab64()
+    with rt.Problem(spec) as p:
+        x = dev(W.random_field(p.n, 3))
+        y = torch.empty_like(x)
+        rt.profile_enable(True)
+        for k in ("lambda", "sigma", "arnoldi"):
+            rt.profile_read(k)
+        for _ in range(3):
+            p.apply(x, y)
+        rt.profile_enable(False)
+        n_l, ms_l = rt.profile_read("lambda")
+        n_s, ms_s = rt.profile_read("sigma")
+    assert n_l == 3 and n_s == 3 and ms_l > 0 and ms_s > 0
