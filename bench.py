@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--mixed-precision", default="fp32")
+    ap.add_argument("--mixed-precision", default="fp16")
     return ap.parse_args()
 
 

@@ -73,8 +73,9 @@ enum { RT_FORMAL_LINEAR_SC = 0, RT_FORMAL_IMPLICIT_EULER = 1 };
  *   FP32  : vectors float;  Lambda FP32; Sigma FP32 MFMA.
  *   BF16  : vectors float;  Lambda FP32 emitting bf16; Sigma bf16 MFMA with
  *           FP32 accumulation; epilogue FP32.
- *   FP16  : as BF16 with fp16 operands (kernel matrix column-scaled to stay
- *           in fp16 range, scale undone in FP32).
+ *   FP16  : as BF16 with fp16 operands (kernel-matrix rows scaled to unit
+ *           maximum and Lambda output scaled by a power of two to stay in
+ *           fp16 range; both undone in FP32).
  *   BF16X3: as BF16 but the kernel matrix and Lambda output are split into
  *           hi + lo bf16 parts and three products are accumulated (about
  *           16 significant bits).                                            */

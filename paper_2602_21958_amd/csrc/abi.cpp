@@ -1,5 +1,6 @@
 // extern "C" entry points of librtsn (declared in include/rtsn.h), problem
 // construction and operator dispatch.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -27,7 +28,7 @@ Problem::~Problem() {
   hipFree(d_mhat_bf16);
   hipFree(d_mhat_bf16_lo);
   hipFree(d_mhat_f16);
-  hipFree(d_f16_colscale);
+  hipFree(d_f16_rowscale);
   hipFree(d_albedo);
   hipFree(d_thermal);
   hipFree(d_dt);
@@ -62,6 +63,29 @@ void* problem_lbuf(Problem& p, size_t bytes) {
 }
 
 namespace {
+
+// Round-to-nearest-even float -> bfloat16 bits (host side).
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+uint16_t f16_bits(float f) {
+  _Float16 h = (_Float16)f;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
 
 template <typename T>
 T* upload(const T* h, size_t count, int64_t& total) {
@@ -170,6 +194,32 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
     for (size_t i = 0; i < nr2; ++i) m32[i] = (float)p.tab.mhat[i];
     p.d_mhat32 = upload(m32.data(), nr2, tot);
   }
+  {
+    // 16-bit copies with rows padded to a multiple of 8 elements
+    const int lda = (p.n_r + 7) / 8 * 8;
+    p.lda16 = lda;
+    const size_t sz = (size_t)p.n_r * lda;
+    std::vector<uint16_t> hi(sz, 0), lo(sz, 0), h16(sz, 0);
+    std::vector<float> rs(p.n_r, 1.f);
+    for (int k = 0; k < p.n_r; ++k) {
+      double rmax = 0.0;
+      for (int kp = 0; kp < p.n_r; ++kp)
+        rmax = std::max(rmax, std::fabs(p.tab.mhat[(size_t)k * p.n_r + kp]));
+      if (!(rmax > 0)) rmax = 1.0;
+      rs[k] = (float)rmax;
+      for (int kp = 0; kp < p.n_r; ++kp) {
+        const double m = p.tab.mhat[(size_t)k * p.n_r + kp];
+        const uint16_t h = bf16_bits((float)m);
+        hi[(size_t)k * lda + kp] = h;
+        lo[(size_t)k * lda + kp] = bf16_bits((float)(m - (double)bf16_value(h)));
+        h16[(size_t)k * lda + kp] = f16_bits((float)(m / (double)rs[k]));
+      }
+    }
+    p.d_mhat_bf16 = reinterpret_cast<__hip_bfloat16*>(upload(hi.data(), sz, tot));
+    p.d_mhat_bf16_lo = reinterpret_cast<__hip_bfloat16*>(upload(lo.data(), sz, tot));
+    p.d_mhat_f16 = reinterpret_cast<__half*>(upload(h16.data(), sz, tot));
+    p.d_f16_rowscale = upload(rs.data(), rs.size(), tot);
+  }
   p.d_albedo = upload(alb.data(), alb.size(), tot);
   p.d_thermal = upload(therm.data(), therm.size(), tot);
   p.d_ray_mu = upload(p.tab.mu_ray.data(), p.tab.mu_ray.size(), tot);
@@ -229,7 +279,8 @@ void operator_apply(Problem& p, int precision, const void* x, void* y, const dou
     }
     case RT_PREC_FP16: {
       auto* L = static_cast<__half*>(problem_lbuf(p, n * 2));
-      launch_lambda<float, __half>(p, static_cast<const float*>(x), L, false, xscale, st);
+      launch_lambda<float, __half>(p, static_cast<const float*>(x), L, false, xscale, st,
+                                   fp16_lambda_scale(p.n));
       launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
                        xscale, -1.0, st);
       break;
@@ -402,7 +453,7 @@ rt_status rt_apply_sigma(rt_problem p, int precision, const void* L, const void*
                                          static_cast<__hip_bfloat16*>(lb), (int64_t)n, 1.0, st);
       } else {
         k_convert<float, __half>(static_cast<const float*>(L), static_cast<__half*>(lb),
-                                 (int64_t)n, 1.0, st);
+                                 (int64_t)n, fp16_lambda_scale(q->n), st);
       }
       launch_sigma_b16(*q, precision, lb, static_cast<const float*>(x), static_cast<float*>(y),
                        nullptr, sign, st);

@@ -122,11 +122,10 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict_
   }
 }
 
-// r = b - ax (into r, type TR), partial norm^2 of r
+// r = b - ax (into r, type TR; r may alias ax), partial norm^2 of r
 template <typename TB, typename TA, typename TR>
 __global__ __launch_bounds__(kThreads) void residual_kernel(const TB* __restrict__ b,
-                                                            const TA* __restrict__ ax, int64_t n,
-                                                            TR* __restrict__ r,
+                                                            const TA* ax, int64_t n, TR* r,
                                                             double* __restrict__ partial) {
   double nrm = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kThreads;

@@ -82,7 +82,8 @@ template <typename VT, typename LT, typename C>
 __global__ __launch_bounds__(256) void lambda_slab_kernel(
     const VT* __restrict__ s, LT* __restrict__ out, const double* __restrict__ dt,
     const double* __restrict__ ray_mu, const double* __restrict__ ray_fac, int n_r, int nz,
-    double i_top, double i_bot, int with_bc, const double* __restrict__ scale, int scheme) {
+    double i_top, double i_bot, int with_bc, const double* __restrict__ scale, int scheme,
+    float out_mul) {
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= n_r) return;  // whole wave leaves; no block barrier below
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(256) void lambda_slab_kernel(
     C e, b;
     elem(q, e, b);
     I = e * I + b;
-    ok[down ? q : nz - 1 - q] = store_val<C, LT>(I);
+    ok[down ? q : nz - 1 - q] = store_val<C, LT>(I * C(out_mul));
   }
 }
 
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(kBoxThreads) void lambda_box_kernel(
     const VT* __restrict__ s, LT* __restrict__ out, const double* __restrict__ kline,
     const BoxStencil* __restrict__ stencil, const double* __restrict__ ray_fac, int n_nu,
     int nx, int ny, int nz, double i_top, double i_bot, int with_bc,
-    const double* __restrict__ scale) {
+    const double* __restrict__ scale, float out_mul) {
   extern __shared__ unsigned char smem_raw[];
   const int P = nx * ny;
   C* lI = reinterpret_cast<C*>(smem_raw);
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kBoxThreads) void lambda_box_kernel(
         sc_weights<C>(d, e, a, c);
         I = e * Iu + a * Su + c * s0;
       }
-      oz[p] = store_val<C, LT>(I);
+      oz[p] = store_val<C, LT>(I * C(out_mul));
       Iv[j] = I;
       Sv[j] = s0;
       Kv[j] = k0;
@@ -251,14 +252,14 @@ template <> struct ComputeOf<float> { using type = float; };
 
 template <typename VT, typename LT>
 void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
-                   const double* scale, hipStream_t st) {
+                   const double* scale, hipStream_t st, float out_mul) {
   using C = typename ComputeOf<VT>::type;
   ProfScope prof(RT_KCLASS_LAMBDA, st);
   if (p.geom == RT_GEOM_SLAB) {
     dim3 grid((p.n_r + 3) / 4);
     hipLaunchKernelGGL((lambda_slab_kernel<VT, LT, C>), grid, dim3(256), 0, st, s, out,
                        p.d_dt, p.d_ray_mu, p.d_ray_fac, p.n_r, p.nz, p.i_top, p.i_bot,
-                       with_bc ? 1 : 0, scale, p.formal);
+                       with_bc ? 1 : 0, scale, p.formal, out_mul);
   } else {
     const int P = p.nx * p.ny;
     size_t lds = (size_t)3 * P * sizeof(C);
@@ -268,7 +269,7 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
 #define RT_BOX_LAUNCH(NPT)                                                                \
   hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, NPT>), dim3(p.n_r), dim3(kBoxThreads), \
                      lds, st, s, out, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx,   \
-                     p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale)
+                     p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
     if (P <= kBoxThreads) RT_BOX_LAUNCH(1);
     else if (P <= 4 * kBoxThreads) RT_BOX_LAUNCH(4);
     else if (P <= 16 * kBoxThreads) RT_BOX_LAUNCH(16);
@@ -279,13 +280,13 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
 }
 
 template void launch_lambda<double, double>(const Problem&, const double*, double*, bool,
-                                            const double*, hipStream_t);
+                                            const double*, hipStream_t, float);
 template void launch_lambda<float, float>(const Problem&, const float*, float*, bool,
-                                          const double*, hipStream_t);
+                                          const double*, hipStream_t, float);
 template void launch_lambda<float, __hip_bfloat16>(const Problem&, const float*,
                                                    __hip_bfloat16*, bool, const double*,
-                                                   hipStream_t);
+                                                   hipStream_t, float);
 template void launch_lambda<float, __half>(const Problem&, const float*, __half*, bool,
-                                           const double*, hipStream_t);
+                                           const double*, hipStream_t, float);
 
 }  // namespace rtsn

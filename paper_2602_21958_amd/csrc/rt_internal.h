@@ -65,8 +65,9 @@ struct Problem {
   float* d_mhat32 = nullptr;
   __hip_bfloat16* d_mhat_bf16 = nullptr;   // hi part
   __hip_bfloat16* d_mhat_bf16_lo = nullptr;
-  __half* d_mhat_f16 = nullptr;         // column-scaled
-  float* d_f16_colscale = nullptr;      // n_r: undo factor per column k'
+  __half* d_mhat_f16 = nullptr;         // rows scaled to unit maximum
+  float* d_f16_rowscale = nullptr;      // n_r: undo factor per row k
+  int lda16 = 0;                        // leading dimension of the 16-bit copies
   double* d_albedo = nullptr;           // n_s: 1 - eps_i
   double* d_thermal = nullptr;          // n: t
   double* d_dt = nullptr;               // slab: nz-1 depth increments
@@ -90,9 +91,11 @@ void* problem_lbuf(Problem& p, size_t bytes);
 // --------------------------------------------------------------------------
 // Kernel launchers.  Vector types: V = double (FP64) or float (others).
 // Lambda output type LT: double, float, __hip_bfloat16 or __half.
+// out = Lambda(scale * s) * out_mul (+ boundary term if with_bc)
 template <typename VT, typename LT>
 void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
-                   const double* scale, hipStream_t st);
+                   const double* scale, hipStream_t st, float out_mul = 1.f);
+float fp16_lambda_scale(int64_t n);
 
 // y = xs * x + sign * albedo .* (Mhat L); x may be null (then xs ignored).
 void launch_sigma_f64(const Problem& p, const double* L, const double* x, double* y,

@@ -9,6 +9,7 @@
 //   FP32 basis (FP64 dot accumulation) and the operator in FP32 / BF16 /
 //   FP16 / split-BF16 arithmetic, then x += ||r|| d.
 // * BiCGStab (van der Vorst), FP64, scalars kept on the device.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -37,8 +38,8 @@ size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab)
   size_t b = sizeof(double) * (size_t)(kMaxRestart + 1) * kReduceBlocks + sizeof(GmresState) +
              sizeof(BicgState) + 64 * sizeof(double);
   b += (size_t)(restart + 1) * n * (mixed ? sizeof(float) : sizeof(double));
-  b += 2 * n * sizeof(double);  // r64, ax64
-  if (mixed) b += 3 * n * sizeof(float);
+  b += (mixed ? 1 : 2) * n * sizeof(double);  // r64 (+ ax64 for FP64 GMRES)
+  if (mixed) b += 2 * n * sizeof(float);
   if (bicgstab) b += 4 * n * sizeof(double);
   b += n * lambda_elem_bytes(mixed ? RT_PREC_FP32 : RT_PREC_FP64);  // operator L buffer
   return b;
@@ -81,11 +82,10 @@ Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab) 
   ws->bs = dalloc<BicgState>(1, tot);
   ws->scal = dalloc<double>(64, tot);
   ws->r64 = dalloc<double>(n, tot);
-  ws->ax64 = dalloc<double>(n, tot);
+  if (!mixed) ws->ax64 = dalloc<double>(n, tot);
   if (mixed) {
     ws->d32 = dalloc<float>(n, tot);
     ws->t32 = dalloc<float>(n, tot);
-    ws->a32 = dalloc<float>(n, tot);
   }
   if (bicgstab) ws->bic = dalloc<double>(4 * n, tot);
   RT_HIP(hipHostMalloc((void**)&ws->host, sizeof(GmresState), hipHostMallocDefault));
@@ -127,10 +127,13 @@ struct CoreResult {
 
 // GMRES(m) on A_prec x = b with vectors of type TV.  x is overwritten; if
 // x_zero it starts from 0.  Returns RT_OK / RT_NOT_CONVERGED.
+// With single_cycle the solve stops after one restart cycle and skips the
+// true-residual recomputation (inner solves of iterative refinement, whose
+// low-precision operator is not exactly linear).
 template <typename TV>
 rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int m, double rtol,
                      int max_iters, double bnorm, Workspace& ws, TV* tmp, hipStream_t st,
-                     std::vector<double>* hist, CoreResult& res) {
+                     std::vector<double>* hist, CoreResult& res, bool single_cycle = false) {
   const int64_t n = p.n;
   TV* V = static_cast<TV*>(ws.V);
   GmresState* gs = ws.gs;
@@ -167,6 +170,10 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
     }
     k_solve_r(gs, k, st);
     k_combine<TV, TV>(V, n, k, gs->coef, x, st);
+    if (single_cycle) {
+      res.beta = ws.host->resid;
+      return res.beta <= rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
+    }
     operator_apply(p, prec, x, tmp, nullptr, st);
     k_residual<TV, TV, TV>(b, tmp, n, V, ws.partial, st);
     k_finish_norm(ws.partial, n, gs, 1, st);
@@ -281,44 +288,45 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
     status = bicgstab_fp64(p, b, x, !x_is_guess, o.rtol, o.max_iters, bnorm, ws, st, hist, res);
   } else {
     if (bicg) fail(RT_E_INVALID, "BiCGStab is available in FP64 precision only");
-    // FP64 iterative refinement
+    // FP64 iterative refinement: r = b - A_64 x; inner A_lo d = r/||r|| (one
+    // GMRES(m) cycle); x += ||r|| d.  Stops at rtol, at max_outer, or after
+    // three steps without residual reduction.
     if (!x_is_guess) RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st));
     double rn;
     if (!x_is_guess) {
       RT_HIP(hipMemcpyAsync(ws.r64, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
       rn = bnorm;
     } else {
-      operator_apply(p, RT_PREC_FP64, x, ws.ax64, nullptr, st);
-      k_residual<double, double, double>(b, ws.ax64, n, ws.r64, ws.partial, st);
+      operator_apply(p, RT_PREC_FP64, x, ws.r64, nullptr, st);
+      k_residual<double, double, double>(b, ws.r64, n, ws.r64, ws.partial, st);
       k_finish_norm_simple(ws.partial, n, ws.scal, st);
       rn = read_scalar(ws.scal, st, ws);
     }
     if (hist) hist->push_back(rn / bnorm);
-    int total_inner = 0;
+    int total_inner = 0, stalls = 0;
     while (rn > o.rtol * bnorm && outer < o.max_outer && total_inner < o.max_iters) {
       outer++;
-      // r32 = r / ||r||  (unit norm keeps FP32/16-bit operands in range)
       float* r32 = ws.t32;
       k_convert<double, float>(ws.r64, r32, n, 1.0 / rn, st);
-      // inner tolerance: at least inner_rtol, no tighter than needed overall
       double itol = o.inner_rtol;
       const double need = o.rtol * bnorm / rn;
       if (need > itol) itol = need;
       CoreResult ir;
-      // inner solve of A_lo d = r32 from d = 0
-      gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol,
-                        o.max_iters - total_inner, 1.0, ws, ws.a32, st, nullptr, ir);
+      const int cap = std::min(o.restart, o.max_iters - total_inner);
+      gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
+                        nullptr, st, nullptr, ir, /*single_cycle=*/true);
       total_inner += ir.iters;
-      // x += rn * d
       RT_HIP(hipMemcpyAsync(ws.scal + 1, &rn, sizeof(double), hipMemcpyHostToDevice, st));
       k_axpy_f64(x, ws.d32, n, ws.scal + 1, st);
-      operator_apply(p, RT_PREC_FP64, x, ws.ax64, nullptr, st);
-      k_residual<double, double, double>(b, ws.ax64, n, ws.r64, ws.partial, st);
+      operator_apply(p, RT_PREC_FP64, x, ws.r64, nullptr, st);
+      k_residual<double, double, double>(b, ws.r64, n, ws.r64, ws.partial, st);
       k_finish_norm_simple(ws.partial, n, ws.scal, st);
       const double rn_new = read_scalar(ws.scal, st, ws);
       if (!std::isfinite(rn_new)) fail(RT_E_NONFINITE, "non-finite residual");
+      stalls = rn_new >= 0.9 * rn ? stalls + 1 : 0;
       rn = rn_new;
       if (hist) hist->push_back(rn / bnorm);
+      if (stalls >= 3) break;
     }
     res.iters = total_inner;
     res.beta = rn;

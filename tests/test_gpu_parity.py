@@ -323,3 +323,59 @@ def test_profile_counts_launches():
         n_l, ms_l = rt.profile_read("lambda")
         n_s, ms_s = rt.profile_read("sigma")
     assert n_l == 3 and n_s == 3 and ms_l > 0 and ms_s > 0
+
+
+# 16-bit scattering GEMM: bound from operand rounding.  With unit roundoff u
+# of the stored operands, each product carries at most ~2u relative error, so
+# |y - y_ref| <= c u (1-eps_i) (|Mhat| |L|)_{k,i} + FP32 rounding of y.
+U16 = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "bf16x3": 2.0 ** -15}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("name", ["slab64", "slab_nz37_mu2_nu1", "box8", "box_12x10x9",
+                                  "box_1x1x5"])
+def test_sigma_16bit_within_rounding_bound(name, prec):
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"sigma {prec} {name}")
+    op = OProblem(spec)
+    L = W.random_field(op.n, 21).astype(np.float32)
+    x = W.random_field(op.n, 22).astype(np.float32)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float32, device="cuda:0")
+        p.apply_sigma(dev(L, torch.float32), dev(x, torch.float32), y, precision=prec)
+        got = host(y).reshape(op.n_r, op.n_s)
+    L64 = L.astype(np.float64).reshape(op.n_r, op.n_s)
+    ref = x.astype(np.float64).reshape(op.n_r, op.n_s) - op.scatter(L64)
+    absprod = op.albedo[None, :] * (np.abs(op.mhat) @ np.abs(L64))
+    # fp16: entries below the fp16 subnormal range of each scaled row vanish
+    floor = 0.0
+    if prec == "fp16":
+        rowmax = np.abs(op.mhat).max(axis=1)
+        floor = (6e-8 * rowmax)[:, None] * np.abs(L64).sum(axis=0)[None, :]
+    bound = 3.0 * U16[prec] * absprod + floor + 2e-7 * np.abs(ref) + 1e-30
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16", "bf16"])
+@pytest.mark.parametrize("name", ["slab64", "box8"])
+def test_mixed_refinement_per_precision(name, prec):
+    """FP64 refinement around each low-precision inner operator; the result is
+    judged by the oracle-evaluated FP64 residual."""
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"mixed {prec} {name}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, precision=prec, max_outer=30)
+        s = host(x)
+    res = op.residual_norm(s)
+    say(f"   {prec} {name}: converged={st['converged']} outer={st['outer_iters']} "
+        f"inner={st['iters']} oracle residual={res:.3e}")
+    if st["converged"]:
+        assert res <= 1.05e-8
+    else:
+        # a precision too coarse for this conditioning: reported, not hidden
+        assert prec == "bf16", st
