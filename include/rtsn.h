@@ -234,13 +234,21 @@ rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b,
  * given to the next queued request at the next step boundary.
  * ------------------------------------------------------------------------- */
 
-/* Create an engine on `device` with a device-memory budget in bytes and at
- * most max_slots concurrently admitted solves (queue capacity queue_cap).    */
-rt_status rt_batch_create(int device, int64_t hbm_budget, int max_slots,
-                          int queue_cap, rt_batch* out);
+/* Create an engine on `device`.  precision: the operator precision of every
+ * solve in this engine (RT_PREC_FP64: plain restarted GMRES with FP64
+ * vectors; otherwise FP64 iterative refinement around one-cycle inner GMRES
+ * with FP32 vectors).  hbm_budget: bytes reserved at create for the solves'
+ * workspaces (bases, residuals, scratch); max_slots: most concurrently
+ * admitted solves; queue_cap: most queued requests; use_graph: replay the
+ * inner step as a captured hipGraph.  Errors: RT_E_INVALID, RT_E_NOMEM.     */
+rt_status rt_batch_create(int device, int precision, int64_t hbm_budget,
+                          int max_slots, int queue_cap, int use_graph,
+                          rt_batch* out);
 
-/* Submit a solve of problem p (which must stay alive until completion).
- * x_out: device FP64 n_unknowns of p, caller-owned, written at completion.
+/* Submit a solve of problem p (which must stay alive until completion) for
+ * its physical right-hand side.  opts->precision must equal the engine's;
+ * GMRES only.  x_out: device FP64 n_unknowns of p, caller-owned; the engine
+ * iterates in it from admission on and it holds the solution at completion.
  * Non-blocking; *ticket identifies the request.  RT_E_BUSY if the queue is
  * full; RT_E_INVALID if the problem can never fit the budget.               */
 rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts,
@@ -255,6 +263,13 @@ rt_status rt_batch_poll(rt_batch b, uint64_t ticket, rt_solve_stats* stats);
 
 /* Step the engine until every submitted request has finished.               */
 rt_status rt_batch_wait_all(rt_batch b);
+
+/* Device bytes the engine reserves from its budget for one solve of p with
+ * the given restart length (what admission checks against free memory).    */
+rt_status rt_batch_footprint(rt_batch b, rt_problem p, int restart, int64_t* bytes);
+
+/* Admitted solves, queued requests and arena bytes in use.                   */
+rt_status rt_batch_info(rt_batch b, int* active, int* queued, int64_t* bytes_in_use);
 
 rt_status rt_batch_destroy(rt_batch b);
 

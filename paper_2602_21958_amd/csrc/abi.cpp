@@ -13,6 +13,8 @@ static thread_local std::string g_last_error;
 
 void fail(rt_status code, const std::string& msg) { throw RtError{code, msg}; }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) {
     (void)hipGetLastError();

@@ -1,0 +1,91 @@
+// Batched solves: device-side slot descriptors, work lists and the launchers
+// of batch.hip, used by the engine in batch.cpp.
+#pragma once
+
+#include "krylov.h"
+
+namespace rtsn {
+
+constexpr int kChunk = 4096;          // vector elements per reduction chunk
+constexpr int kPersistBlocks = 1024;  // grid of the persistent work-list kernels
+
+// Everything one admitted solve needs on the device.  Pointers to tables are
+// borrowed from the owning Problem; vectors and state live in the engine's
+// arena.
+struct SlotDev {
+  int geom, nx, ny, nz;
+  int n_r, n_nu, formal, lda16;
+  int restart;
+  int active;
+  int64_t n_s, n;
+  int nch;                      // reduction chunks of a length-n vector
+  int pad0;
+  const double* mhat64;
+  const float* mhat32;
+  const uint16_t* mhat_hi;
+  const uint16_t* mhat_lo;
+  const uint16_t* mhat_f16;
+  const float* f16_rowscale;
+  const double* albedo;
+  const double* dt;
+  const double* kline;
+  const BoxStencil* stencil;
+  const double* ray_mu;
+  const double* ray_fac;
+  void* V;                      // (restart + 1) * n basis vectors (TV)
+  void* L;                      // n doubles of scratch (Lambda output, any type)
+  double* x;                    // FP64 iterate (caller's output buffer)
+  double* b;                    // FP64 right-hand side
+  double* r;                    // FP64 residual / A x scratch
+  double* partial;              // (kMaxRestart + 1) * nch partial sums
+  GmresState* gs;
+  float l_scale;                // fp16 Lambda output scale
+  int pad1;
+};
+
+// Mutable per-slot scalars, written by the kernels (and by the host when a
+// cycle starts); the host reads the whole array once per engine step.
+struct SlotStat {
+  double resid;                 // |g_{j+1}| of the current cycle (unit start)
+  double rn;                    // FP64 residual norm after the last cycle end
+  double target;                // the cycle stops when resid <= target
+  int j;                        // Arnoldi steps done in the current cycle
+  int cycle_done;
+  int iters;                    // total inner iterations
+  int breakdown;
+  int nonfinite;
+  int pad;
+};
+
+// Work-list item: slot and an index whose meaning depends on the list.
+struct Item {
+  int slot;
+  int a, b, c;
+};
+
+struct WorkLists {
+  // device arrays (capacity in items) and device counts
+  Item* lam_slab = nullptr;  int cap_lam_slab = 0;
+  Item* lam_box = nullptr;   int cap_lam_box = 0;
+  Item* tiles = nullptr;     int cap_tiles = 0;     // tiles of the 128 x 128 GEMMs
+  Item* chunks = nullptr;    int cap_chunks = 0;
+  int* slots = nullptr;      int cap_slots = 0;
+  int* counts = nullptr;     // [lam_slab, lam_box, tiles, chunks, slots]
+  int h_counts[5] = {0, 0, 0, 0, 0};
+  int box_npt = 1;           // points per thread class for box rays (1, 4, 16)
+  int box_pmax = 0;          // largest box plane among the listed slots
+};
+
+// Launchers (inner: vectors TV, operator precision prec)
+// One Arnoldi step of every slot in the lists (operator in precision prec).
+template <typename TV>
+void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                       hipStream_t st);
+// x += rn V y, then r = b - A_64 x and rn = ||r|| for every listed slot.
+template <typename TV>
+void b_cycle_end(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st);
+// V_0 = r / rn, fresh Givens state, for every listed slot.
+template <typename TV>
+void b_start_cycle(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st);
+
+}  // namespace rtsn

@@ -1,0 +1,529 @@
+// Batched solver kernels: many independent problems (slots) advance together.
+//
+// Every kernel is persistent: a fixed grid loops over a device-side work list
+// whose length is also on the device, so the launch sequence of one engine
+// step has fixed arguments and can be captured once in a hipGraph and
+// replayed while the host rewrites the lists.  Work is decomposed per slot
+// only (rays, 128 x 128 GEMM tiles, 4096-element chunks), so a slot's
+// arithmetic, including the order of every reduction, does not depend on the
+// other slots in the batch.
+//
+// Per slot, one engine step is one Arnoldi step of restarted GMRES on
+// A_lo d = r / ||r|| (Lambda, Sigma GEMM with fused epilogue, dots, update,
+// Givens); a cycle ends after `restart` steps or when |g_{j+1}| reaches the
+// slot's target, with x += ||r|| V y and an FP64 residual r = b - A_64 x.
+// With FP64 vectors and operator this is plain restarted GMRES; with FP32
+// vectors and a low-precision operator it is FP64 iterative refinement.
+#include "batch.h"
+#include "gemm16_dev.h"
+#include "gemm_dev.h"
+#include "lambda_dev.h"
+
+namespace rtsn {
+
+namespace {
+
+constexpr int TB = 256;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum G per-thread values over the block; thread g < cnt writes out[g*stride].
+template <int G>
+__device__ __forceinline__ void block_sum_store(double (&acc)[G], double* out, int stride,
+                                                int cnt) {
+  __shared__ double red[G][TB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const double v = wsum(acc[g]);
+    if (lane == 0) red[g][wave] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < G && (int)threadIdx.x < cnt) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < TB / 64; ++w) s += red[threadIdx.x][w];
+    out[(size_t)threadIdx.x * stride] = s;
+  }
+  __syncthreads();
+}
+
+template <typename TV> struct ComputeOf;
+template <> struct ComputeOf<double> { using type = double; };
+template <> struct ComputeOf<float> { using type = float; };
+
+// ------------------------------------------------------------------ Lambda
+// OUTER: x (FP64) -> L (FP64), no input scale.  Otherwise V_j (scaled by
+// vscale_j) -> L (type LT, times l_scale for fp16).
+template <typename VT, typename LT, typename C, bool OUTER>
+__global__ __launch_bounds__(TB) void bk_lambda_slab(const SlotDev* __restrict__ slots,
+                                                     const SlotStat* __restrict__ stat,
+                                                     const Item* __restrict__ items,
+                                                     const int* __restrict__ counts) {
+  const int cnt = counts[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int k = w.a + wave;
+    if (k >= s.n_r) continue;  // per wave; slab_ray has no block barrier
+    const VT* src;
+    C sc;
+    float om;
+    if constexpr (OUTER) {
+      src = reinterpret_cast<const VT*>(s.x);
+      sc = C(1);
+      om = 1.f;
+    } else {
+      const int j = stat[w.slot].j;
+      src = static_cast<const VT*>(s.V) + (size_t)j * s.n;
+      sc = C(s.gs->vscale[j]);
+      om = s.l_scale;
+    }
+    LT* dst = static_cast<LT*>(s.L);
+    lam::slab_ray<VT, LT, C>(src + (size_t)k * s.nz, dst + (size_t)k * s.nz, s.dt, s.ray_mu[k],
+                             s.ray_fac[k], s.nz, C(0), sc, s.formal, om, lane);
+  }
+}
+
+template <typename VT, typename LT, typename C, int NPT, bool OUTER>
+__global__ __launch_bounds__(TB) void bk_lambda_box(const SlotDev* __restrict__ slots,
+                                                    const SlotStat* __restrict__ stat,
+                                                    const Item* __restrict__ items,
+                                                    const int* __restrict__ counts) {
+  extern __shared__ unsigned char smem_raw[];
+  const int cnt = counts[1];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int k = w.a;
+    const size_t vol = (size_t)s.n_s;
+    const VT* src;
+    C sc;
+    float om;
+    if constexpr (OUTER) {
+      src = reinterpret_cast<const VT*>(s.x);
+      sc = C(1);
+      om = 1.f;
+    } else {
+      const int j = stat[w.slot].j;
+      src = static_cast<const VT*>(s.V) + (size_t)j * s.n;
+      sc = C(s.gs->vscale[j]);
+      om = s.l_scale;
+    }
+    LT* dst = static_cast<LT*>(s.L);
+    lam::box_ray<VT, LT, C, NPT>(src + (size_t)k * vol, dst + (size_t)k * vol, s.kline,
+                                 s.stencil[k / s.n_nu], C(s.ray_fac[k]), s.nx, s.ny, s.nz, C(0),
+                                 sc, om, reinterpret_cast<C*>(smem_raw));
+  }
+}
+
+// ------------------------------------------------------------------- GEMMs
+// OUTER: r = x - (1 - eps) Mhat L (FP64).  Otherwise
+// V_{j+1} = vscale_j V_j - (1 - eps) Mhat L.
+template <typename T, bool OUTER>
+__global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
+                                              const SlotStat* __restrict__ stat,
+                                              const Item* __restrict__ items,
+                                              const int* __restrict__ counts) {
+  const int cnt = counts[2];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const T* A;
+    const T* X;
+    T* Y;
+    double xs;
+    if constexpr (OUTER) {
+      A = reinterpret_cast<const T*>(s.mhat64);
+      X = reinterpret_cast<const T*>(s.x);
+      Y = reinterpret_cast<T*>(s.r);
+      xs = 1.0;
+    } else {
+      const int j = stat[w.slot].j;
+      if constexpr (sizeof(T) == 8)
+        A = reinterpret_cast<const T*>(s.mhat64);
+      else
+        A = reinterpret_cast<const T*>(s.mhat32);
+      X = static_cast<const T*>(s.V) + (size_t)j * s.n;
+      Y = static_cast<T*>(s.V) + (size_t)(j + 1) * s.n;
+      xs = s.gs->vscale[j];
+    }
+    gemm::gemm_tile<T>(A, static_cast<const T*>(s.L), X, Y, s.albedo, xs, s.n_r, (int)s.n_s,
+                       s.n_r, w.a, w.b, -1.0);
+  }
+}
+
+template <bool IS_BF16, bool SPLIT>
+__global__ __launch_bounds__(TB) void bk_gemm16(const SlotDev* __restrict__ slots,
+                                                const SlotStat* __restrict__ stat,
+                                                const Item* __restrict__ items,
+                                                const int* __restrict__ counts) {
+  const int cnt = counts[2];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int j = stat[w.slot].j;
+    const float* X = static_cast<const float*>(s.V) + (size_t)j * s.n;
+    float* Y = static_cast<float*>(s.V) + (size_t)(j + 1) * s.n;
+    const uint16_t* hi = IS_BF16 ? s.mhat_hi : s.mhat_f16;
+    gemm16::gemm16_tile<IS_BF16, SPLIT>(hi, s.mhat_lo, s.lda16, s.L, X, Y, s.albedo,
+                                        IS_BF16 ? nullptr : s.f16_rowscale, 1.f / s.l_scale,
+                                        (float)s.gs->vscale[j], s.n_r, (int)s.n_s, s.n_r, w.a,
+                                        w.b, -1.f);
+  }
+}
+
+// --------------------------------------------------------------- Arnoldi
+template <typename TV>
+__global__ __launch_bounds__(TB) void bk_mdot(const SlotDev* __restrict__ slots,
+                                              const SlotStat* __restrict__ stat,
+                                              const Item* __restrict__ items,
+                                              const int* __restrict__ counts) {
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int j = stat[w.slot].j;
+    const TV* V = static_cast<const TV*>(s.V);
+    const TV* wv = V + (size_t)(j + 1) * s.n;
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
+    for (int i0 = 0; i0 <= j; i0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int g = 0; g < 16; ++g) acc[g] = 0.0;
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+        const double x = (double)wv[e];
+#pragma unroll
+        for (int g = 0; g < 16; ++g)
+          if (i0 + g <= j) acc[g] += (double)V[(size_t)(i0 + g) * s.n + e] * x;
+      }
+      const int c = j + 1 - i0 < 16 ? j + 1 - i0 : 16;
+      block_sum_store<16>(acc, s.partial + (size_t)i0 * s.nch + w.a, s.nch, c);
+    }
+  }
+}
+
+__global__ __launch_bounds__(TB) void bk_reduce_rows(const SlotDev* __restrict__ slots,
+                                                     const SlotStat* __restrict__ stat,
+                                                     const int* __restrict__ list,
+                                                     const int* __restrict__ counts) {
+  const int cnt = counts[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int si = list[it];
+    const SlotDev& s = slots[si];
+    const int j = stat[si].j;
+    for (int i = wave; i <= j; i += TB / 64) {
+      double v = 0.0;
+      for (int c = lane; c < s.nch; c += 64) v += s.partial[(size_t)i * s.nch + c];
+      v = wsum(v);
+      if (lane == 0) s.gs->h[i] = s.gs->vscale[i] * v;
+    }
+  }
+}
+
+template <typename TV>
+__global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slots,
+                                                const SlotStat* __restrict__ stat,
+                                                const Item* __restrict__ items,
+                                                const int* __restrict__ counts) {
+  __shared__ double coef[kMaxRestart + 1];
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int j = stat[w.slot].j;
+    for (int i = threadIdx.x; i <= j; i += TB) coef[i] = s.gs->h[i] * s.gs->vscale[i];
+    __syncthreads();
+    TV* V = static_cast<TV*>(s.V);
+    TV* wv = V + (size_t)(j + 1) * s.n;
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
+    double nrm = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+      double v = (double)wv[e];
+      for (int i = 0; i <= j; ++i) v -= coef[i] * (double)V[(size_t)i * s.n + e];
+      const TV q = (TV)v;
+      wv[e] = q;
+      nrm += (double)q * (double)q;
+    }
+    double a[1] = {nrm};
+    block_sum_store<1>(a, s.partial + (size_t)(s.restart + 1) * s.nch + w.a, 1, 1);
+  }
+}
+
+__global__ __launch_bounds__(64) void bk_givens(const SlotDev* __restrict__ slots,
+                                                SlotStat* __restrict__ stat,
+                                                const int* __restrict__ list,
+                                                const int* __restrict__ counts) {
+  const int cnt = counts[4];
+  const int lane = threadIdx.x;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int si = list[it];
+    const SlotDev& s = slots[si];
+    SlotStat& z = stat[si];
+    double v = 0.0;
+    for (int c = lane; c < s.nch; c += 64) v += s.partial[(size_t)(s.restart + 1) * s.nch + c];
+    v = wsum(v);
+    if (lane == 0) {
+      GmresState* gs = s.gs;
+      const int j = z.j;
+      const double hn = sqrt(v);
+      double* col = gs->R + (size_t)j * (kMaxRestart + 1);
+      for (int i = 0; i <= j; ++i) col[i] = gs->h[i];
+      const double raw_diag = col[j];
+      col[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double t1 = gs->cs[i] * col[i] + gs->sn[i] * col[i + 1];
+        col[i + 1] = -gs->sn[i] * col[i] + gs->cs[i] * col[i + 1];
+        col[i] = t1;
+      }
+      double c = 1.0, sn = 0.0;
+      if (col[j + 1] != 0.0) {
+        const double hh = hypot(col[j], col[j + 1]);
+        c = col[j] / hh;
+        sn = col[j + 1] / hh;
+      }
+      gs->cs[j] = c;
+      gs->sn[j] = sn;
+      col[j] = c * col[j] + sn * col[j + 1];
+      col[j + 1] = 0.0;
+      gs->g[j + 1] = -sn * gs->g[j];
+      gs->g[j] = c * gs->g[j];
+      const int breakdown = !(hn > 1e-14 * fabs(raw_diag) + 1e-300);
+      gs->vscale[j + 1] = breakdown ? 0.0 : 1.0 / hn;
+      const double resid = fabs(gs->g[j + 1]);
+      z.resid = resid;
+      z.breakdown = breakdown;
+      z.nonfinite = !isfinite(hn) || !isfinite(resid);
+      z.j = j + 1;
+      z.iters += 1;
+      z.cycle_done = (j + 1 >= s.restart) || resid <= z.target || breakdown || z.nonfinite;
+    }
+  }
+}
+
+// ------------------------------------------------------------- cycle end
+__global__ __launch_bounds__(64) void bk_solve_r(const SlotDev* __restrict__ slots,
+                                                 const SlotStat* __restrict__ stat,
+                                                 const int* __restrict__ list,
+                                                 const int* __restrict__ counts) {
+  const int cnt = counts[4];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    if (threadIdx.x != 0) continue;
+    const int si = list[it];
+    GmresState* gs = slots[si].gs;
+    const int k = stat[si].j;
+    const double rn = stat[si].rn;
+    for (int i = k - 1; i >= 0; --i) {
+      double v = gs->g[i];
+      for (int l = i + 1; l < k; ++l) v -= gs->R[(size_t)l * (kMaxRestart + 1) + i] * gs->y[l];
+      gs->y[i] = v / gs->R[(size_t)i * (kMaxRestart + 1) + i];
+    }
+    for (int i = 0; i < k; ++i) gs->coef[i] = gs->y[i] * gs->vscale[i] * rn;
+  }
+}
+
+template <typename TV>
+__global__ __launch_bounds__(TB) void bk_combine(const SlotDev* __restrict__ slots,
+                                                 const SlotStat* __restrict__ stat,
+                                                 const Item* __restrict__ items,
+                                                 const int* __restrict__ counts) {
+  __shared__ double coef[kMaxRestart + 1];
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int k = stat[w.slot].j;
+    for (int i = threadIdx.x; i < k; i += TB) coef[i] = s.gs->coef[i];
+    __syncthreads();
+    const TV* V = static_cast<const TV*>(s.V);
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+      double v = s.x[e];
+      for (int i = 0; i < k; ++i) v += coef[i] * (double)V[(size_t)i * s.n + e];
+      s.x[e] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// r = b - r (r holds A x), partial norms
+__global__ __launch_bounds__(TB) void bk_residual(const SlotDev* __restrict__ slots,
+                                                  const Item* __restrict__ items,
+                                                  const int* __restrict__ counts) {
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
+    double nrm = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+      const double v = s.b[e] - s.r[e];
+      s.r[e] = v;
+      nrm += v * v;
+    }
+    double a[1] = {nrm};
+    block_sum_store<1>(a, s.partial + (size_t)(s.restart + 1) * s.nch + w.a, 1, 1);
+  }
+}
+
+__global__ __launch_bounds__(64) void bk_finish_rn(const SlotDev* __restrict__ slots,
+                                                   SlotStat* __restrict__ stat,
+                                                   const int* __restrict__ list,
+                                                   const int* __restrict__ counts) {
+  const int cnt = counts[4];
+  const int lane = threadIdx.x;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const int si = list[it];
+    const SlotDev& s = slots[si];
+    double v = 0.0;
+    for (int c = lane; c < s.nch; c += 64) v += s.partial[(size_t)(s.restart + 1) * s.nch + c];
+    v = wsum(v);
+    if (lane == 0) {
+      stat[si].rn = sqrt(v);
+      stat[si].nonfinite = !isfinite(v);
+    }
+  }
+}
+
+// ----------------------------------------------------------- cycle start
+template <typename TV>
+__global__ __launch_bounds__(TB) void bk_v0(const SlotDev* __restrict__ slots,
+                                            const SlotStat* __restrict__ stat,
+                                            const Item* __restrict__ items,
+                                            const int* __restrict__ counts) {
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    const double inv = 1.0 / stat[w.slot].rn;
+    TV* V = static_cast<TV*>(s.V);
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) V[e] = (TV)(s.r[e] * inv);
+  }
+}
+
+__global__ __launch_bounds__(64) void bk_init_cycle(const SlotDev* __restrict__ slots,
+                                                    const int* __restrict__ list,
+                                                    const int* __restrict__ counts) {
+  const int cnt = counts[4];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    GmresState* gs = slots[list[it]].gs;
+    for (int i = threadIdx.x; i <= kMaxRestart; i += 64) gs->g[i] = i == 0 ? 1.0 : 0.0;
+    if (threadIdx.x == 0) gs->vscale[0] = 1.0;
+  }
+}
+
+template <typename K, typename... Args>
+void persist(K kernel, int threads, size_t lds, hipStream_t st, Args... args) {
+  hipLaunchKernelGGL(kernel, dim3(kPersistBlocks), dim3(threads), lds, st, args...);
+  RT_HIP(hipGetLastError());
+}
+
+template <typename VT, typename LT, typename C, bool OUTER>
+void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
+                     hipStream_t st) {
+  ProfScope prof(RT_KCLASS_LAMBDA, st);
+  if (wl.h_counts[0] > 0)
+    persist(bk_lambda_slab<VT, LT, C, OUTER>, TB, 0, st, slots, stat, wl.lam_slab, wl.counts);
+  if (wl.h_counts[1] > 0) {
+    const size_t lds = (size_t)3 * wl.box_pmax * sizeof(C);
+    if (wl.box_npt <= 1)
+      persist(bk_lambda_box<VT, LT, C, 1, OUTER>, TB, lds, st, slots, stat, wl.lam_box, wl.counts);
+    else if (wl.box_npt <= 4)
+      persist(bk_lambda_box<VT, LT, C, 4, OUTER>, TB, lds, st, slots, stat, wl.lam_box, wl.counts);
+    else
+      persist(bk_lambda_box<VT, LT, C, 16, OUTER>, TB, lds, st, slots, stat, wl.lam_box,
+              wl.counts);
+  }
+}
+
+}  // namespace
+
+template <typename TV>
+void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                       hipStream_t st) {
+  using C = typename ComputeOf<TV>::type;
+  if constexpr (sizeof(TV) == 8) {
+    if (prec != RT_PREC_FP64) fail(RT_E_INVALID, "FP64 vectors need the FP64 operator");
+    launch_b_lambda<double, double, double, false>(slots, stat, wl, st);
+    ProfScope prof(RT_KCLASS_SIGMA, st);
+    persist(bk_gemm<double, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+  } else {
+    switch (prec) {
+      case RT_PREC_FP32: {
+        launch_b_lambda<float, float, C, false>(slots, stat, wl, st);
+        ProfScope prof(RT_KCLASS_SIGMA, st);
+        persist(bk_gemm<float, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        break;
+      }
+      case RT_PREC_BF16: {
+        launch_b_lambda<float, __hip_bfloat16, C, false>(slots, stat, wl, st);
+        ProfScope prof(RT_KCLASS_SIGMA, st);
+        persist(bk_gemm16<true, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        break;
+      }
+      case RT_PREC_FP16: {
+        launch_b_lambda<float, __half, C, false>(slots, stat, wl, st);
+        ProfScope prof(RT_KCLASS_SIGMA, st);
+        persist(bk_gemm16<false, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        break;
+      }
+      case RT_PREC_BF16X3: {
+        launch_b_lambda<float, float, C, false>(slots, stat, wl, st);
+        ProfScope prof(RT_KCLASS_SIGMA, st);
+        persist(bk_gemm16<true, true>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        break;
+      }
+      default:
+        fail(RT_E_INVALID, "unknown precision");
+    }
+  }
+  {
+    ProfScope prof(RT_KCLASS_ARNOLDI, st);
+    persist(bk_mdot<TV>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+    persist(bk_reduce_rows, TB, 0, st, slots, stat, wl.slots, wl.counts);
+    persist(bk_update<TV>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+  }
+  persist(bk_givens, 64, 0, st, slots, stat, wl.slots, wl.counts);
+}
+
+template <typename TV>
+void b_cycle_end(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st) {
+  persist(bk_solve_r, 64, 0, st, slots, stat, wl.slots, wl.counts);
+  persist(bk_combine<TV>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+  launch_b_lambda<double, double, double, true>(slots, stat, wl, st);
+  {
+    ProfScope prof(RT_KCLASS_SIGMA, st);
+    persist(bk_gemm<double, true>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+  }
+  persist(bk_residual, TB, 0, st, slots, wl.chunks, wl.counts);
+  persist(bk_finish_rn, 64, 0, st, slots, stat, wl.slots, wl.counts);
+}
+
+template <typename TV>
+void b_start_cycle(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st) {
+  persist(bk_v0<TV>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+  persist(bk_init_cycle, 64, 0, st, slots, wl.slots, wl.counts);
+}
+
+template void b_inner_iteration<double>(const SlotDev*, SlotStat*, const WorkLists&, int,
+                                        hipStream_t);
+template void b_inner_iteration<float>(const SlotDev*, SlotStat*, const WorkLists&, int,
+                                       hipStream_t);
+template void b_cycle_end<double>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
+template void b_cycle_end<float>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
+template void b_start_cycle<double>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
+template void b_start_cycle<float>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
+
+}  // namespace rtsn

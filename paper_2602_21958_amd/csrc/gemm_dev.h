@@ -1,0 +1,140 @@
+// Device body of the FP64 / FP32 MFMA scattering GEMM tile, shared by the
+// single-problem and the grouped (batched) kernels (see sigma_gemm.hip).
+#pragma once
+
+#include "rt_internal.h"
+
+namespace rtsn {
+namespace gemm {
+
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Result element r of lane l sits at row dr(l, r), column l % 16 of the
+// 16 x 16 block: f64 interleaves rows (l/16 + 4r), f32 stacks them (4(l/16) + r).
+template <> struct Mfma<double> {
+  using acc_t = d4_t;
+  static __device__ __forceinline__ int dr(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using acc_t = f4_t;
+  static __device__ __forceinline__ int dr(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int PAD = 16;  // LDS row padding (elements) against bank conflicts
+
+// Map a linear workgroup id to (m tile, n tile): workgroups are dealt to the
+// 8 XCDs round-robin, so regroup ids per XCD and walk m fastest.
+__device__ __forceinline__ void tile_of(int bid, int n_tiles_m, int n_tiles, int& tm, int& tn) {
+  const int xcd = bid & 7;
+  const int local = bid >> 3;
+  const int per_xcd = (n_tiles + 7) >> 3;
+  int t = xcd * per_xcd + local;
+  if ((n_tiles & 7) != 0) t = bid;  // uneven split: keep the plain order
+  tm = t % n_tiles_m;
+  tn = t / n_tiles_m;
+}
+
+// One 128 x 128 output tile at (m0, n0) computed by a 256-thread workgroup.
+// xs multiplies x in the epilogue (ignored when X is null).
+template <typename T>
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ A, const T* __restrict__ B,
+                                          const T* X, T* Y, const double* __restrict__ albedo,
+                                          double xs, int M, int N, int K, int m0, int n0,
+                                          double sign) {
+  using MF = Mfma<T>;
+  using acc_t = typename MF::acc_t;
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // global -> register staging assignment
+  const int a_m = tid >> 1, a_k = (tid & 1) * 8;     // A: 128 rows x 16 k
+  const int b_k = tid >> 4, b_n = (tid & 15) * 8;    // B: 16 k x 128 cols
+  T ra[8], rb[8];
+
+  auto load_tile = [&](int k0) {
+    const int gm = m0 + a_m;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int gk = k0 + a_k + j;
+      ra[j] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : T(0);
+    }
+    const int gk = k0 + b_k;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int gn = n0 + b_n + j;
+      rb[j] = (gk < K && gn < N) ? B[(size_t)gk * N + gn] : T(0);
+    }
+  };
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  load_tile(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) As[a_k + j][a_m] = ra[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Bs[b_k][b_n + j] = rb[j];
+    __syncthreads();
+    if (k0 + BK < K) load_tile(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const int c = lane & 15;
+      T af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[kr][wm * 64 + i * 16 + c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[kr][wn * 64 + j * 16 + c];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(af[i], bf[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+    if (col >= N) continue;
+    const double alb = sign * albedo[col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 64 + i * 16 + MF::dr(lane, r);
+        if (row < M) {
+          const size_t idx = (size_t)row * N + col;
+          double v = alb * (double)acc[i][j][r];
+          if (X != nullptr) v += xs * (double)X[idx];
+          Y[idx] = (T)v;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace gemm
+}  // namespace rtsn

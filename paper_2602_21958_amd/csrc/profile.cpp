@@ -20,6 +20,8 @@ std::vector<Record> g_records;
 
 }  // namespace
 
+bool profile_enabled() { return g_on.load(std::memory_order_relaxed); }
+
 ProfScope::ProfScope(int kclass, hipStream_t st) : kclass_(kclass), st_(st) {
   if (!g_on.load(std::memory_order_relaxed)) return;
   if (hipEventCreate(&start_) != hipSuccess) { start_ = nullptr; return; }

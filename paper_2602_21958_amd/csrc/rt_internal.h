@@ -20,6 +20,8 @@ struct RtError {
   std::string msg;
 };
 [[noreturn]] void fail(rt_status code, const std::string& msg);
+void set_last_error(const std::string& msg);
+bool profile_enabled();
 void hip_check(hipError_t e, const char* what);
 #define RT_HIP(call) ::rtsn::hip_check((call), #call)
 

@@ -86,7 +86,11 @@ _sig = {
     "rt_solver_opts_default": (None, [C.POINTER(SolverOpts)]),
     "rt_solve": (C.c_int, [_vp, C.POINTER(SolverOpts), _vp, _vp, C.c_int,
                            C.POINTER(SolveStats), _vp]),
-    "rt_batch_create": (C.c_int, [C.c_int, C.c_int64, C.c_int, C.c_int, C.POINTER(_vp)]),
+    "rt_batch_create": (C.c_int, [C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                  C.POINTER(_vp)]),
+    "rt_batch_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int64)]),
+    "rt_batch_footprint": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(C.c_int64)]),
     "rt_batch_submit": (C.c_int, [_vp, _vp, C.POINTER(SolverOpts), _vp,
                                   C.POINTER(C.c_uint64)]),
     "rt_batch_step": (C.c_int, [_vp, C.POINTER(C.c_int)]),
@@ -284,6 +288,75 @@ class Problem:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Batch:
+    """Batch / serving engine (rt_batch_*): many independent solves on one
+    device, admitted by HBM footprint, advanced together."""
+
+    def __init__(self, precision: str = "fp64", hbm_budget: int = 8 << 30,
+                 max_slots: int = 512, queue_cap: int = 100000, use_graph: bool = True,
+                 device: int = 0):
+        h = _vp()
+        _check(_lib.rt_batch_create(int(device), PREC[precision], int(hbm_budget),
+                                    int(max_slots), int(queue_cap), int(bool(use_graph)),
+                                    C.byref(h)), "rt_batch_create")
+        self.handle = h
+        self.precision = precision
+
+    def submit(self, problem: "Problem", x_out, **opts) -> int:
+        o = default_opts()
+        o.precision = PREC[self.precision]
+        for k, v in opts.items():
+            if k == "precision":
+                v = PREC[v] if isinstance(v, str) else v
+            setattr(o, k, v)
+        t = C.c_uint64()
+        _check(_lib.rt_batch_submit(self.handle, problem.handle, C.byref(o), _ptr(x_out),
+                                    C.byref(t)), "rt_batch_submit")
+        return int(t.value)
+
+    def step(self) -> int:
+        n = C.c_int()
+        _check(_lib.rt_batch_step(self.handle, C.byref(n)), "rt_batch_step")
+        return int(n.value)
+
+    def poll(self, ticket: int):
+        """None while pending, else a dict of solve statistics."""
+        st = SolveStats()
+        code = _lib.rt_batch_poll(self.handle, C.c_uint64(ticket), C.byref(st))
+        if code == RT_E_BUSY:
+            return None
+        _check(code, "rt_batch_poll", allow=(RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE))
+        hist = [st.history[i] for i in range(st.history_len)] if st.history_len else []
+        return dict(status=STATUS_NAMES[code], iters=st.iters, outer_iters=st.outer_iters,
+                    converged=bool(st.converged), relres=st.relres, ms=st.ms, history=hist)
+
+    def wait_all(self):
+        _check(_lib.rt_batch_wait_all(self.handle), "rt_batch_wait_all")
+
+    def footprint(self, problem: "Problem", restart: int = 30) -> int:
+        b = C.c_int64()
+        _check(_lib.rt_batch_footprint(self.handle, problem.handle, int(restart), C.byref(b)),
+               "rt_batch_footprint")
+        return int(b.value)
+
+    def info(self):
+        a, q, b = C.c_int(), C.c_int(), C.c_int64()
+        _check(_lib.rt_batch_info(self.handle, C.byref(a), C.byref(q), C.byref(b)),
+               "rt_batch_info")
+        return dict(active=a.value, queued=q.value, bytes_in_use=b.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 KCLASS = {"lambda": 0, "sigma": 1, "arnoldi": 2}
