@@ -1,6 +1,9 @@
-"""Benchmark: FP64 GMRES(30) solves of the 32^3 periodic-box workload on one GPU.
+"""Benchmark of the S_N radiative-transfer Krylov path on one GPU.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                [--workload box32|batch512|serve|box64]
+
+Default workload (box32): FP64 GMRES(30) solves of the 32^3 periodic box.
 
 One step is one complete solve of A s = b to a true relative residual of
 1e-8: right-hand side (boundary sweep + scattering), then restarted GMRES
@@ -44,6 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-precision", default="fp16")
+    ap.add_argument("--workload", default="box32",
+                    choices=["box32", "batch512", "serve", "box64"])
+    ap.add_argument("--precision", default=None,
+                    help="operator precision for batch512 / serve / box64")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: stream length (s)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     return ap.parse_args()
 
 
@@ -98,6 +107,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}),
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch512":
+        return bench_batch512(args)
+    if args.workload == "serve":
+        return bench_serve(args)
+    if args.workload == "box64":
+        return bench_box64(args)
     import torch
     import workloads as W
     from paper_2602_21958_amd import rt
@@ -202,6 +217,266 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, stats[-1]["iters"], stats[-1]["outer_iters"])
 
+    p.close()
+    print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------------------
+def _profile_summary(rt, names=("lambda", "sigma", "arnoldi")):
+    return {k: dict(zip(("launches", "total_ms"), rt.profile_read(k, reset=True))) for k in names}
+
+
+def bench_batch512(args):
+    """512 independent slabs (N_z, N_nu, N_mu, eps, depth drawn per slab) in one
+    engine; one step = all 512 solved to the FP64 1e-8 residual."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2602_21958_amd import rt
+
+    prec = args.precision or "bf16x3"
+    specs = W.batch_slabs(512)
+    probs = [rt.Problem(s) for s in specs]
+    n_tot = sum(p.n for p in probs)
+    xs = [torch.empty(p.n, dtype=torch.float64, device="cuda:0") for p in probs]
+
+    def run(precision, profile=False):
+        eng = rt.Batch(precision=precision, hbm_budget=64 << 30, max_slots=512)
+        tk = [eng.submit(p, x, restart=30, rtol=1e-8, max_iters=4000, max_outer=200)
+              for p, x in zip(probs, xs)]
+        if profile:
+            rt.profile_enable(True)
+            _profile_summary(rt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        while eng.step() > 0:
+            steps += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = None
+        if profile:
+            rt.profile_enable(False)
+            prof = _profile_summary(rt)
+        st = [eng.poll(t) for t in tk]
+        eng.close()
+        return el, steps, st, prof
+
+    for _ in range(args.warmup):
+        run(prec)
+    times, st, prof, steps = [], None, None, 0
+    for k in range(args.steps):
+        el, steps, st, pr = run(prec, profile=(k == args.steps - 1))
+        times.append(el)
+        prof = pr or prof
+    el = sum(times) / len(times)
+    conv = sum(1 for s in st if s["converged"])
+    its = np.array([s["iters"] for s in st])
+    variants = {}
+    for v in ("fp64", "fp16", "bf16"):
+        if v == prec:
+            continue
+        e2, s2, st2, _ = run(v)
+        variants[v] = {"solves_per_s": 512 / e2, "converged": sum(1 for s in st2 if s["converged"]),
+                       "iters_median": float(np.median([s["iters"] for s in st2])), "steps": s2}
+    # per-slab FP64 loop through the single-problem solver on a sample
+    sample = list(range(0, 512, 16))
+    t0 = time.perf_counter()
+    for i in sample:
+        probs[i].solve(xs[i], rtol=1e-8, restart=30, record_history=0)
+    torch.cuda.synchronize()
+    loop_per_slab = (time.perf_counter() - t0) / len(sample)
+    sig = prof["sigma"]
+    out = {
+        "metric": "solves/s to 1e-8 residual (512 heterogeneous slabs, one engine)",
+        "value": 512 / el, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "batch512: 512 slabs, N_z~U[32,256], N_nu~U[16,64], "
+                               "N_mu in {8..16}, eps log-U[1e-6,1e-2], depth log-U[1e2,1e6]; "
+                               f"FP32 Lambda + {prec} Sigma + FP64 refinement; GMRES(30) "
+                               "inner cycles; hipGraph-replayed engine steps",
+                   "n_unknowns_total": n_tot},
+        "converged": conv, "engine_steps": steps,
+        "iters": {"median": float(np.median(its)), "p90": float(np.percentile(its, 90)),
+                  "max": int(its.max()), "min": int(its.min())},
+        "kernel_ms_per_step": {k: v["total_ms"] for k, v in prof.items()},
+        "variants": variants,
+        "per_slab_fp64_loop": {"s_per_slab": loop_per_slab, "solves_per_s": 1 / loop_per_slab,
+                               "sample": f"{len(sample)} slabs through rt_solve FP64",
+                               "engine_speedup": (512 / el) * loop_per_slab},
+        "sigma_avg_ms": sig["total_ms"] / max(sig["launches"], 1),
+    }
+    if not args.no_cpu_baseline:
+        from oracle import Problem as OProblem, gmres
+        t0 = time.perf_counter()
+        done = 0
+        for i in range(0, 512, 64):
+            op = OProblem(specs[i])
+            gmres(op.apply, op.rhs(), restart=30, tol=1e-8)
+            done += 1
+            if time.perf_counter() - t0 > 20:
+                break
+        per = (time.perf_counter() - t0) / done
+        out["cpu_baseline"] = {"value": 1 / per, "unit": "solves/s", "cores": _threads(),
+                               "kind": "oracle",
+                               "sample": f"full oracle GMRES(30) solves of {done} of the 512 "
+                                         "slabs (every 64th); solves/s = 1 / mean time"}
+    for p in probs:
+        p.close()
+    print(json.dumps(out), flush=True)
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:
+        return 1
+
+
+def bench_serve(args):
+    """Continuous batching: Poisson arrivals (90 % slabs, 10 % 16^3 boxes); a
+    producer thread builds each request's problem at its arrival time, the
+    main loop submits and steps the engine; latency = completion - arrival."""
+    import queue as pyqueue
+    import threading
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2602_21958_amd import rt
+
+    prec = args.precision or "bf16x3"
+    stream = W.serve_stream(duration_s=args.duration, rate_hz=args.rate)
+    eng = rt.Batch(precision=prec, hbm_budget=96 << 30, max_slots=1024)
+    ready = pyqueue.Queue()
+    t_start = time.perf_counter() + 0.5
+
+    def producer(lo, step):
+        for i in range(lo, len(stream), step):
+            t_arr, kind, seed = stream[i]
+            delay = t_start + t_arr - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            spec = W.serve_request(kind, seed)
+            ready.put((i, t_arr, kind, rt.Problem(spec)))
+
+    threads = [threading.Thread(target=producer, args=(k, 4), daemon=True) for k in range(4)]
+    for th in threads:
+        th.start()
+    live = {}
+    lat = {"slab": [], "box": []}
+    timeline = []
+    done = 0
+    n_req = len(stream)
+    last_tl = 0.0
+    while done < n_req:
+        try:
+            while True:
+                i, t_arr, kind, prob = ready.get_nowait()
+                x = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+                tk = eng.submit(prob, x, restart=30, rtol=1e-8, max_iters=4000, max_outer=200,
+                                record_history=0)
+                live[tk] = (t_arr, kind, prob, x)
+        except pyqueue.Empty:
+            pass
+        if live:
+            eng.step()
+        else:
+            time.sleep(0.0005)
+        now = time.perf_counter() - t_start
+        for tk in list(live):
+            st = eng.poll(tk)
+            if st is not None:
+                t_arr, kind, prob, x = live.pop(tk)
+                lat[kind].append((now - t_arr) * 1e3 if st["converged"] else float("nan"))
+                prob.close()
+                done += 1
+        if now - last_tl >= 1.0:
+            inf = eng.info()
+            timeline.append([round(now, 2), inf["active"], inf["queued"], done,
+                             round(inf["bytes_in_use"] / 2**30, 2)])
+            last_tl = now
+    wall = time.perf_counter() - t_start
+    allv = np.array([v for k in lat for v in lat[k]])
+    ok = allv[np.isfinite(allv)]
+    out = {
+        "metric": "serving: p50/p99 latency (ms) and solves/s, 1e-8 residual",
+        "value": len(ok) / wall, "unit": "solves/s", "n_gpus": 1, "steps": n_req, "warmup": 0,
+        "ms_per_step": wall * 1e3 / max(n_req, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"serve: Poisson {args.rate}/s for {args.duration}s, 90% slabs "
+                               "(batch512 recipe) / 10% 16^3 boxes (4 mu x 8 az, 24 freq); "
+                               f"{prec} Sigma + FP32 Lambda + FP64 refinement; admission by "
+                               "HBM footprint (96 GiB arena)"},
+        "requests": n_req, "converged": int(len(ok)),
+        "latency_ms": {"p50": float(np.percentile(ok, 50)), "p99": float(np.percentile(ok, 99)),
+                       "slab_p50": float(np.nanpercentile(lat["slab"], 50)) if lat["slab"] else None,
+                       "box_p50": float(np.nanpercentile(lat["box"], 50)) if lat["box"] else None,
+                       "box_p99": float(np.nanpercentile(lat["box"], 99)) if lat["box"] else None},
+        "timeline_t_active_queued_done_GiB": timeline[:: max(1, len(timeline) // 30)],
+    }
+    eng.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_box64(args):
+    """The 64^3 box (128 ordinates x 48 frequencies, N = 1.61e9) in mixed
+    precision: FP32 Lambda, 16-bit Sigma, FP64 refinement, GMRES(20) inner
+    cycles (an FP32 GMRES(30) basis would not leave room for the FP64 vectors
+    in 288 GB)."""
+    import torch
+    import workloads as W
+    from paper_2602_21958_amd import rt
+
+    spec = W.box64()
+    p = rt.Problem(spec)
+    n, n_r, n_s = p.n, p.n_r, p.n_s
+    x = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    res = {}
+    variants = [args.precision] if args.precision else ["fp16", "bf16x3", "bf16", "fp32"]
+    for prec in variants:
+        rt.profile_enable(True)
+        _profile_summary(rt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = p.solve(x, rtol=1e-8, restart=20, precision=prec, max_outer=40, max_iters=2000)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rt.profile_enable(False)
+        prof = _profile_summary(rt)
+        res[prec] = {"s_per_solve": el, "converged": st["converged"], "relres_fp64": st["relres"],
+                     "inner_iters": st["iters"], "outer_iters": st["outer_iters"],
+                     "kernel_ms": {k: v["total_ms"] for k, v in prof.items()},
+                     "sigma_launches": prof["sigma"]["launches"]}
+        print(json.dumps({"box64_variant": prec, **res[prec]}), file=sys.stderr, flush=True)
+    best = min((v["s_per_solve"], k) for k, v in res.items() if v["converged"])
+    # single-apply kernel rates at full size
+    xf = torch.randn(n, dtype=torch.float32, device="cuda:0")
+    yf = torch.empty_like(xf)
+    rt.profile_enable(True)
+    _profile_summary(rt)
+    for _ in range(3):
+        p.apply(xf, yf, precision=best[1])
+    torch.cuda.synchronize()
+    rt.profile_enable(False)
+    pr = _profile_summary(rt)
+    sig_ms = pr["sigma"]["total_ms"] / max(pr["sigma"]["launches"], 1)
+    lam_ms = pr["lambda"]["total_ms"] / max(pr["lambda"]["launches"], 1)
+    flops = 2.0 * n_r * n_r * n_s
+    out = {
+        "metric": "solves/s to 1e-8 residual (64^3 box, mixed precision)",
+        "value": 1.0 / best[0], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": best[0] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": best[1], "data": "synthetic",
+        "config": {"workload": "box64: 64^3 box, 128 ordinates (8 mu x 16 az), 48 frequencies, "
+                               "N = 1.61e9; FP32 Lambda + 16-bit Sigma + FP64 refinement, "
+                               "GMRES(20) inner cycles", "n_unknowns": n},
+        "variants": res,
+        "sigma": {"precision": best[1], "avg_ms": sig_ms, "TFLOP/s": flops / sig_ms / 1e9,
+                  "frac_of_2.5PF": flops / sig_ms / 1e9 / PEAK_BF16_TFLOPS},
+        "lambda": {"avg_ms": lam_ms, "GB/s_at_6B_per_unknown": 6.0 * n / lam_ms / 1e6},
+    }
     p.close()
     print(json.dumps(out), flush=True)
 

@@ -15,6 +15,11 @@ void fail(rt_status code, const std::string& msg) { throw RtError{code, msg}; }
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
+std::shared_mutex& capture_mutex() {
+  static std::shared_mutex mu;
+  return mu;
+}
+
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -361,6 +366,7 @@ rt_status rt_problem_create(const rt_problem_desc* desc, int device, rt_problem*
     int ndev = 0;
     RT_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(RT_E_INVALID, "bad device index");
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
     RT_HIP(hipSetDevice(device));
     Problem* p = new Problem();
     p->device = device;
@@ -378,6 +384,7 @@ rt_status rt_problem_destroy(rt_problem p) {
   return guarded([&] {
     if (!p) return;
     Problem* q = reinterpret_cast<Problem*>(p);
+    std::shared_lock<std::shared_mutex> lk(capture_mutex());
     RT_HIP(hipSetDevice(q->device));
     RT_HIP(hipDeviceSynchronize());
     delete q;

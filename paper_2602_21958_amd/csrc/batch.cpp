@@ -130,6 +130,7 @@ struct Engine {
   hipGraph_t graph = nullptr;
   uint64_t graph_key = ~0ull;
   bool iter_dirty = true;
+  int graph_failures = 0;
   uint64_t next_ticket = 1;
   std::deque<Request*> queue;
   std::map<uint64_t, Request*> requests;
@@ -158,14 +159,17 @@ void wl_free(WorkLists& wl) {
   wl = WorkLists();
 }
 
+// Grow a device list buffer; a reallocation changes its address, so it bumps
+// the generation that keys the captured graph.
 template <typename T>
-void ensure_cap(T*& p, int& cap, int need) {
+void ensure_cap(T*& p, int& cap, int need, uint64_t& gen) {
   if (need <= cap) return;
   hipFree(p);
   p = nullptr;
-  int c = std::max(need, cap * 2);
+  int c = std::max(std::max(need, cap * 2), 4096);
   RT_HIP(hipMalloc(&p, (size_t)c * sizeof(T)));
   cap = c;
+  ++gen;
 }
 
 int nchunks(int64_t n) { return (int)((n + kChunk - 1) / kChunk); }
@@ -309,12 +313,15 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
       for (int m0 = 0; m0 < d.n_r; m0 += 128) tiles.push_back(Item{s, m0, n0, 0});
     for (int c = 0; c < d.nch; ++c) chunks.push_back(Item{s, c, 0, 0});
   }
-  ensure_cap(wl.lam_slab, wl.cap_lam_slab, (int)slab.size() + 1);
-  ensure_cap(wl.lam_box, wl.cap_lam_box, (int)box.size() + 1);
-  ensure_cap(wl.tiles, wl.cap_tiles, (int)tiles.size() + 1);
-  ensure_cap(wl.chunks, wl.cap_chunks, (int)chunks.size() + 1);
-  ensure_cap(wl.slots, wl.cap_slots, (int)slots.size() + 1);
-  if (!wl.counts) RT_HIP(hipMalloc(&wl.counts, 8 * sizeof(int)));
+  ensure_cap(wl.lam_slab, wl.cap_lam_slab, (int)slab.size() + 1, wl.gen);
+  ensure_cap(wl.lam_box, wl.cap_lam_box, (int)box.size() + 1, wl.gen);
+  ensure_cap(wl.tiles, wl.cap_tiles, (int)tiles.size() + 1, wl.gen);
+  ensure_cap(wl.chunks, wl.cap_chunks, (int)chunks.size() + 1, wl.gen);
+  ensure_cap(wl.slots, wl.cap_slots, (int)slots.size() + 1, wl.gen);
+  if (!wl.counts) {
+    RT_HIP(hipMalloc(&wl.counts, 8 * sizeof(int)));
+    ++wl.gen;
+  }
   // stage through pinned memory, then copy to the device lists
   const size_t total = slab.size() + box.size() + tiles.size() + chunks.size() +
                        (slots.size() + 3) / 4 + 2;
@@ -357,30 +364,62 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
 
 void Engine::run_inner() {
   const bool profiling = profile_enabled();
-  // launch shape of the inner step: which geometries, which box class
-  const uint64_t key = (uint64_t)(wl_iter.h_counts[0] > 0) | ((uint64_t)(wl_iter.h_counts[1] > 0) << 1) |
-                       ((uint64_t)wl_iter.box_npt << 2) | ((uint64_t)wl_iter.box_pmax << 8);
+  // The captured graph bakes in the launch shape (which geometries, box class
+  // and LDS size) and the addresses of the list buffers: any change of either
+  // needs a new capture.
+  const uint64_t key = (uint64_t)(wl_iter.h_counts[0] > 0) |
+                       ((uint64_t)(wl_iter.h_counts[1] > 0) << 1) |
+                       ((uint64_t)wl_iter.box_npt << 2) | ((uint64_t)wl_iter.box_pmax << 8) |
+                       (wl_iter.gen << 24);
+  auto direct = [&] {
+    if (fp64)
+      b_inner_iteration<double>(d_slots, d_stat, wl_iter, precision, stream);
+    else
+      b_inner_iteration<float>(d_slots, d_stat, wl_iter, precision, stream);
+  };
   if (use_graph && !profiling) {
     if (key != graph_key) {
       if (graph_exec) hipGraphExecDestroy(graph_exec);
       if (graph) hipGraphDestroy(graph);
       graph_exec = nullptr;
       graph = nullptr;
-      RT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      if (fp64)
-        b_inner_iteration<double>(d_slots, d_stat, wl_iter, precision, stream);
-      else
-        b_inner_iteration<float>(d_slots, d_stat, wl_iter, precision, stream);
-      RT_HIP(hipStreamEndCapture(stream, &graph));
-      RT_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
-      graph_key = key;
+      graph_key = ~0ull;
+      std::unique_lock<std::shared_mutex> lk(capture_mutex());
+      bool ok = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+      if (ok) {
+        try {
+          direct();
+        } catch (const RtError&) {
+          ok = false;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(stream, &g);
+        ok = ok && e == hipSuccess && g != nullptr;
+        if (ok) {
+          ok = hipGraphInstantiate(&graph_exec, g, nullptr, nullptr, 0) == hipSuccess;
+          graph = g;
+        } else if (g) {
+          hipGraphDestroy(g);
+        }
+      }
+      (void)hipGetLastError();
+      if (ok) {
+        graph_key = key;
+      } else {
+        // capture was invalidated: nothing of it ran; launch directly
+        if (graph_exec) hipGraphExecDestroy(graph_exec);
+        if (graph) hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_failures++;
+        if (graph_failures >= 3) use_graph = false;
+        direct();
+        return;
+      }
     }
     RT_HIP(hipGraphLaunch(graph_exec, stream));
   } else {
-    if (fp64)
-      b_inner_iteration<double>(d_slots, d_stat, wl_iter, precision, stream);
-    else
-      b_inner_iteration<float>(d_slots, d_stat, wl_iter, precision, stream);
+    direct();
   }
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_fp16.h>
 
 #include <cstdint>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,10 @@ struct RtError {
 [[noreturn]] void fail(rt_status code, const std::string& msg);
 void set_last_error(const std::string& msg);
 bool profile_enabled();
+// Held shared by problem create/destroy (device allocations) and exclusively
+// while a batch engine captures a hipGraph, so no allocation from another
+// thread lands inside a capture.
+std::shared_mutex& capture_mutex();
 void hip_check(hipError_t e, const char* what);
 #define RT_HIP(call) ::rtsn::hip_check((call), #call)
 

@@ -173,3 +173,17 @@ def test_batch_rejects_bad_requests():
         assert e.value.code == rt.RT_E_INVALID
         big.close()
     eng.close()
+
+
+def test_batch_lists_grow_after_graph_capture():
+    """Requests that arrive after the inner step was captured enlarge the work
+    lists beyond their first capacity (4096 items); the engine must re-capture
+    (the list buffers move) and give the same bits as launches without a graph."""
+    specs = small_slabs(1, 6) + [W.small_box(16, 4, 8, 6, seed=100 + i) for i in range(22)]
+    say("lists grow after capture")
+    ref, rst, _ = run_engine(specs, precision="bf16x3", graph=False)
+    late = {i: 2 + i for i in range(1, len(specs))}
+    got, gst, _ = run_engine(specs, precision="bf16x3", graph=True, late=late)
+    for a, b, s1, s2 in zip(ref, got, rst, gst):
+        assert s1["converged"] and s2["converged"]
+        assert np.array_equal(a, b)
