@@ -24,6 +24,10 @@ FLAGS = [
     # packed FP32 instructions stay off: hipcc generates them from plain float
     # code otherwise
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: without this the compiler keeps
+    # them in VGPRs across the K loop and copies them to and from AGPRs
+    # around every tile's MFMA block
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
     f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]

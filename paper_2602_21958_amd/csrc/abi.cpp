@@ -194,12 +194,20 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
 
   int64_t tot = 0;
   RT_HIP(hipSetDevice(p.device));
-  const size_t nr2 = (size_t)p.n_r * p.n_r;
-  p.d_mhat64 = upload(p.tab.mhat.data(), nr2, tot);
   {
-    std::vector<float> m32(nr2);
-    for (size_t i = 0; i < nr2; ++i) m32[i] = (float)p.tab.mhat[i];
-    p.d_mhat32 = upload(m32.data(), nr2, tot);
+    // FP64 / FP32 copies with rows padded (zeros) to a multiple of 32
+    const int lda = (p.n_r + 31) / 32 * 32;
+    p.lda_mhat = lda;
+    const size_t sz = (size_t)p.n_r * lda;
+    std::vector<double> m64(sz, 0.0);
+    std::vector<float> m32(sz, 0.f);
+    for (int k = 0; k < p.n_r; ++k)
+      for (int kp = 0; kp < p.n_r; ++kp) {
+        m64[(size_t)k * lda + kp] = p.tab.mhat[(size_t)k * p.n_r + kp];
+        m32[(size_t)k * lda + kp] = (float)p.tab.mhat[(size_t)k * p.n_r + kp];
+      }
+    p.d_mhat64 = upload(m64.data(), sz, tot);
+    p.d_mhat32 = upload(m32.data(), sz, tot);
   }
   {
     // 16-bit copies with rows padded to a multiple of 8 elements

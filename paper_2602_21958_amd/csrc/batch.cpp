@@ -222,6 +222,7 @@ bool Engine::setup_slot(Request* r, int s) {
   d.n_nu = p.n_nu;
   d.formal = p.formal;
   d.lda16 = p.lda16;
+  d.lda_mhat = p.lda_mhat;
   d.restart = m;
   d.active = 1;
   d.n_s = p.n_s;

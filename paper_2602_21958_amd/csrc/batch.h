@@ -15,6 +15,7 @@ constexpr int kPersistBlocks = 1024;  // grid of the persistent work-list kernel
 struct SlotDev {
   int geom, nx, ny, nz;
   int n_r, n_nu, formal, lda16;
+  int lda_mhat, pad2;
   int restart;
   int active;
   int64_t n_s, n;

@@ -153,8 +153,8 @@ __global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
       Y = static_cast<T*>(s.V) + (size_t)(j + 1) * s.n;
       xs = s.gs->vscale[j];
     }
-    gemm::gemm_tile<T>(A, static_cast<const T*>(s.L), X, Y, s.albedo, xs, s.n_r, (int)s.n_s,
-                       s.n_r, w.a, w.b, -1.0);
+    gemm::gemm_tile<T, 16>(A, s.lda_mhat, static_cast<const T*>(s.L), X, Y, s.albedo, xs,
+                           s.n_r, (int)s.n_s, s.n_r, w.a, w.b, -1.0);
   }
 }
 

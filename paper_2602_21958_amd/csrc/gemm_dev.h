@@ -29,8 +29,9 @@ template <> struct Mfma<float> {
   }
 };
 
-constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int PAD = 16;  // LDS row padding (elements) against bank conflicts
+constexpr int BM = 128, BN = 128;
+constexpr int PAD = 16;   // LDS row padding (elements) against bank conflicts
+constexpr int KPAD = 32;  // Mhat rows are padded (with zeros) to a multiple of this
 
 // Map a linear workgroup id to (m tile, n tile): workgroups are dealt to the
 // 8 XCDs round-robin, so regroup ids per XCD and walk m fastest.
@@ -44,40 +45,66 @@ __device__ __forceinline__ void tile_of(int bid, int n_tiles_m, int n_tiles, int
   tn = t / n_tiles_m;
 }
 
-// One 128 x 128 output tile at (m0, n0) computed by a 256-thread workgroup.
-// xs multiplies x in the epilogue (ignored when X is null).
-template <typename T>
-__device__ __forceinline__ void gemm_tile(const T* __restrict__ A, const T* __restrict__ B,
-                                          const T* X, T* Y, const double* __restrict__ albedo,
-                                          double xs, int M, int N, int K, int m0, int n0,
-                                          double sign) {
+// 16-byte vector of T
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+
+// One 128 x 128 output tile at (m0, n0) computed by a 256-thread workgroup,
+// K staged BK at a time.  A (Mhat) has leading dimension lda, a multiple of
+// KPAD >= K, zero beyond K.  xs multiplies x in the epilogue (ignored when X
+// is null).  Operand tiles are read with 16-byte loads, consecutive lanes on
+// consecutive addresses.
+template <typename T, int BK>
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int lda,
+                                          const T* __restrict__ B, const T* X, T* Y,
+                                          const double* __restrict__ albedo, double xs, int M,
+                                          int N, int K, int m0, int n0, double sign) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int A_CH = BM * BK / VN / 256;   // 16-byte chunks per thread
+  constexpr int B_CH = BK * BN / VN / 256;
+  constexpr int A_PER_ROW = BK / VN;
+  constexpr int B_PER_ROW = BN / VN;
+  static_assert(A_CH >= 1 && B_CH >= 1, "tile too small");
+  __shared__ __align__(16) T As[BK][BM + PAD];
+  __shared__ __align__(16) T Bs[BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  const bool b_vec = (N % VN) == 0;
 
-  // global -> register staging assignment
-  const int a_m = tid >> 1, a_k = (tid & 1) * 8;     // A: 128 rows x 16 k
-  const int b_k = tid >> 4, b_n = (tid & 15) * 8;    // B: 16 k x 128 cols
-  T ra[8], rb[8];
+  V ra[A_CH], rb[B_CH];
 
   auto load_tile = [&](int k0) {
-    const int gm = m0 + a_m;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int gk = k0 + a_k + j;
-      ra[j] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : T(0);
+    for (int i = 0; i < A_CH; ++i) {
+      const int c = tid + 256 * i;
+      const int row = c / A_PER_ROW, kc = (c % A_PER_ROW) * VN;
+      const int gm = m0 + row;
+      if (gm < M) {
+        ra[i] = *reinterpret_cast<const V*>(A + (size_t)gm * lda + k0 + kc);
+      } else {
+        ra[i] = V{};
+      }
     }
-    const int gk = k0 + b_k;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int gn = n0 + b_n + j;
-      rb[j] = (gk < K && gn < N) ? B[(size_t)gk * N + gn] : T(0);
+    for (int i = 0; i < B_CH; ++i) {
+      const int c = tid + 256 * i;
+      const int row = c / B_PER_ROW, nc = (c % B_PER_ROW) * VN;
+      const int gk = k0 + row, gn = n0 + nc;
+      if (gk < K && b_vec && gn + VN - 1 < N) {
+        rb[i] = *reinterpret_cast<const V*>(B + (size_t)gk * N + gn);
+      } else {
+        T* e = reinterpret_cast<T*>(&rb[i]);
+#pragma unroll
+        for (int v = 0; v < VN; ++v)
+          e[v] = (gk < K && gn + v < N) ? B[(size_t)gk * N + gn + v] : T(0);
+      }
     }
   };
 
@@ -92,9 +119,19 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, const T* __re
   load_tile(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) As[a_k + j][a_m] = ra[j];
+    for (int i = 0; i < A_CH; ++i) {
+      const int c = tid + 256 * i;
+      const int row = c / A_PER_ROW, kc = (c % A_PER_ROW) * VN;
+      const T* e = reinterpret_cast<const T*>(&ra[i]);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Bs[b_k][b_n + j] = rb[j];
+      for (int v = 0; v < VN; ++v) As[kc + v][row] = e[v];
+    }
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i) {
+      const int c = tid + 256 * i;
+      const int row = c / B_PER_ROW, nc = (c % B_PER_ROW) * VN;
+      *reinterpret_cast<V*>(&Bs[row][nc]) = rb[i];
+    }
     __syncthreads();
     if (k0 + BK < K) load_tile(k0 + BK);
 #pragma unroll

@@ -97,7 +97,15 @@ __global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
     double v = (double)w[e];
-    for (int i = 0; i < cnt; ++i) v -= coef[i] * (double)V[(size_t)i * n + e];
+    int i = 0;
+    for (; i + 8 <= cnt; i += 8) {  // eight independent loads in flight
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = (double)V[(size_t)(i + u) * n + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v -= coef[i + u] * a[u];
+    }
+    for (; i < cnt; ++i) v -= coef[i] * (double)V[(size_t)i * n + e];
     const TV vs = (TV)v;
     w[e] = vs;
     nrm += (double)vs * (double)vs;
@@ -117,7 +125,15 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict_
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
     double v = (double)x[e];
-    for (int i = 0; i < cnt; ++i) v += coef[i] * (double)V[(size_t)i * n + e];
+    int i = 0;
+    for (; i + 8 <= cnt; i += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = (double)V[(size_t)(i + u) * n + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += coef[i + u] * a[u];
+    }
+    for (; i < cnt; ++i) v += coef[i] * (double)V[(size_t)i * n + e];
     x[e] = (TX)v;
   }
 }

@@ -165,18 +165,40 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
   const C w00 = (C(1) - ty) * (C(1) - tx), w01 = (C(1) - ty) * tx;
   const C w10 = ty * (C(1) - tx), w11 = ty * tx;
 
-  for (int t = 0; t < nz; ++t) {
+  // source and opacity of the next plane are loaded one plane ahead
+  C Sn[kBoxMaxPts], Kn[kBoxMaxPts];
+  auto load_plane = [&](int t) {
     const int z = st.up ? t : nz - 1 - t;
     const VT* sz = sk + (size_t)z * plane_stride;
-    LT* oz = ok + (size_t)z * plane_stride;
     const double* kz = kline + (size_t)z * plane_stride;
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
       const int p = threadIdx.x + j * kBoxThreads;
+      if (p < P) {
+        Sn[j] = sc * C(sz[p]);
+        Kn[j] = C(kz[p]);
+      }
+    }
+  };
+  load_plane(0);
+  for (int t = 0; t < nz; ++t) {
+    const int z = st.up ? t : nz - 1 - t;
+    LT* oz = ok + (size_t)z * plane_stride;
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      if (j >= npt) break;
+      Sv[j] = Sn[j];
+      Kv[j] = Kn[j];
+    }
+    if (t + 1 < nz) load_plane(t + 1);
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      if (j >= npt) break;
+      const int p = threadIdx.x + j * kBoxThreads;
       if (p >= P) break;
-      const C s0 = sc * C(sz[p]);
-      const C k0 = C(kz[p]);
+      const C s0 = Sv[j];
+      const C k0 = Kv[j];
       C I;
       if (t == 0) {
         I = i_in;
@@ -191,8 +213,6 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
       }
       oz[p] = store_val<C, LT>(I * C(out_mul));
       Iv[j] = I;
-      Sv[j] = s0;
-      Kv[j] = k0;
     }
     __syncthreads();
 #pragma unroll

@@ -68,8 +68,9 @@ struct Problem {
   std::vector<BoxStencil> stencil;      // box: per ordinate
 
   // device data
-  double* d_mhat64 = nullptr;           // n_r x n_r
-  float* d_mhat32 = nullptr;
+  double* d_mhat64 = nullptr;           // n_r rows, leading dimension lda_mhat
+  float* d_mhat32 = nullptr;            // same layout
+  int lda_mhat = 0;                     // n_r rounded up to a multiple of 32
   __hip_bfloat16* d_mhat_bf16 = nullptr;   // hi part
   __hip_bfloat16* d_mhat_bf16_lo = nullptr;
   __half* d_mhat_f16 = nullptr;         // rows scaled to unit maximum

@@ -15,15 +15,26 @@
 // ([k][n]); the next K tile is prefetched into registers while the current
 // one is multiplied.  Tiles are assigned so that consecutive workgroups on
 // the same XCD share the same column strip of L (L2 reuse).
+#include <cstdlib>
+
 #include "gemm_dev.h"
 
 namespace rtsn {
 
 namespace {
 
-template <typename T>
+// K-tile depth of the FP64/FP32 GEMM (tuning override: RTSN_GEMM_BK=16|32).
+int gemm_bk() {
+  static const int bk = [] {
+    const char* e = std::getenv("RTSN_GEMM_BK");
+    return (e && std::atoi(e) == 32) ? 32 : 16;
+  }();
+  return bk;
+}
+
+template <typename T, int BK>
 __global__ __launch_bounds__(256) void sigma_gemm_kernel(
-    const T* __restrict__ A, const T* __restrict__ B, const T* X, T* Y,
+    const T* __restrict__ A, int lda, const T* __restrict__ B, const T* X, T* Y,
     const double* __restrict__ albedo, const double* __restrict__ xscale, int M, int N, int K,
     double sign) {
   using namespace gemm;
@@ -32,7 +43,7 @@ __global__ __launch_bounds__(256) void sigma_gemm_kernel(
   int tm, tn;
   tile_of(blockIdx.x, n_tiles_m, n_tiles_m * n_tiles_n, tm, tn);
   const double xs = (X != nullptr && xscale != nullptr) ? *xscale : 1.0;
-  gemm_tile<T>(A, B, X, Y, albedo, xs, M, N, K, tm * BM, tn * BN, sign);
+  gemm_tile<T, BK>(A, lda, B, X, Y, albedo, xs, M, N, K, tm * BM, tn * BN, sign);
 }
 
 template <typename T>
@@ -41,8 +52,12 @@ void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* 
   const int M = p.n_r, N = (int)p.n_s, K = p.n_r;
   const int tiles = ((M + gemm::BM - 1) / gemm::BM) * ((N + gemm::BN - 1) / gemm::BN);
   ProfScope prof(RT_KCLASS_SIGMA, st);
-  hipLaunchKernelGGL((sigma_gemm_kernel<T>), dim3(tiles), dim3(256), 0, st, mhat, L, x, y,
-                     p.d_albedo, xscale, M, N, K, sign);
+  if (gemm_bk() == 32)
+    hipLaunchKernelGGL((sigma_gemm_kernel<T, 32>), dim3(tiles), dim3(256), 0, st, mhat,
+                       p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign);
+  else
+    hipLaunchKernelGGL((sigma_gemm_kernel<T, 16>), dim3(tiles), dim3(256), 0, st, mhat,
+                       p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign);
   RT_HIP(hipGetLastError());
 }
 
