@@ -90,8 +90,8 @@ __global__ __launch_bounds__(TB) void bk_lambda_slab(const SlotDev* __restrict__
   }
 }
 
-template <typename VT, typename LT, typename C, int NPT, bool OUTER>
-__global__ __launch_bounds__(TB) void bk_lambda_box(const SlotDev* __restrict__ slots,
+template <typename VT, typename LT, typename C, int NPT, int NT, bool OUTER>
+__global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ slots,
                                                     const SlotStat* __restrict__ stat,
                                                     const Item* __restrict__ items,
                                                     const int* __restrict__ counts) {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(TB) void bk_lambda_box(const SlotDev* __restrict__ 
       om = s.l_scale;
     }
     LT* dst = static_cast<LT*>(s.L);
-    lam::box_ray<VT, LT, C, NPT>(src + (size_t)k * vol, dst + (size_t)k * vol, s.kline,
+    lam::box_ray<VT, LT, C, NPT, NT>(src + (size_t)k * vol, dst + (size_t)k * vol, s.kline,
                                  s.stencil[k / s.n_nu], C(s.ray_fac[k]), s.nx, s.ny, s.nz, C(0),
                                  sc, om, reinterpret_cast<C*>(smem_raw));
   }
@@ -439,11 +439,16 @@ void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists
   if (wl.h_counts[1] > 0) {
     const size_t lds = (size_t)3 * wl.box_pmax * sizeof(C);
     if (wl.box_npt <= 1)
-      persist(bk_lambda_box<VT, LT, C, 1, OUTER>, TB, lds, st, slots, stat, wl.lam_box, wl.counts);
+      persist(bk_lambda_box<VT, LT, C, 1, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
+              wl.counts);
     else if (wl.box_npt <= 4)
-      persist(bk_lambda_box<VT, LT, C, 4, OUTER>, TB, lds, st, slots, stat, wl.lam_box, wl.counts);
+      persist(bk_lambda_box<VT, LT, C, 4, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
+              wl.counts);
+    else if (sizeof(C) == 4)
+      persist(bk_lambda_box<VT, LT, C, 4, 1024, OUTER>, 1024, lds, st, slots, stat, wl.lam_box,
+              wl.counts);
     else
-      persist(bk_lambda_box<VT, LT, C, 16, OUTER>, TB, lds, st, slots, stat, wl.lam_box,
+      persist(bk_lambda_box<VT, LT, C, 8, 512, OUTER>, 512, lds, st, slots, stat, wl.lam_box,
               wl.counts);
   }
 }

@@ -6,7 +6,7 @@
 namespace rtsn {
 
 constexpr int kMaxRestart = 128;
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 1024;  // dots; the update pass uses twice as many
 
 // GMRES state kept in device memory.  The first fields are what the host
 // reads back after each step.

@@ -50,21 +50,58 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[G], double* out
   __syncthreads();
 }
 
-// partial[i * nb + b] = sum over block b's elements of W_i[n] * w[n]
+// 16-byte vector of a basis element type
+template <typename TV> struct Vec16;
+template <> struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+  static __device__ __forceinline__ double dot(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }
+};
+template <> struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+  static __device__ __forceinline__ double dot(float4 a, float4 b) {
+    return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+  }
+};
+
+// partial[i * nb + b] = sum over block b's range of W_i[e] * w[e].  Each block
+// streams one contiguous range of every vector (16-byte loads when the vector
+// length keeps them aligned); this keeps each DRAM stream sequential.
 template <typename TV, int G>
 __global__ __launch_bounds__(kThreads) void mdot_kernel(const TV* __restrict__ V, int64_t n,
                                                         int i0, int cnt,
                                                         const TV* __restrict__ w,
                                                         double* __restrict__ partial) {
+  using VT = typename Vec16<TV>::type;
+  constexpr int W = Vec16<TV>::n;
   double acc[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) acc[g] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-    const double wv = (double)w[e];
+  if (n % W == 0) {
+    // vector starts are 16-byte aligned: stream with 16-byte loads
+    const int64_t nv = n / W;
+    const int64_t per = (nv + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = b0 + per < nv ? b0 + per : nv;
+    const VT* wv = reinterpret_cast<const VT*>(w);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const VT x = wv[e];
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-      if (g < cnt) acc[g] += (double)V[(size_t)(i0 + g) * n + e] * wv;
+      for (int g = 0; g < G; ++g)
+        if (g < cnt)
+          acc[g] += Vec16<TV>::dot(reinterpret_cast<const VT*>(V + (size_t)(i0 + g) * n)[e], x);
+    }
+  } else {
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const double x = (double)w[e];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (g < cnt) acc[g] += (double)V[(size_t)(i0 + g) * n + e] * x;
+    }
   }
   block_reduce_store<G>(acc, partial + (size_t)i0 * gridDim.x + blockIdx.x, gridDim.x, cnt);
 }
@@ -376,6 +413,13 @@ int grid_for(int64_t n) {
   return (int)(g < kReduceBlocks ? (g < 1 ? 1 : g) : kReduceBlocks);
 }
 
+// The update / norm pass streams (j+2) vectors and writes one: a larger grid
+// keeps more writes in flight.
+int grid_update(int64_t n) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  return (int)(g < 2 * kReduceBlocks ? (g < 1 ? 1 : g) : 2 * kReduceBlocks);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -402,8 +446,8 @@ template <typename TV>
 void k_update(const TV* V, int64_t n, int cnt, const double* h, const double* vscale, TV* w,
               double* partial, hipStream_t st) {
   ProfScope prof(RT_KCLASS_ARNOLDI, st);
-  hipLaunchKernelGGL((update_kernel<TV>), dim3(grid_for(n)), dim3(kThreads), 0, st, V, n, cnt, h,
-                     vscale, w, partial);
+  hipLaunchKernelGGL((update_kernel<TV>), dim3(grid_update(n)), dim3(kThreads), 0, st, V, n, cnt,
+                     h, vscale, w, partial);
   RT_HIP(hipGetLastError());
 }
 
@@ -441,7 +485,7 @@ void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStre
 }
 
 void k_givens(const double* partial, int64_t n, GmresState* gs, int j, hipStream_t st) {
-  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_for(n), gs, j);
+  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j);
   RT_HIP(hipGetLastError());
 }
 

@@ -44,8 +44,8 @@ __global__ __launch_bounds__(256) void lambda_slab_kernel(
                            i_in, sc, scheme, out_mul, lane);
 }
 
-template <typename VT, typename LT, typename C, int NPT>
-__global__ __launch_bounds__(kBoxThreads) void lambda_box_kernel(
+template <typename VT, typename LT, typename C, int NPT, int NT>
+__global__ __launch_bounds__(NT) void lambda_box_kernel(
     const VT* __restrict__ s, LT* __restrict__ out, const double* __restrict__ kline,
     const BoxStencil* __restrict__ stencil, const double* __restrict__ ray_fac, int n_nu,
     int nx, int ny, int nz, double i_top, double i_bot, int with_bc,
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBoxThreads) void lambda_box_kernel(
   const size_t vol = (size_t)nx * ny * nz;
   const C sc = scale ? C(*scale) : C(1);
   const C i_in = with_bc ? C(st.up ? i_bot : i_top) : C(0);
-  lam::box_ray<VT, LT, C, NPT>(s + (size_t)k * vol, out + (size_t)k * vol, kline, st,
+  lam::box_ray<VT, LT, C, NPT, NT>(s + (size_t)k * vol, out + (size_t)k * vol, kline, st,
                                C(ray_fac[k]), nx, ny, nz, i_in, sc, out_mul,
                                reinterpret_cast<C*>(smem_raw));
 }
@@ -83,13 +83,16 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
     int max_lds = 0;
     RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     if (lds > (size_t)max_lds) fail(RT_E_INVALID, "box plane too large for LDS in this precision");
-#define RT_BOX_LAUNCH(NPT)                                                                \
-  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, NPT>), dim3(p.n_r), dim3(kBoxThreads), \
-                     lds, st, s, out, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx,   \
-                     p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
-    if (P <= kBoxThreads) RT_BOX_LAUNCH(1);
-    else if (P <= 4 * kBoxThreads) RT_BOX_LAUNCH(4);
-    else if (P <= 16 * kBoxThreads) RT_BOX_LAUNCH(16);
+#define RT_BOX_LAUNCH(NPT, NT)                                                           \
+  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, NPT, NT>), dim3(p.n_r), dim3(NT), lds, st, \
+                     s, out, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx, p.ny, p.nz,   \
+                     p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
+    // planes up to 1024 points: 256 threads; larger planes: 1024 threads
+    // (FP32) or 512 threads (FP64, which needs twice the registers per point)
+    if (P <= 256) RT_BOX_LAUNCH(1, 256);
+    else if (P <= 1024) RT_BOX_LAUNCH(4, 256);
+    else if (P <= 4096 && sizeof(C) == 4) RT_BOX_LAUNCH(4, 1024);
+    else if (P <= 4096) RT_BOX_LAUNCH(8, 512);
     else fail(RT_E_INVALID, "box plane larger than 4096 points");
 #undef RT_BOX_LAUNCH
   }

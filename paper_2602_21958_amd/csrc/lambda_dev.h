@@ -12,30 +12,38 @@ template <typename C> struct Series;
 template <> struct Series<double> { static constexpr int terms = 16; };
 template <> struct Series<float> { static constexpr int terms = 9; };
 
-// 1/(n+1)! for n = 1..16
-static __device__ __constant__ double kInvFact[16] = {
-    1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
-    1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0,
-    1.0 / 479001600.0, 1.0 / 6227020800.0, 1.0 / 87178291200.0,
-    1.0 / 1307674368000.0, 1.0 / 20922789888000.0, 1.0 / 355687428096000.0};
+// 1/n! for n = 0..17
+static __device__ __constant__ double kInvFactN[18] = {
+    1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
+    1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
+    1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0,
+    1.0 / 355687428096000.0};
 
+// Weights of one linear short-characteristics step of optical length d:
+// e = e^{-d}, a = (1 - e)/d - e, c = 1 - (1 - e)/d.  One transcendental at
+// most: below d = 1/2 all three come from their Taylor polynomials,
+//   e = sum_n (-d)^n/n!,  c = sum_{n>=1} (-1)^{n+1} d^n/(n+1)!,
+//   a = sum_{n>=1} (-1)^{n+1} n d^n/(n+1)!;
+// above it e = exp(-d) and q = (1 - e)/d has no cancellation.
 template <typename C>
 __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
-  e = exp(-d);
   if (d < C(0.5)) {
-    // c = sum_{n>=1} (-1)^{n+1} d^n/(n+1)!,  a = sum_{n>=1} (-1)^{n+1} n d^n/(n+1)!
     constexpr int T = Series<C>::terms;
-    C cs = C(0), as = C(0);
+    C cs = C(0), as = C(0), es = C(0);
 #pragma unroll
     for (int n = T; n >= 1; --n) {
-      C sg = (n & 1) ? C(1) : C(-1);
-      cs = cs * d + sg * C(kInvFact[n - 1]);
-      as = as * d + sg * C(n) * C(kInvFact[n - 1]);
+      const C sg = (n & 1) ? C(1) : C(-1);
+      const C f = C(kInvFactN[n + 1]);
+      cs = cs * d + sg * f;
+      as = as * d + sg * C(n) * f;
+      es = es * d + (-sg) * C(kInvFactN[n]);   // coefficient of d^n in e^{-d}
     }
     c = cs * d;
     a = as * d;
+    e = es * d + C(1);
   } else {
-    C q = -expm1(-d) / d;
+    e = exp(-d);
+    const C q = (C(1) - e) / d;
     a = q - e;
     c = C(1) - q;
   }
@@ -127,7 +135,7 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, LT* __restri
 // sk / ok: the ray's nz*P source / output values.
 constexpr int kBoxThreads = 256;
 
-template <typename VT, typename LT, typename C, int kBoxMaxPts>
+template <typename VT, typename LT, typename C, int kBoxMaxPts, int NT = kBoxThreads>
 __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restrict__ ok,
                                         const double* __restrict__ kline, const BoxStencil st,
                                         C fac, int nx, int ny, int nz, C i_in, C sc,
@@ -140,14 +148,14 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
   const C tx = C(st.tx), ty = C(st.ty);
   const size_t plane_stride = (size_t)P;
 
-  const int npt = (P + kBoxThreads - 1) / kBoxThreads;
+  const int npt = (P + NT - 1) / NT;
   C Iv[kBoxMaxPts], Sv[kBoxMaxPts], Kv[kBoxMaxPts];
   // upwind bilinear source offsets per owned point (fixed for the ordinate)
   int n00[kBoxMaxPts], n01[kBoxMaxPts], n10[kBoxMaxPts], n11[kBoxMaxPts];
 #pragma unroll
   for (int j = 0; j < kBoxMaxPts; ++j) {
     if (j >= npt) break;
-    const int p = threadIdx.x + j * kBoxThreads;
+    const int p = threadIdx.x + j * NT;
     if (p < P) {
       const int x = p % nx, y = p / nx;
       int xa = x + st.i0; if (xa >= nx) xa -= nx;
@@ -174,7 +182,7 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
-      const int p = threadIdx.x + j * kBoxThreads;
+      const int p = threadIdx.x + j * NT;
       if (p < P) {
         Sn[j] = sc * C(sz[p]);
         Kn[j] = C(kz[p]);
@@ -195,7 +203,7 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
-      const int p = threadIdx.x + j * kBoxThreads;
+      const int p = threadIdx.x + j * NT;
       if (p >= P) break;
       const C s0 = Sv[j];
       const C k0 = Kv[j];
@@ -218,7 +226,7 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
-      const int p = threadIdx.x + j * kBoxThreads;
+      const int p = threadIdx.x + j * NT;
       if (p >= P) break;
       lI[p] = Iv[j];
       lS[p] = Sv[j];

@@ -35,7 +35,7 @@ Workspace::~Workspace() {
 
 size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab) {
   const size_t n = (size_t)p.n;
-  size_t b = sizeof(double) * (size_t)(kMaxRestart + 1) * kReduceBlocks + sizeof(GmresState) +
+  size_t b = sizeof(double) * (size_t)(kMaxRestart + 1) * 2 * kReduceBlocks + sizeof(GmresState) +
              sizeof(BicgState) + 64 * sizeof(double);
   b += (size_t)(restart + 1) * n * (mixed ? sizeof(float) : sizeof(double));
   b += (mixed ? 1 : 2) * n * sizeof(double);  // r64 (+ ax64 for FP64 GMRES)
@@ -77,7 +77,7 @@ Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab) 
     ws->V = dalloc<float>((size_t)(restart + 1) * n, tot);
   else
     ws->V = dalloc<double>((size_t)(restart + 1) * n, tot);
-  ws->partial = dalloc<double>((size_t)(kMaxRestart + 1) * kReduceBlocks, tot);
+  ws->partial = dalloc<double>((size_t)(kMaxRestart + 1) * 2 * kReduceBlocks, tot);
   ws->gs = dalloc<GmresState>(1, tot);
   ws->bs = dalloc<BicgState>(1, tot);
   ws->scal = dalloc<double>(64, tot);

@@ -97,7 +97,11 @@ def test_batch_fp64_matches_single_solver_and_oracle():
             xs = host(x)
         assert abs(ref["iters"] - st["iters"]) <= 1
         diff = np.linalg.norm(s - xs) / np.linalg.norm(xs)
-        assert diff < (1e-9 if ref["iters"] == st["iters"] else 1e-5), diff
+        # Two GMRES implementations at the same step differ by Gram-Schmidt
+        # rounding (different reduction orders) amplified by kappa(A) ~ 5e2
+        # over ~100 steps: ~1e-13 * 5e2 * 1e2 < 1e-8.  One step apart, both
+        # meet the 1e-8 residual and differ by up to kappa * 1e-8.
+        assert diff < (1e-8 if ref["iters"] == st["iters"] else 1e-5), diff
 
 
 @pytest.mark.parametrize("precision", ["fp64", "bf16", "fp16", "bf16x3"])
