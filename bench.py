@@ -34,6 +34,37 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 
+# HBM traffic of the dominant kernels from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the dispatches of
+# one solve), scaled by what the same counters read for a 2 GiB device copy
+# (read x2.000, write x1.000).  Each entry holds a hash of the kernel's
+# sources at the time of measurement: once they change the figure is stale
+# and the bench reports null.
+TRAFFIC = {
+    "sigma_f64_box32": {"files": ("gemm_dev.h", "sigma_gemm.hip"), "sha": "b18051976c54eb72",
+                        "fetch_kib": 2.429e6, "write_kib": 5.243e5,
+                        "fetch_scale": 2.000, "write_scale": 1.000,
+                        "profile": "profiles/sigma_gemm_f64_box32_counters.md"},
+}
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2602_21958_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(key):
+    """Calibrated HBM bytes per launch, or None when the kernel changed."""
+    t = TRAFFIC.get(key)
+    if t is None or source_hash(t["files"]) != t["sha"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
+
 WORKLOAD = ("box32: 3D box 32x32x32 periodic in x,y; 64 ordinates (8 Gauss-Legendre mu x 8 "
             "azimuths), 32 frequencies; exponential + 20% log-normal opacity; eps 1e-4; "
             "dipole x PRD kernel as a dense 2048x2048 matrix; GMRES(30) to 1e-8; FP64")
@@ -53,6 +84,9 @@ def parse():
                     help="operator precision for batch512 / serve / box64")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: stream length (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 2 GiB device-to-device copy before the timed region; its "
+                         "memory counters calibrate the HBM traffic of the other kernels")
     return ap.parse_args()
 
 
@@ -118,6 +152,12 @@ def main():
     from paper_2602_21958_amd import rt
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     spec = W.box32()
     p = rt.Problem(spec, 0)
     n, n_r, n_s = p.n, p.n_r, p.n_s
@@ -180,7 +220,9 @@ def main():
         "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
         "roofline": {"kernel": "sigma_gemm_kernel<double> (FP64 MFMA 16x16x4)",
                      "bound": "mfma", "achieved": sig_tf, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": sig_tf / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": sig_tf / PEAK_FP64_TFLOPS,
+                     "traffic": traffic_bytes("sigma_f64_box32"),
+                     "traffic_unit": "B per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                      "launches": sig_n, "avg_ms": sig_avg,
                      "algorithmic_per_launch": f"2*N_r^2*N_s = {sig_flops:.4g} flop"},
         "lambda": {"kernel": "lambda_box_kernel<double>", "bound": "hbm", "achieved": lam_gbs,
