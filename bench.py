@@ -254,7 +254,10 @@ def main():
                         "relres_fp64": mst["relres"], "converged": mst["converged"],
                         "inner_iters": mst["iters"], "outer_iters": mst["outer_iters"],
                         "rel_diff_vs_fp64_solution": diff,
-                        "sigma_avg_ms": ms_ms / max(ms_n, 1)}
+                        "sigma_avg_ms": ms_ms / max(ms_n, 1),
+                        "sigma_tflops": sig_flops / (ms_ms / max(ms_n, 1) * 1e-3) / 1e12,
+                        "sigma_tile": p.gemm16_tile(prec) if prec in ("bf16", "fp16", "bf16x3")
+                        else "FP32 MFMA 128x128"}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, stats[-1]["iters"], stats[-1]["outer_iters"])
@@ -490,7 +493,8 @@ def bench_box64(args):
         res[prec] = {"s_per_solve": el, "converged": st["converged"], "relres_fp64": st["relres"],
                      "inner_iters": st["iters"], "outer_iters": st["outer_iters"],
                      "kernel_ms": {k: v["total_ms"] for k, v in prof.items()},
-                     "sigma_launches": prof["sigma"]["launches"]}
+                     "sigma_launches": prof["sigma"]["launches"],
+                     "sigma_tile": p.gemm16_tile(prec) if prec != "fp32" else "FP32 MFMA"}
         print(json.dumps({"box64_variant": prec, **res[prec]}), file=sys.stderr, flush=True)
     best = min((v["s_per_solve"], k) for k, v in res.items() if v["converged"])
     # single-apply kernel rates at full size

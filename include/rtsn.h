@@ -286,6 +286,14 @@ enum { RT_KCLASS_LAMBDA = 0, RT_KCLASS_SIGMA = 1, RT_KCLASS_ARNOLDI = 2, RT_KCLA
 rt_status rt_profile_enable(int on);
 rt_status rt_profile_read(int kclass, int64_t* launches, double* total_ms, int reset);
 
+/* Tile shape the 16-bit scattering GEMM uses for problem p in `precision`
+ * (RT_PREC_BF16 / FP16 / BF16X3): chosen the first time the problem applies
+ * that precision by timing the candidate shapes on the problem's own
+ * operands, or forced with the environment variable RTSN_GEMM16_CFG=<index>.
+ * Returns a static string ("untuned" before the first use, "" for other
+ * precisions or a NULL problem).                                            */
+const char* rt_gemm16_tile(rt_problem p, int precision);
+
 /* Thread-local message of the last failed call on this thread.              */
 const char* rt_last_error(void);
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "gemm16_dev.h"
 #include "krylov.h"
 
 namespace rtsn {
@@ -32,9 +33,10 @@ Problem::~Problem() {
   delete ws;
   hipFree(d_mhat64);
   hipFree(d_mhat32);
-  hipFree(d_mhat_bf16);
-  hipFree(d_mhat_bf16_lo);
-  hipFree(d_mhat_f16);
+  hipFree(d_a8_bf16);
+  hipFree(d_a8_bf16_lo);
+  hipFree(d_a8_f16);
+  hipFree(d_l16);
   hipFree(d_f16_rowscale);
   hipFree(d_albedo);
   hipFree(d_thermal);
@@ -56,6 +58,17 @@ size_t lambda_elem_bytes(int precision) {
     case RT_PREC_BF16X3: return 4;
     default: return 8;
   }
+}
+
+int64_t l16_part_elems(const Problem& p) { return (int64_t)p.kp16 * p.np16; }
+
+uint16_t* problem_l16(Problem& p, hipStream_t st) {
+  if (!p.d_l16) {
+    const size_t bytes = 2 * (size_t)l16_part_elems(p) * sizeof(uint16_t);
+    RT_HIP(hipMalloc(&p.d_l16, bytes));
+    RT_HIP(hipMemsetAsync(p.d_l16, 0, bytes, st));
+  }
+  return p.d_l16;
 }
 
 void* problem_lbuf(Problem& p, size_t bytes) {
@@ -210,10 +223,12 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
     p.d_mhat32 = upload(m32.data(), sz, tot);
   }
   {
-    // 16-bit copies with rows padded to a multiple of 8 elements
-    const int lda = (p.n_r + 7) / 8 * 8;
-    p.lda16 = lda;
-    const size_t sz = (size_t)p.n_r * lda;
+    // 16-bit copies in the k8 layout of the MFMA GEMM (see gemm16_dev.h):
+    // element (k, k') at ((k' / 8) * mp16 + k) * 8 + k' % 8, zero padded
+    p.mp16 = (int)g16::round_up(p.n_r, g16::kMAlign);
+    p.kp16 = (int)g16::round_up(p.n_r, g16::kKAlign);
+    p.np16 = g16::round_up(p.n_s, g16::kMAlign);
+    const size_t sz = (size_t)p.mp16 * p.kp16;
     std::vector<uint16_t> hi(sz, 0), lo(sz, 0), h16(sz, 0);
     std::vector<float> rs(p.n_r, 1.f);
     for (int k = 0; k < p.n_r; ++k) {
@@ -224,15 +239,16 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
       rs[k] = (float)rmax;
       for (int kp = 0; kp < p.n_r; ++kp) {
         const double m = p.tab.mhat[(size_t)k * p.n_r + kp];
+        const size_t at = ((size_t)(kp / 8) * p.mp16 + k) * 8 + kp % 8;
         const uint16_t h = bf16_bits((float)m);
-        hi[(size_t)k * lda + kp] = h;
-        lo[(size_t)k * lda + kp] = bf16_bits((float)(m - (double)bf16_value(h)));
-        h16[(size_t)k * lda + kp] = f16_bits((float)(m / (double)rs[k]));
+        hi[at] = h;
+        lo[at] = bf16_bits((float)(m - (double)bf16_value(h)));
+        h16[at] = f16_bits((float)(m / (double)rs[k]));
       }
     }
-    p.d_mhat_bf16 = reinterpret_cast<__hip_bfloat16*>(upload(hi.data(), sz, tot));
-    p.d_mhat_bf16_lo = reinterpret_cast<__hip_bfloat16*>(upload(lo.data(), sz, tot));
-    p.d_mhat_f16 = reinterpret_cast<__half*>(upload(h16.data(), sz, tot));
+    p.d_a8_bf16 = upload(hi.data(), sz, tot);
+    p.d_a8_bf16_lo = upload(lo.data(), sz, tot);
+    p.d_a8_f16 = upload(h16.data(), sz, tot);
     p.d_f16_rowscale = upload(rs.data(), rs.size(), tot);
   }
   p.d_albedo = upload(alb.data(), alb.size(), tot);
@@ -285,25 +301,13 @@ void operator_apply(Problem& p, int precision, const void* x, void* y, const dou
                        st);
       break;
     }
-    case RT_PREC_BF16: {
-      auto* L = static_cast<__hip_bfloat16*>(problem_lbuf(p, n * 2));
-      launch_lambda<float, __hip_bfloat16>(p, static_cast<const float*>(x), L, false, xscale, st);
-      launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
-                       xscale, -1.0, st);
-      break;
-    }
-    case RT_PREC_FP16: {
-      auto* L = static_cast<__half*>(problem_lbuf(p, n * 2));
-      launch_lambda<float, __half>(p, static_cast<const float*>(x), L, false, xscale, st,
-                                   fp16_lambda_scale(p.n));
-      launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
-                       xscale, -1.0, st);
-      break;
-    }
+    case RT_PREC_BF16:
+    case RT_PREC_FP16:
     case RT_PREC_BF16X3: {
-      float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
-      launch_lambda<float, float>(p, static_cast<const float*>(x), L, false, xscale, st);
-      launch_sigma_b16(p, precision, L, static_cast<const float*>(x), static_cast<float*>(y),
+      uint16_t* L = problem_l16(p, st);
+      uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
+      launch_lambda_k4(p, precision, static_cast<const float*>(x), L, Llo, xscale, st);
+      launch_sigma_b16(p, precision, L, Llo, static_cast<const float*>(x), static_cast<float*>(y),
                        xscale, -1.0, st);
       break;
     }
@@ -364,6 +368,15 @@ void check_prec(int prec) {
 extern "C" {
 
 const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+const char* rt_gemm16_tile(rt_problem p, int precision) {
+  if (!p) return "";
+  const Problem* q = reinterpret_cast<const Problem*>(p);
+  const int mode = precision == RT_PREC_BF16 ? 0 : precision == RT_PREC_FP16 ? 1
+                   : precision == RT_PREC_BF16X3 ? 2 : -1;
+  if (mode < 0) return "";
+  return gemm16_config_name(q->g16_cfg[mode]);
+}
 
 int rt_version(void) { return RTSN_VERSION; }
 
@@ -461,18 +474,10 @@ rt_status rt_apply_sigma(rt_problem p, int precision, const void* L, const void*
                        static_cast<float*>(y), nullptr, sign, st);
     } else {
       // 16-bit operand paths take an FP32 L and round it like the operator does
-      const size_t n = (size_t)q->n;
-      void* lb = problem_lbuf(*q, n * lambda_elem_bytes(precision));
-      if (precision == RT_PREC_BF16X3) {
-        RT_HIP(hipMemcpyAsync(lb, L, n * sizeof(float), hipMemcpyDeviceToDevice, st));
-      } else if (precision == RT_PREC_BF16) {
-        k_convert<float, __hip_bfloat16>(static_cast<const float*>(L),
-                                         static_cast<__hip_bfloat16*>(lb), (int64_t)n, 1.0, st);
-      } else {
-        k_convert<float, __half>(static_cast<const float*>(L), static_cast<__half*>(lb),
-                                 (int64_t)n, fp16_lambda_scale(q->n), st);
-      }
-      launch_sigma_b16(*q, precision, lb, static_cast<const float*>(x), static_cast<float*>(y),
+      uint16_t* lb = problem_l16(*q, st);
+      uint16_t* lo = precision == RT_PREC_BF16X3 ? lb + l16_part_elems(*q) : nullptr;
+      convert_to_k4(*q, precision, static_cast<const float*>(L), lb, lo, st);
+      launch_sigma_b16(*q, precision, lb, lo, static_cast<const float*>(x), static_cast<float*>(y),
                        nullptr, sign, st);
     }
   });

@@ -197,6 +197,7 @@ size_t Engine::footprint(const Problem& p, int restart) const {
   size_t b = 0;
   b += align_up((size_t)(restart + 1) * n * tv);              // basis
   b += align_up(n * sizeof(double));                          // L scratch
+  if (!fp64) b += align_up(2 * (size_t)l16_part_elems(p) * sizeof(uint16_t));  // 16-bit L
   b += 2 * align_up(n * sizeof(double));                      // b, r
   b += align_up((size_t)(restart + 2) * nchunks(p.n) * sizeof(double));  // partials
   b += align_up(sizeof(GmresState));
@@ -221,8 +222,10 @@ bool Engine::setup_slot(Request* r, int s) {
   d.n_r = p.n_r;
   d.n_nu = p.n_nu;
   d.formal = p.formal;
-  d.lda16 = p.lda16;
   d.lda_mhat = p.lda_mhat;
+  d.mp16 = p.mp16;
+  d.kp16 = p.kp16;
+  d.np16 = p.np16;
   d.restart = m;
   d.active = 1;
   d.n_s = p.n_s;
@@ -230,9 +233,9 @@ bool Engine::setup_slot(Request* r, int s) {
   d.nch = nchunks(p.n);
   d.mhat64 = p.d_mhat64;
   d.mhat32 = p.d_mhat32;
-  d.mhat_hi = reinterpret_cast<const uint16_t*>(p.d_mhat_bf16);
-  d.mhat_lo = reinterpret_cast<const uint16_t*>(p.d_mhat_bf16_lo);
-  d.mhat_f16 = reinterpret_cast<const uint16_t*>(p.d_mhat_f16);
+  d.a8_hi = p.d_a8_bf16;
+  d.a8_lo = p.d_a8_bf16_lo;
+  d.a8_f16 = p.d_a8_f16;
   d.f16_rowscale = p.d_f16_rowscale;
   d.albedo = p.d_albedo;
   d.dt = p.d_dt;
@@ -242,6 +245,12 @@ bool Engine::setup_slot(Request* r, int s) {
   d.ray_fac = p.d_ray_fac;
   d.V = q;                                      q += align_up((size_t)(m + 1) * n * tv);
   d.L = q;                                      q += align_up(n * sizeof(double));
+  if (!fp64) {
+    const size_t lb = 2 * (size_t)l16_part_elems(p) * sizeof(uint16_t);
+    d.l16 = reinterpret_cast<uint16_t*>(q);     q += align_up(lb);
+    // padding rows of the operand must read as zeros
+    RT_HIP(hipMemsetAsync(d.l16, 0, lb, stream));
+  }
   d.b = reinterpret_cast<double*>(q);           q += align_up(n * sizeof(double));
   d.r = reinterpret_cast<double*>(q);           q += align_up(n * sizeof(double));
   d.partial = reinterpret_cast<double*>(q);     q += align_up((size_t)(m + 2) * d.nch * 8);

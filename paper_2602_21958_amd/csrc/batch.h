@@ -14,8 +14,9 @@ constexpr int kPersistBlocks = 1024;  // grid of the persistent work-list kernel
 // arena.
 struct SlotDev {
   int geom, nx, ny, nz;
-  int n_r, n_nu, formal, lda16;
-  int lda_mhat, pad2;
+  int n_r, n_nu, formal, lda_mhat;
+  int mp16, kp16;               // 16-bit operand padding (see gemm16_dev.h)
+  int64_t np16;
   int restart;
   int active;
   int64_t n_s, n;
@@ -23,9 +24,10 @@ struct SlotDev {
   int pad0;
   const double* mhat64;
   const float* mhat32;
-  const uint16_t* mhat_hi;
-  const uint16_t* mhat_lo;
-  const uint16_t* mhat_f16;
+  const uint16_t* a8_hi;        // Mhat, k8 layout: bf16 (hi part)
+  const uint16_t* a8_lo;        // bf16 of Mhat - hi
+  const uint16_t* a8_f16;       // fp16, rows scaled
+  uint16_t* l16;                // Lambda output, k4 layout: hi part, then lo part
   const float* f16_rowscale;
   const double* albedo;
   const double* dt;

@@ -58,8 +58,18 @@ template <> struct ComputeOf<float> { using type = float; };
 
 // ------------------------------------------------------------------ Lambda
 // OUTER: x (FP64) -> L (FP64), no input scale.  Otherwise V_j (scaled by
-// vscale_j) -> L (type LT, times l_scale for fp16).
-template <typename VT, typename LT, typename C, bool OUTER>
+// vscale_j) -> L (type LT; with K4 >= 0 the k4 16-bit GEMM operand, times
+// l_scale for fp16).
+template <typename LT, int K4>
+__device__ __forceinline__ auto slot_out(const SlotDev& s, int k, size_t len) {
+  if constexpr (K4 < 0)
+    return lam::PlainOut<LT>{static_cast<LT*>(s.L) + (size_t)k * len};
+  else
+    return lam::k4_ray<K4>(s.l16, K4 == lam::K4_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr,
+                           k, s.np16);
+}
+
+template <typename VT, typename LT, typename C, int K4, bool OUTER>
 __global__ __launch_bounds__(TB) void bk_lambda_slab(const SlotDev* __restrict__ slots,
                                                      const SlotStat* __restrict__ stat,
                                                      const Item* __restrict__ items,
@@ -84,13 +94,12 @@ __global__ __launch_bounds__(TB) void bk_lambda_slab(const SlotDev* __restrict__
       sc = C(s.gs->vscale[j]);
       om = s.l_scale;
     }
-    LT* dst = static_cast<LT*>(s.L);
-    lam::slab_ray<VT, LT, C>(src + (size_t)k * s.nz, dst + (size_t)k * s.nz, s.dt, s.ray_mu[k],
-                             s.ray_fac[k], s.nz, C(0), sc, s.formal, om, lane);
+    lam::slab_ray<VT>(src + (size_t)k * s.nz, slot_out<LT, K4>(s, k, s.nz), s.dt, s.ray_mu[k],
+                      s.ray_fac[k], s.nz, C(0), sc, s.formal, om, lane);
   }
 }
 
-template <typename VT, typename LT, typename C, int NPT, int NT, bool OUTER>
+template <typename VT, typename LT, typename C, int K4, int NPT, int NT, bool OUTER>
 __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ slots,
                                                     const SlotStat* __restrict__ stat,
                                                     const Item* __restrict__ items,
@@ -115,10 +124,9 @@ __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ 
       sc = C(s.gs->vscale[j]);
       om = s.l_scale;
     }
-    LT* dst = static_cast<LT*>(s.L);
-    lam::box_ray<VT, LT, C, NPT, NT>(src + (size_t)k * vol, dst + (size_t)k * vol, s.kline,
-                                 s.stencil[k / s.n_nu], C(s.ray_fac[k]), s.nx, s.ny, s.nz, C(0),
-                                 sc, om, reinterpret_cast<C*>(smem_raw));
+    lam::box_ray<VT, decltype(slot_out<LT, K4>(s, k, vol)), C, NPT, NT>(
+        src + (size_t)k * vol, slot_out<LT, K4>(s, k, vol), s.kline, s.stencil[k / s.n_nu],
+        C(s.ray_fac[k]), s.nx, s.ny, s.nz, C(0), sc, om, reinterpret_cast<C*>(smem_raw));
   }
 }
 
@@ -158,11 +166,16 @@ __global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
   }
 }
 
-template <bool IS_BF16, bool SPLIT>
-__global__ __launch_bounds__(TB) void bk_gemm16(const SlotDev* __restrict__ slots,
-                                                const SlotStat* __restrict__ stat,
-                                                const Item* __restrict__ items,
-                                                const int* __restrict__ counts) {
+// 16-bit operands, one fixed tile shape for every slot (tiles of the lists
+// are 128 x 128): V_{j+1} = vscale_j V_j - (1 - eps) Mhat L.
+using BatchCfg16 = g16::Cfg<128, 128, 2, 2, 32, true>;
+
+template <int MODE>
+__global__ __launch_bounds__(BatchCfg16::NT) void bk_gemm16(const SlotDev* __restrict__ slots,
+                                                          const SlotStat* __restrict__ stat,
+                                                          const Item* __restrict__ items,
+                                                          const int* __restrict__ counts) {
+  __shared__ __align__(16) uint8_t lds[BatchCfg16::lds_bytes<MODE>()];
   const int cnt = counts[2];
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
@@ -170,11 +183,12 @@ __global__ __launch_bounds__(TB) void bk_gemm16(const SlotDev* __restrict__ slot
     const int j = stat[w.slot].j;
     const float* X = static_cast<const float*>(s.V) + (size_t)j * s.n;
     float* Y = static_cast<float*>(s.V) + (size_t)(j + 1) * s.n;
-    const uint16_t* hi = IS_BF16 ? s.mhat_hi : s.mhat_f16;
-    gemm16::gemm16_tile<IS_BF16, SPLIT>(hi, s.mhat_lo, s.lda16, s.L, X, Y, s.albedo,
-                                        IS_BF16 ? nullptr : s.f16_rowscale, 1.f / s.l_scale,
-                                        (float)s.gs->vscale[j], s.n_r, (int)s.n_s, s.n_r, w.a,
-                                        w.b, -1.f);
+    const uint16_t* ahi = MODE == g16::MODE_FP16 ? s.a8_f16 : s.a8_hi;
+    const uint16_t* blo = MODE == g16::MODE_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr;
+    g16::tile<MODE, BatchCfg16>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X, Y,
+                                s.albedo, MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr,
+                                1.f / s.l_scale, (float)s.gs->vscale[j], -1.f, s.n_r, (int)s.n_s,
+                                w.a, w.b, lds);
   }
 }
 
@@ -430,25 +444,25 @@ void persist(K kernel, int threads, size_t lds, hipStream_t st, Args... args) {
   RT_HIP(hipGetLastError());
 }
 
-template <typename VT, typename LT, typename C, bool OUTER>
+template <typename VT, typename LT, typename C, int K4, bool OUTER>
 void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
                      hipStream_t st) {
   ProfScope prof(RT_KCLASS_LAMBDA, st);
   if (wl.h_counts[0] > 0)
-    persist(bk_lambda_slab<VT, LT, C, OUTER>, TB, 0, st, slots, stat, wl.lam_slab, wl.counts);
+    persist(bk_lambda_slab<VT, LT, C, K4, OUTER>, TB, 0, st, slots, stat, wl.lam_slab, wl.counts);
   if (wl.h_counts[1] > 0) {
     const size_t lds = (size_t)3 * wl.box_pmax * sizeof(C);
     if (wl.box_npt <= 1)
-      persist(bk_lambda_box<VT, LT, C, 1, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
+      persist(bk_lambda_box<VT, LT, C, K4, 1, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
               wl.counts);
     else if (wl.box_npt <= 4)
-      persist(bk_lambda_box<VT, LT, C, 4, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
+      persist(bk_lambda_box<VT, LT, C, K4, 4, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
               wl.counts);
     else if (sizeof(C) == 4)
-      persist(bk_lambda_box<VT, LT, C, 4, 1024, OUTER>, 1024, lds, st, slots, stat, wl.lam_box,
+      persist(bk_lambda_box<VT, LT, C, K4, 4, 1024, OUTER>, 1024, lds, st, slots, stat, wl.lam_box,
               wl.counts);
     else
-      persist(bk_lambda_box<VT, LT, C, 8, 512, OUTER>, 512, lds, st, slots, stat, wl.lam_box,
+      persist(bk_lambda_box<VT, LT, C, K4, 8, 512, OUTER>, 512, lds, st, slots, stat, wl.lam_box,
               wl.counts);
   }
 }
@@ -461,33 +475,36 @@ void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl
   using C = typename ComputeOf<TV>::type;
   if constexpr (sizeof(TV) == 8) {
     if (prec != RT_PREC_FP64) fail(RT_E_INVALID, "FP64 vectors need the FP64 operator");
-    launch_b_lambda<double, double, double, false>(slots, stat, wl, st);
+    launch_b_lambda<double, double, double, -1, false>(slots, stat, wl, st);
     ProfScope prof(RT_KCLASS_SIGMA, st);
     persist(bk_gemm<double, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
   } else {
     switch (prec) {
       case RT_PREC_FP32: {
-        launch_b_lambda<float, float, C, false>(slots, stat, wl, st);
+        launch_b_lambda<float, float, C, -1, false>(slots, stat, wl, st);
         ProfScope prof(RT_KCLASS_SIGMA, st);
         persist(bk_gemm<float, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
         break;
       }
       case RT_PREC_BF16: {
-        launch_b_lambda<float, __hip_bfloat16, C, false>(slots, stat, wl, st);
+        launch_b_lambda<float, float, C, lam::K4_BF16, false>(slots, stat, wl, st);
         ProfScope prof(RT_KCLASS_SIGMA, st);
-        persist(bk_gemm16<true, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        persist(bk_gemm16<g16::MODE_BF16>, BatchCfg16::NT, 0, st, slots, stat, wl.tiles,
+                wl.counts);
         break;
       }
       case RT_PREC_FP16: {
-        launch_b_lambda<float, __half, C, false>(slots, stat, wl, st);
+        launch_b_lambda<float, float, C, lam::K4_FP16, false>(slots, stat, wl, st);
         ProfScope prof(RT_KCLASS_SIGMA, st);
-        persist(bk_gemm16<false, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        persist(bk_gemm16<g16::MODE_FP16>, BatchCfg16::NT, 0, st, slots, stat, wl.tiles,
+                wl.counts);
         break;
       }
       case RT_PREC_BF16X3: {
-        launch_b_lambda<float, float, C, false>(slots, stat, wl, st);
+        launch_b_lambda<float, float, C, lam::K4_SPLIT, false>(slots, stat, wl, st);
         ProfScope prof(RT_KCLASS_SIGMA, st);
-        persist(bk_gemm16<true, true>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
+        persist(bk_gemm16<g16::MODE_SPLIT>, BatchCfg16::NT, 0, st, slots, stat, wl.tiles,
+                wl.counts);
         break;
       }
       default:
@@ -507,7 +524,7 @@ template <typename TV>
 void b_cycle_end(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st) {
   persist(bk_solve_r, 64, 0, st, slots, stat, wl.slots, wl.counts);
   persist(bk_combine<TV>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
-  launch_b_lambda<double, double, double, true>(slots, stat, wl, st);
+  launch_b_lambda<double, double, double, -1, true>(slots, stat, wl, st);
   {
     ProfScope prof(RT_KCLASS_SIGMA, st);
     persist(bk_gemm<double, true>, TB, 0, st, slots, stat, wl.tiles, wl.counts);

@@ -1,201 +1,244 @@
 // Device body of the 16-bit (bf16 / fp16 / split-bf16) MFMA scattering GEMM
-// tile, shared by the single-problem and the grouped kernels (see
-// sigma_b16.hip).
+// tile, shared by the single-problem kernels (sigma_b16.hip) and the grouped
+// kernel of the batch engine (batch.hip).
+//
+//   Y[m, n] = xs X[m, n] + sign * albedo[n] * rowfac[m] * sum_k A[m, k] B[k, n]
+//
+// Operand layouts (16-bit values, zero padded):
+//   A (Mhat)      "k8": element (m, k) at ((k / 8) * Mp + m) * 8 + k % 8, k < Kp
+//   B (Lambda's   "k4": element (k, n) at ((k / 4) * Np + n) * 4 + k % 4
+//      output)
+// with Mp, Np multiples of 256 and Kp a multiple of 64.  A 16-byte chunk of A
+// is 8 consecutive k of one row, the operand of one MFMA lane; a 16-byte
+// chunk of B holds 4 consecutive k of two neighbouring points, and the two
+// k4 groups a lane needs are staged one LDS block apart so that one
+// ds_read2_b64 fetches them.  Global memory is read in 16-byte chunks, 64
+// lanes on 1 KB of contiguous memory, into registers one K stage ahead, then
+// stored into a double-buffered LDS ring (one barrier per stage).
+//
+// MFMA: v_mfma_f32_16x16x32 (F32 = false) or v_mfma_f32_32x32x16 (F32 =
+// true) on bf16 or fp16.  A lane's 8 operand values are 8 consecutive k for
+// both A and B, so the k order inside an instruction is the natural one.
 #pragma once
 
 #include "rt_internal.h"
 
 namespace rtsn {
-namespace gemm16 {
-
+namespace g16 {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, BK = 64;
-constexpr int LDK = BK + 8;  // LDS row length (elements): 144 B rows
+enum { MODE_BF16 = 0, MODE_FP16 = 1, MODE_SPLIT = 2 };
 
-template <bool IS_BF16> struct Op16;
-template <> struct Op16<true> {
-  static __device__ __forceinline__ uint16_t bits(float v) {
-    return __bfloat16_as_ushort(__float2bfloat16(v));
-  }
-  static __device__ __forceinline__ float value(uint16_t b) {
-    return __bfloat162float(__ushort_as_bfloat16(b));
-  }
-  static __device__ __forceinline__ f32x4_t mma(uint4 a, uint4 b, f32x4_t c) {
+constexpr int kMAlign = 256;   // Mp, Np multiple of this
+constexpr int kKAlign = 64;    // Kp multiple of this
+
+__host__ __device__ constexpr int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+template <bool IS_BF16, bool BIG> struct Mma;
+template <> struct Mma<true, false> {
+  using acc_t = f32x4_t;
+  static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
                                                    __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
   }
 };
-template <> struct Op16<false> {
-  static __device__ __forceinline__ uint16_t bits(float v) {
-    return __half_as_ushort(__float2half(v));
-  }
-  static __device__ __forceinline__ float value(uint16_t b) {
-    return __half2float(__ushort_as_half(b));
-  }
-  static __device__ __forceinline__ f32x4_t mma(uint4 a, uint4 b, f32x4_t c) {
+template <> struct Mma<false, false> {
+  using acc_t = f32x4_t;
+  static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8_t, a),
                                                   __builtin_bit_cast(f16x8_t, b), c, 0, 0, 0);
   }
 };
+template <> struct Mma<true, true> {
+  using acc_t = f32x16_t;
+  static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                   __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+  }
+};
+template <> struct Mma<false, true> {
+  using acc_t = f32x16_t;
+  static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a),
+                                                  __builtin_bit_cast(f16x8_t, b), c, 0, 0, 0);
+  }
+};
 
-__device__ __forceinline__ void tile_of(int bid, int n_tiles_m, int n_tiles, int& tm, int& tn) {
-  const int xcd = bid & 7;
-  const int local = bid >> 3;
-  const int per_xcd = (n_tiles + 7) >> 3;
-  int t = xcd * per_xcd + local;
-  if ((n_tiles & 7) != 0) t = bid;
-  tm = t % n_tiles_m;
-  tn = t / n_tiles_m;
-}
+// Tile configuration: BM x BN output tile, WGM x WGN waves, K stage BK,
+// BIG = 32x32x16 instructions (else 16x16x32).
+template <int BM_, int BN_, int WGM_, int WGN_, int BK_, bool BIG_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, BK = BK_;
+  static constexpr bool BIG = BIG_;
+  static constexpr int NW = WGM * WGN, NT = 64 * NW;
+  static constexpr int WM = BM / WGM, WN = BN / WGN;
+  static constexpr int MI = BIG ? 32 : 16;           // instruction tile
+  static constexpr int TI = WM / MI, TJ = WN / MI;
+  static constexpr int HB = BN / 128;                // 128-point halves of a B stage block row
+  static constexpr int RB = BM / 64;                 // 64-row blocks of an A stage
+  static constexpr int BLKA = 1024;
+  static constexpr int BLKB = 1024 + 64 / HB;        // padding spreads the two k4 reads over all banks
+  static constexpr int A_BLK = (BK / 8) * RB;        // 1 KB blocks per stage and operand part
+  static constexpr int B_BLK = (BK / 4) * HB;
+  static constexpr int ASB = A_BLK * BLKA, BSB = B_BLK * BLKB;
+  static constexpr int AU = A_BLK / NW, BU = B_BLK / NW;
+  static_assert(A_BLK % NW == 0 && B_BLK % NW == 0, "stage loads must split evenly over waves");
+  static_assert(TI >= 1 && TJ >= 1 && BM % 64 == 0 && BN % 128 == 0 && BK % 32 == 0, "shape");
+  template <int MODE> static constexpr int lds_bytes() {
+    return 2 * (MODE == MODE_SPLIT ? 2 : 1) * (ASB + BSB);
+  }
+};
 
-__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) {
-  return (uint32_t)lo | ((uint32_t)hi << 16);
-}
+// One output tile at (m0, n0).  lds: Cfg::lds_bytes<MODE>() bytes, 16-byte
+// aligned.  Caller guarantees m0 + BM <= Mp, n0 + BN <= Np, K4p % (BK/4) == 0.
+// The function starts with a barrier, so a persistent caller may reuse lds.
+template <int MODE, typename C>
+__device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
+                                     const uint16_t* __restrict__ Alo, int Mp,
+                                     const uint16_t* __restrict__ Bhi,
+                                     const uint16_t* __restrict__ Blo, int Np, int K4p,
+                                     const float* X, float* Y, const double* __restrict__ albedo,
+                                     const float* __restrict__ rowscale, float colmul, float xs,
+                                     float sign, int M, int N, int m0, int n0, uint8_t* lds) {
+  constexpr bool SPLIT = MODE == MODE_SPLIT;
+  constexpr int NP = SPLIT ? 2 : 1;   // operand parts (hi, lo)
+  using MM = Mma<MODE != MODE_FP16, C::BIG>;
+  using acc_t = typename MM::acc_t;
+  constexpr int NR = C::BIG ? 16 : 4;
+  constexpr int STAGE = NP * (C::ASB + C::BSB);
 
-// IS_BF16: bf16 (true) or fp16 operands.  SPLIT: three-product split bf16.
-// B is uint16_t L (not SPLIT) or float L (SPLIT).
-// One 128 x 128 output tile at (m0, n0); xs multiplies x in the epilogue.
-template <bool IS_BF16, bool SPLIT>
-__device__ __forceinline__ void gemm16_tile(
-    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int lda,
-    const void* __restrict__ Bv, const float* X, float* Y, const double* __restrict__ albedo,
-    const float* __restrict__ rowscale, float bscale_inv, float xs, int M, int N, int K,
-    int m0, int n0, float sign) {
-  using OP = Op16<IS_BF16>;
-  constexpr int NA = SPLIT ? 2 : 1;
-  __shared__ __align__(16) uint16_t As[NA][BM][LDK];
-  __shared__ __align__(16) uint16_t Bs[NA][BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / C::WGN, wn = wave % C::WGN;
 
-  // B staging: thread owns 8 k-rows x 4 points
-  const int b_k = (tid >> 5) * 8;
-  const int b_n = (tid & 31) * 4;
-  const bool b_vec = (N % 4) == 0;
+  u32x4_t ra[NP][C::AU], rb[NP][C::BU];
+  const uint16_t* Ap[2] = {Ahi, Alo};
+  const uint16_t* Bp[2] = {Bhi, Blo};
 
-  uint4 ra[NA][4];
-  uint16_t rb[NA][8][4];
-
-  auto load_tile = [&](int k0) {
+  auto gload = [&](int kg4) {
+    const int kg8 = kg4 >> 1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int c = tid + 256 * i;
-      const int row = c >> 3, kc = (c & 7) * 8;
-      const int gm = m0 + row, gk = k0 + kc;
-      const bool ok = gm < M && gk < lda;
-      const size_t off = (size_t)gm * lda + gk;
-      ra[0][i] = ok ? *reinterpret_cast<const uint4*>(Ahi + off) : make_uint4(0, 0, 0, 0);
-      if constexpr (SPLIT)
-        ra[1][i] = ok ? *reinterpret_cast<const uint4*>(Alo + off) : make_uint4(0, 0, 0, 0);
+    for (int s = 0; s < NP; ++s) {
+#pragma unroll
+      for (int u = 0; u < C::AU; ++u) {
+        const int b = wave + C::NW * u;
+        const int g8 = b / C::RB, rbk = b % C::RB;
+        ra[s][u] = *reinterpret_cast<const u32x4_t*>(
+            Ap[s] + ((size_t)(kg8 + g8) * Mp + m0 + rbk * 64 + lane) * 8);
+      }
+#pragma unroll
+      for (int u = 0; u < C::BU; ++u) {
+        const int b = wave + C::NW * u;
+        const int g4 = b / C::HB, hb = b % C::HB;
+        rb[s][u] = *reinterpret_cast<const u32x4_t*>(
+            Bp[s] + ((size_t)(kg4 + g4) * Np + n0 + hb * 128 + 2 * lane) * 4);
+      }
     }
+  };
+  auto lstore = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int gk = k0 + b_k + kk;
-      const int gn = n0 + b_n;
-      if constexpr (SPLIT) {
-        const float* B = static_cast<const float*>(Bv);
-        float v[4];
-        if (gk < K && b_vec && gn + 3 < N) {
-          const float4 q = *reinterpret_cast<const float4*>(B + (size_t)gk * N + gn);
-          v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-        } else {
+    for (int s = 0; s < NP; ++s) {
+      uint8_t* As = lds + buf * STAGE + s * (C::ASB + C::BSB);
+      uint8_t* Bs = As + C::ASB;
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            v[j] = (gk < K && gn + j < N) ? B[(size_t)gk * N + gn + j] : 0.f;
-        }
+      for (int u = 0; u < C::AU; ++u) {
+        const int b = wave + C::NW * u;
+        *reinterpret_cast<u32x4_t*>(As + b * C::BLKA + 16 * lane) = ra[s][u];
+      }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint16_t h = Op16<true>::bits(v[j]);
-          rb[0][kk][j] = h;
-          rb[1][kk][j] = Op16<true>::bits(v[j] - Op16<true>::value(h));
-        }
-      } else {
-        const uint16_t* B = static_cast<const uint16_t*>(Bv);
-        if (gk < K && b_vec && gn + 3 < N) {
-          const uint2 q = *reinterpret_cast<const uint2*>(B + (size_t)gk * N + gn);
-          rb[0][kk][0] = q.x & 0xffff; rb[0][kk][1] = q.x >> 16;
-          rb[0][kk][2] = q.y & 0xffff; rb[0][kk][3] = q.y >> 16;
-        } else {
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            rb[0][kk][j] = (gk < K && gn + j < N) ? B[(size_t)gk * N + gn + j] : (uint16_t)0;
-        }
+      for (int u = 0; u < C::BU; ++u) {
+        const int b = wave + C::NW * u;
+        const int g4 = b / C::HB, hb = b % C::HB;
+        *reinterpret_cast<u32x4_t*>(
+            Bs + ((g4 >> 1) * 2 * C::HB + hb * 2 + (g4 & 1)) * C::BLKB + 16 * lane) = rb[s][u];
       }
     }
   };
 
-  f32x4_t acc[4][4];
+  acc_t acc[C::TI][C::TJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < C::TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < C::TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[i][j][r] = 0.f;
 
-  load_tile(0);
-  for (int k0 = 0; k0 < lda; k0 += BK) {
+  // lane roles: 16x16x32 -> 4 groups of 16 lanes (k8 chunk q, row/col r16);
+  // 32x32x16 -> 2 groups of 32 lanes (k8 chunk p, row/col r32)
+  const int kgrp = C::BIG ? (lane >> 5) : (lane >> 4);
+  const int rc = C::BIG ? (lane & 31) : (lane & 15);
+  constexpr int KSTEP = C::BIG ? 16 : 32;      // k per instruction
+  constexpr int KCH = KSTEP / 8;               // k8 chunks per instruction
+
+  const int nst = K4p / (C::BK / 4);
+  __syncthreads();   // lds may still be read by a previous tile of this workgroup
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    gload(min(st + 1, nst - 1) * (C::BK / 4));   // the last stage reloads itself (unused)
+    __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
 #pragma unroll
-    for (int s = 0; s < NA; ++s) {
+    for (int h = 0; h < C::BK / KSTEP; ++h) {
+      const int c8 = KCH * h + kgrp;             // k8 chunk of this lane within the stage
+      u32x4_t bf[NP][C::TJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int c = tid + 256 * i;
-        *reinterpret_cast<uint4*>(&As[s][c >> 3][(c & 7) * 8]) = ra[s][i];
+      for (int s = 0; s < NP; ++s) {
+        const uint8_t* Bs = lds + buf * STAGE + s * (C::ASB + C::BSB) + C::ASB;
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) {
+          const int n = wn * C::WN + C::MI * j + rc;
+          const uint8_t* p0 = Bs + (c8 * 2 * C::HB + (n >> 7) * 2) * C::BLKB + (n & 127) * 8;
+          const uint2 lo = *reinterpret_cast<const uint2*>(p0);
+          const uint2 hi = *reinterpret_cast<const uint2*>(p0 + C::BLKB);
+          bf[s][j] = u32x4_t{lo.x, lo.y, hi.x, hi.y};
+        }
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        uint4 w;
-        w.x = pack2(rb[s][0][j], rb[s][1][j]);
-        w.y = pack2(rb[s][2][j], rb[s][3][j]);
-        w.z = pack2(rb[s][4][j], rb[s][5][j]);
-        w.w = pack2(rb[s][6][j], rb[s][7][j]);
-        *reinterpret_cast<uint4*>(&Bs[s][b_n + j][b_k]) = w;
-      }
-    }
-    __syncthreads();
-    if (k0 + BK < lda) load_tile(k0 + BK);
+      for (int i = 0; i < C::TI; ++i) {
+        const int m = wm * C::WM + C::MI * i + rc;
+        u32x4_t af[NP];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 32) {
-      const int kq = kk + 8 * (lane >> 4);
-      const int c = lane & 15;
-      uint4 af[NA][4], bf[NA][4];
+        for (int s = 0; s < NP; ++s) {
+          const uint8_t* As = lds + buf * STAGE + s * (C::ASB + C::BSB);
+          af[s] = *reinterpret_cast<const u32x4_t*>(As + (c8 * C::RB + (m >> 6)) * C::BLKA +
+                                                   (m & 63) * 16);
+        }
 #pragma unroll
-      for (int s = 0; s < NA; ++s) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          af[s][i] = *reinterpret_cast<const uint4*>(&As[s][wm * 64 + i * 16 + c][kq]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          bf[s][j] = *reinterpret_cast<const uint4*>(&Bs[s][wn * 64 + j * 16 + c][kq]);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j] = OP::mma(af[0][i], bf[0][j], acc[i][j]);
+        for (int j = 0; j < C::TJ; ++j) {
+          acc[i][j] = MM::run(af[0], bf[0][j], acc[i][j]);
           if constexpr (SPLIT) {
-            acc[i][j] = OP::mma(af[0][i], bf[1][j], acc[i][j]);
-            acc[i][j] = OP::mma(af[1][i], bf[0][j], acc[i][j]);
+            acc[i][j] = MM::run(af[0], bf[1][j], acc[i][j]);
+            acc[i][j] = MM::run(af[1], bf[0][j], acc[i][j]);
           }
         }
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
+    lstore(buf ^ 1);
     __syncthreads();
   }
 
+  // epilogue
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+  for (int j = 0; j < C::TJ; ++j) {
+    const int col = n0 + wn * C::WN + C::MI * j + rc;
     if (col >= N) continue;
-    const float alb = sign * (float)albedo[col] * bscale_inv;
+    const float cf = sign * (float)albedo[col] * colmul;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < C::TI; ++i) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+      for (int r = 0; r < NR; ++r) {
+        const int row = m0 + wm * C::WM + C::MI * i +
+                        (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
         if (row < M) {
           const size_t idx = (size_t)row * N + col;
-          float v = alb * (rowscale ? rowscale[row] : 1.f) * acc[i][j][r];
+          float v = cf * (rowscale ? rowscale[row] : 1.f) * acc[i][j][r];
           if (X != nullptr) v += xs * X[idx];
           Y[idx] = v;
         }
@@ -204,5 +247,23 @@ __device__ __forceinline__ void gemm16_tile(
   }
 }
 
-}  // namespace gemm16
+// Workgroups are dealt to the 8 XCDs round-robin: give each XCD a contiguous
+// range of tiles, ordered GM row tiles at a time so that the tiles in flight
+// on one XCD share operand rows and columns in its L2.  Returns false for the
+// few padding workgroups of a grid of 8 * ceil(T / 8).
+__device__ __forceinline__ bool tile_of(int bid, int Mt, int Nt, int GM, int& tm, int& tn) {
+  const int T = Mt * Nt;
+  const int per = (T + 7) >> 3;
+  const int t = (bid & 7) * per + (bid >> 3);
+  if (t >= T) return false;
+  const int gsz = GM * Nt;
+  const int grp = t / gsz, in = t % gsz;
+  const int gm0 = grp * GM;
+  const int gmw = min(GM, Mt - gm0);
+  tm = gm0 + in % gmw;
+  tn = in / gmw;
+  return true;
+}
+
+}  // namespace g16
 }  // namespace rtsn

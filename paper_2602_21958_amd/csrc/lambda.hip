@@ -28,9 +28,19 @@ namespace {
 
 using lam::kBoxThreads;
 
-template <typename VT, typename LT, typename C>
+// Output of ray k: plain ray-major array of LT (K4 < 0) or the k4-interleaved
+// 16-bit GEMM operand (K4 = lam::K4_BF16 / K4_FP16 / K4_SPLIT).
+template <typename LT, int K4>
+__device__ __forceinline__ auto ray_out(void* o0, void* o1, int k, size_t len, int64_t Np) {
+  if constexpr (K4 < 0)
+    return lam::PlainOut<LT>{static_cast<LT*>(o0) + (size_t)k * len};
+  else
+    return lam::k4_ray<K4>(static_cast<uint16_t*>(o0), static_cast<uint16_t*>(o1), k, Np);
+}
+
+template <typename VT, typename LT, typename C, int K4>
 __global__ __launch_bounds__(256) void lambda_slab_kernel(
-    const VT* __restrict__ s, LT* __restrict__ out, const double* __restrict__ dt,
+    const VT* __restrict__ s, void* out0, void* out1, int64_t Np, const double* __restrict__ dt,
     const double* __restrict__ ray_mu, const double* __restrict__ ray_fac, int n_r, int nz,
     double i_top, double i_bot, int with_bc, const double* __restrict__ scale, int scheme,
     float out_mul) {
@@ -40,25 +50,25 @@ __global__ __launch_bounds__(256) void lambda_slab_kernel(
   const double mu = ray_mu[k];
   const C sc = scale ? C(*scale) : C(1);
   const C i_in = with_bc ? C(mu < 0.0 ? i_top : i_bot) : C(0);
-  lam::slab_ray<VT, LT, C>(s + (size_t)k * nz, out + (size_t)k * nz, dt, mu, ray_fac[k], nz,
-                           i_in, sc, scheme, out_mul, lane);
+  lam::slab_ray<VT>(s + (size_t)k * nz, ray_out<LT, K4>(out0, out1, k, nz, Np), dt, mu,
+                    ray_fac[k], nz, i_in, sc, scheme, out_mul, lane);
 }
 
-template <typename VT, typename LT, typename C, int NPT, int NT>
+template <typename VT, typename LT, typename C, int K4, int NPT, int NT>
 __global__ __launch_bounds__(NT) void lambda_box_kernel(
-    const VT* __restrict__ s, LT* __restrict__ out, const double* __restrict__ kline,
-    const BoxStencil* __restrict__ stencil, const double* __restrict__ ray_fac, int n_nu,
-    int nx, int ny, int nz, double i_top, double i_bot, int with_bc,
-    const double* __restrict__ scale, float out_mul) {
+    const VT* __restrict__ s, void* out0, void* out1, int64_t Np,
+    const double* __restrict__ kline, const BoxStencil* __restrict__ stencil,
+    const double* __restrict__ ray_fac, int n_nu, int nx, int ny, int nz, double i_top,
+    double i_bot, int with_bc, const double* __restrict__ scale, float out_mul) {
   extern __shared__ unsigned char smem_raw[];
   const int k = blockIdx.x;
   const BoxStencil st = stencil[k / n_nu];
   const size_t vol = (size_t)nx * ny * nz;
   const C sc = scale ? C(*scale) : C(1);
   const C i_in = with_bc ? C(st.up ? i_bot : i_top) : C(0);
-  lam::box_ray<VT, LT, C, NPT, NT>(s + (size_t)k * vol, out + (size_t)k * vol, kline, st,
-                               C(ray_fac[k]), nx, ny, nz, i_in, sc, out_mul,
-                               reinterpret_cast<C*>(smem_raw));
+  lam::box_ray<VT, decltype(ray_out<LT, K4>(out0, out1, k, vol, Np)), C, NPT, NT>(
+      s + (size_t)k * vol, ray_out<LT, K4>(out0, out1, k, vol, Np), kline, st, C(ray_fac[k]),
+      nx, ny, nz, i_in, sc, out_mul, reinterpret_cast<C*>(smem_raw));
 }
 
 template <typename VT> struct ComputeOf;
@@ -67,15 +77,15 @@ template <> struct ComputeOf<float> { using type = float; };
 
 }  // namespace
 
-template <typename VT, typename LT>
-void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
-                   const double* scale, hipStream_t st, float out_mul) {
+template <typename VT, typename LT, int K4>
+void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int64_t Np,
+                     bool with_bc, const double* scale, hipStream_t st, float out_mul) {
   using C = typename ComputeOf<VT>::type;
   ProfScope prof(RT_KCLASS_LAMBDA, st);
   if (p.geom == RT_GEOM_SLAB) {
     dim3 grid((p.n_r + 3) / 4);
-    hipLaunchKernelGGL((lambda_slab_kernel<VT, LT, C>), grid, dim3(256), 0, st, s, out,
-                       p.d_dt, p.d_ray_mu, p.d_ray_fac, p.n_r, p.nz, p.i_top, p.i_bot,
+    hipLaunchKernelGGL((lambda_slab_kernel<VT, LT, C, K4>), grid, dim3(256), 0, st, s, out0,
+                       out1, Np, p.d_dt, p.d_ray_mu, p.d_ray_fac, p.n_r, p.nz, p.i_top, p.i_bot,
                        with_bc ? 1 : 0, scale, p.formal, out_mul);
   } else {
     const int P = p.nx * p.ny;
@@ -83,10 +93,10 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
     int max_lds = 0;
     RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     if (lds > (size_t)max_lds) fail(RT_E_INVALID, "box plane too large for LDS in this precision");
-#define RT_BOX_LAUNCH(NPT, NT)                                                           \
-  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, NPT, NT>), dim3(p.n_r), dim3(NT), lds, st, \
-                     s, out, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx, p.ny, p.nz,   \
-                     p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
+#define RT_BOX_LAUNCH(NPT, NT)                                                               \
+  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, NPT, NT>), dim3(p.n_r), dim3(NT), lds, \
+                     st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx,  \
+                     p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
     // planes up to 1024 points: 256 threads; larger planes: 1024 threads
     // (FP32) or 512 threads (FP64, which needs twice the registers per point)
     if (P <= 256) RT_BOX_LAUNCH(1, 256);
@@ -99,14 +109,34 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
   RT_HIP(hipGetLastError());
 }
 
+template <typename VT, typename LT>
+void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
+                   const double* scale, hipStream_t st, float out_mul) {
+  lambda_dispatch<VT, LT, -1>(p, s, out, nullptr, 0, with_bc, scale, st, out_mul);
+}
+
+void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t* hi,
+                      uint16_t* lo, const double* scale, hipStream_t st) {
+  const int64_t Np = p.np16;
+  switch (precision) {
+    case RT_PREC_BF16:
+      lambda_dispatch<float, float, lam::K4_BF16>(p, s, hi, nullptr, Np, false, scale, st, 1.f);
+      break;
+    case RT_PREC_FP16:
+      lambda_dispatch<float, float, lam::K4_FP16>(p, s, hi, nullptr, Np, false, scale, st,
+                                                  fp16_lambda_scale(p.n));
+      break;
+    case RT_PREC_BF16X3:
+      lambda_dispatch<float, float, lam::K4_SPLIT>(p, s, hi, lo, Np, false, scale, st, 1.f);
+      break;
+    default:
+      fail(RT_E_INVALID, "launch_lambda_k4: not a 16-bit precision");
+  }
+}
+
 template void launch_lambda<double, double>(const Problem&, const double*, double*, bool,
                                             const double*, hipStream_t, float);
 template void launch_lambda<float, float>(const Problem&, const float*, float*, bool,
                                           const double*, hipStream_t, float);
-template void launch_lambda<float, __hip_bfloat16>(const Problem&, const float*,
-                                                   __hip_bfloat16*, bool, const double*,
-                                                   hipStream_t, float);
-template void launch_lambda<float, __half>(const Problem&, const float*, __half*, bool,
-                                           const double*, hipStream_t, float);
 
 }  // namespace rtsn

@@ -66,11 +66,54 @@ __device__ __forceinline__ LT store_val(C v) {
   else return to_outf<LT>(v);
 }
 
+// Where a ray's values go.  PlainOut: element i of the ray at o[i] (the
+// ray-major vector layout).  K4Out: the 16-bit B operand of the scattering
+// GEMM, element i of ray k at base[((k / 4) * Np + i) * 4 + k % 4]; the
+// pointers are already offset to the ray, so element i is at [4 i].
+template <typename LT>
+struct PlainOut {
+  LT* o;
+  template <typename C>
+  __device__ __forceinline__ void put(size_t i, C v) const { o[i] = store_val<C, LT>(v); }
+};
+
+enum { K4_BF16 = 0, K4_FP16 = 1, K4_SPLIT = 2 };
+
+__device__ __forceinline__ uint16_t bf16_rne(float v) {
+  return __bfloat16_as_ushort(__float2bfloat16(v));
+}
+
+template <int MODE>
+struct K4Out {
+  uint16_t* hi;
+  uint16_t* lo;   // SPLIT only: v - bf16(v), rounded to bf16
+  template <typename C>
+  __device__ __forceinline__ void put(size_t i, C cv) const {
+    const float v = (float)cv;
+    if constexpr (MODE == K4_FP16) {
+      hi[4 * i] = __half_as_ushort(__float2half(v));
+    } else {
+      const uint16_t h = bf16_rne(v);
+      hi[4 * i] = h;
+      if constexpr (MODE == K4_SPLIT)
+        lo[4 * i] = bf16_rne(v - __bfloat162float(__ushort_as_bfloat16(h)));
+    }
+  }
+};
+
+// 16-bit operand of ray k inside a k4 buffer (Np points per k4 group).
+template <int MODE>
+__device__ __forceinline__ K4Out<MODE> k4_ray(uint16_t* hi, uint16_t* lo, int k, int64_t Np) {
+  const size_t off = ((size_t)(k >> 2) * Np) * 4 + (k & 3);
+  return K4Out<MODE>{hi + off, lo ? lo + off : nullptr};
+}
+
 // ---------------------------------------------------------------------------
 // One slab ray, swept by one 64-lane wavefront (all lanes of the wave call
-// this together).  sk / ok: the ray's nz source / output values.
-template <typename VT, typename LT, typename C>
-__device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, LT* __restrict__ ok,
+// this together).  sk: the ray's nz source values; out: where its nz output
+// values go.
+template <typename VT, typename OUT, typename C>
+__device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT out,
                                          const double* __restrict__ dt, double mu, double fac,
                                          int nz, C i_in, C sc, int scheme, float out_mul,
                                          int lane) {
@@ -125,18 +168,18 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, LT* __restri
     C e, b;
     elem(q, e, b);
     I = e * I + b;
-    ok[down ? q : nz - 1 - q] = store_val<C, LT>(I * C(out_mul));
+    out.put(down ? q : nz - 1 - q, I * C(out_mul));
   }
 }
 
 // ---------------------------------------------------------------------------
 // One box ray (ordinate stencil st, frequency factor fac), swept plane by
 // plane by a whole 256-thread workgroup; smem holds 3 P values of type C.
-// sk / ok: the ray's nz*P source / output values.
+// sk: the ray's nz*P source values; out: where its nz*P output values go.
 constexpr int kBoxThreads = 256;
 
-template <typename VT, typename LT, typename C, int kBoxMaxPts, int NT = kBoxThreads>
-__device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restrict__ ok,
+template <typename VT, typename OUT, typename C, int kBoxMaxPts, int NT = kBoxThreads>
+__device__ __forceinline__ void box_ray(const VT* __restrict__ sk, const OUT out,
                                         const double* __restrict__ kline, const BoxStencil st,
                                         C fac, int nx, int ny, int nz, C i_in, C sc,
                                         float out_mul, C* smem) {
@@ -192,7 +235,7 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
   load_plane(0);
   for (int t = 0; t < nz; ++t) {
     const int z = st.up ? t : nz - 1 - t;
-    LT* oz = ok + (size_t)z * plane_stride;
+    const size_t oz = (size_t)z * plane_stride;
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
@@ -219,7 +262,7 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, LT* __restric
         sc_weights<C>(d, e, a, c);
         I = e * Iu + a * Su + c * s0;
       }
-      oz[p] = store_val<C, LT>(I * C(out_mul));
+      out.put(oz + p, I * C(out_mul));
       Iv[j] = I;
     }
     __syncthreads();

@@ -71,11 +71,20 @@ struct Problem {
   double* d_mhat64 = nullptr;           // n_r rows, leading dimension lda_mhat
   float* d_mhat32 = nullptr;            // same layout
   int lda_mhat = 0;                     // n_r rounded up to a multiple of 32
-  __hip_bfloat16* d_mhat_bf16 = nullptr;   // hi part
-  __hip_bfloat16* d_mhat_bf16_lo = nullptr;
-  __half* d_mhat_f16 = nullptr;         // rows scaled to unit maximum
+  // 16-bit copies of Mhat for the MFMA GEMM, "k8" layout: element (k, k') at
+  // ((k' / 8) * mp16 + k) * 8 + k' % 8, zero padded to mp16 rows and kp16
+  // columns.
+  uint16_t* d_a8_bf16 = nullptr;        // bf16 (hi part of the split)
+  uint16_t* d_a8_bf16_lo = nullptr;     // bf16 of Mhat - hi
+  uint16_t* d_a8_f16 = nullptr;         // fp16, rows scaled to unit maximum
   float* d_f16_rowscale = nullptr;      // n_r: undo factor per row k
-  int lda16 = 0;                        // leading dimension of the 16-bit copies
+  int mp16 = 0, kp16 = 0;               // n_r rounded up to 256 / to 64
+  int64_t np16 = 0;                     // n_s rounded up to 256
+  // 16-bit B operand (Lambda output), "k4" layout: element (k, i) at
+  // ((k / 4) * np16 + i) * 4 + k % 4; two parts (hi, lo) of kp16 * np16
+  // values each.  Zero-filled at allocation: padding rows must stay zero.
+  uint16_t* d_l16 = nullptr;
+  int g16_cfg[3] = {-1, -1, -1};        // tuned tile configuration per 16-bit mode
   double* d_albedo = nullptr;           // n_s: 1 - eps_i
   double* d_thermal = nullptr;          // n: t
   double* d_dt = nullptr;               // slab: nz-1 depth increments
@@ -103,15 +112,29 @@ void* problem_lbuf(Problem& p, size_t bytes);
 template <typename VT, typename LT>
 void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
                    const double* scale, hipStream_t st, float out_mul = 1.f);
+// Lambda (no boundary term) of an FP32 vector into the k4 16-bit operand of
+// the scattering GEMM (hi; lo for BF16X3), scaled for FP16.
+void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t* hi,
+                      uint16_t* lo, const double* scale, hipStream_t st);
 float fp16_lambda_scale(int64_t n);
+// Size in elements of one part of the k4 operand; allocation of the
+// problem's (zeroed) two-part buffer.
+int64_t l16_part_elems(const Problem& p);
+uint16_t* problem_l16(Problem& p, hipStream_t st);
+const char* gemm16_config_name(int cfg);
+// FP32 ray-major L -> k4 16-bit operand (rounded like Lambda's output).
+void convert_to_k4(const Problem& p, int precision, const float* L, uint16_t* hi, uint16_t* lo,
+                   hipStream_t st);
 
 // y = xs * x + sign * albedo .* (Mhat L); x may be null (then xs ignored).
 void launch_sigma_f64(const Problem& p, const double* L, const double* x, double* y,
                       const double* xscale, double sign, hipStream_t st);
 void launch_sigma_f32(const Problem& p, const float* L, const float* x, float* y,
                       const double* xscale, double sign, hipStream_t st);
-void launch_sigma_b16(const Problem& p, int precision, const void* L, const float* x,
-                      float* y, const double* xscale, double sign, hipStream_t st);
+// 16-bit operands: L16 = k4 operand (hi, lo parts for BF16X3).
+void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
+                      const float* x, float* y, const double* xscale, double sign,
+                      hipStream_t st);
 
 // Operator y = A (xs x) in the given precision, using the problem's L buffer.
 void operator_apply(Problem& p, int precision, const void* x, void* y,

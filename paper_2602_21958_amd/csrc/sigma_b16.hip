@@ -3,43 +3,185 @@
 // (the operator epilogue of the FP64 GEMM; Mhat' / L' are the stored 16-bit
 // operands, rs_k undoes their scaling).
 //
-// Operands: v_mfma_f32_16x16x32_{bf16,f16}.  A lane holds 8 consecutive k of
-// one row of A (Mhat) and 8 consecutive k of one column of B (L); both are
-// staged in LDS k-contiguous.  Mhat is stored with a leading dimension padded
-// to a multiple of 8 so its rows load as aligned 16-byte vectors; the L tile
-// (row-major, points contiguous) is read as 8 k x 4 points per thread and
-// transposed in registers before the LDS store.
-//
 // Modes: BF16 (Lambda emits bf16), FP16 (Lambda emits fp16 scaled by a power
 // of two, Mhat rows scaled to unit maximum; both undone in FP32 in the
 // epilogue) and split BF16 ("bf16x3": Mhat = hi + lo and L = hi + lo in bf16,
-// hi*hi + hi*lo + lo*hi accumulated; L arrives as FP32 and is split while it
-// is staged).
+// hi*hi + hi*lo + lo*hi accumulated).
+//
+// Operand layouts and the tile body are in gemm16_dev.h.  The tile shape is
+// chosen per problem and mode by timing the candidates below on the
+// problem's own operands the first time the mode is used (the tile choice
+// changes the speed only: every candidate accumulates each output in the same
+// k order up to the MFMA's internal order).  RTSN_GEMM16_CFG=<index> forces a
+// candidate.
 #include <cmath>
+#include <cstdlib>
 
 #include "gemm16_dev.h"
+#include "lambda_dev.h"
 
 namespace rtsn {
 
 namespace {
 
-template <bool IS_BF16, bool SPLIT>
-__global__ __launch_bounds__(256) void sigma_b16_kernel(
-    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int lda,
-    const void* __restrict__ Bv, const float* X, float* Y, const double* __restrict__ albedo,
-    const float* __restrict__ rowscale, float bscale_inv, const double* __restrict__ xscale,
-    int M, int N, int K, float sign) {
-  using namespace gemm16;
-  const int n_tiles_m = (M + BM - 1) / BM;
-  const int n_tiles_n = (N + BN - 1) / BN;
+using namespace g16;
+
+template <int MODE, typename C, int OCC>
+__global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(1, OCC))) void sigma16_kernel(
+    const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int Mp,
+    const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, int64_t Np, int K4p,
+    const float* X, float* Y, const double* __restrict__ albedo, const float* __restrict__ rowscale,
+    float colmul, const double* __restrict__ xscale, float sign, int M, int N, int GM) {
+  __shared__ __align__(16) uint8_t lds[C::template lds_bytes<MODE>()];
   int tm, tn;
-  tile_of(blockIdx.x, n_tiles_m, n_tiles_m * n_tiles_n, tm, tn);
+  if (!tile_of(blockIdx.x, Mp / C::BM, (N + C::BN - 1) / C::BN, GM, tm, tn)) return;
   const float xs = (X != nullptr && xscale != nullptr) ? (float)*xscale : 1.f;
-  gemm16_tile<IS_BF16, SPLIT>(Ahi, Alo, lda, Bv, X, Y, albedo, rowscale, bscale_inv, xs, M, N, K,
-                              tm * BM, tn * BN, sign);
+  tile<MODE, C>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs, sign, M,
+                N, tm * C::BM, tn * C::BN, lds);
+}
+
+// Candidate tile shapes (BM x BN, waves, K stage, instruction) and the
+// occupancy each is compiled for.  The split mode stages twice the operands,
+// so its widest candidate uses the shorter K stage.
+using C0 = Cfg<256, 256, 2, 4, 64, true>;
+using C0s = Cfg<256, 256, 2, 4, 32, true>;
+using C1 = Cfg<256, 128, 2, 2, 32, false>;
+using C2 = Cfg<128, 128, 2, 2, 32, true>;
+using C3 = Cfg<128, 128, 2, 2, 64, false>;
+constexpr int kNumCfg = 4;
+const char* const kCfgName[kNumCfg] = {"256x256 32x32x16 K64", "256x128 16x16x32 K32",
+                                       "128x128 32x32x16 K32", "128x128 16x16x32 K64"};
+
+struct Args {
+  const uint16_t *ahi, *alo;
+  int Mp;
+  const uint16_t *bhi, *blo;
+  int64_t Np;
+  int K4p;
+  const float* x;
+  float* y;
+  const double* albedo;
+  const float* rowscale;
+  float colmul;
+  const double* xscale;
+  float sign;
+  int M, N;
+};
+
+template <int MODE, typename C, int OCC>
+void launch_cfg(const Args& a, hipStream_t st) {
+  const int Mt = a.Mp / C::BM, Nt = (a.N + C::BN - 1) / C::BN;
+  if (a.Mp % C::BM || a.K4p % (C::BK / 4) || (int64_t)Nt * C::BN > a.Np)
+    fail(RT_E_INVALID, "16-bit GEMM: operand padding does not fit the tile");
+  const int T = Mt * Nt;
+  const int grid = 8 * ((T + 7) / 8);
+  hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC>), dim3(grid), dim3(C::NT), 0, st, a.ahi,
+                     a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, a.x, a.y, a.albedo, a.rowscale,
+                     a.colmul, a.xscale, a.sign, a.M, a.N, 8);
+}
+
+template <int MODE>
+void launch_index(int cfg, const Args& a, hipStream_t st) {
+  switch (cfg) {
+    case 0:
+      if constexpr (MODE == MODE_SPLIT) launch_cfg<MODE, C0s, 2>(a, st);
+      else launch_cfg<MODE, C0, 2>(a, st);
+      break;
+    case 1: launch_cfg<MODE, C1, 2>(a, st); break;
+    case 2: launch_cfg<MODE, C2, 4>(a, st); break;
+    default: launch_cfg<MODE, C3, 2>(a, st); break;
+  }
+}
+
+void launch_mode(int mode, int cfg, const Args& a, hipStream_t st) {
+  if (mode == MODE_BF16) launch_index<MODE_BF16>(cfg, a, st);
+  else if (mode == MODE_FP16) launch_index<MODE_FP16>(cfg, a, st);
+  else launch_index<MODE_SPLIT>(cfg, a, st);
+}
+
+// Time every candidate on a column slice of the real operands (scratch
+// output, no epilogue input) and keep the fastest.
+int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
+  if (const char* e = std::getenv("RTSN_GEMM16_CFG")) {
+    const int c = std::atoi(e);
+    if (c >= 0 && c < kNumCfg) return c;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  RT_HIP(hipStreamIsCapturing(st, &cs));
+  if (cs != hipStreamCaptureStatusNone) return 2;   // cannot time inside a capture
+  Args a = full;
+  const int64_t want = round_up(std::max<int64_t>(4096, (int64_t(1) << 27) / std::max(1, a.M)), 256);
+  a.N = (int)std::min<int64_t>(a.N, want);
+  a.x = nullptr;
+  a.xscale = nullptr;
+  float* scratch = nullptr;
+  RT_HIP(hipMalloc(&scratch, (size_t)a.M * a.N * sizeof(float)));
+  a.y = scratch;
+  hipEvent_t e0, e1;
+  RT_HIP(hipEventCreate(&e0));
+  RT_HIP(hipEventCreate(&e1));
+  int best = 2;
+  float best_ms = 1e30f;
+  for (int c = 0; c < kNumCfg; ++c) {
+    launch_mode(mode, c, a, st);   // warm-up
+    float ms = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      RT_HIP(hipEventRecord(e0, st));
+      launch_mode(mode, c, a, st);
+      RT_HIP(hipEventRecord(e1, st));
+      RT_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      RT_HIP(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, t);
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  RT_HIP(hipEventDestroy(e0));
+  RT_HIP(hipEventDestroy(e1));
+  RT_HIP(hipFree(scratch));
+  (void)p;
+  return best;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void to_k4_kernel(const float* __restrict__ L, uint16_t* hi,
+                                                   uint16_t* lo, int n_r, int64_t n_s,
+                                                   int64_t Np, float mul) {
+  const int64_t n = (int64_t)n_r * n_s;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / n_s);
+    const int64_t i = e - (int64_t)k * n_s;
+    lam::k4_ray<MODE>(hi, lo, k, Np).put(i, L[e] * mul);
+  }
 }
 
 }  // namespace
+
+void convert_to_k4(const Problem& p, int precision, const float* L, uint16_t* hi, uint16_t* lo,
+                   hipStream_t st) {
+  const dim3 grid(2048), block(256);
+  switch (precision) {
+    case RT_PREC_BF16:
+      hipLaunchKernelGGL(to_k4_kernel<lam::K4_BF16>, grid, block, 0, st, L, hi, lo, p.n_r,
+                         p.n_s, p.np16, 1.f);
+      break;
+    case RT_PREC_FP16:
+      hipLaunchKernelGGL(to_k4_kernel<lam::K4_FP16>, grid, block, 0, st, L, hi, lo, p.n_r,
+                         p.n_s, p.np16, fp16_lambda_scale(p.n));
+      break;
+    case RT_PREC_BF16X3:
+      hipLaunchKernelGGL(to_k4_kernel<lam::K4_SPLIT>, grid, block, 0, st, L, hi, lo, p.n_r,
+                         p.n_s, p.np16, 1.f);
+      break;
+    default:
+      fail(RT_E_INVALID, "convert_to_k4: not a 16-bit precision");
+  }
+  RT_HIP(hipGetLastError());
+}
 
 // Power-of-two scale applied to Lambda's fp16 output (keeps unit-norm Krylov
 // vectors of n entries near 1 in magnitude).
@@ -48,34 +190,51 @@ float fp16_lambda_scale(int64_t n) {
   return (float)std::ldexp(1.0, (int)e);
 }
 
-void launch_sigma_b16(const Problem& p, int precision, const void* L, const float* x, float* y,
-                      const double* xscale, double sign, hipStream_t st) {
-  const int M = p.n_r, N = (int)p.n_s, K = p.n_r;
-  const int tiles = ((M + gemm16::BM - 1) / gemm16::BM) * ((N + gemm16::BN - 1) / gemm16::BN);
-  ProfScope prof(RT_KCLASS_SIGMA, st);
-  const int lda = p.lda16;
-  const auto* hi = reinterpret_cast<const uint16_t*>(p.d_mhat_bf16);
-  const auto* lo = reinterpret_cast<const uint16_t*>(p.d_mhat_bf16_lo);
-  const auto* h16 = reinterpret_cast<const uint16_t*>(p.d_mhat_f16);
+const char* gemm16_config_name(int cfg) {
+  return (cfg >= 0 && cfg < kNumCfg) ? kCfgName[cfg] : "untuned";
+}
+
+void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
+                      const float* x, float* y, const double* xscale, double sign,
+                      hipStream_t st) {
+  Args a{};
+  int mode;
   switch (precision) {
     case RT_PREC_BF16:
-      hipLaunchKernelGGL((sigma_b16_kernel<true, false>), dim3(tiles), dim3(256), 0, st,
-                         hi, nullptr, lda, L, x, y, p.d_albedo, nullptr, 1.f, xscale,
-                         M, N, K, (float)sign);
+      mode = MODE_BF16;
+      a.ahi = p.d_a8_bf16;
+      a.colmul = 1.f;
       break;
     case RT_PREC_FP16:
-      hipLaunchKernelGGL((sigma_b16_kernel<false, false>), dim3(tiles), dim3(256), 0, st,
-                         h16, nullptr, lda, L, x, y, p.d_albedo, p.d_f16_rowscale,
-                         1.f / fp16_lambda_scale(p.n), xscale, M, N, K, (float)sign);
+      mode = MODE_FP16;
+      a.ahi = p.d_a8_f16;
+      a.rowscale = p.d_f16_rowscale;
+      a.colmul = 1.f / fp16_lambda_scale(p.n);
       break;
     case RT_PREC_BF16X3:
-      hipLaunchKernelGGL((sigma_b16_kernel<true, true>), dim3(tiles), dim3(256), 0, st,
-                         hi, lo, lda, L, x, y, p.d_albedo, nullptr, 1.f,
-                         xscale, M, N, K, (float)sign);
+      mode = MODE_SPLIT;
+      a.ahi = p.d_a8_bf16;
+      a.alo = p.d_a8_bf16_lo;
+      a.blo = l_lo;
+      a.colmul = 1.f;
       break;
     default:
       fail(RT_E_INVALID, "launch_sigma_b16: not a 16-bit precision");
   }
+  a.Mp = p.mp16;
+  a.bhi = l_hi;
+  a.Np = p.np16;
+  a.K4p = p.kp16 / 4;
+  a.x = x;
+  a.y = y;
+  a.albedo = p.d_albedo;
+  a.xscale = xscale;
+  a.sign = (float)sign;
+  a.M = p.n_r;
+  a.N = (int)p.n_s;
+  if (p.g16_cfg[mode] < 0) p.g16_cfg[mode] = autotune(p, mode, a, st);
+  ProfScope prof(RT_KCLASS_SIGMA, st);
+  launch_mode(mode, p.g16_cfg[mode], a, st);
   RT_HIP(hipGetLastError());
 }
 

@@ -100,6 +100,7 @@ _sig = {
     "rt_profile_enable": (C.c_int, [C.c_int]),
     "rt_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.c_int]),
+    "rt_gemm16_tile": (C.c_char_p, [_vp, C.c_int]),
     "rt_last_error": (C.c_char_p, []),
     "rt_version": (C.c_int, []),
 }
@@ -213,6 +214,10 @@ class Problem:
         _check(_lib.rt_problem_footprint(self.handle, int(restart), C.byref(info)),
                "rt_problem_footprint")
         return info
+
+    def gemm16_tile(self, precision: str) -> str:
+        """Tile shape of the 16-bit scattering GEMM for this problem."""
+        return _lib.rt_gemm16_tile(self.handle, PREC[precision]).decode()
 
     def tables(self):
         nr = self.n_r

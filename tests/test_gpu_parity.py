@@ -267,7 +267,11 @@ def test_bicgstab_fp64():
         s = host(x)
     assert st["converged"]
     assert op.residual_norm(s) <= 1e-8
-    assert abs(st["iters"] - ref["iters"]) <= 2
+    # BiCGStab's residual is not monotone and its recurrences amplify the
+    # rounding of the inner products (which differ in reduction order between
+    # the two implementations), so the step at which 1e-8 is first crossed
+    # moves by a few iterations; the FP64 residual above is the criterion.
+    assert abs(st["iters"] - ref["iters"]) <= max(2, ref["iters"] // 10)
 
 
 def test_invalid_arguments_raise():
@@ -349,6 +353,37 @@ def test_sigma_16bit_within_rounding_bound(name, prec):
     ref = x.astype(np.float64).reshape(op.n_r, op.n_s) - op.scatter(L64)
     absprod = op.albedo[None, :] * (np.abs(op.mhat) @ np.abs(L64))
     # fp16: entries below the fp16 subnormal range of each scaled row vanish
+    floor = 0.0
+    if prec == "fp16":
+        rowmax = np.abs(op.mhat).max(axis=1)
+        floor = (6e-8 * rowmax)[:, None] * np.abs(L64).sum(axis=0)[None, :]
+    bound = 3.0 * U16[prec] * absprod + floor + 2e-7 * np.abs(ref) + 1e-30
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+def test_sigma_16bit_every_tile_shape(cfg, prec, monkeypatch):
+    """Every candidate tile shape of the 16-bit GEMM (forced instead of tuned)
+    on a ragged problem: 288 rays (not a multiple of the 64-wide K stage or
+    of the 128/256-row tiles) and 1080 points (not a multiple of the column
+    tiles), several K stages and row tiles."""
+    rt = _rt()
+    monkeypatch.setenv("RTSN_GEMM16_CFG", str(cfg))
+    spec = W.small_box(12, 4, 8, 9, seed=5, nz=9, ny=10)
+    say(f"sigma {prec} tile shape {cfg}")
+    op = OProblem(spec)
+    assert (op.n_r, op.n_s) == (288, 1080)
+    L = W.random_field(op.n, 23).astype(np.float32)
+    x = W.random_field(op.n, 24).astype(np.float32)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float32, device="cuda:0")
+        p.apply_sigma(dev(L, torch.float32), dev(x, torch.float32), y, precision=prec)
+        got = host(y).reshape(op.n_r, op.n_s)
+    L64 = L.astype(np.float64).reshape(op.n_r, op.n_s)
+    ref = x.astype(np.float64).reshape(op.n_r, op.n_s) - op.scatter(L64)
+    absprod = op.albedo[None, :] * (np.abs(op.mhat) @ np.abs(L64))
     floor = 0.0
     if prec == "fp16":
         rowmax = np.abs(op.mhat).max(axis=1)
