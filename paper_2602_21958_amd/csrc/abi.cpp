@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "gemm16_dev.h"
+#include "gemm_dev.h"
 #include "krylov.h"
 
 namespace rtsn {
@@ -208,16 +209,20 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
   int64_t tot = 0;
   RT_HIP(hipSetDevice(p.device));
   {
-    // FP64 / FP32 copies with rows padded (zeros) to a multiple of 32
-    const int lda = (p.n_r + 31) / 32 * 32;
+    // FP64 / FP32 copies, transposed for the MFMA GEMM: element (k, k') at
+    // k' * lda + k, lda = n_r rounded up to the 128-row tile, zero rows up to
+    // a multiple of 32 in k'
+    const int lda = (p.n_r + gemm::MPAD - 1) / gemm::MPAD * gemm::MPAD;
+    const int kp = (p.n_r + gemm::KPAD - 1) / gemm::KPAD * gemm::KPAD;
     p.lda_mhat = lda;
-    const size_t sz = (size_t)p.n_r * lda;
+    const size_t sz = (size_t)kp * lda;
     std::vector<double> m64(sz, 0.0);
     std::vector<float> m32(sz, 0.f);
     for (int k = 0; k < p.n_r; ++k)
-      for (int kp = 0; kp < p.n_r; ++kp) {
-        m64[(size_t)k * lda + kp] = p.tab.mhat[(size_t)k * p.n_r + kp];
-        m32[(size_t)k * lda + kp] = (float)p.tab.mhat[(size_t)k * p.n_r + kp];
+      for (int kp2 = 0; kp2 < p.n_r; ++kp2) {
+        const double m = p.tab.mhat[(size_t)k * p.n_r + kp2];
+        m64[(size_t)kp2 * lda + k] = m;
+        m32[(size_t)kp2 * lda + k] = (float)m;
       }
     p.d_mhat64 = upload(m64.data(), sz, tot);
     p.d_mhat32 = upload(m32.data(), sz, tot);

@@ -109,6 +109,7 @@ struct Request {
 
 struct Engine {
   int device = 0;
+  int max_lds = 0;            // LDS bytes per workgroup of the device (queried once)
   int precision = RT_PREC_FP64;
   bool fp64 = true;
   bool use_graph = true;
@@ -310,14 +311,23 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   std::vector<Item> slab, box, tiles, chunks;
   std::vector<int> slots;
   int pmax = 0;
+  for (int s : set)
+    if (h_slots[s].geom != RT_GEOM_SLAB) pmax = std::max(pmax, h_slots[s].nx * h_slots[s].ny);
+  if (max_lds == 0)
+    RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+  // frequencies per box work item: one list serves the FP64 (cycle end) and
+  // the low-precision sweeps, so size it for FP64
+  const int bf = pmax > 0 ? std::max(1, box_chunk(pmax, (int)sizeof(double), max_lds)) : 1;
   for (int s : set) {
     const SlotDev& d = h_slots[s];
     slots.push_back(s);
     if (d.geom == RT_GEOM_SLAB) {
       for (int k = 0; k < d.n_r; k += 4) slab.push_back(Item{s, k, 0, 0});
     } else {
-      for (int k = 0; k < d.n_r; ++k) box.push_back(Item{s, k, 0, 0});
-      pmax = std::max(pmax, d.nx * d.ny);
+      const int n_omega = d.n_r / d.n_nu;
+      for (int o = 0; o < n_omega; ++o)
+        for (int nu0 = 0; nu0 < d.n_nu; nu0 += bf)
+          box.push_back(Item{s, o * d.n_nu + nu0, std::min(bf, d.n_nu - nu0), 0});
     }
     for (int n0 = 0; n0 < (int)d.n_s; n0 += 128)
       for (int m0 = 0; m0 < d.n_r; m0 += 128) tiles.push_back(Item{s, m0, n0, 0});
@@ -370,6 +380,7 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   RT_HIP(hipMemcpyAsync(wl.counts, hc, 5 * sizeof(int), hipMemcpyHostToDevice, stream));
   wl.box_pmax = pmax;
   wl.box_npt = pmax <= 256 ? 1 : (pmax <= 1024 ? 4 : 16);
+  wl.box_f = bf;
 }
 
 void Engine::run_inner() {

@@ -99,7 +99,17 @@ __global__ __launch_bounds__(TB) void bk_lambda_slab(const SlotDev* __restrict__
   }
 }
 
-template <typename VT, typename LT, typename C, int K4, int NPT, int NT, bool OUTER>
+// Box items: rays k0 .. k0 + nf - 1 of one ordinate (Item a = k0, b = nf).
+template <typename LT, int K4>
+__device__ __forceinline__ auto slot_outs(const SlotDev& s, int k0, size_t len) {
+  if constexpr (K4 < 0)
+    return lam::PlainOuts<LT>{static_cast<LT*>(s.L) + (size_t)k0 * len, len};
+  else
+    return lam::K4Outs<K4>{s.l16, K4 == lam::K4_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr,
+                           s.np16, k0};
+}
+
+template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT, bool OUTER>
 __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ slots,
                                                     const SlotStat* __restrict__ stat,
                                                     const Item* __restrict__ items,
@@ -109,7 +119,7 @@ __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ 
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
     const SlotDev& s = slots[w.slot];
-    const int k = w.a;
+    const int k0 = w.a, nf = w.b;
     const size_t vol = (size_t)s.n_s;
     const VT* src;
     C sc;
@@ -124,9 +134,13 @@ __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ 
       sc = C(s.gs->vscale[j]);
       om = s.l_scale;
     }
-    lam::box_ray<VT, decltype(slot_out<LT, K4>(s, k, vol)), C, NPT, NT>(
-        src + (size_t)k * vol, slot_out<LT, K4>(s, k, vol), s.kline, s.stencil[k / s.n_nu],
-        C(s.ray_fac[k]), s.nx, s.ny, s.nz, C(0), sc, om, reinterpret_cast<C*>(smem_raw));
+    C fac[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) fac[f] = f < nf ? C(s.ray_fac[k0 + f]) : C(0);
+    const auto outs = slot_outs<LT, K4>(s, k0, vol);
+    lam::box_rays<VT, decltype(outs), C, F, NPT, NT>(
+        src + (size_t)k0 * vol, vol, nf, outs, s.kline, s.stencil[k0 / s.n_nu], fac, s.nx,
+        s.ny, s.nz, C(0), sc, om, reinterpret_cast<C*>(smem_raw));
   }
 }
 
@@ -451,19 +465,20 @@ void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists
   if (wl.h_counts[0] > 0)
     persist(bk_lambda_slab<VT, LT, C, K4, OUTER>, TB, 0, st, slots, stat, wl.lam_slab, wl.counts);
   if (wl.h_counts[1] > 0) {
-    const size_t lds = (size_t)3 * wl.box_pmax * sizeof(C);
-    if (wl.box_npt <= 1)
-      persist(bk_lambda_box<VT, LT, C, K4, 1, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
-              wl.counts);
-    else if (wl.box_npt <= 4)
-      persist(bk_lambda_box<VT, LT, C, K4, 4, 256, OUTER>, 256, lds, st, slots, stat, wl.lam_box,
-              wl.counts);
-    else if (sizeof(C) == 4)
-      persist(bk_lambda_box<VT, LT, C, K4, 4, 1024, OUTER>, 1024, lds, st, slots, stat, wl.lam_box,
-              wl.counts);
-    else
-      persist(bk_lambda_box<VT, LT, C, K4, 8, 512, OUTER>, 512, lds, st, slots, stat, wl.lam_box,
-              wl.counts);
+    const size_t lds = (size_t)(2 * wl.box_f + 1) * wl.box_pmax * sizeof(C);
+#define RT_BBOX(FF, NPT, NT) \
+  persist(bk_lambda_box<VT, LT, C, K4, FF, NPT, NT, OUTER>, NT, lds, st, slots, stat, wl.lam_box, \
+          wl.counts)
+    if (wl.box_f == 4) {
+      if (wl.box_npt <= 1) RT_BBOX(4, 1, 256);
+      else RT_BBOX(4, 1, 1024);
+    } else {
+      if (wl.box_npt <= 1) RT_BBOX(1, 1, 256);
+      else if (wl.box_npt <= 4) RT_BBOX(1, 4, 256);
+      else if (sizeof(C) == 4) RT_BBOX(1, 4, 1024);
+      else RT_BBOX(1, 8, 512);
+    }
+#undef RT_BBOX
   }
 }
 

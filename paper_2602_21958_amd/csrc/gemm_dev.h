@@ -10,6 +10,7 @@ namespace gemm {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 template <typename T> struct Mfma;
 // Result element r of lane l sits at row dr(l, r), column l % 16 of the
@@ -30,8 +31,11 @@ template <> struct Mfma<float> {
 };
 
 constexpr int BM = 128, BN = 128;
-constexpr int PAD = 16;   // LDS row padding (elements) against bank conflicts
-constexpr int KPAD = 32;  // Mhat rows are padded (with zeros) to a multiple of this
+constexpr int PAD = 16;   // LDS row padding (elements)
+// Mhat is stored transposed, element (k, k') at k' * lda + k, with lda a
+// multiple of MPAD >= n_r and KPAD-row padding (zeros) below n_r.
+constexpr int MPAD = 128;
+constexpr int KPAD = 32;
 
 // Map a linear workgroup id to (m tile, n tile): workgroups are dealt to the
 // 8 XCDs round-robin, so regroup ids per XCD and walk m fastest.
@@ -45,18 +49,20 @@ __device__ __forceinline__ void tile_of(int bid, int n_tiles_m, int n_tiles, int
   tn = t / n_tiles_m;
 }
 
-// 16-byte vector of T
+// 16-byte native vector of T
 template <typename T> struct Vec16;
-template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
-template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = d2_t; static constexpr int n = 2; };
+template <> struct Vec16<float> { using type = f4_t; static constexpr int n = 4; };
 
 // One 128 x 128 output tile at (m0, n0) computed by a 256-thread workgroup,
-// K staged BK at a time.  A (Mhat) has leading dimension lda, a multiple of
-// KPAD >= K, zero beyond K.  xs multiplies x in the epilogue (ignored when X
-// is null).  Operand tiles are read with 16-byte loads, consecutive lanes on
-// consecutive addresses.
+// K staged BK at a time.  At: Mhat transposed ([k'][k], leading dimension
+// lda, zero rows up to a multiple of KPAD >= K).  xs multiplies x in the
+// epilogue (ignored when X is null).  Both operand tiles arrive [k][m] /
+// [k][n] with 16-byte loads of consecutive addresses and are stored to LDS
+// as loaded; the next K stage is loaded into registers while the current one
+// is multiplied from a double-buffered LDS ring (one barrier per stage).
 template <typename T, int BK>
-__device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int lda,
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
                                           const T* __restrict__ B, const T* X, T* Y,
                                           const double* __restrict__ albedo, double xs, int M,
                                           int N, int K, int m0, int n0, double sign) {
@@ -64,33 +70,30 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int lda,
   using acc_t = typename MF::acc_t;
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
-  constexpr int A_CH = BM * BK / VN / 256;   // 16-byte chunks per thread
+  constexpr int A_CH = BK * BM / VN / 256;   // 16-byte chunks per thread
   constexpr int B_CH = BK * BN / VN / 256;
-  constexpr int A_PER_ROW = BK / VN;
+  constexpr int A_PER_ROW = BM / VN;
   constexpr int B_PER_ROW = BN / VN;
   static_assert(A_CH >= 1 && B_CH >= 1, "tile too small");
-  __shared__ __align__(16) T As[BK][BM + PAD];
-  __shared__ __align__(16) T Bs[BK][BN + PAD];
+  static_assert(KPAD % BK == 0, "K stage must divide the row padding of Mhat");
+  __shared__ __align__(16) T As[2][BK][BM + PAD];
+  __shared__ __align__(16) T Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const bool b_vec = (N % VN) == 0;
+  const int Kp = (K + BK - 1) / BK * BK;
 
   V ra[A_CH], rb[B_CH];
 
-  auto load_tile = [&](int k0) {
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
       const int c = tid + 256 * i;
-      const int row = c / A_PER_ROW, kc = (c % A_PER_ROW) * VN;
-      const int gm = m0 + row;
-      if (gm < M) {
-        ra[i] = *reinterpret_cast<const V*>(A + (size_t)gm * lda + k0 + kc);
-      } else {
-        ra[i] = V{};
-      }
+      const int row = c / A_PER_ROW, mc = (c % A_PER_ROW) * VN;
+      ra[i] = *reinterpret_cast<const V*>(At + (size_t)(k0 + row) * lda + m0 + mc);
     }
 #pragma unroll
     for (int i = 0; i < B_CH; ++i) {
@@ -100,11 +103,24 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int lda,
       if (gk < K && b_vec && gn + VN - 1 < N) {
         rb[i] = *reinterpret_cast<const V*>(B + (size_t)gk * N + gn);
       } else {
-        T* e = reinterpret_cast<T*>(&rb[i]);
+        V v;
 #pragma unroll
-        for (int v = 0; v < VN; ++v)
-          e[v] = (gk < K && gn + v < N) ? B[(size_t)gk * N + gn + v] : T(0);
+        for (int e = 0; e < VN; ++e)
+          v[e] = (gk < K && gn + e < N) ? B[(size_t)gk * N + gn + e] : T(0);
+        rb[i] = v;
       }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<V*>(&As[buf][c / A_PER_ROW][(c % A_PER_ROW) * VN]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_CH; ++i) {
+      const int c = tid + 256 * i;
+      *reinterpret_cast<V*>(&Bs[buf][c / B_PER_ROW][(c % B_PER_ROW) * VN]) = rb[i];
     }
   };
 
@@ -116,38 +132,31 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int lda,
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  load_tile(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
-#pragma unroll
-    for (int i = 0; i < A_CH; ++i) {
-      const int c = tid + 256 * i;
-      const int row = c / A_PER_ROW, kc = (c % A_PER_ROW) * VN;
-      const T* e = reinterpret_cast<const T*>(&ra[i]);
-#pragma unroll
-      for (int v = 0; v < VN; ++v) As[kc + v][row] = e[v];
-    }
-#pragma unroll
-    for (int i = 0; i < B_CH; ++i) {
-      const int c = tid + 256 * i;
-      const int row = c / B_PER_ROW, nc = (c % B_PER_ROW) * VN;
-      *reinterpret_cast<V*>(&Bs[row][nc]) = rb[i];
-    }
-    __syncthreads();
-    if (k0 + BK < K) load_tile(k0 + BK);
+  const int nst = Kp / BK;
+  __syncthreads();   // a persistent caller may still read LDS of its previous tile
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int buf = s & 1;
+    gload(min(s + 1, nst - 1) * BK);   // the last stage reloads itself (unused)
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
       const int c = lane & 15;
       T af[4], bf[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = As[kr][wm * 64 + i * 16 + c];
+      for (int i = 0; i < 4; ++i) af[i] = As[buf][kr][wm * 64 + i * 16 + c];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[j] = Bs[kr][wn * 64 + j * 16 + c];
+      for (int j = 0; j < 4; ++j) bf[j] = Bs[buf][kr][wn * 64 + j * 16 + c];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(af[i], bf[j], acc[i][j]);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    lstore(buf ^ 1);
     __syncthreads();
   }
 

@@ -20,6 +20,8 @@
 // upwind order; the previous plane's intensity, source and opacity sit in
 // LDS and the upwind point of every node is a fixed bilinear stencil of that
 // plane (uniform grid, one offset per ordinate), with periodic wrap.
+#include <cstdlib>
+
 #include "lambda_dev.h"
 
 namespace rtsn {
@@ -54,21 +56,39 @@ __global__ __launch_bounds__(256) void lambda_slab_kernel(
                     ray_fac[k], nz, i_in, sc, scheme, out_mul, lane);
 }
 
-template <typename VT, typename LT, typename C, int K4, int NPT, int NT>
+// Outputs of rays k0 .. k0 + F - 1 (plain ray-major array or k4 operand).
+template <typename LT, int K4>
+__device__ __forceinline__ auto rays_out(void* o0, void* o1, int k0, size_t len, int64_t Np) {
+  if constexpr (K4 < 0)
+    return lam::PlainOuts<LT>{static_cast<LT*>(o0) + (size_t)k0 * len, len};
+  else
+    return lam::K4Outs<K4>{static_cast<uint16_t*>(o0), static_cast<uint16_t*>(o1), Np, k0};
+}
+
+// One workgroup per (ordinate, chunk of F frequencies).
+template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT>
 __global__ __launch_bounds__(NT) void lambda_box_kernel(
     const VT* __restrict__ s, void* out0, void* out1, int64_t Np,
     const double* __restrict__ kline, const BoxStencil* __restrict__ stencil,
     const double* __restrict__ ray_fac, int n_nu, int nx, int ny, int nz, double i_top,
     double i_bot, int with_bc, const double* __restrict__ scale, float out_mul) {
   extern __shared__ unsigned char smem_raw[];
-  const int k = blockIdx.x;
-  const BoxStencil st = stencil[k / n_nu];
+  const int nch = (n_nu + F - 1) / F;
+  const int o = blockIdx.x / nch;
+  const int nu0 = (blockIdx.x % nch) * F;
+  const int nf = min(F, n_nu - nu0);
+  const int k0 = o * n_nu + nu0;
+  const BoxStencil st = stencil[o];
   const size_t vol = (size_t)nx * ny * nz;
   const C sc = scale ? C(*scale) : C(1);
   const C i_in = with_bc ? C(st.up ? i_bot : i_top) : C(0);
-  lam::box_ray<VT, decltype(ray_out<LT, K4>(out0, out1, k, vol, Np)), C, NPT, NT>(
-      s + (size_t)k * vol, ray_out<LT, K4>(out0, out1, k, vol, Np), kline, st, C(ray_fac[k]),
-      nx, ny, nz, i_in, sc, out_mul, reinterpret_cast<C*>(smem_raw));
+  C fac[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) fac[f] = f < nf ? C(ray_fac[k0 + f]) : C(0);
+  const auto outs = rays_out<LT, K4>(out0, out1, k0, vol, Np);
+  lam::box_rays<VT, decltype(outs), C, F, NPT, NT>(s + (size_t)k0 * vol, vol, nf, outs, kline,
+                                                   st, fac, nx, ny, nz, i_in, sc, out_mul,
+                                                   reinterpret_cast<C*>(smem_raw));
 }
 
 template <typename VT> struct ComputeOf;
@@ -76,6 +96,27 @@ template <> struct ComputeOf<double> { using type = double; };
 template <> struct ComputeOf<float> { using type = float; };
 
 }  // namespace
+
+// Frequencies per box workgroup.  One by default: sweeping four frequencies
+// of an ordinate together shares the upwind stencil and opacity but needs
+// 4x the per-thread state, and at the occupancy that leaves the sweep is
+// slower (measured on the 32^3 box).  RTSN_LAMBDA_F=4 selects four for
+// planes of up to 1024 points (one point per thread of a 1024-thread group
+// when the plane is larger than 256 points); 0 when not even one ray's
+// (2F + 1) LDS planes fit.
+int box_chunk(int P, int elem_bytes, int max_lds) {
+  static const int want = [] {
+    const char* e = std::getenv("RTSN_LAMBDA_F");
+    return (e && std::atoi(e) >= 4) ? 4 : 1;
+  }();
+  // (FP64 state of four rays per thread fits a 1024-thread group only for
+  // planes of up to 256 points)
+  if (want == 4 && P <= (elem_bytes == 4 ? 1024 : 256) &&
+      (size_t)9 * P * elem_bytes <= (size_t)max_lds)
+    return 4;
+  if ((size_t)3 * P * elem_bytes <= (size_t)max_lds) return 1;
+  return 0;
+}
 
 template <typename VT, typename LT, int K4>
 void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int64_t Np,
@@ -89,21 +130,28 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
                        with_bc ? 1 : 0, scale, p.formal, out_mul);
   } else {
     const int P = p.nx * p.ny;
-    size_t lds = (size_t)3 * P * sizeof(C);
     int max_lds = 0;
     RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
-    if (lds > (size_t)max_lds) fail(RT_E_INVALID, "box plane too large for LDS in this precision");
-#define RT_BOX_LAUNCH(NPT, NT)                                                               \
-  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, NPT, NT>), dim3(p.n_r), dim3(NT), lds, \
+    const int F = box_chunk(P, (int)sizeof(C), max_lds);
+    if (F == 0) fail(RT_E_INVALID, "box plane too large for LDS in this precision");
+    const size_t lds = (size_t)(2 * F + 1) * P * sizeof(C);
+    const int grid = p.n_omega * ((p.n_nu + F - 1) / F);
+#define RT_BOX_LAUNCH(FF, NPT, NT)                                                              \
+  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT>), dim3(grid), dim3(NT), lds, \
                      st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx,  \
                      p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
     // planes up to 1024 points: 256 threads; larger planes: 1024 threads
     // (FP32) or 512 threads (FP64, which needs twice the registers per point)
-    if (P <= 256) RT_BOX_LAUNCH(1, 256);
-    else if (P <= 1024) RT_BOX_LAUNCH(4, 256);
-    else if (P <= 4096 && sizeof(C) == 4) RT_BOX_LAUNCH(4, 1024);
-    else if (P <= 4096) RT_BOX_LAUNCH(8, 512);
-    else fail(RT_E_INVALID, "box plane larger than 4096 points");
+    if (F == 4) {
+      if (P <= 256) RT_BOX_LAUNCH(4, 1, 256);
+      else RT_BOX_LAUNCH(4, 1, 1024);
+    } else {
+      if (P <= 256) RT_BOX_LAUNCH(1, 1, 256);
+      else if (P <= 1024) RT_BOX_LAUNCH(1, 4, 256);
+      else if (P <= 4096 && sizeof(C) == 4) RT_BOX_LAUNCH(1, 4, 1024);
+      else if (P <= 4096) RT_BOX_LAUNCH(1, 8, 512);
+      else fail(RT_E_INVALID, "box plane larger than 4096 points");
+    }
 #undef RT_BOX_LAUNCH
   }
   RT_HIP(hipGetLastError());

@@ -8,9 +8,12 @@ namespace rtsn {
 namespace lam {
 
 
+// Terms of the series for phi_2(d) = sum_{m>=0} (-d)^m / (m+2)! below d = 1/2:
+// the first omitted term is below the type's unit roundoff relative to
+// phi_2 >= 0.42 there.
 template <typename C> struct Series;
-template <> struct Series<double> { static constexpr int terms = 16; };
-template <> struct Series<float> { static constexpr int terms = 9; };
+template <> struct Series<double> { static constexpr int terms = 14; };
+template <> struct Series<float> { static constexpr int terms = 8; };
 
 // 1/n! for n = 0..17
 static __device__ __constant__ double kInvFactN[18] = {
@@ -20,30 +23,31 @@ static __device__ __constant__ double kInvFactN[18] = {
     1.0 / 355687428096000.0};
 
 // Weights of one linear short-characteristics step of optical length d:
-// e = e^{-d}, a = (1 - e)/d - e, c = 1 - (1 - e)/d.  One transcendental at
-// most: below d = 1/2 all three come from their Taylor polynomials,
-//   e = sum_n (-d)^n/n!,  c = sum_{n>=1} (-1)^{n+1} d^n/(n+1)!,
-//   a = sum_{n>=1} (-1)^{n+1} n d^n/(n+1)!;
-// above it e = exp(-d) and q = (1 - e)/d has no cancellation.
+// e = e^{-d}, a = (1 - e)/d - e, c = 1 - (1 - e)/d.  With q = (1 - e)/d the
+// three follow from c alone: q = 1 - c, e = 1 - d q = 1 - d + d c and
+// a = q - e = d - (1 + d) c, none of which cancels for d <= 1/2, where
+// c = d phi_2(d) comes from its series (one Horner chain).  Above 1/2,
+// e = exp(-d) and q = (1 - e)/d have no cancellation.  FP32 uses the
+// hardware exponential and reciprocal (about 1 ulp each).
 template <typename C>
 __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
   if (d < C(0.5)) {
     constexpr int T = Series<C>::terms;
-    C cs = C(0), as = C(0), es = C(0);
+    C ph = C(0);
 #pragma unroll
-    for (int n = T; n >= 1; --n) {
-      const C sg = (n & 1) ? C(1) : C(-1);
-      const C f = C(kInvFactN[n + 1]);
-      cs = cs * d + sg * f;
-      as = as * d + sg * C(n) * f;
-      es = es * d + (-sg) * C(kInvFactN[n]);   // coefficient of d^n in e^{-d}
-    }
-    c = cs * d;
-    a = as * d;
-    e = es * d + C(1);
+    for (int m = T - 1; m >= 0; --m) ph = ph * (-d) + C(kInvFactN[m + 2]);
+    c = d * ph;
+    e = (C(1) - d) + d * c;
+    a = d - (C(1) + d) * c;
   } else {
-    e = exp(-d);
-    const C q = (C(1) - e) / d;
+    C q;
+    if constexpr (sizeof(C) == 8) {
+      e = exp(-d);
+      q = (C(1) - e) / d;
+    } else {
+      e = __expf(-d);
+      q = __fdividef(C(1) - e, d);
+    }
     a = q - e;
     c = C(1) - q;
   }
@@ -98,6 +102,57 @@ struct K4Out {
       if constexpr (MODE == K4_SPLIT)
         lo[4 * i] = bf16_rne(v - __bfloat162float(__ushort_as_bfloat16(h)));
     }
+  }
+};
+
+// Outputs of F consecutive rays k0 .. k0 + F - 1.
+template <typename LT>
+struct PlainOuts {
+  LT* o;          // ray k0
+  size_t stride;  // elements per ray
+  __device__ __forceinline__ bool grouped() const { return false; }
+  template <typename C>
+  __device__ __forceinline__ void put(int f, size_t i, C v) const {
+    o[(size_t)f * stride + i] = store_val<C, LT>(v);
+  }
+  template <typename C>
+  __device__ __forceinline__ void put4(size_t, C, C, C, C) const {}
+};
+
+template <int MODE>
+struct K4Outs {
+  uint16_t* hi;   // k4 buffer parts (not offset)
+  uint16_t* lo;
+  int64_t Np;
+  int k0;
+  __device__ __forceinline__ bool grouped() const { return (k0 & 3) == 0; }
+  template <typename C>
+  __device__ __forceinline__ void put(int f, size_t i, C v) const {
+    const int k = k0 + f;
+    const size_t off = ((size_t)(k >> 2) * Np) * 4 + (k & 3);
+    K4Out<MODE>{hi + off, lo ? lo + off : nullptr}.put(i, v);
+  }
+  // the four values of k4 group k0 / 4 at point i: one 8-byte store per part
+  template <typename C>
+  __device__ __forceinline__ void put4(size_t i, C v0, C v1, C v2, C v3) const {
+    const size_t at = ((size_t)(k0 >> 2) * Np + i) * 4;
+    const float v[4] = {(float)v0, (float)v1, (float)v2, (float)v3};
+    uint16_t h[4], l[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if constexpr (MODE == K4_FP16) {
+        h[f] = __half_as_ushort(__float2half(v[f]));
+      } else {
+        h[f] = bf16_rne(v[f]);
+        if constexpr (MODE == K4_SPLIT)
+          l[f] = bf16_rne(v[f] - __bfloat162float(__ushort_as_bfloat16(h[f])));
+      }
+    }
+    *reinterpret_cast<uint2*>(hi + at) =
+        make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    if constexpr (MODE == K4_SPLIT)
+      *reinterpret_cast<uint2*>(lo + at) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
+                                                      (uint32_t)l[2] | ((uint32_t)l[3] << 16));
   }
 };
 
@@ -173,27 +228,33 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
 }
 
 // ---------------------------------------------------------------------------
-// One box ray (ordinate stencil st, frequency factor fac), swept plane by
-// plane by a whole 256-thread workgroup; smem holds 3 P values of type C.
-// sk: the ray's nz*P source values; out: where its nz*P output values go.
+// Box sweep of F rays that share one ordinate (frequencies nu0 .. nu0 + nf - 1,
+// nf <= F), plane by plane, by a whole NT-thread workgroup.  The upwind
+// stencil, the interpolated opacity and the step's optical depth up to the
+// frequency factor are computed once per point and used by all F rays; the
+// previous plane's intensities and sources (per ray) and opacity sit in LDS,
+// (2F + 1) P values of type C.
+//
+// src(f): the ray's nz*P source values; fac[f]: phi_nu + r of ray f;
+// out.put(f, i, v) stores value i of ray f, out.put4(i, v0..v3) the four rays
+// at once when nf == 4 and out.grouped() (the rays form one k4 group of the
+// 16-bit operand).
 constexpr int kBoxThreads = 256;
 
-template <typename VT, typename OUT, typename C, int kBoxMaxPts, int NT = kBoxThreads>
-__device__ __forceinline__ void box_ray(const VT* __restrict__ sk, const OUT out,
-                                        const double* __restrict__ kline, const BoxStencil st,
-                                        C fac, int nx, int ny, int nz, C i_in, C sc,
-                                        float out_mul, C* smem) {
+template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads>
+__device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_stride, int nf,
+                                         const OUT& out, const double* __restrict__ kline,
+                                         const BoxStencil st, const C* fac, int nx, int ny,
+                                         int nz, C i_in, C sc, float out_mul, C* smem) {
   const int P = nx * ny;
-  C* lI = smem;
-  C* lS = lI + P;
-  C* lK = lS + P;
+  C* lK = smem;
+  C* lI = lK + P;          // [F][P]
+  C* lS = lI + F * P;      // [F][P]
   const C path = C(st.path);
   const C tx = C(st.tx), ty = C(st.ty);
   const size_t plane_stride = (size_t)P;
 
   const int npt = (P + NT - 1) / NT;
-  C Iv[kBoxMaxPts], Sv[kBoxMaxPts], Kv[kBoxMaxPts];
-  // upwind bilinear source offsets per owned point (fixed for the ordinate)
   int n00[kBoxMaxPts], n01[kBoxMaxPts], n10[kBoxMaxPts], n11[kBoxMaxPts];
 #pragma unroll
   for (int j = 0; j < kBoxMaxPts; ++j) {
@@ -215,20 +276,24 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, const OUT out
   }
   const C w00 = (C(1) - ty) * (C(1) - tx), w01 = (C(1) - ty) * tx;
   const C w10 = ty * (C(1) - tx), w11 = ty * tx;
+  const C om = C(out_mul);
 
-  // source and opacity of the next plane are loaded one plane ahead
-  C Sn[kBoxMaxPts], Kn[kBoxMaxPts];
+  // sources and opacity of the next plane are loaded one plane ahead
+  C Sn[F][kBoxMaxPts], Kn[kBoxMaxPts];
+  C Sv[F][kBoxMaxPts], Iv[F][kBoxMaxPts], Kv[kBoxMaxPts];
   auto load_plane = [&](int t) {
     const int z = st.up ? t : nz - 1 - t;
-    const VT* sz = sk + (size_t)z * plane_stride;
     const double* kz = kline + (size_t)z * plane_stride;
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
       const int p = threadIdx.x + j * NT;
       if (p < P) {
-        Sn[j] = sc * C(sz[p]);
         Kn[j] = C(kz[p]);
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          Sn[f][j] = f < nf ? sc * C(s0[(size_t)f * ray_stride + (size_t)z * plane_stride + p])
+                            : C(0);
       }
     }
   };
@@ -239,8 +304,9 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, const OUT out
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
-      Sv[j] = Sn[j];
       Kv[j] = Kn[j];
+#pragma unroll
+      for (int f = 0; f < F; ++f) Sv[f][j] = Sn[f][j];
     }
     if (t + 1 < nz) load_plane(t + 1);
 #pragma unroll
@@ -248,22 +314,39 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, const OUT out
       if (j >= npt) break;
       const int p = threadIdx.x + j * NT;
       if (p >= P) break;
-      const C s0 = Sv[j];
-      const C k0 = Kv[j];
-      C I;
+      C I[F];
       if (t == 0) {
-        I = i_in;
+#pragma unroll
+        for (int f = 0; f < F; ++f) I[f] = i_in;
       } else {
         const C ku = w00 * lK[n00[j]] + w01 * lK[n01[j]] + w10 * lK[n10[j]] + w11 * lK[n11[j]];
-        const C Iu = w00 * lI[n00[j]] + w01 * lI[n01[j]] + w10 * lI[n10[j]] + w11 * lI[n11[j]];
-        const C Su = w00 * lS[n00[j]] + w01 * lS[n01[j]] + w10 * lS[n10[j]] + w11 * lS[n11[j]];
-        const C d = C(0.5) * (ku + k0) * path * fac;
-        C e, a, c;
-        sc_weights<C>(d, e, a, c);
-        I = e * Iu + a * Su + c * s0;
+        const C base = C(0.5) * (ku + Kv[j]) * path;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const C* If = lI + f * P;
+          const C* Sf = lS + f * P;
+          const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
+          const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
+          C e, a, c;
+          sc_weights<C>(base * fac[f], e, a, c);
+          I[f] = e * Iu + a * Su + c * Sv[f][j];
+        }
       }
-      out.put(oz + p, I * C(out_mul));
-      Iv[j] = I;
+      if constexpr (F == 4) {
+        if (nf == 4 && out.grouped()) {   // all four rays of one k4 group are here
+          out.put4(oz + p, I[0] * om, I[1] * om, I[2] * om, I[3] * om);
+        } else {
+#pragma unroll
+          for (int f = 0; f < F; ++f)
+            if (f < nf) out.put(f, oz + p, I[f] * om);
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          if (f < nf) out.put(f, oz + p, I[f] * om);
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f) Iv[f][j] = I[f];
     }
     __syncthreads();
 #pragma unroll
@@ -271,9 +354,12 @@ __device__ __forceinline__ void box_ray(const VT* __restrict__ sk, const OUT out
       if (j >= npt) break;
       const int p = threadIdx.x + j * NT;
       if (p >= P) break;
-      lI[p] = Iv[j];
-      lS[p] = Sv[j];
       lK[p] = Kv[j];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        lI[f * P + p] = Iv[f][j];
+        lS[f * P + p] = Sv[f][j];
+      }
     }
     __syncthreads();
   }

@@ -68,9 +68,9 @@ struct Problem {
   std::vector<BoxStencil> stencil;      // box: per ordinate
 
   // device data
-  double* d_mhat64 = nullptr;           // n_r rows, leading dimension lda_mhat
+  double* d_mhat64 = nullptr;           // Mhat transposed: (k, k') at k' * lda_mhat + k
   float* d_mhat32 = nullptr;            // same layout
-  int lda_mhat = 0;                     // n_r rounded up to a multiple of 32
+  int lda_mhat = 0;                     // n_r rounded up to a multiple of 128
   // 16-bit copies of Mhat for the MFMA GEMM, "k8" layout: element (k, k') at
   // ((k' / 8) * mp16 + k) * 8 + k' % 8, zero padded to mp16 rows and kp16
   // columns.
@@ -117,6 +117,8 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
 void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t* hi,
                       uint16_t* lo, const double* scale, hipStream_t st);
 float fp16_lambda_scale(int64_t n);
+// Frequencies swept together by one box workgroup for planes of P points.
+int box_chunk(int P, int elem_bytes, int max_lds);
 // Size in elements of one part of the k4 operand; allocation of the
 // problem's (zeroed) two-part buffer.
 int64_t l16_part_elems(const Problem& p);

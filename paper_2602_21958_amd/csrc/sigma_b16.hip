@@ -99,8 +99,8 @@ void launch_mode(int mode, int cfg, const Args& a, hipStream_t st) {
   else launch_index<MODE_SPLIT>(cfg, a, st);
 }
 
-// Time every candidate on a column slice of the real operands (scratch
-// output, no epilogue input) and keep the fastest.
+// Time every candidate on a column slice of the real operands and epilogue
+// input (scratch output) and keep the fastest.
 int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   if (const char* e = std::getenv("RTSN_GEMM16_CFG")) {
     const int c = std::atoi(e);
@@ -111,9 +111,13 @@ int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   if (cs != hipStreamCaptureStatusNone) return 2;   // cannot time inside a capture
   Args a = full;
   const int64_t want = round_up(std::max<int64_t>(4096, (int64_t(1) << 27) / std::max(1, a.M)), 256);
+  // the slice keeps the leading dimension N of x: rows of the slice are
+  // strided, so time full rows when the slice would not be contiguous
   a.N = (int)std::min<int64_t>(a.N, want);
-  a.x = nullptr;
-  a.xscale = nullptr;
+  if (a.N != full.N) {
+    a.x = nullptr;
+    a.xscale = nullptr;
+  }
   float* scratch = nullptr;
   RT_HIP(hipMalloc(&scratch, (size_t)a.M * a.N * sizeof(float)));
   a.y = scratch;

@@ -11,10 +11,12 @@
 // FP64 / FP32 path: v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32 (one
 // operand element per lane).  Workgroup tile 128 x 128, K tile 16, four
 // waves in a 2 x 2 arrangement each owning a 64 x 64 sub-tile (4 x 4 MFMA
-// blocks).  A (Mhat) is staged transposed in LDS ([k][m]), B (L) as loaded
-// ([k][n]); the next K tile is prefetched into registers while the current
-// one is multiplied.  Tiles are assigned so that consecutive workgroups on
-// the same XCD share the same column strip of L (L2 reuse).
+// blocks).  Mhat is kept transposed in HBM so that both operand tiles are
+// [k][m] / [k][n] row segments, loaded with 16-byte vectors and stored to LDS
+// unchanged; the next K tile is prefetched into registers while the current
+// one is multiplied from a double-buffered LDS ring.  Tiles are assigned so
+// that consecutive workgroups on the same XCD share the same column strip of
+// L (L2 reuse).
 #include <cstdlib>
 
 #include "gemm_dev.h"

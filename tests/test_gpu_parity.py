@@ -393,6 +393,43 @@ def test_sigma_16bit_every_tile_shape(cfg, prec, monkeypatch):
     assert np.all(err <= bound), float(np.max(err / bound))
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("shape", [(8, 8, 8, 4, 8, 8), (8, 8, 6, 2, 4, 5), (12, 12, 9, 4, 4, 6),
+                                   (40, 40, 6, 2, 4, 4)])
+def test_operator_16bit_box(shape, prec):
+    """Whole 16-bit operator y = x - (1-eps) Mhat Lambda x on boxes whose
+    frequency count is a multiple of 4 (one k4 group per workgroup, 8-byte
+    stores) or not (groups straddle ordinates; partial last chunk), and a plane
+    larger than 1024 points (one frequency per workgroup).  Bound: 16-bit
+    operand rounding of Mhat and of the FP32 Lambda output, plus the FP32
+    Lambda itself."""
+    rt = _rt()
+    nx, ny, nz, n_mu, n_az, n_nu = shape
+    spec = W.small_box(nx, n_mu, n_az, n_nu, seed=7, nz=nz, ny=ny)
+    say(f"operator {prec} box {shape}")
+    op = OProblem(spec)
+    x = W.random_field(op.n, 25, positive=True).astype(np.float32)
+    with rt.Problem(spec) as p:
+        y = torch.empty(op.n, dtype=torch.float32, device="cuda:0")
+        p.apply(dev(x, torch.float32), y, precision=prec)
+        got = host(y)
+    x64 = x.astype(np.float64)
+    L = op.lam(x64.reshape(op.n_r, op.n_s), with_bc=False)
+    ref = x64 - op.scatter(L).ravel()
+    absprod = (op.albedo[None, :] * (np.abs(op.mhat) @ np.abs(L))).ravel()
+    floor = 0.0
+    if prec == "fp16":
+        rowmax = np.abs(op.mhat).max(axis=1)
+        floor = ((6e-8 * rowmax)[:, None] * np.abs(L).sum(axis=0)[None, :]).ravel()
+    # 3u for the two operand roundings and accumulation; FP32 Lambda within
+    # 2e-5 of its largest value (the FP32 Lambda test's criterion) per entry
+    lam32 = 2e-5 * np.max(np.abs(L)) * (np.abs(op.mhat).sum(axis=1)[:, None] *
+                                        op.albedo[None, :]).ravel()
+    bound = 3.0 * U16[prec] * absprod + lam32 + floor + 2e-7 * np.abs(ref) + 1e-30
+    err = np.abs(got - ref)
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16", "bf16"])
 @pytest.mark.parametrize("name", ["slab64", "box8"])
 def test_mixed_refinement_per_precision(name, prec):
