@@ -21,6 +21,7 @@
 // both A and B, so the k order inside an instruction is the natural one.
 #pragma once
 
+#include "gemm_dev.h"
 #include "rt_internal.h"
 
 namespace rtsn {
@@ -97,14 +98,15 @@ struct Cfg {
 // One output tile at (m0, n0).  lds: Cfg::lds_bytes<MODE>() bytes, 16-byte
 // aligned.  Caller guarantees m0 + BM <= Mp, n0 + BN <= Np, K4p % (BK/4) == 0.
 // The function starts with a barrier, so a persistent caller may reuse lds.
-template <int MODE, typename C>
+template <int MODE, typename C, bool DOTS = false>
 __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
                                      const uint16_t* __restrict__ Alo, int Mp,
                                      const uint16_t* __restrict__ Bhi,
                                      const uint16_t* __restrict__ Blo, int Np, int K4p,
                                      const float* X, float* Y, const double* __restrict__ albedo,
                                      const float* __restrict__ rowscale, float colmul, float xs,
-                                     float sign, int M, int N, int m0, int n0, uint8_t* lds) {
+                                     float sign, int M, int N, int m0, int n0, uint8_t* lds,
+                                     gemm::TileDots dots = {}, int slot = 0) {
   constexpr bool SPLIT = MODE == MODE_SPLIT;
   constexpr int NP = SPLIT ? 2 : 1;   // operand parts (hi, lo)
   using MM = Mma<MODE != MODE_FP16, C::BIG>;
@@ -224,25 +226,60 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
     __syncthreads();
   }
 
-  // epilogue
+  // epilogue (the final values stay in acc for the fused dots; zero outside)
 #pragma unroll
   for (int j = 0; j < C::TJ; ++j) {
     const int col = n0 + wn * C::WN + C::MI * j + rc;
-    if (col >= N) continue;
-    const float cf = sign * (float)albedo[col] * colmul;
+    const float cf = col < N ? sign * (float)albedo[col] * colmul : 0.f;
 #pragma unroll
     for (int i = 0; i < C::TI; ++i) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const int row = m0 + wm * C::WM + C::MI * i +
                         (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
-        if (row < M) {
+        if (row < M && col < N) {
           const size_t idx = (size_t)row * N + col;
           float v = cf * (rowscale ? rowscale[row] : 1.f) * acc[i][j][r];
           if (X != nullptr) v += xs * X[idx];
           Y[idx] = v;
+          acc[i][j][r] = v;
+        } else {
+          acc[i][j][r] = 0.f;
         }
       }
+    }
+  }
+  if constexpr (DOTS) {
+    // LDS is free: the K loop ended with a barrier after its last reads
+    double* red = reinterpret_cast<double*>(lds);
+    const float* V = static_cast<const float*>(dots.V);
+    for (int q = 0; q < dots.nv; ++q) {
+      const float* Vq = V + (size_t)q * dots.stride;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < C::TJ; ++j) {
+        const int col = n0 + wn * C::WN + C::MI * j + rc;
+#pragma unroll
+        for (int i = 0; i < C::TI; ++i) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const int row = m0 + wm * C::WM + C::MI * i +
+                            (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
+            if (row < M && col < N)
+              s += (double)Vq[(size_t)row * N + col] * (double)acc[i][j][r];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
+      }
+      s = gemm::wave_sum_d(s);
+      if (lane == 0) red[q * C::NW + wave] = s;
+    }
+    __syncthreads();
+    for (int q = tid; q < dots.nv; q += C::NT) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < C::NW; ++w) t += red[q * C::NW + w];
+      dots.part[(size_t)q * dots.ldp + slot] = t;
     }
   }
 }

@@ -49,6 +49,24 @@ __device__ __forceinline__ void tile_of(int bid, int n_tiles_m, int n_tiles, int
   tn = t / n_tiles_m;
 }
 
+// Optional Arnoldi dot products fused into the epilogue: with the tile's
+// final outputs y still in registers, partial sums of V_q . y over the tile
+// are formed for q < nv and stored to part[q * ldp + slot] (one slot per
+// tile; fixed summation order).
+struct TileDots {
+  const void* V;     // basis base (element type of the GEMM output)
+  int64_t stride;    // elements between basis vectors
+  int nv;            // number of basis vectors
+  double* part;
+  int ldp;           // slots per vector
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // 16-byte native vector of T
 template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = d2_t; static constexpr int n = 2; };
@@ -61,11 +79,12 @@ template <> struct Vec16<float> { using type = f4_t; static constexpr int n = 4;
 // [k][n] with 16-byte loads of consecutive addresses and are stored to LDS
 // as loaded; the next K stage is loaded into registers while the current one
 // is multiplied from a double-buffered LDS ring (one barrier per stage).
-template <typename T, int BK>
+template <typename T, int BK, bool DOTS = false>
 __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
                                           const T* __restrict__ B, const T* X, T* Y,
                                           const double* __restrict__ albedo, double xs, int M,
-                                          int N, int K, int m0, int n0, double sign) {
+                                          int N, int K, int m0, int n0, double sign,
+                                          TileDots dots = {}, int slot = 0) {
   using MF = Mfma<T>;
   using acc_t = typename MF::acc_t;
   using V = typename Vec16<T>::type;
@@ -160,25 +179,57 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
     __syncthreads();
   }
 
-  // epilogue
+  // epilogue (the final values stay in acc for the fused dots; zero outside)
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int col = n0 + wn * 64 + j * 16 + (lane & 15);
-    if (col >= N) continue;
-    const double alb = sign * albedo[col];
+    const double alb = col < N ? sign * albedo[col] : 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm * 64 + i * 16 + MF::dr(lane, r);
-        if (row < M) {
+        if (row < M && col < N) {
           const size_t idx = (size_t)row * N + col;
           double v = alb * (double)acc[i][j][r];
           if (X != nullptr) v += xs * (double)X[idx];
-          Y[idx] = (T)v;
+          const T t = (T)v;
+          Y[idx] = t;
+          acc[i][j][r] = t;
+        } else {
+          acc[i][j][r] = 0;
         }
       }
     }
+  }
+  if constexpr (DOTS) {
+    // LDS is free: the K loop ended with a barrier after its last reads
+    double* red = reinterpret_cast<double*>(&As[0][0][0]);
+    const T* V = static_cast<const T*>(dots.V);
+    for (int q = 0; q < dots.nv; ++q) {
+      const T* Vq = V + (size_t)q * dots.stride;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = m0 + wm * 64 + i * 16 + MF::dr(lane, r);
+            if (row < M && col < N)
+              s += (double)Vq[(size_t)row * N + col] * (double)acc[i][j][r];
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
+      }
+      s = wave_sum_d(s);
+      if (lane == 0) red[q * 4 + wave] = s;
+    }
+    __syncthreads();
+    for (int q = tid; q < dots.nv; q += 256)
+      dots.part[(size_t)q * dots.ldp + slot] =
+          (red[q * 4] + red[q * 4 + 1]) + (red[q * 4 + 2] + red[q * 4 + 3]);
   }
 }
 

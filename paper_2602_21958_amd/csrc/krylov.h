@@ -32,6 +32,9 @@ struct BicgState {
 
 template <typename TV>
 void k_mdot(const TV* V, int64_t n, int cnt, const TV* w, double* partial, hipStream_t st);
+// Same with an explicit number nb of partial slots per row.
+void k_reduce_rows_nb(const double* partial, int nb, int nrows, const double* scale, double* out,
+                      hipStream_t st);
 void k_reduce_rows(const double* partial, int64_t n, int nrows, const double* scale, double* out,
                    hipStream_t st);
 template <typename TV>
@@ -70,7 +73,9 @@ struct Workspace {
   bool mixed = false;
   size_t bytes = 0;
   void* V = nullptr;            // (restart + 1) * n basis (double, or float if mixed)
-  double* partial = nullptr;    // (kMaxRestart + 1) * kReduceBlocks
+  double* partial = nullptr;    // partial_elems partial sums
+  size_t partial_elems = 0;
+  int dot_slots = 0;            // slots per vector of the dots fused into the GEMM
   GmresState* gs = nullptr;
   BicgState* bs = nullptr;
   double* scal = nullptr;       // small device scalars

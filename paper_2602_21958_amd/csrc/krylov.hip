@@ -435,6 +435,14 @@ void k_mdot(const TV* V, int64_t n, int cnt, const TV* w, double* partial, hipSt
   RT_HIP(hipGetLastError());
 }
 
+void k_reduce_rows_nb(const double* partial, int nb, int nrows, const double* scale, double* out,
+                      hipStream_t st) {
+  ProfScope prof(RT_KCLASS_ARNOLDI, st);
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, st, partial, nb, nrows,
+                     scale, out);
+  RT_HIP(hipGetLastError());
+}
+
 void k_reduce_rows(const double* partial, int64_t n, int nrows, const double* scale, double* out,
                    hipStream_t st) {
   hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kThreads), 0, st, partial, grid_for(n),

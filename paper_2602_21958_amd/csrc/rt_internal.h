@@ -128,19 +128,29 @@ const char* gemm16_config_name(int cfg);
 void convert_to_k4(const Problem& p, int precision, const float* L, uint16_t* hi, uint16_t* lo,
                    hipStream_t st);
 
+namespace gemm { struct TileDots; }
 // y = xs * x + sign * albedo .* (Mhat L); x may be null (then xs ignored).
+// With dots, the GEMM also forms partial sums of V_q . y (q < dots->nv) in
+// dots->part[q * ldp + tile]: dots->ldp holds the capacity on entry
+// (sigma_dot_slots gives the largest count any tile shape needs) and the
+// number of tiles, every slot written, on return.
 void launch_sigma_f64(const Problem& p, const double* L, const double* x, double* y,
-                      const double* xscale, double sign, hipStream_t st);
+                      const double* xscale, double sign, hipStream_t st,
+                      gemm::TileDots* dots = nullptr);
 void launch_sigma_f32(const Problem& p, const float* L, const float* x, float* y,
-                      const double* xscale, double sign, hipStream_t st);
+                      const double* xscale, double sign, hipStream_t st,
+                      gemm::TileDots* dots = nullptr);
 // 16-bit operands: L16 = k4 operand (hi, lo parts for BF16X3).
 void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
                       const float* x, float* y, const double* xscale, double sign,
-                      hipStream_t st);
+                      hipStream_t st, gemm::TileDots* dots = nullptr);
+int sigma_dot_slots(const Problem& p, int precision);
 
-// Operator y = A (xs x) in the given precision, using the problem's L buffer.
+// Operator y = A (xs x) in the given precision, using the problem's L buffer;
+// with dots, also the partial sums of V_q . y (see launch_sigma_f64).
 void operator_apply(Problem& p, int precision, const void* x, void* y,
-                    const double* xscale, hipStream_t st);
+                    const double* xscale, hipStream_t st,
+                    gemm::TileDots* dots = nullptr);
 size_t lambda_elem_bytes(int precision);
 const double* physical_rhs(Problem& p, hipStream_t st);
 

@@ -26,18 +26,20 @@ namespace {
 
 using namespace g16;
 
-template <int MODE, typename C, int OCC>
+template <int MODE, typename C, int OCC, bool DOTS>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(1, OCC))) void sigma16_kernel(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int Mp,
     const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, int64_t Np, int K4p,
     const float* X, float* Y, const double* __restrict__ albedo, const float* __restrict__ rowscale,
-    float colmul, const double* __restrict__ xscale, float sign, int M, int N, int GM) {
+    float colmul, const double* __restrict__ xscale, float sign, int M, int N, int GM,
+    gemm::TileDots dots) {
   __shared__ __align__(16) uint8_t lds[C::template lds_bytes<MODE>()];
+  const int Mt = Mp / C::BM;
   int tm, tn;
-  if (!tile_of(blockIdx.x, Mp / C::BM, (N + C::BN - 1) / C::BN, GM, tm, tn)) return;
+  if (!tile_of(blockIdx.x, Mt, (N + C::BN - 1) / C::BN, GM, tm, tn)) return;
   const float xs = (X != nullptr && xscale != nullptr) ? (float)*xscale : 1.f;
-  tile<MODE, C>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs, sign, M,
-                N, tm * C::BM, tn * C::BN, lds);
+  tile<MODE, C, DOTS>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs,
+                      sign, M, N, tm * C::BM, tn * C::BN, lds, dots, tn * Mt + tm);
 }
 
 // Candidate tile shapes (BM x BN, waves, K stage, instruction) and the
@@ -66,6 +68,7 @@ struct Args {
   const double* xscale;
   float sign;
   int M, N;
+  gemm::TileDots* dots;
 };
 
 template <int MODE, typename C, int OCC>
@@ -75,9 +78,17 @@ void launch_cfg(const Args& a, hipStream_t st) {
     fail(RT_E_INVALID, "16-bit GEMM: operand padding does not fit the tile");
   const int T = Mt * Nt;
   const int grid = 8 * ((T + 7) / 8);
-  hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC>), dim3(grid), dim3(C::NT), 0, st, a.ahi,
-                     a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, a.x, a.y, a.albedo, a.rowscale,
-                     a.colmul, a.xscale, a.sign, a.M, a.N, 8);
+  if (a.dots) {
+    if (a.dots->ldp < T) fail(RT_E_INVALID, "fused dots: too few partial slots");
+    a.dots->ldp = T;   // one slot per tile, all written
+    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, true>), dim3(grid), dim3(C::NT), 0, st,
+                       a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, a.x, a.y, a.albedo,
+                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, *a.dots);
+  } else {
+    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, false>), dim3(grid), dim3(C::NT), 0, st,
+                       a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, a.x, a.y, a.albedo,
+                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, gemm::TileDots{});
+  }
 }
 
 template <int MODE>
@@ -110,6 +121,7 @@ int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   RT_HIP(hipStreamIsCapturing(st, &cs));
   if (cs != hipStreamCaptureStatusNone) return 2;   // cannot time inside a capture
   Args a = full;
+  a.dots = nullptr;
   const int64_t want = round_up(std::max<int64_t>(4096, (int64_t(1) << 27) / std::max(1, a.M)), 256);
   // the slice keeps the leading dimension N of x: rows of the slice are
   // strided, so time full rows when the slice would not be contiguous
@@ -200,7 +212,7 @@ const char* gemm16_config_name(int cfg) {
 
 void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
                       const float* x, float* y, const double* xscale, double sign,
-                      hipStream_t st) {
+                      hipStream_t st, gemm::TileDots* dots) {
   Args a{};
   int mode;
   switch (precision) {
@@ -236,7 +248,9 @@ void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uin
   a.sign = (float)sign;
   a.M = p.n_r;
   a.N = (int)p.n_s;
+  a.dots = nullptr;
   if (p.g16_cfg[mode] < 0) p.g16_cfg[mode] = autotune(p, mode, a, st);
+  a.dots = dots;
   ProfScope prof(RT_KCLASS_SIGMA, st);
   launch_mode(mode, p.g16_cfg[mode], a, st);
   RT_HIP(hipGetLastError());

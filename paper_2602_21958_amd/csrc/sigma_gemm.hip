@@ -23,6 +23,8 @@
 
 namespace rtsn {
 
+using gemm::TileDots;
+
 namespace {
 
 // K-tile depth of the FP64/FP32 GEMM (tuning override: RTSN_GEMM_BK=16|32).
@@ -34,45 +36,61 @@ int gemm_bk() {
   return bk;
 }
 
-template <typename T, int BK>
+template <typename T, int BK, bool DOTS>
 __global__ __launch_bounds__(256) void sigma_gemm_kernel(
     const T* __restrict__ A, int lda, const T* __restrict__ B, const T* X, T* Y,
     const double* __restrict__ albedo, const double* __restrict__ xscale, int M, int N, int K,
-    double sign) {
+    double sign, TileDots dots) {
   using namespace gemm;
   const int n_tiles_m = (M + BM - 1) / BM;
   const int n_tiles_n = (N + BN - 1) / BN;
   int tm, tn;
   tile_of(blockIdx.x, n_tiles_m, n_tiles_m * n_tiles_n, tm, tn);
   const double xs = (X != nullptr && xscale != nullptr) ? *xscale : 1.0;
-  gemm_tile<T, BK>(A, lda, B, X, Y, albedo, xs, M, N, K, tm * BM, tn * BN, sign);
+  gemm_tile<T, BK, DOTS>(A, lda, B, X, Y, albedo, xs, M, N, K, tm * BM, tn * BN, sign, dots,
+                         tn * n_tiles_m + tm);
 }
 
 template <typename T>
 void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* y,
-                    const double* xscale, double sign, hipStream_t st) {
+                    const double* xscale, double sign, hipStream_t st, TileDots* dots) {
   const int M = p.n_r, N = (int)p.n_s, K = p.n_r;
   const int tiles = ((M + gemm::BM - 1) / gemm::BM) * ((N + gemm::BN - 1) / gemm::BN);
   ProfScope prof(RT_KCLASS_SIGMA, st);
-  if (gemm_bk() == 32)
-    hipLaunchKernelGGL((sigma_gemm_kernel<T, 32>), dim3(tiles), dim3(256), 0, st, mhat,
-                       p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign);
-  else
-    hipLaunchKernelGGL((sigma_gemm_kernel<T, 16>), dim3(tiles), dim3(256), 0, st, mhat,
-                       p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign);
+  if (dots) {
+    if (dots->ldp < tiles) fail(RT_E_INVALID, "fused dots: too few partial slots");
+    dots->ldp = tiles;   // one slot per tile, all written
+  }
+  const TileDots d = dots ? *dots : TileDots{};
+#define RT_SIGMA_LAUNCH(BKV, DV)                                                              \
+  hipLaunchKernelGGL((sigma_gemm_kernel<T, BKV, DV>), dim3(tiles), dim3(256), 0, st, mhat,   \
+                     p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign, d)
+  if (gemm_bk() == 32) {
+    if (dots) RT_SIGMA_LAUNCH(32, true); else RT_SIGMA_LAUNCH(32, false);
+  } else {
+    if (dots) RT_SIGMA_LAUNCH(16, true); else RT_SIGMA_LAUNCH(16, false);
+  }
+#undef RT_SIGMA_LAUNCH
   RT_HIP(hipGetLastError());
 }
 
 }  // namespace
 
 void launch_sigma_f64(const Problem& p, const double* L, const double* x, double* y,
-                      const double* xscale, double sign, hipStream_t st) {
-  launch_sigma_t<double>(p, p.d_mhat64, L, x, y, xscale, sign, st);
+                      const double* xscale, double sign, hipStream_t st, TileDots* dots) {
+  launch_sigma_t<double>(p, p.d_mhat64, L, x, y, xscale, sign, st, dots);
 }
 
 void launch_sigma_f32(const Problem& p, const float* L, const float* x, float* y,
-                      const double* xscale, double sign, hipStream_t st) {
-  launch_sigma_t<float>(p, p.d_mhat32, L, x, y, xscale, sign, st);
+                      const double* xscale, double sign, hipStream_t st, TileDots* dots) {
+  launch_sigma_t<float>(p, p.d_mhat32, L, x, y, xscale, sign, st, dots);
+}
+
+int sigma_dot_slots(const Problem& p, int precision) {
+  if (precision == RT_PREC_FP64 || precision == RT_PREC_FP32)
+    return ((p.n_r + gemm::BM - 1) / gemm::BM) * (int)((p.n_s + gemm::BN - 1) / gemm::BN);
+  // 16-bit: the smallest candidate tile is 128 x 128 over mp16 rows
+  return (p.mp16 / 128) * (int)((p.n_s + 127) / 128);
 }
 
 }  // namespace rtsn

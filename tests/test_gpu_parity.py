@@ -216,6 +216,23 @@ def test_gmres_fp64_matches_oracle(name):
         assert diff < 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_gmres_with_dots_fused_into_sigma(prec, monkeypatch):
+    """The opt-in variant that forms the Arnoldi inner products in the Sigma
+    GEMM's epilogue reaches the same FP64 residual as the default path."""
+    rt = _rt()
+    monkeypatch.setenv("RTSN_FUSED_DOTS", "1")
+    spec = W.small_box(12, 4, 8, 9, seed=5, nz=9, ny=10)
+    say(f"gmres fused dots {prec}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, restart=30, precision=prec)
+        s = host(x)
+    assert st["converged"]
+    assert op.residual_norm(s) <= 1.05e-8
+
+
 def test_gmres_tight_solution_matches_oracle():
     rt = _rt()
     spec = W.slab64()
