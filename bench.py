@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--mixed-precision", default="fp16")
     ap.add_argument("--workload", default="box32",
-                    choices=["box32", "batch512", "serve", "box64"])
+                    choices=["box32", "batch512", "serve", "box64", "slab64"])
     ap.add_argument("--precision", default=None,
                     help="operator precision for batch512 / serve / box64")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: stream length (s)")
@@ -147,6 +147,8 @@ def main():
         return bench_serve(args)
     if args.workload == "box64":
         return bench_box64(args)
+    if args.workload == "slab64":
+        return bench_slab64(args)
     import torch
     import workloads as W
     from paper_2602_21958_amd import rt
@@ -465,6 +467,91 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_slab64(args):
+    """The 1D slab (64 depths, 8 mu, 21 frequencies, N = 10 752) in FP64:
+    K GMRES(30) solves to 1e-8; the oracle's full solve is the CPU baseline."""
+    import torch
+    import workloads as W
+    from paper_2602_21958_amd import rt
+
+    spec = W.slab64()
+    p = rt.Problem(spec)
+    x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        p.solve(x, rtol=1e-8, restart=30, stream=stream)
+    torch.cuda.synchronize()
+    lat, st = [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        st = p.solve(x, rtol=1e-8, restart=30, stream=stream)
+        lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {
+        "metric": "solves/s to 1e-8 residual (1D slab, FP64)", "value": args.steps / el,
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "slab64: 64 log-spaced depths (tau_c 1e-4..1e4), 8 mu, 21 "
+                               "frequencies, eps 1e-4, dipole x PRD; GMRES(30) to 1e-8; FP64",
+                   "n_unknowns": p.n},
+        "converged": st["converged"], "iters": st["iters"], "relres": st["relres"],
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99)},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import Problem as OProblem, gmres
+        t0 = time.perf_counter()
+        op = OProblem(spec)
+        ref = gmres(op.apply, op.rhs().ravel(), restart=30, tol=1e-8)
+        t_or = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / t_or, "unit": "solves/s", "cores": _blas_threads(),
+                               "kind": "oracle",
+                               "sample": f"one full oracle GMRES(30) solve ({ref['iters']} "
+                                         f"iterations, set-up included)"}
+    p.close()
+    print(json.dumps(out), flush=True)
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:
+        return 1
+
+
+def box64_cpu_baseline(spec, n_apply):
+    """Oracle on a bounded sample of box64: Lambda for 2 of the 128 ordinates
+    (all 48 frequencies) and the Sigma product for 4096 of the 262 144 points,
+    each scaled to the full operator; an FP64 oracle solve at this size would
+    hold a 30-vector basis of 12.9 GB vectors in host memory, so the solve time
+    is extrapolated as n_apply operator applications."""
+    import numpy as np
+    from oracle import Problem as OProblem
+    from oracle.transfer import sweep_box
+    op = OProblem(spec)
+    n_om = op.omega.shape[0]
+    n_nu = spec.n_nu
+    sub_o, sub_p = 2, 4096
+    s = np.random.default_rng(0).standard_normal((sub_o * n_nu, spec.nz, spec.ny, spec.nx))
+    t0 = time.perf_counter()
+    sweep_box(spec.k_line, op.omega[:sub_o], op.phi + spec.r, s)
+    t_lam = (time.perf_counter() - t0) * n_om / sub_o
+    L = np.random.default_rng(1).standard_normal((op.n_r, sub_p))
+    t0 = time.perf_counter()
+    op.albedo[None, :sub_p] * (op.mhat @ L)
+    t_sig = (time.perf_counter() - t0) * op.n_s / sub_p
+    t_solve = n_apply * (t_lam + t_sig)
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": _blas_threads(),
+            "kind": "oracle",
+            "sample": f"Lambda of 2/{n_om} ordinates and Sigma on {sub_p}/{op.n_s} points, "
+                      f"scaled to one operator application (Lambda {t_lam:.1f} s + Sigma "
+                      f"{t_sig:.1f} s) and extrapolated to {n_apply} applications (the GPU "
+                      f"solve's inner + outer iterations)"}
+
+
 def bench_box64(args):
     """The 64^3 box (128 ordinates x 48 frequencies, N = 1.61e9) in mixed
     precision: FP32 Lambda, 16-bit Sigma, FP64 refinement, GMRES(20) inner
@@ -524,6 +611,9 @@ def bench_box64(args):
         "lambda": {"avg_ms": lam_ms, "GB/s_at_6B_per_unknown": 6.0 * n / lam_ms / 1e6},
     }
     p.close()
+    if not args.no_cpu_baseline:
+        v = res[best[1]]
+        out["cpu_baseline"] = box64_cpu_baseline(spec, v["inner_iters"] + v["outer_iters"])
     print(json.dumps(out), flush=True)
 
 
