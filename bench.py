@@ -306,6 +306,7 @@ def bench_batch512(args):
             rt.profile_enable(False)
             prof = _profile_summary(rt)
         st = [eng.poll(t) for t in tk]
+        run.tile = eng.gemm16_tile()
         eng.close()
         return el, steps, st, prof
 
@@ -316,6 +317,7 @@ def bench_batch512(args):
         el, steps, st, pr = run(prec, profile=(k == args.steps - 1))
         times.append(el)
         prof = pr or prof
+    tile = run.tile
     el = sum(times) / len(times)
     conv = sum(1 for s in st if s["converged"])
     its = np.array([s["iters"] for s in st])
@@ -347,12 +349,13 @@ def bench_batch512(args):
         "converged": conv, "engine_steps": steps,
         "iters": {"median": float(np.median(its)), "p90": float(np.percentile(its, 90)),
                   "max": int(its.max()), "min": int(its.min())},
-        "kernel_ms_per_step": {k: v["total_ms"] for k, v in prof.items()},
+        "kernel_ms_per_run": {k: v["total_ms"] for k, v in prof.items()},
         "variants": variants,
         "per_slab_fp64_loop": {"s_per_slab": loop_per_slab, "solves_per_s": 1 / loop_per_slab,
                                "sample": f"{len(sample)} slabs through rt_solve FP64",
                                "engine_speedup": (512 / el) * loop_per_slab},
         "sigma_avg_ms": sig["total_ms"] / max(sig["launches"], 1),
+        "sigma_tile": tile,
     }
     if not args.no_cpu_baseline:
         from oracle import Problem as OProblem, gmres

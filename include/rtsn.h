@@ -286,6 +286,14 @@ enum { RT_KCLASS_LAMBDA = 0, RT_KCLASS_SIGMA = 1, RT_KCLASS_ARNOLDI = 2, RT_KCLA
 rt_status rt_profile_enable(int on);
 rt_status rt_profile_read(int kclass, int64_t* launches, double* total_ms, int reset);
 
+/* Shape the engine's grouped 16-bit scattering GEMM uses: a fixed 128x128
+ * tile body (the same for every engine, so that a solve rounds identically
+ * alone and in any mix) and a persistent grid size chosen at the engine's
+ * first inner step by timing 512, 1024 and 2048 workgroups on the live work
+ * lists.  RTSN_BATCH_GEMM16="<cfg>,<grid>" forces both.  Returns a string
+ * owned by the engine ("untuned" before the first step, "" for NULL).       */
+const char* rt_batch_gemm16_tile(rt_batch b);
+
 /* Tile shape the 16-bit scattering GEMM uses for problem p in `precision`
  * (RT_PREC_BF16 / FP16 / BF16X3): chosen the first time the problem applies
  * that precision by timing the candidate shapes on the problem's own

@@ -14,10 +14,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 
 #include "batch.h"
 
@@ -110,6 +113,9 @@ struct Request {
 struct Engine {
   int device = 0;
   int max_lds = 0;            // LDS bytes per workgroup of the device (queried once)
+  BatchTune tune;             // shape of the grouped 16-bit GEMM
+  bool tuned = false;
+  std::string tune_name = "untuned";
   int precision = RT_PREC_FP64;
   bool fp64 = true;
   bool use_graph = true;
@@ -140,6 +146,7 @@ struct Engine {
 
   ~Engine();
   size_t footprint(const Problem& p, int restart) const;
+  void tune_gemm16();
   void admit();
   bool setup_slot(Request* r, int s);
   void release_slot(int s, rt_status st);
@@ -383,20 +390,69 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   wl.box_f = bf;
 }
 
+// Time the grouped 16-bit GEMM's persistent grid sizes on the live work
+// lists, once, before the first capture: Lambda runs once to provide the
+// operand, then each size twice after a warm-up (the GEMM recomputes the same
+// V_{j+1} every time).  The tile body stays fixed: a different MFMA
+// instruction would round differently, and a solve must give the same bits
+// alone and in any mix of other solves.  RTSN_BATCH_GEMM16 forces a body.
+void Engine::tune_gemm16() {
+  tuned = true;
+  if (fp64 || precision == RT_PREC_FP32 || wl_iter.h_counts[2] == 0) return;
+  if (const char* e = std::getenv("RTSN_BATCH_GEMM16")) {   // "<cfg>,<grid>"
+    int c = 0, g = kPersistBlocks;
+    if (std::sscanf(e, "%d,%d", &c, &g) >= 1 && c >= 0 && c < kBatchGemm16Cfgs && g > 0) {
+      tune = BatchTune{c, g};
+      tune_name = std::string(batch_gemm16_name(c)) + ", " + std::to_string(g) + " workgroups";
+      return;
+    }
+  }
+  b_lambda16(d_slots, d_stat, wl_iter, precision, stream);
+  hipEvent_t e0, e1;
+  RT_HIP(hipEventCreate(&e0));
+  RT_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (int c = 0; c < 1; ++c) {
+    for (int g : {512, 1024, 2048}) {
+      const BatchTune t{c, g};
+      b_time_gemm16(d_slots, d_stat, wl_iter, precision, stream, t);
+      float ms = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        RT_HIP(hipEventRecord(e0, stream));
+        b_time_gemm16(d_slots, d_stat, wl_iter, precision, stream, t);
+        RT_HIP(hipEventRecord(e1, stream));
+        RT_HIP(hipEventSynchronize(e1));
+        float v = 0.f;
+        RT_HIP(hipEventElapsedTime(&v, e0, e1));
+        ms = std::min(ms, v);
+      }
+      if (ms < best) {
+        best = ms;
+        tune = t;
+      }
+    }
+  }
+  RT_HIP(hipEventDestroy(e0));
+  RT_HIP(hipEventDestroy(e1));
+  tune_name = std::string(batch_gemm16_name(tune.cfg)) + ", " + std::to_string(tune.grid) +
+              " workgroups";
+}
+
 void Engine::run_inner() {
   const bool profiling = profile_enabled();
+  if (!tuned) tune_gemm16();
   // The captured graph bakes in the launch shape (which geometries, box class
   // and LDS size) and the addresses of the list buffers: any change of either
   // needs a new capture.
   const uint64_t key = (uint64_t)(wl_iter.h_counts[0] > 0) |
                        ((uint64_t)(wl_iter.h_counts[1] > 0) << 1) |
                        ((uint64_t)wl_iter.box_npt << 2) | ((uint64_t)wl_iter.box_pmax << 8) |
-                       (wl_iter.gen << 24);
+                       (wl_iter.gen << 24) | ((uint64_t)tune.cfg << 60);
   auto direct = [&] {
     if (fp64)
       b_inner_iteration<double>(d_slots, d_stat, wl_iter, precision, stream);
     else
-      b_inner_iteration<float>(d_slots, d_stat, wl_iter, precision, stream);
+      b_inner_iteration<float>(d_slots, d_stat, wl_iter, precision, stream, tune);
   };
   if (use_graph && !profiling) {
     if (key != graph_key) {
@@ -686,6 +742,11 @@ rt_status rt_batch_info(rt_batch b, int* active, int* queued, int64_t* bytes_in_
     if (queued) *queued = (int)e->queue.size();
     if (bytes_in_use) *bytes_in_use = (int64_t)e->arena.used();
   });
+}
+
+const char* rt_batch_gemm16_tile(rt_batch b) {
+  if (!b) return "";
+  return reinterpret_cast<Engine*>(b)->tune_name.c_str();
 }
 
 rt_status rt_batch_footprint(rt_batch b, rt_problem p, int restart, int64_t* bytes) {

@@ -82,11 +82,27 @@ struct WorkLists {
                              // captured with the old addresses must not be replayed
 };
 
+// Shape of the grouped 16-bit GEMM: tile body (index into the candidates of
+// batch.hip) and persistent grid size.
+struct BatchTune {
+  int cfg = 0;
+  int grid = kPersistBlocks;
+};
+constexpr int kBatchGemm16Cfgs = 2;
+const char* batch_gemm16_name(int cfg);
+
 // Launchers (inner: vectors TV, operator precision prec)
 // One Arnoldi step of every slot in the lists (operator in precision prec).
 template <typename TV>
 void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
-                       hipStream_t st);
+                       hipStream_t st, const BatchTune& tune = {});
+// Lambda of the current basis vector followed by the grouped 16-bit GEMM in
+// the given shape (the same work as the first half of an inner iteration;
+// used to time the shapes).
+void b_time_gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                   hipStream_t st, const BatchTune& tune);
+void b_lambda16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                hipStream_t st);
 // x += rn V y, then r = b - A_64 x and rn = ||r|| for every listed slot.
 template <typename TV>
 void b_cycle_end(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st);

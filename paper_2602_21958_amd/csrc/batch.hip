@@ -180,16 +180,19 @@ __global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
   }
 }
 
-// 16-bit operands, one fixed tile shape for every slot (tiles of the lists
-// are 128 x 128): V_{j+1} = vscale_j V_j - (1 - eps) Mhat L.
-using BatchCfg16 = g16::Cfg<128, 128, 2, 2, 32, true>;
+// 16-bit operands, one tile shape for every slot (tiles of the lists are
+// 128 x 128): V_{j+1} = vscale_j V_j - (1 - eps) Mhat L.  Two tile bodies
+// are candidates for the engine's tuner (32x32x16 with K stage 32, and
+// 16x16x32 with K stage 64).
+using BatchCfg16a = g16::Cfg<128, 128, 2, 2, 32, true>;
+using BatchCfg16b = g16::Cfg<128, 128, 2, 2, 64, false>;
 
-template <int MODE>
-__global__ __launch_bounds__(BatchCfg16::NT) void bk_gemm16(const SlotDev* __restrict__ slots,
-                                                          const SlotStat* __restrict__ stat,
-                                                          const Item* __restrict__ items,
-                                                          const int* __restrict__ counts) {
-  __shared__ __align__(16) uint8_t lds[BatchCfg16::lds_bytes<MODE>()];
+template <int MODE, typename C>
+__global__ __launch_bounds__(C::NT) void bk_gemm16(const SlotDev* __restrict__ slots,
+                                                   const SlotStat* __restrict__ stat,
+                                                   const Item* __restrict__ items,
+                                                   const int* __restrict__ counts) {
+  __shared__ __align__(16) uint8_t lds[C::template lds_bytes<MODE>()];
   const int cnt = counts[2];
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
@@ -199,19 +202,41 @@ __global__ __launch_bounds__(BatchCfg16::NT) void bk_gemm16(const SlotDev* __res
     float* Y = static_cast<float*>(s.V) + (size_t)(j + 1) * s.n;
     const uint16_t* ahi = MODE == g16::MODE_FP16 ? s.a8_f16 : s.a8_hi;
     const uint16_t* blo = MODE == g16::MODE_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr;
-    g16::tile<MODE, BatchCfg16>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X, Y,
-                                s.albedo, MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr,
-                                1.f / s.l_scale, (float)s.gs->vscale[j], -1.f, s.n_r, (int)s.n_s,
-                                w.a, w.b, lds);
+    g16::tile<MODE, C>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X, Y, s.albedo,
+                       MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr, 1.f / s.l_scale,
+                       (float)s.gs->vscale[j], -1.f, s.n_r, (int)s.n_s, w.a, w.b, lds);
   }
 }
 
 // --------------------------------------------------------------- Arnoldi
+// 16-byte vectors of the basis type (used when a slot's length keeps every
+// basis vector 16-byte aligned).
+template <typename TV> struct BVec;
+template <> struct BVec<float> {
+  typedef float T __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <> struct BVec<double> {
+  typedef double T __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
+template <typename TV>
+__device__ __forceinline__ double vdot(typename BVec<TV>::T a, typename BVec<TV>::T b) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < BVec<TV>::n; ++q) s += (double)a[q] * (double)b[q];
+  return s;
+}
+
+// Dots of the slot's basis with w over one kChunk-element chunk.
 template <typename TV>
 __global__ __launch_bounds__(TB) void bk_mdot(const SlotDev* __restrict__ slots,
                                               const SlotStat* __restrict__ stat,
                                               const Item* __restrict__ items,
                                               const int* __restrict__ counts) {
+  using VT = typename BVec<TV>::T;
+  constexpr int W = BVec<TV>::n;
   const int cnt = counts[3];
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
@@ -221,15 +246,27 @@ __global__ __launch_bounds__(TB) void bk_mdot(const SlotDev* __restrict__ slots,
     const TV* wv = V + (size_t)(j + 1) * s.n;
     const int64_t e0 = (int64_t)w.a * kChunk;
     const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
+    const bool vec = (s.n % W) == 0;   // uniform per slot
     for (int i0 = 0; i0 <= j; i0 += 16) {
       double acc[16];
 #pragma unroll
       for (int g = 0; g < 16; ++g) acc[g] = 0.0;
-      for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
-        const double x = (double)wv[e];
+      if (vec) {
+        const VT* wq = reinterpret_cast<const VT*>(wv);
+        for (int64_t e = e0 / W + threadIdx.x; e < e1 / W; e += TB) {
+          const VT x = wq[e];
 #pragma unroll
-        for (int g = 0; g < 16; ++g)
-          if (i0 + g <= j) acc[g] += (double)V[(size_t)(i0 + g) * s.n + e] * x;
+          for (int g = 0; g < 16; ++g)
+            if (i0 + g <= j)
+              acc[g] += vdot<TV>(reinterpret_cast<const VT*>(V + (size_t)(i0 + g) * s.n)[e], x);
+        }
+      } else {
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+          const double x = (double)wv[e];
+#pragma unroll
+          for (int g = 0; g < 16; ++g)
+            if (i0 + g <= j) acc[g] += (double)V[(size_t)(i0 + g) * s.n + e] * x;
+        }
       }
       const int c = j + 1 - i0 < 16 ? j + 1 - i0 : 16;
       block_sum_store<16>(acc, s.partial + (size_t)i0 * s.nch + w.a, s.nch, c);
@@ -263,10 +300,13 @@ __global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slot
                                                 const int* __restrict__ counts) {
   __shared__ double coef[kMaxRestart + 1];
   const int cnt = counts[3];
+  using VT = typename BVec<TV>::T;
+  constexpr int W = BVec<TV>::n;
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
     const SlotDev& s = slots[w.slot];
     const int j = stat[w.slot].j;
+    __syncthreads();   // coef of the previous item is no longer read
     for (int i = threadIdx.x; i <= j; i += TB) coef[i] = s.gs->h[i] * s.gs->vscale[i];
     __syncthreads();
     TV* V = static_cast<TV*>(s.V);
@@ -274,12 +314,34 @@ __global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slot
     const int64_t e0 = (int64_t)w.a * kChunk;
     const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
     double nrm = 0.0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
-      double v = (double)wv[e];
-      for (int i = 0; i <= j; ++i) v -= coef[i] * (double)V[(size_t)i * s.n + e];
-      const TV q = (TV)v;
-      wv[e] = q;
-      nrm += (double)q * (double)q;
+    if ((s.n % W) == 0) {   // uniform per slot
+      VT* wq = reinterpret_cast<VT*>(wv);
+      for (int64_t e = e0 / W + threadIdx.x; e < e1 / W; e += TB) {
+        const VT x = wq[e];
+        double v[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) v[q] = (double)x[q];
+        for (int i = 0; i <= j; ++i) {
+          const VT b = reinterpret_cast<const VT*>(V + (size_t)i * s.n)[e];
+#pragma unroll
+          for (int q = 0; q < W; ++q) v[q] -= coef[i] * (double)b[q];
+        }
+        VT r;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          r[q] = (TV)v[q];
+          nrm += (double)r[q] * (double)r[q];
+        }
+        wq[e] = r;
+      }
+    } else {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+        double v = (double)wv[e];
+        for (int i = 0; i <= j; ++i) v -= coef[i] * (double)V[(size_t)i * s.n + e];
+        const TV q = (TV)v;
+        wv[e] = q;
+        nrm += (double)q * (double)q;
+      }
     }
     double a[1] = {nrm};
     block_sum_store<1>(a, s.partial + (size_t)(s.restart + 1) * s.nch + w.a, 1, 1);
@@ -458,6 +520,24 @@ void persist(K kernel, int threads, size_t lds, hipStream_t st, Args... args) {
   RT_HIP(hipGetLastError());
 }
 
+template <typename K, typename... Args>
+void persist_grid(K kernel, int grid, int threads, size_t lds, hipStream_t st, Args... args) {
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, args...);
+  RT_HIP(hipGetLastError());
+}
+
+template <int MODE>
+void launch_b_gemm16(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
+                     const BatchTune& tune, hipStream_t st) {
+  ProfScope prof(RT_KCLASS_SIGMA, st);
+  if (tune.cfg == 1)
+    persist_grid(bk_gemm16<MODE, BatchCfg16b>, tune.grid, BatchCfg16b::NT, 0, st, slots, stat,
+                 wl.tiles, wl.counts);
+  else
+    persist_grid(bk_gemm16<MODE, BatchCfg16a>, tune.grid, BatchCfg16a::NT, 0, st, slots, stat,
+                 wl.tiles, wl.counts);
+}
+
 template <typename VT, typename LT, typename C, int K4, bool OUTER>
 void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
                      hipStream_t st) {
@@ -484,9 +564,40 @@ void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists
 
 }  // namespace
 
+const char* batch_gemm16_name(int cfg) {
+  return cfg == 1 ? "128x128 16x16x32 K64" : "128x128 32x32x16 K32";
+}
+
+void b_lambda16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                hipStream_t st) {
+  switch (prec) {
+    case RT_PREC_BF16:
+      launch_b_lambda<float, float, float, lam::K4_BF16, false>(slots, stat, wl, st);
+      break;
+    case RT_PREC_FP16:
+      launch_b_lambda<float, float, float, lam::K4_FP16, false>(slots, stat, wl, st);
+      break;
+    case RT_PREC_BF16X3:
+      launch_b_lambda<float, float, float, lam::K4_SPLIT, false>(slots, stat, wl, st);
+      break;
+    default:
+      fail(RT_E_INVALID, "b_lambda16: not a 16-bit precision");
+  }
+}
+
+void b_time_gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                   hipStream_t st, const BatchTune& tune) {
+  switch (prec) {
+    case RT_PREC_BF16: launch_b_gemm16<g16::MODE_BF16>(slots, stat, wl, tune, st); break;
+    case RT_PREC_FP16: launch_b_gemm16<g16::MODE_FP16>(slots, stat, wl, tune, st); break;
+    case RT_PREC_BF16X3: launch_b_gemm16<g16::MODE_SPLIT>(slots, stat, wl, tune, st); break;
+    default: fail(RT_E_INVALID, "b_time_gemm16: not a 16-bit precision");
+  }
+}
+
 template <typename TV>
 void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
-                       hipStream_t st) {
+                       hipStream_t st, const BatchTune& tune) {
   using C = typename ComputeOf<TV>::type;
   if constexpr (sizeof(TV) == 8) {
     if (prec != RT_PREC_FP64) fail(RT_E_INVALID, "FP64 vectors need the FP64 operator");
@@ -501,27 +612,12 @@ void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl
         persist(bk_gemm<float, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
         break;
       }
-      case RT_PREC_BF16: {
-        launch_b_lambda<float, float, C, lam::K4_BF16, false>(slots, stat, wl, st);
-        ProfScope prof(RT_KCLASS_SIGMA, st);
-        persist(bk_gemm16<g16::MODE_BF16>, BatchCfg16::NT, 0, st, slots, stat, wl.tiles,
-                wl.counts);
+      case RT_PREC_BF16:
+      case RT_PREC_FP16:
+      case RT_PREC_BF16X3:
+        b_lambda16(slots, stat, wl, prec, st);
+        b_time_gemm16(slots, stat, wl, prec, st, tune);
         break;
-      }
-      case RT_PREC_FP16: {
-        launch_b_lambda<float, float, C, lam::K4_FP16, false>(slots, stat, wl, st);
-        ProfScope prof(RT_KCLASS_SIGMA, st);
-        persist(bk_gemm16<g16::MODE_FP16>, BatchCfg16::NT, 0, st, slots, stat, wl.tiles,
-                wl.counts);
-        break;
-      }
-      case RT_PREC_BF16X3: {
-        launch_b_lambda<float, float, C, lam::K4_SPLIT, false>(slots, stat, wl, st);
-        ProfScope prof(RT_KCLASS_SIGMA, st);
-        persist(bk_gemm16<g16::MODE_SPLIT>, BatchCfg16::NT, 0, st, slots, stat, wl.tiles,
-                wl.counts);
-        break;
-      }
       default:
         fail(RT_E_INVALID, "unknown precision");
     }
@@ -555,9 +651,9 @@ void b_start_cycle(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hi
 }
 
 template void b_inner_iteration<double>(const SlotDev*, SlotStat*, const WorkLists&, int,
-                                        hipStream_t);
+                                        hipStream_t, const BatchTune&);
 template void b_inner_iteration<float>(const SlotDev*, SlotStat*, const WorkLists&, int,
-                                       hipStream_t);
+                                       hipStream_t, const BatchTune&);
 template void b_cycle_end<double>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
 template void b_cycle_end<float>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
 template void b_start_cycle<double>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);

@@ -101,6 +101,7 @@ _sig = {
     "rt_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                   C.c_int]),
     "rt_gemm16_tile": (C.c_char_p, [_vp, C.c_int]),
+    "rt_batch_gemm16_tile": (C.c_char_p, [_vp]),
     "rt_last_error": (C.c_char_p, []),
     "rt_version": (C.c_int, []),
 }
@@ -339,6 +340,10 @@ class Batch:
 
     def wait_all(self):
         _check(_lib.rt_batch_wait_all(self.handle), "rt_batch_wait_all")
+
+    def gemm16_tile(self) -> str:
+        """Shape of the engine's grouped 16-bit GEMM (tile body, grid)."""
+        return _lib.rt_batch_gemm16_tile(self.handle).decode()
 
     def footprint(self, problem: "Problem", restart: int = 30) -> int:
         b = C.c_int64()

@@ -161,6 +161,19 @@ def test_batch_mixed_precision_reaches_fp64_residual(precision):
             assert precision == "bf16", st
 
 
+@pytest.mark.parametrize("force", ["1,512", "0,2048"])
+def test_batch_gemm16_forced_shapes(force, monkeypatch):
+    """The grouped 16-bit GEMM in a forced tile body / grid (the engine's tuner
+    only varies the grid) still reaches the FP64 residual."""
+    monkeypatch.setenv("RTSN_BATCH_GEMM16", force)
+    specs = small_slabs(3, 7) + [W.small_box(8, 4, 8, 8, seed=3)]
+    say(f"batch forced shape {force}")
+    sols, stats, _ = run_engine(specs, precision="fp16")
+    for spec, s, st in zip(specs, sols, stats):
+        assert st["converged"], st
+        assert OProblem(spec).residual_norm(s) <= 1.05e-8
+
+
 def test_batch_rejects_bad_requests():
     rt = _rt()
     with pytest.raises(rt.RtError):
