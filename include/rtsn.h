@@ -198,6 +198,12 @@ typedef struct {
   double inner_rtol;      /* mixed: inner relative tolerance (default 1e-3)         */
   int max_outer;          /* mixed: outer refinement cap (default 50)               */
   int record_history;     /* keep the per-iteration residual estimates              */
+  int basis_fp16;         /* mixed with a 16-bit operator precision (RT_PREC_BF16,
+                             RT_PREC_FP16, RT_PREC_BF16X3): keep the inner Krylov
+                             basis in fp16, scaled by a power of two near
+                             sqrt(n_unknowns), which halves the bytes of every
+                             Arnoldi pass (default 0: FP32 basis).  RT_E_INVALID
+                             with any other precision.                           */
 } rt_solver_opts;
 
 typedef struct {
@@ -250,7 +256,8 @@ rt_status rt_batch_create(int device, int precision, int64_t hbm_budget,
  * GMRES only.  x_out: device FP64 n_unknowns of p, caller-owned; the engine
  * iterates in it from admission on and it holds the solution at completion.
  * Non-blocking; *ticket identifies the request.  RT_E_BUSY if the queue is
- * full; RT_E_INVALID if the problem can never fit the budget.               */
+ * full; RT_E_INVALID if the problem can never fit the budget or if
+ * opts->basis_fp16 is set (the engine keeps FP32 / FP64 bases).             */
 rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts,
                           double* x_out, uint64_t* ticket);
 

@@ -321,6 +321,16 @@ void operator_apply(Problem& p, int precision, const void* x, void* y, const dou
   }
 }
 
+void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
+                      const double* xscale, float ymul, hipStream_t st) {
+  if (precision != RT_PREC_BF16 && precision != RT_PREC_FP16 && precision != RT_PREC_BF16X3)
+    fail(RT_E_INVALID, "an fp16 basis needs a 16-bit operator precision");
+  uint16_t* L = problem_l16(p, st);
+  uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
+  launch_lambda_k4(p, precision, x, L, Llo, xscale, st);
+  launch_sigma_b16_h(p, precision, L, Llo, x, y, ymul, xscale, -1.0, st);
+}
+
 const double* physical_rhs(Problem& p, hipStream_t st) {
   const size_t n = (size_t)p.n;
   if (!p.d_rhs) RT_HIP(hipMalloc(&p.d_rhs, n * sizeof(double)));
@@ -547,6 +557,9 @@ rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, do
     if (o.precision != RT_PREC_FP64 && !(o.inner_rtol > 0 && o.inner_rtol < 1))
       fail(RT_E_INVALID, "inner_rtol must be in (0, 1)");
     if (o.max_outer < 1) o.max_outer = 1;
+    if (o.basis_fp16 && o.precision != RT_PREC_BF16 && o.precision != RT_PREC_FP16 &&
+        o.precision != RT_PREC_BF16X3)
+      fail(RT_E_INVALID, "basis_fp16 needs a 16-bit operator precision");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double* bb = b ? b : physical_rhs(*q, st);
     status = solve(*q, o, bb, x, x_is_guess, stats, st);

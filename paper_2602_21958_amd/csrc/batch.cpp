@@ -679,6 +679,7 @@ rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts, 
     if (o.precision != e->precision) fail(RT_E_INVALID, "precision differs from the engine's");
     if (o.restart < 1 || o.restart > kMaxRestart) fail(RT_E_INVALID, "restart out of range");
     if (!(o.rtol > 0)) fail(RT_E_INVALID, "rtol must be > 0");
+    if (o.basis_fp16) fail(RT_E_INVALID, "the batch engine keeps FP32 / FP64 bases");
     if (o.max_outer < 1) o.max_outer = 1;
     std::lock_guard<std::mutex> lk(e->mu);
     if (e->footprint(*q, o.restart) > e->arena.size())

@@ -2,7 +2,7 @@
 // tile, shared by the single-problem kernels (sigma_b16.hip) and the grouped
 // kernel of the batch engine (batch.hip).
 //
-//   Y[m, n] = xs X[m, n] + sign * albedo[n] * rowfac[m] * sum_k A[m, k] B[k, n]
+//   Y[m, n] = ymul (xs X[m, n] + sign * albedo[n] * rowfac[m] * sum_k A[m, k] B[k, n])
 //
 // Operand layouts (16-bit values, zero padded):
 //   A (Mhat)      "k8": element (m, k) at ((k / 8) * Mp + m) * 8 + k % 8, k < Kp
@@ -98,15 +98,18 @@ struct Cfg {
 // One output tile at (m0, n0).  lds: Cfg::lds_bytes<MODE>() bytes, 16-byte
 // aligned.  Caller guarantees m0 + BM <= Mp, n0 + BN <= Np, K4p % (BK/4) == 0.
 // The function starts with a barrier, so a persistent caller may reuse lds.
-template <int MODE, typename C, bool DOTS = false>
+// TY: element type of X and Y (float, or _Float16 for a scaled fp16 Krylov
+// basis); ymul multiplies the whole output (the basis scale; 1 otherwise).
+template <int MODE, typename C, bool DOTS = false, typename TY = float>
 __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
                                      const uint16_t* __restrict__ Alo, int Mp,
                                      const uint16_t* __restrict__ Bhi,
                                      const uint16_t* __restrict__ Blo, int Np, int K4p,
-                                     const float* X, float* Y, const double* __restrict__ albedo,
+                                     const TY* X, TY* Y, const double* __restrict__ albedo,
                                      const float* __restrict__ rowscale, float colmul, float xs,
                                      float sign, int M, int N, int m0, int n0, uint8_t* lds,
-                                     gemm::TileDots dots = {}, int slot = 0) {
+                                     gemm::TileDots dots = {}, int slot = 0, float ymul = 1.f) {
+  static_assert(!DOTS || sizeof(TY) == 4, "fused dots need an FP32 output");
   constexpr bool SPLIT = MODE == MODE_SPLIT;
   constexpr int NP = SPLIT ? 2 : 1;   // operand parts (hi, lo)
   using MM = Mma<MODE != MODE_FP16, C::BIG>;
@@ -240,9 +243,10 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
         if (row < M && col < N) {
           const size_t idx = (size_t)row * N + col;
           float v = cf * (rowscale ? rowscale[row] : 1.f) * acc[i][j][r];
-          if (X != nullptr) v += xs * X[idx];
-          Y[idx] = v;
-          acc[i][j][r] = v;
+          if (X != nullptr) v += xs * (float)X[idx];
+          const TY t = (TY)(ymul * v);
+          Y[idx] = t;
+          acc[i][j][r] = (float)t;
         } else {
           acc[i][j][r] = 0.f;
         }

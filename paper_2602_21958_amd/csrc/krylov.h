@@ -72,7 +72,8 @@ struct Workspace {
   int restart = 0;
   bool mixed = false;
   size_t bytes = 0;
-  void* V = nullptr;            // (restart + 1) * n basis (double, or float if mixed)
+  void* V = nullptr;            // (restart + 1) * n basis (double; float or fp16 if mixed)
+  size_t vbytes = 0;
   double* partial = nullptr;    // partial_elems partial sums
   size_t partial_elems = 0;
   int dot_slots = 0;            // slots per vector of the dots fused into the GEMM
@@ -89,7 +90,9 @@ struct Workspace {
   ~Workspace();
 };
 
-size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab);
+// basis_elem: bytes per basis element (0: 8 for FP64, 4 for mixed)
+size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab,
+                       int basis_elem = 0);
 
 rt_status solve(Problem& p, const rt_solver_opts& o, const double* b, double* x, int x_is_guess,
                 rt_solve_stats* stats, hipStream_t st);

@@ -50,20 +50,52 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[G], double* out
   __syncthreads();
 }
 
-// 16-byte vector of a basis element type
+// 16-byte vector of a basis element type (clang vector types: arrays of
+// them stay in registers)
 template <typename TV> struct Vec16;
 template <> struct Vec16<double> {
-  using type = double2;
+  typedef double type __attribute__((ext_vector_type(2)));
   static constexpr int n = 2;
-  static __device__ __forceinline__ double dot(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }
+  static __device__ __forceinline__ double dot(type a, type b) { return a.x * b.x + a.y * b.y; }
 };
 template <> struct Vec16<float> {
-  using type = float4;
+  typedef float type __attribute__((ext_vector_type(4)));
   static constexpr int n = 4;
-  static __device__ __forceinline__ double dot(float4 a, float4 b) {
+  static __device__ __forceinline__ double dot(type a, type b) {
     return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
   }
 };
+
+// fp16 basis (stored scaled so that its entries are of order one): products
+// of two halves are exact in FP32, so a 16-byte group is summed in FP32
+template <> struct Vec16<_Float16> {
+  typedef _Float16 type __attribute__((ext_vector_type(8)));
+  static constexpr int n = 8;
+  static __device__ __forceinline__ double dot(type a, type b) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += (float)a[q] * (float)b[q];
+    return (double)s;
+  }
+};
+
+// Arithmetic type of the Gram-Schmidt update: FP64 for FP64 / FP32 vectors,
+// FP32 for the fp16 basis (whose own rounding is 2^-11)
+template <typename TV> struct UpdAcc { using type = double; };
+template <> struct UpdAcc<_Float16> { using type = float; };
+
+// W-wide vector of the element type of x in the cycle-end update
+template <typename T, int W> struct VecN {
+  typedef T type __attribute__((ext_vector_type(W)));
+};
+
+// Contiguous range [b0, b1) of n items owned by this block: every pass
+// streams each vector in long sequential runs per block.
+__device__ __forceinline__ void block_range(int64_t n, int64_t& b0, int64_t& b1) {
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  b0 = (int64_t)blockIdx.x * per;
+  b1 = b0 + per < n ? b0 + per : n;
+}
 
 // partial[i * nb + b] = sum over block b's range of W_i[e] * w[e].  Each block
 // streams one contiguous range of every vector (16-byte loads when the vector
@@ -80,10 +112,8 @@ __global__ __launch_bounds__(kThreads) void mdot_kernel(const TV* __restrict__ V
   for (int g = 0; g < G; ++g) acc[g] = 0.0;
   if (n % W == 0) {
     // vector starts are 16-byte aligned: stream with 16-byte loads
-    const int64_t nv = n / W;
-    const int64_t per = (nv + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = (int64_t)blockIdx.x * per;
-    const int64_t b1 = b0 + per < nv ? b0 + per : nv;
+    int64_t b0, b1;
+    block_range(n / W, b0, b1);
     const VT* wv = reinterpret_cast<const VT*>(w);
     for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
       const VT x = wv[e];
@@ -93,9 +123,8 @@ __global__ __launch_bounds__(kThreads) void mdot_kernel(const TV* __restrict__ V
           acc[g] += Vec16<TV>::dot(reinterpret_cast<const VT*>(V + (size_t)(i0 + g) * n)[e], x);
     }
   } else {
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = (int64_t)blockIdx.x * per;
-    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    int64_t b0, b1;
+    block_range(n, b0, b1);
     for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
       const double x = (double)w[e];
 #pragma unroll
@@ -121,37 +150,69 @@ __global__ __launch_bounds__(kThreads) void reduce_rows_kernel(const double* __r
 }
 
 // w -= sum_i coef_i W_i with coef_i = h_i * s_i; partial norm^2 of new w.
+// Each block owns one contiguous range (16-byte loads when the vector length
+// keeps them aligned); eight basis loads are kept in flight per thread.
 template <typename TV>
 __global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__ V, int64_t n,
                                                           int cnt, const double* __restrict__ h,
                                                           const double* __restrict__ vscale,
                                                           TV* __restrict__ w,
                                                           double* __restrict__ partial) {
-  __shared__ double coef[kMaxRestart + 1];
-  for (int i = threadIdx.x; i < cnt; i += kThreads) coef[i] = h[i] * vscale[i];
+  using AT = typename UpdAcc<TV>::type;
+  __shared__ AT coef[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < cnt; i += kThreads) coef[i] = (AT)(h[i] * vscale[i]);
   __syncthreads();
+  using VT = typename Vec16<TV>::type;
+  constexpr int W = Vec16<TV>::n;
   double nrm = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-    double v = (double)w[e];
-    int i = 0;
-    for (; i + 8 <= cnt; i += 8) {  // eight independent loads in flight
-      double a[8];
+  int64_t b0, b1;
+  if (n % W == 0) {
+    block_range(n / W, b0, b1);
+    VT* wv = reinterpret_cast<VT*>(w);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const VT x = wv[e];
+      AT v[W];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = (double)V[(size_t)(i + u) * n + e];
+      for (int q = 0; q < W; ++q) v[q] = (AT)x[q];
+      int i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        VT a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v -= coef[i + u] * a[u];
+        for (int u = 0; u < 8; ++u) a[u] = reinterpret_cast<const VT*>(V + (size_t)(i + u) * n)[e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < W; ++q) v[q] -= coef[i + u] * (AT)a[u][q];
+      }
+      for (; i < cnt; ++i) {
+        const VT a = reinterpret_cast<const VT*>(V + (size_t)i * n)[e];
+#pragma unroll
+        for (int q = 0; q < W; ++q) v[q] -= coef[i] * (AT)a[q];
+      }
+      VT r;
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        r[q] = (TV)v[q];
+        nrm += (double)r[q] * (double)r[q];
+      }
+      wv[e] = r;
     }
-    for (; i < cnt; ++i) v -= coef[i] * (double)V[(size_t)i * n + e];
-    const TV vs = (TV)v;
-    w[e] = vs;
-    nrm += (double)vs * (double)vs;
+  } else {
+    block_range(n, b0, b1);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      AT v = (AT)w[e];
+      for (int i = 0; i < cnt; ++i) v -= coef[i] * (AT)V[(size_t)i * n + e];
+      const TV vs = (TV)v;
+      w[e] = vs;
+      nrm += (double)vs * (double)vs;
+    }
   }
   double a[1] = {nrm};
   block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
 }
 
-// x += sum_i coef_i W_i (coef on device, cnt <= kMaxRestart+1)
+// x += sum_i coef_i W_i (coef on device, cnt <= kMaxRestart+1); same block
+// ranges and vector loads as the update.
 template <typename TV, typename TX>
 __global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict__ V, int64_t n,
                                                            int cnt, const double* __restrict__ coef_d,
@@ -159,19 +220,45 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict_
   __shared__ double coef[kMaxRestart + 1];
   for (int i = threadIdx.x; i < cnt; i += kThreads) coef[i] = coef_d[i];
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-    double v = (double)x[e];
-    int i = 0;
-    for (; i + 8 <= cnt; i += 8) {
-      double a[8];
+  using VT = typename Vec16<TV>::type;
+  constexpr int W = Vec16<TV>::n;
+  using XT = typename VecN<TX, W>::type;
+  int64_t b0, b1;
+  if (n % W == 0) {
+    block_range(n / W, b0, b1);
+    XT* xv = reinterpret_cast<XT*>(x);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const XT x0 = xv[e];
+      double v[W];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = (double)V[(size_t)(i + u) * n + e];
+      for (int q = 0; q < W; ++q) v[q] = (double)x0[q];
+      int i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        VT a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v += coef[i + u] * a[u];
+        for (int u = 0; u < 8; ++u) a[u] = reinterpret_cast<const VT*>(V + (size_t)(i + u) * n)[e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < W; ++q) v[q] += coef[i + u] * (double)a[u][q];
+      }
+      for (; i < cnt; ++i) {
+        const VT a = reinterpret_cast<const VT*>(V + (size_t)i * n)[e];
+#pragma unroll
+        for (int q = 0; q < W; ++q) v[q] += coef[i] * (double)a[q];
+      }
+      XT r;
+#pragma unroll
+      for (int q = 0; q < W; ++q) r[q] = (TX)v[q];
+      xv[e] = r;
     }
-    for (; i < cnt; ++i) v += coef[i] * (double)V[(size_t)i * n + e];
-    x[e] = (TX)v;
+  } else {
+    block_range(n, b0, b1);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      double v = (double)x[e];
+      for (int i = 0; i < cnt; ++i) v += coef[i] * (double)V[(size_t)i * n + e];
+      x[e] = (TX)v;
+    }
   }
 }
 
@@ -578,6 +665,14 @@ template void k_bicg_s<double>(double*, const double*, int64_t, const BicgState*
                                hipStream_t);
 template void k_bicg_xr<double>(double*, const double*, double*, const double*, int64_t,
                                 const BicgState*, int, double*, hipStream_t);
+template void k_mdot<_Float16>(const _Float16*, int64_t, int, const _Float16*, double*,
+                               hipStream_t);
+template void k_update<_Float16>(const _Float16*, int64_t, int, const double*, const double*,
+                                 _Float16*, double*, hipStream_t);
+template void k_combine<_Float16, float>(const _Float16*, int64_t, int, const double*, float*,
+                                         hipStream_t);
+template void k_norm_partial<_Float16>(const _Float16*, int64_t, double*, hipStream_t);
+template void k_convert<double, _Float16>(const double*, _Float16*, int64_t, double, hipStream_t);
 template void k_convert<double, float>(const double*, float*, int64_t, double, hipStream_t);
 template void k_convert<float, double>(const float*, double*, int64_t, double, hipStream_t);
 template void k_convert<float, __hip_bfloat16>(const float*, __hip_bfloat16*, int64_t, double,

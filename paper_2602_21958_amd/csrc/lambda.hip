@@ -94,6 +94,7 @@ __global__ __launch_bounds__(NT) void lambda_box_kernel(
 template <typename VT> struct ComputeOf;
 template <> struct ComputeOf<double> { using type = double; };
 template <> struct ComputeOf<float> { using type = float; };
+template <> struct ComputeOf<_Float16> { using type = float; };
 
 }  // namespace
 
@@ -163,23 +164,34 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
   lambda_dispatch<VT, LT, -1>(p, s, out, nullptr, 0, with_bc, scale, st, out_mul);
 }
 
-void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t* hi,
-                      uint16_t* lo, const double* scale, hipStream_t st) {
+template <typename VT>
+void lambda_k4(const Problem& p, int precision, const VT* s, uint16_t* hi, uint16_t* lo,
+               const double* scale, hipStream_t st) {
   const int64_t Np = p.np16;
   switch (precision) {
     case RT_PREC_BF16:
-      lambda_dispatch<float, float, lam::K4_BF16>(p, s, hi, nullptr, Np, false, scale, st, 1.f);
+      lambda_dispatch<VT, float, lam::K4_BF16>(p, s, hi, nullptr, Np, false, scale, st, 1.f);
       break;
     case RT_PREC_FP16:
-      lambda_dispatch<float, float, lam::K4_FP16>(p, s, hi, nullptr, Np, false, scale, st,
-                                                  fp16_lambda_scale(p.n));
+      lambda_dispatch<VT, float, lam::K4_FP16>(p, s, hi, nullptr, Np, false, scale, st,
+                                               fp16_lambda_scale(p.n));
       break;
     case RT_PREC_BF16X3:
-      lambda_dispatch<float, float, lam::K4_SPLIT>(p, s, hi, lo, Np, false, scale, st, 1.f);
+      lambda_dispatch<VT, float, lam::K4_SPLIT>(p, s, hi, lo, Np, false, scale, st, 1.f);
       break;
     default:
       fail(RT_E_INVALID, "launch_lambda_k4: not a 16-bit precision");
   }
+}
+
+void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t* hi,
+                      uint16_t* lo, const double* scale, hipStream_t st) {
+  lambda_k4<float>(p, precision, s, hi, lo, scale, st);
+}
+
+void launch_lambda_k4(const Problem& p, int precision, const _Float16* s, uint16_t* hi,
+                      uint16_t* lo, const double* scale, hipStream_t st) {
+  lambda_k4<_Float16>(p, precision, s, hi, lo, scale, st);
 }
 
 template void launch_lambda<double, double>(const Problem&, const double*, double*, bool,

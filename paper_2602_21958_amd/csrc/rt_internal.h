@@ -116,6 +116,9 @@ void launch_lambda(const Problem& p, const VT* s, LT* out, bool with_bc,
 // the scattering GEMM (hi; lo for BF16X3), scaled for FP16.
 void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t* hi,
                       uint16_t* lo, const double* scale, hipStream_t st);
+// Same for an fp16 vector (a Krylov basis vector stored in half precision).
+void launch_lambda_k4(const Problem& p, int precision, const _Float16* s, uint16_t* hi,
+                      uint16_t* lo, const double* scale, hipStream_t st);
 float fp16_lambda_scale(int64_t n);
 // Frequencies swept together by one box workgroup for planes of P points.
 int box_chunk(int P, int elem_bytes, int max_lds);
@@ -144,6 +147,10 @@ void launch_sigma_f32(const Problem& p, const float* L, const float* x, float* y
 void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
                       const float* x, float* y, const double* xscale, double sign,
                       hipStream_t st, gemm::TileDots* dots = nullptr);
+// Same with x and y in fp16 and the whole output multiplied by ymul.
+void launch_sigma_b16_h(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
+                        const _Float16* x, _Float16* y, float ymul, const double* xscale,
+                        double sign, hipStream_t st);
 int sigma_dot_slots(const Problem& p, int precision);
 
 // Operator y = A (xs x) in the given precision, using the problem's L buffer;
@@ -151,6 +158,9 @@ int sigma_dot_slots(const Problem& p, int precision);
 void operator_apply(Problem& p, int precision, const void* x, void* y,
                     const double* xscale, hipStream_t st,
                     gemm::TileDots* dots = nullptr);
+// 16-bit operator precisions on an fp16 basis: y = ymul A (xs x).
+void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
+                      const double* xscale, float ymul, hipStream_t st);
 size_t lambda_elem_bytes(int precision);
 const double* physical_rhs(Problem& p, hipStream_t st);
 

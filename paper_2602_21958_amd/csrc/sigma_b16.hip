@@ -26,20 +26,20 @@ namespace {
 
 using namespace g16;
 
-template <int MODE, typename C, int OCC, bool DOTS>
+template <int MODE, typename C, int OCC, bool DOTS, typename TY>
 __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(1, OCC))) void sigma16_kernel(
     const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, int Mp,
     const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo, int64_t Np, int K4p,
-    const float* X, float* Y, const double* __restrict__ albedo, const float* __restrict__ rowscale,
+    const TY* X, TY* Y, const double* __restrict__ albedo, const float* __restrict__ rowscale,
     float colmul, const double* __restrict__ xscale, float sign, int M, int N, int GM,
-    gemm::TileDots dots) {
+    gemm::TileDots dots, float ymul) {
   __shared__ __align__(16) uint8_t lds[C::template lds_bytes<MODE>()];
   const int Mt = Mp / C::BM;
   int tm, tn;
   if (!tile_of(blockIdx.x, Mt, (N + C::BN - 1) / C::BN, GM, tm, tn)) return;
   const float xs = (X != nullptr && xscale != nullptr) ? (float)*xscale : 1.f;
-  tile<MODE, C, DOTS>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs,
-                      sign, M, N, tm * C::BM, tn * C::BN, lds, dots, tn * Mt + tm);
+  tile<MODE, C, DOTS, TY>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs,
+                          sign, M, N, tm * C::BM, tn * C::BN, lds, dots, tn * Mt + tm, ymul);
 }
 
 // Candidate tile shapes (BM x BN, waves, K stage, instruction) and the
@@ -60,8 +60,10 @@ struct Args {
   const uint16_t *bhi, *blo;
   int64_t Np;
   int K4p;
-  const float* x;
-  float* y;
+  const void* x;   // float, or _Float16 when half_xy
+  void* y;
+  bool half_xy;
+  float ymul;
   const double* albedo;
   const float* rowscale;
   float colmul;
@@ -78,16 +80,26 @@ void launch_cfg(const Args& a, hipStream_t st) {
     fail(RT_E_INVALID, "16-bit GEMM: operand padding does not fit the tile");
   const int T = Mt * Nt;
   const int grid = 8 * ((T + 7) / 8);
-  if (a.dots) {
+  const float* xf = static_cast<const float*>(a.x);
+  float* yf = static_cast<float*>(a.y);
+  if (a.half_xy) {
+    if (a.dots) fail(RT_E_INVALID, "fused dots need an FP32 output");
+    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, false, _Float16>), dim3(grid), dim3(C::NT),
+                       0, st, a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p,
+                       static_cast<const _Float16*>(a.x), static_cast<_Float16*>(a.y), a.albedo,
+                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, gemm::TileDots{},
+                       a.ymul);
+  } else if (a.dots) {
     if (a.dots->ldp < T) fail(RT_E_INVALID, "fused dots: too few partial slots");
     a.dots->ldp = T;   // one slot per tile, all written
-    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, true>), dim3(grid), dim3(C::NT), 0, st,
-                       a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, a.x, a.y, a.albedo,
-                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, *a.dots);
+    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, true, float>), dim3(grid), dim3(C::NT), 0,
+                       st, a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, xf, yf, a.albedo,
+                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, *a.dots, a.ymul);
   } else {
-    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, false>), dim3(grid), dim3(C::NT), 0, st,
-                       a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, a.x, a.y, a.albedo,
-                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, gemm::TileDots{});
+    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, false, float>), dim3(grid), dim3(C::NT), 0,
+                       st, a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, xf, yf, a.albedo,
+                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, gemm::TileDots{},
+                       a.ymul);
   }
 }
 
@@ -122,6 +134,12 @@ int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   if (cs != hipStreamCaptureStatusNone) return 2;   // cannot time inside a capture
   Args a = full;
   a.dots = nullptr;
+  if (a.half_xy) {   // time the FP32-output form (same tile body)
+    a.half_xy = false;
+    a.x = nullptr;
+    a.xscale = nullptr;
+    a.ymul = 1.f;
+  }
   const int64_t want = round_up(std::max<int64_t>(4096, (int64_t(1) << 27) / std::max(1, a.M)), 256);
   // the slice keeps the leading dimension N of x: rows of the slice are
   // strided, so time full rows when the slice would not be contiguous
@@ -210,10 +228,14 @@ const char* gemm16_config_name(int cfg) {
   return (cfg >= 0 && cfg < kNumCfg) ? kCfgName[cfg] : "untuned";
 }
 
-void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
-                      const float* x, float* y, const double* xscale, double sign,
-                      hipStream_t st, gemm::TileDots* dots) {
+namespace {
+
+void launch_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
+                const void* x, void* y, bool half_xy, float ymul, const double* xscale,
+                double sign, hipStream_t st, gemm::TileDots* dots) {
   Args a{};
+  a.half_xy = half_xy;
+  a.ymul = ymul;
   int mode;
   switch (precision) {
     case RT_PREC_BF16:
@@ -254,6 +276,20 @@ void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uin
   ProfScope prof(RT_KCLASS_SIGMA, st);
   launch_mode(mode, p.g16_cfg[mode], a, st);
   RT_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_sigma_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
+                      const float* x, float* y, const double* xscale, double sign,
+                      hipStream_t st, gemm::TileDots* dots) {
+  launch_b16(p, precision, l_hi, l_lo, x, y, false, 1.f, xscale, sign, st, dots);
+}
+
+void launch_sigma_b16_h(Problem& p, int precision, const uint16_t* l_hi, const uint16_t* l_lo,
+                        const _Float16* x, _Float16* y, float ymul, const double* xscale,
+                        double sign, hipStream_t st) {
+  launch_b16(p, precision, l_hi, l_lo, x, y, true, ymul, xscale, sign, st, nullptr);
 }
 
 }  // namespace rtsn

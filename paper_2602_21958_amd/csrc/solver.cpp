@@ -7,7 +7,8 @@
 // * Mixed precision: FP64 iterative refinement around a low-precision inner
 //   GMRES: r = b - A_64 x in FP64, inner solve of A_lo d = r / ||r|| with an
 //   FP32 basis (FP64 dot accumulation) and the operator in FP32 / BF16 /
-//   FP16 / split-BF16 arithmetic, then x += ||r|| d.
+//   FP16 / split-BF16 arithmetic, then x += ||r|| d.  Optionally (basis_fp16)
+//   the inner basis is kept in fp16, scaled to entries of order one.
 // * BiCGStab (van der Vorst), FP64, scalars kept on the device.
 #include <algorithm>
 #include <cstdlib>
@@ -35,11 +36,13 @@ Workspace::~Workspace() {
   if (host) hipHostFree(host);
 }
 
-size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab) {
+size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab,
+                       int basis_elem) {
   const size_t n = (size_t)p.n;
+  if (basis_elem <= 0) basis_elem = mixed ? 4 : 8;
   size_t b = sizeof(double) * (size_t)(kMaxRestart + 1) * 2 * kReduceBlocks + sizeof(GmresState) +
              sizeof(BicgState) + 64 * sizeof(double);
-  b += (size_t)(restart + 1) * n * (mixed ? sizeof(float) : sizeof(double));
+  b += (size_t)(restart + 1) * n * basis_elem;
   b += (mixed ? 1 : 2) * n * sizeof(double);  // r64 (+ ax64 for FP64 GMRES)
   if (mixed) b += 2 * n * sizeof(float);
   if (bicgstab) b += 4 * n * sizeof(double);
@@ -72,9 +75,11 @@ bool fuse_dots() {
   return e && e[0] == '1';
 }
 
-Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab) {
+// basis_elem: bytes per basis element (8 FP64, 4 FP32, 2 fp16)
+Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab, int basis_elem) {
   Workspace* ws = p.ws;
-  const bool ok = ws && ws->restart >= restart && ws->mixed == mixed &&
+  const size_t vbytes = (size_t)(restart + 1) * (size_t)p.n * basis_elem;
+  const bool ok = ws && ws->restart >= restart && ws->mixed == mixed && ws->vbytes >= vbytes &&
                   (!bicgstab || ws->bic != nullptr);
   if (ok) return *ws;
   delete p.ws;
@@ -85,10 +90,8 @@ Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab) 
   size_t tot = 0;
   ws->restart = restart;
   ws->mixed = mixed;
-  if (mixed)
-    ws->V = dalloc<float>((size_t)(restart + 1) * n, tot);
-  else
-    ws->V = dalloc<double>((size_t)(restart + 1) * n, tot);
+  ws->V = dalloc<char>(vbytes, tot);
+  ws->vbytes = vbytes;
   // partial sums: reduction kernels use (kMaxRestart + 1) x 2 kReduceBlocks;
   // the dots fused into the Sigma GEMM one slot per output tile and basis
   // vector (the 16-bit GEMM's smallest tile gives the most slots)
@@ -210,6 +213,44 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   return s.beta <= rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
 }
 
+// One GMRES(m) cycle of the refinement's inner solve A_lo d = r / ||r|| with
+// the basis in fp16.  Stored basis vectors are S times the FP32 basis's
+// (S = the power of two >= sqrt(n) that also scales Lambda's fp16 output), so
+// that entries of a unit vector are of order one: the cycle runs Arnoldi on
+// the operator S A with right-hand side S r / ||r||, whose Hessenberg matrix
+// is S times A's and whose least-squares solution y, and hence d = sum y_i
+// v_i, is the unscaled one.  Returns the inner iteration count.
+int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* d, int m,
+                     double itol, int cap, Workspace& ws, hipStream_t st) {
+  const int64_t n = p.n;
+  _Float16* V = static_cast<_Float16*>(ws.V);   // the FP32 basis's memory, half used
+  GmresState* gs = ws.gs;
+  const float S = fp16_lambda_scale(n);
+  k_convert<double, _Float16>(r64, V, n, (double)S / rn, st);
+  RT_HIP(hipMemsetAsync(d, 0, (size_t)n * sizeof(float), st));
+  k_norm_partial<_Float16>(V, n, ws.partial, st);
+  k_finish_norm(ws.partial, n, gs, 1, st);
+  const Status s0 = read_status(ws, st);
+  if (!(s0.beta > 0.0) || !std::isfinite(s0.beta))
+    fail(RT_E_NONFINITE, "fp16 basis: right-hand side out of range");
+  int k = 0;
+  for (int j = 0; j < std::min(m, cap); ++j) {
+    _Float16* w = V + (size_t)(j + 1) * n;
+    operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st);
+    k_mdot<_Float16>(V, n, j + 1, w, ws.partial, st);
+    k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
+    k_update<_Float16>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
+    k_givens(ws.partial, n, gs, j, st);
+    const Status g = read_status(ws, st);
+    k = j + 1;
+    if (g.nonfinite) fail(RT_E_NONFINITE, "non-finite value in the fp16 Arnoldi process");
+    if (g.breakdown || g.resid <= itol * s0.beta) break;
+  }
+  k_solve_r(gs, k, st);
+  k_combine<_Float16, float>(V, n, k, gs->coef, d, st);
+  return k;
+}
+
 rt_status bicgstab_fp64(Problem& p, const double* b, double* x, bool x_zero, double rtol,
                         int max_iters, double bnorm, Workspace& ws, hipStream_t st,
                         std::vector<double>* hist, CoreResult& res) {
@@ -291,7 +332,8 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
   auto t0 = std::chrono::steady_clock::now();
   const bool mixed = o.precision != RT_PREC_FP64;
   const bool bicg = o.krylov == RT_KRYLOV_BICGSTAB;
-  Workspace& ws = ensure_workspace(p, o.restart, mixed, bicg);
+  Workspace& ws = ensure_workspace(p, o.restart, mixed, bicg,
+                                   !mixed ? 8 : (o.basis_fp16 ? 2 : 4));
   const int64_t n = p.n;
   p.history.clear();
   std::vector<double>* hist = o.record_history ? &p.history : nullptr;
@@ -332,15 +374,20 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
     while (rn > o.rtol * bnorm && outer < o.max_outer && total_inner < o.max_iters) {
       outer++;
       float* r32 = ws.t32;
-      k_convert<double, float>(ws.r64, r32, n, 1.0 / rn, st);
+      if (!o.basis_fp16) k_convert<double, float>(ws.r64, r32, n, 1.0 / rn, st);
       double itol = o.inner_rtol;
       const double need = o.rtol * bnorm / rn;
       if (need > itol) itol = need;
-      CoreResult ir;
       const int cap = std::min(o.restart, o.max_iters - total_inner);
-      gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
-                        nullptr, st, nullptr, ir, /*single_cycle=*/true);
-      total_inner += ir.iters;
+      if (o.basis_fp16) {
+        total_inner += inner_cycle_fp16(p, o.precision, ws.r64, rn, ws.d32, o.restart, itol, cap,
+                                        ws, st);
+      } else {
+        CoreResult ir;
+        gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
+                          nullptr, st, nullptr, ir, /*single_cycle=*/true);
+        total_inner += ir.iters;
+      }
       RT_HIP(hipMemcpyAsync(ws.scal + 1, &rn, sizeof(double), hipMemcpyHostToDevice, st));
       k_axpy_f64(x, ws.d32, n, ws.scal + 1, st);
       operator_apply(p, RT_PREC_FP64, x, ws.r64, nullptr, st);

@@ -216,6 +216,50 @@ def test_gmres_fp64_matches_oracle(name):
         assert diff < 1e-5
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16x3", "bf16"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "small_box_ragged"])
+def test_mixed_refinement_fp16_basis(name, prec):
+    """Refinement whose inner GMRES keeps its basis in (scaled) fp16 reaches
+    the same oracle-evaluated FP64 residual as with the FP32 basis."""
+    rt = _rt()
+    spec = (W.small_box(12, 4, 8, 9, seed=5, nz=9, ny=10) if name == "small_box_ragged"
+            else ALL[name]())
+    say(f"mixed {prec} fp16 basis {name}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, precision=prec, max_outer=30, basis_fp16=1)
+        s = host(x)
+        ref = p.solve(torch.empty_like(x), rtol=1e-8, precision=prec, max_outer=30)
+    res = op.residual_norm(s)
+    say(f"   {prec} {name}: converged={st['converged']} outer={st['outer_iters']} "
+        f"inner={st['iters']} (FP32 basis: outer={ref['outer_iters']}) residual={res:.3e}")
+    if ref["converged"]:
+        assert st["converged"], st
+        assert res <= 1.05e-8
+        # the basis rounding (2^-11) must not cost the refinement extra steps
+        # beyond a small margin
+        assert st["outer_iters"] <= ref["outer_iters"] + 2, (st, ref)
+    else:
+        assert prec == "bf16", ref
+
+
+def test_fp16_basis_rejected_outside_16bit_operators():
+    rt = _rt()
+    spec = W.small_box(8, 4, 4, 4, seed=1)
+    with rt.Problem(spec) as p:
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        for prec in ("fp64", "fp32"):
+            with pytest.raises(rt.RtError):
+                p.solve(x, precision=prec, basis_fp16=1)
+        eng = rt.Batch(precision="fp16", hbm_budget=1 << 30, max_slots=4)
+        try:
+            with pytest.raises(rt.RtError):
+                eng.submit(p, x, basis_fp16=1)
+        finally:
+            eng.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_gmres_with_dots_fused_into_sigma(prec, monkeypatch):
     """The opt-in variant that forms the Arnoldi inner products in the Sigma
