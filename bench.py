@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--precision", default=None,
                     help="operator precision for batch512 / serve / box64")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: stream length (s)")
+    ap.add_argument("--basis16", action="store_true",
+                    help="serve: fp16 Krylov bases in the engine (16-bit precisions)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB device-to-device copy before the timed region; its "
@@ -304,8 +306,9 @@ def bench_batch512(args):
     n_tot = sum(p.n for p in probs)
     xs = [torch.empty(p.n, dtype=torch.float64, device="cuda:0") for p in probs]
 
-    def run(precision, profile=False):
-        eng = rt.Batch(precision=precision, hbm_budget=64 << 30, max_slots=512)
+    def run(precision, profile=False, basis_fp16=False):
+        eng = rt.Batch(precision=precision, hbm_budget=64 << 30, max_slots=512,
+                       basis_fp16=basis_fp16)
         tk = [eng.submit(p, x, restart=30, rtol=1e-8, max_iters=4000, max_outer=200)
               for p, x in zip(probs, xs)]
         if profile:
@@ -339,12 +342,18 @@ def bench_batch512(args):
     conv = sum(1 for s in st if s["converged"])
     its = np.array([s["iters"] for s in st])
     variants = {}
-    for v in ("fp64", "fp16", "bf16"):
-        if v == prec:
+    for v, b16 in (("fp64", False), ("fp16", False), ("bf16", False), ("fp16", True),
+                   (prec, True)):
+        if v == prec and not b16:
             continue
-        e2, s2, st2, _ = run(v)
-        variants[v] = {"solves_per_s": 512 / e2, "converged": sum(1 for s in st2 if s["converged"]),
-                       "iters_median": float(np.median([s["iters"] for s in st2])), "steps": s2}
+        label = v + ("/basis16" if b16 else "")
+        if label in variants:
+            continue
+        e2, s2, st2, _ = run(v, basis_fp16=b16)
+        variants[label] = {"solves_per_s": 512 / e2,
+                           "converged": sum(1 for s in st2 if s["converged"]),
+                           "iters_median": float(np.median([s["iters"] for s in st2])),
+                           "steps": s2}
     # per-slab FP64 loop through the single-problem solver on a sample
     sample = list(range(0, 512, 16))
     t0 = time.perf_counter()
@@ -415,7 +424,8 @@ def bench_serve(args):
 
     prec = args.precision or "bf16x3"
     stream = W.serve_stream(duration_s=args.duration, rate_hz=args.rate)
-    eng = rt.Batch(precision=prec, hbm_budget=96 << 30, max_slots=1024)
+    eng = rt.Batch(precision=prec, hbm_budget=96 << 30, max_slots=1024,
+                   basis_fp16=args.basis16)
     ready = pyqueue.Queue()
     t_start = time.perf_counter() + 0.5
 
@@ -475,7 +485,8 @@ def bench_serve(args):
         "config": {"workload": f"serve: Poisson {args.rate}/s for {args.duration}s, 90% slabs "
                                "(batch512 recipe) / 10% 16^3 boxes (4 mu x 8 az, 24 freq); "
                                f"{prec} Sigma + FP32 Lambda + FP64 refinement; admission by "
-                               "HBM footprint (96 GiB arena)"},
+                               "HBM footprint (96 GiB arena)",
+                   "krylov_basis": "fp16" if args.basis16 else "fp32"},
         "requests": n_req, "converged": int(len(ok)),
         "latency_ms": {"p50": float(np.percentile(ok, 50)), "p99": float(np.percentile(ok, 99)),
                        "slab_p50": float(np.nanpercentile(lat["slab"], 50)) if lat["slab"] else None,

@@ -200,9 +200,11 @@ typedef struct {
   int record_history;     /* keep the per-iteration residual estimates              */
   int basis_fp16;         /* mixed with a 16-bit operator precision (RT_PREC_BF16,
                              RT_PREC_FP16, RT_PREC_BF16X3): keep the inner Krylov
-                             basis in fp16, scaled by a power of two near
-                             sqrt(n_unknowns), which halves the bytes of every
-                             Arnoldi pass (default 0: FP32 basis).  RT_E_INVALID
+                             basis in fp16, stored times 2^11, which halves the
+                             bytes of every Arnoldi pass (default 0: FP32
+                             basis).  An inner cycle then gains at most about
+                             kappa(A) 2^-11: on ill-conditioned problems the
+                             refinement takes more outer steps.  RT_E_INVALID
                              with any other precision.                           */
 } rt_solver_opts;
 
@@ -251,13 +253,26 @@ rt_status rt_batch_create(int device, int precision, int64_t hbm_budget,
                           int max_slots, int queue_cap, int use_graph,
                           rt_batch* out);
 
+/* Flags of rt_batch_create_ex.  RT_BATCH_BASIS_FP16: the inner Krylov bases
+ * are fp16, scaled like rt_solver_opts.basis_fp16 (16-bit operator
+ * precisions only); every submitted request must then set basis_fp16.      */
+enum { RT_BATCH_BASIS_FP16 = 1 };
+
+/* rt_batch_create with flags (0 or RT_BATCH_BASIS_FP16).  Errors as
+ * rt_batch_create; RT_E_INVALID for unknown flags or an fp16 basis with a
+ * precision other than RT_PREC_BF16, RT_PREC_FP16, RT_PREC_BF16X3.         */
+rt_status rt_batch_create_ex(int device, int precision, int64_t hbm_budget,
+                             int max_slots, int queue_cap, int use_graph,
+                             int flags, rt_batch* out);
+
 /* Submit a solve of problem p (which must stay alive until completion) for
  * its physical right-hand side.  opts->precision must equal the engine's;
  * GMRES only.  x_out: device FP64 n_unknowns of p, caller-owned; the engine
  * iterates in it from admission on and it holds the solution at completion.
  * Non-blocking; *ticket identifies the request.  RT_E_BUSY if the queue is
  * full; RT_E_INVALID if the problem can never fit the budget or if
- * opts->basis_fp16 is set (the engine keeps FP32 / FP64 bases).             */
+ * opts->basis_fp16 differs from the engine's basis (set iff it was created
+ * with RT_BATCH_BASIS_FP16).                                                */
 rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts,
                           double* x_out, uint64_t* ticket);
 

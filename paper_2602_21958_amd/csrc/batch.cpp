@@ -118,6 +118,7 @@ struct Engine {
   std::string tune_name = "untuned";
   int precision = RT_PREC_FP64;
   bool fp64 = true;
+  bool basis16 = false;       // fp16 Krylov bases (16-bit operator precisions)
   bool use_graph = true;
   int max_slots = 0;
   int queue_cap = 0;
@@ -201,7 +202,7 @@ Engine::~Engine() {
 
 size_t Engine::footprint(const Problem& p, int restart) const {
   const size_t n = (size_t)p.n;
-  const size_t tv = fp64 ? sizeof(double) : sizeof(float);
+  const size_t tv = fp64 ? sizeof(double) : (basis16 ? 2 : sizeof(float));
   size_t b = 0;
   b += align_up((size_t)(restart + 1) * n * tv);              // basis
   b += align_up(n * sizeof(double));                          // L scratch
@@ -221,7 +222,7 @@ bool Engine::setup_slot(Request* r, int s) {
   r->off = off;
   char* q = base + off;
   const size_t n = (size_t)p.n;
-  const size_t tv = fp64 ? sizeof(double) : sizeof(float);
+  const size_t tv = fp64 ? sizeof(double) : (basis16 ? 2 : sizeof(float));
   SlotDev d{};
   d.geom = p.geom;
   d.nx = p.nx;
@@ -265,6 +266,7 @@ bool Engine::setup_slot(Request* r, int s) {
   d.gs = reinterpret_cast<GmresState*>(q);
   d.x = r->x_out;
   d.l_scale = precision == RT_PREC_FP16 ? fp16_lambda_scale(p.n) : 1.f;
+  d.vs = basis16 ? fp16_basis_scale(p.n) : 1.f;
   h_slots[s] = d;
   RT_HIP(hipMemcpyAsync(d_slots + s, &h_slots[s], sizeof(SlotDev), hipMemcpyHostToDevice, stream));
   // right-hand side b = (1-eps) Mhat I_bc + t into the slot, x = 0
@@ -407,7 +409,7 @@ void Engine::tune_gemm16() {
       return;
     }
   }
-  b_lambda16(d_slots, d_stat, wl_iter, precision, stream);
+  b_lambda16(d_slots, d_stat, wl_iter, precision, stream, basis16);
   hipEvent_t e0, e1;
   RT_HIP(hipEventCreate(&e0));
   RT_HIP(hipEventCreate(&e1));
@@ -415,11 +417,11 @@ void Engine::tune_gemm16() {
   for (int c = 0; c < 1; ++c) {
     for (int g : {512, 1024, 2048}) {
       const BatchTune t{c, g};
-      b_time_gemm16(d_slots, d_stat, wl_iter, precision, stream, t);
+      b_time_gemm16(d_slots, d_stat, wl_iter, precision, stream, t, basis16);
       float ms = 1e30f;
       for (int rep = 0; rep < 2; ++rep) {
         RT_HIP(hipEventRecord(e0, stream));
-        b_time_gemm16(d_slots, d_stat, wl_iter, precision, stream, t);
+        b_time_gemm16(d_slots, d_stat, wl_iter, precision, stream, t, basis16);
         RT_HIP(hipEventRecord(e1, stream));
         RT_HIP(hipEventSynchronize(e1));
         float v = 0.f;
@@ -451,6 +453,8 @@ void Engine::run_inner() {
   auto direct = [&] {
     if (fp64)
       b_inner_iteration<double>(d_slots, d_stat, wl_iter, precision, stream);
+    else if (basis16)
+      b_inner_iteration<_Float16>(d_slots, d_stat, wl_iter, precision, stream, tune);
     else
       b_inner_iteration<float>(d_slots, d_stat, wl_iter, precision, stream, tune);
   };
@@ -530,6 +534,8 @@ int Engine::step() {
     build_lists(wl_end, end_set);
     if (fp64)
       b_cycle_end<double>(d_slots, d_stat, wl_end, stream);
+    else if (basis16)
+      b_cycle_end<_Float16>(d_slots, d_stat, wl_end, stream);
     else
       b_cycle_end<float>(d_slots, d_stat, wl_end, stream);
     RT_HIP(hipMemcpyAsync(h_stat, d_stat, (size_t)max_slots * sizeof(SlotStat),
@@ -573,6 +579,8 @@ int Engine::step() {
       build_lists(wl_end, start);
       if (fp64)
         b_start_cycle<double>(d_slots, d_stat, wl_end, stream);
+      else if (basis16)
+        b_start_cycle<_Float16>(d_slots, d_stat, wl_end, stream);
       else
         b_start_cycle<float>(d_slots, d_stat, wl_end, stream);
       for (int s : start) phase[s] = kIter;
@@ -621,11 +629,22 @@ extern "C" {
 
 rt_status rt_batch_create(int device, int precision, int64_t hbm_budget, int max_slots,
                           int queue_cap, int use_graph, rt_batch* out) {
+  return rt_batch_create_ex(device, precision, hbm_budget, max_slots, queue_cap, use_graph, 0,
+                            out);
+}
+
+rt_status rt_batch_create_ex(int device, int precision, int64_t hbm_budget, int max_slots,
+                             int queue_cap, int use_graph, int flags, rt_batch* out) {
   if (out) *out = nullptr;
   return guarded_b([&] {
     if (!out) fail(RT_E_INVALID, "null out");
     if (precision < RT_PREC_FP64 || precision > RT_PREC_BF16X3)
       fail(RT_E_INVALID, "unknown precision");
+    if (flags & ~RT_BATCH_BASIS_FP16) fail(RT_E_INVALID, "unknown flags");
+    const bool basis16 = (flags & RT_BATCH_BASIS_FP16) != 0;
+    if (basis16 && precision != RT_PREC_BF16 && precision != RT_PREC_FP16 &&
+        precision != RT_PREC_BF16X3)
+      fail(RT_E_INVALID, "an fp16 basis needs a 16-bit operator precision");
     if (max_slots < 1 || max_slots > 4096) fail(RT_E_INVALID, "max_slots out of range");
     if (queue_cap < 1) fail(RT_E_INVALID, "queue_cap must be >= 1");
     if (hbm_budget < (int64_t)(1 << 20)) fail(RT_E_INVALID, "hbm_budget too small");
@@ -638,6 +657,7 @@ rt_status rt_batch_create(int device, int precision, int64_t hbm_budget, int max
       e->device = device;
       e->precision = precision;
       e->fp64 = precision == RT_PREC_FP64;
+      e->basis16 = basis16;
       e->use_graph = use_graph != 0;
       e->max_slots = max_slots;
       e->queue_cap = queue_cap;
@@ -679,7 +699,8 @@ rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts, 
     if (o.precision != e->precision) fail(RT_E_INVALID, "precision differs from the engine's");
     if (o.restart < 1 || o.restart > kMaxRestart) fail(RT_E_INVALID, "restart out of range");
     if (!(o.rtol > 0)) fail(RT_E_INVALID, "rtol must be > 0");
-    if (o.basis_fp16) fail(RT_E_INVALID, "the batch engine keeps FP32 / FP64 bases");
+    if ((o.basis_fp16 != 0) != e->basis16)
+      fail(RT_E_INVALID, "basis_fp16 differs from the engine's basis");
     if (o.max_outer < 1) o.max_outer = 1;
     std::lock_guard<std::mutex> lk(e->mu);
     if (e->footprint(*q, o.restart) > e->arena.size())

@@ -35,7 +35,8 @@ struct SlotDev {
   const BoxStencil* stencil;
   const double* ray_mu;
   const double* ray_fac;
-  void* V;                      // (restart + 1) * n basis vectors (TV)
+  void* V;                      // (restart + 1) * n basis vectors (TV; fp16 ones stored
+                                // times vs)
   void* L;                      // n doubles of scratch (Lambda output, any type)
   double* x;                    // FP64 iterate (caller's output buffer)
   double* b;                    // FP64 right-hand side
@@ -43,7 +44,8 @@ struct SlotDev {
   double* partial;              // (kMaxRestart + 1) * nch partial sums
   GmresState* gs;
   float l_scale;                // fp16 Lambda output scale
-  int pad1;
+  float vs;                     // basis scale: fp16_basis_scale for an fp16 basis,
+                                // 1 otherwise
 };
 
 // Mutable per-slot scalars, written by the kernels (and by the host when a
@@ -91,7 +93,8 @@ struct BatchTune {
 constexpr int kBatchGemm16Cfgs = 2;
 const char* batch_gemm16_name(int cfg);
 
-// Launchers (inner: vectors TV, operator precision prec)
+// Launchers (inner: vectors TV = double, float or _Float16, operator
+// precision prec)
 // One Arnoldi step of every slot in the lists (operator in precision prec).
 template <typename TV>
 void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
@@ -100,9 +103,9 @@ void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl
 // the given shape (the same work as the first half of an inner iteration;
 // used to time the shapes).
 void b_time_gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
-                   hipStream_t st, const BatchTune& tune);
+                   hipStream_t st, const BatchTune& tune, bool half_basis);
 void b_lambda16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
-                hipStream_t st);
+                hipStream_t st, bool half_basis);
 // x += rn V y, then r = b - A_64 x and rn = ||r|| for every listed slot.
 template <typename TV>
 void b_cycle_end(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st);

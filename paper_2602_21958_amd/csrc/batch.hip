@@ -55,6 +55,7 @@ __device__ __forceinline__ void block_sum_store(double (&acc)[G], double* out, i
 template <typename TV> struct ComputeOf;
 template <> struct ComputeOf<double> { using type = double; };
 template <> struct ComputeOf<float> { using type = float; };
+template <> struct ComputeOf<_Float16> { using type = float; };
 
 // ------------------------------------------------------------------ Lambda
 // OUTER: x (FP64) -> L (FP64), no input scale.  Otherwise V_j (scaled by
@@ -187,7 +188,9 @@ __global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
 using BatchCfg16a = g16::Cfg<128, 128, 2, 2, 32, true>;
 using BatchCfg16b = g16::Cfg<128, 128, 2, 2, 64, false>;
 
-template <int MODE, typename C>
+// TY: basis element type (float, or _Float16 stored times the slot's basis
+// scale vs, which multiplies the whole output).
+template <int MODE, typename C, typename TY>
 __global__ __launch_bounds__(C::NT) void bk_gemm16(const SlotDev* __restrict__ slots,
                                                    const SlotStat* __restrict__ stat,
                                                    const Item* __restrict__ items,
@@ -198,13 +201,14 @@ __global__ __launch_bounds__(C::NT) void bk_gemm16(const SlotDev* __restrict__ s
     const Item w = items[it];
     const SlotDev& s = slots[w.slot];
     const int j = stat[w.slot].j;
-    const float* X = static_cast<const float*>(s.V) + (size_t)j * s.n;
-    float* Y = static_cast<float*>(s.V) + (size_t)(j + 1) * s.n;
+    const TY* X = static_cast<const TY*>(s.V) + (size_t)j * s.n;
+    TY* Y = static_cast<TY*>(s.V) + (size_t)(j + 1) * s.n;
     const uint16_t* ahi = MODE == g16::MODE_FP16 ? s.a8_f16 : s.a8_hi;
     const uint16_t* blo = MODE == g16::MODE_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr;
-    g16::tile<MODE, C>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X, Y, s.albedo,
-                       MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr, 1.f / s.l_scale,
-                       (float)s.gs->vscale[j], -1.f, s.n_r, (int)s.n_s, w.a, w.b, lds);
+    g16::tile<MODE, C, false, TY>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X,
+                                  Y, s.albedo, MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr,
+                                  1.f / s.l_scale, (float)s.gs->vscale[j], -1.f, s.n_r,
+                                  (int)s.n_s, w.a, w.b, lds, gemm::TileDots{}, 0, s.vs);
   }
 }
 
@@ -220,13 +224,27 @@ template <> struct BVec<double> {
   typedef double T __attribute__((ext_vector_type(2)));
   static constexpr int n = 2;
 };
+template <> struct BVec<_Float16> {
+  typedef _Float16 T __attribute__((ext_vector_type(8)));
+  static constexpr int n = 8;
+};
+// arithmetic of the update: FP64 for FP64 / FP32 bases, FP32 for fp16
+template <typename TV> struct BAcc { using type = double; };
+template <> struct BAcc<_Float16> { using type = float; };
 
 template <typename TV>
 __device__ __forceinline__ double vdot(typename BVec<TV>::T a, typename BVec<TV>::T b) {
-  double s = 0.0;
+  if constexpr (sizeof(TV) == 2) {   // products of halves are exact in FP32
+    float s = 0.f;
 #pragma unroll
-  for (int q = 0; q < BVec<TV>::n; ++q) s += (double)a[q] * (double)b[q];
-  return s;
+    for (int q = 0; q < BVec<TV>::n; ++q) s += (float)a[q] * (float)b[q];
+    return (double)s;
+  } else {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < BVec<TV>::n; ++q) s += (double)a[q] * (double)b[q];
+    return s;
+  }
 }
 
 // Dots of the slot's basis with w over one kChunk-element chunk.
@@ -298,7 +316,8 @@ __global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slot
                                                 const SlotStat* __restrict__ stat,
                                                 const Item* __restrict__ items,
                                                 const int* __restrict__ counts) {
-  __shared__ double coef[kMaxRestart + 1];
+  using AT = typename BAcc<TV>::type;
+  __shared__ AT coef[kMaxRestart + 1];
   const int cnt = counts[3];
   using VT = typename BVec<TV>::T;
   constexpr int W = BVec<TV>::n;
@@ -307,7 +326,7 @@ __global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slot
     const SlotDev& s = slots[w.slot];
     const int j = stat[w.slot].j;
     __syncthreads();   // coef of the previous item is no longer read
-    for (int i = threadIdx.x; i <= j; i += TB) coef[i] = s.gs->h[i] * s.gs->vscale[i];
+    for (int i = threadIdx.x; i <= j; i += TB) coef[i] = (AT)(s.gs->h[i] * s.gs->vscale[i]);
     __syncthreads();
     TV* V = static_cast<TV*>(s.V);
     TV* wv = V + (size_t)(j + 1) * s.n;
@@ -318,13 +337,13 @@ __global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slot
       VT* wq = reinterpret_cast<VT*>(wv);
       for (int64_t e = e0 / W + threadIdx.x; e < e1 / W; e += TB) {
         const VT x = wq[e];
-        double v[W];
+        AT v[W];
 #pragma unroll
-        for (int q = 0; q < W; ++q) v[q] = (double)x[q];
+        for (int q = 0; q < W; ++q) v[q] = (AT)x[q];
         for (int i = 0; i <= j; ++i) {
           const VT b = reinterpret_cast<const VT*>(V + (size_t)i * s.n)[e];
 #pragma unroll
-          for (int q = 0; q < W; ++q) v[q] -= coef[i] * (double)b[q];
+          for (int q = 0; q < W; ++q) v[q] -= coef[i] * (AT)b[q];
         }
         VT r;
 #pragma unroll
@@ -336,8 +355,8 @@ __global__ __launch_bounds__(TB) void bk_update(const SlotDev* __restrict__ slot
       }
     } else {
       for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
-        double v = (double)wv[e];
-        for (int i = 0; i <= j; ++i) v -= coef[i] * (double)V[(size_t)i * s.n + e];
+        AT v = (AT)wv[e];
+        for (int i = 0; i <= j; ++i) v -= coef[i] * (AT)V[(size_t)i * s.n + e];
         const TV q = (TV)v;
         wv[e] = q;
         nrm += (double)q * (double)q;
@@ -394,7 +413,9 @@ __global__ __launch_bounds__(64) void bk_givens(const SlotDev* __restrict__ slot
       z.nonfinite = !isfinite(hn) || !isfinite(resid);
       z.j = j + 1;
       z.iters += 1;
-      z.cycle_done = (j + 1 >= s.restart) || resid <= z.target || breakdown || z.nonfinite;
+      // resid is relative to g_0 = vs (the basis scale; 1 unless fp16)
+      z.cycle_done = (j + 1 >= s.restart) || resid <= z.target * (double)s.vs || breakdown ||
+                     z.nonfinite;
     }
   }
 }
@@ -495,7 +516,7 @@ __global__ __launch_bounds__(TB) void bk_v0(const SlotDev* __restrict__ slots,
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
     const SlotDev& s = slots[w.slot];
-    const double inv = 1.0 / stat[w.slot].rn;
+    const double inv = (double)s.vs / stat[w.slot].rn;
     TV* V = static_cast<TV*>(s.V);
     const int64_t e0 = (int64_t)w.a * kChunk;
     const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
@@ -508,9 +529,11 @@ __global__ __launch_bounds__(64) void bk_init_cycle(const SlotDev* __restrict__ 
                                                     const int* __restrict__ counts) {
   const int cnt = counts[4];
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
-    GmresState* gs = slots[list[it]].gs;
-    for (int i = threadIdx.x; i <= kMaxRestart; i += 64) gs->g[i] = i == 0 ? 1.0 : 0.0;
-    if (threadIdx.x == 0) gs->vscale[0] = 1.0;
+    const SlotDev& s = slots[list[it]];
+    GmresState* gs = s.gs;
+    // V_0 = vs r / ||r||: g_0 = vs and unit v_0 = V_0 / vs
+    for (int i = threadIdx.x; i <= kMaxRestart; i += 64) gs->g[i] = i == 0 ? (double)s.vs : 0.0;
+    if (threadIdx.x == 0) gs->vscale[0] = 1.0 / (double)s.vs;
   }
 }
 
@@ -526,16 +549,16 @@ void persist_grid(K kernel, int grid, int threads, size_t lds, hipStream_t st, A
   RT_HIP(hipGetLastError());
 }
 
-template <int MODE>
+template <int MODE, typename TY>
 void launch_b_gemm16(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
                      const BatchTune& tune, hipStream_t st) {
   ProfScope prof(RT_KCLASS_SIGMA, st);
   if (tune.cfg == 1)
-    persist_grid(bk_gemm16<MODE, BatchCfg16b>, tune.grid, BatchCfg16b::NT, 0, st, slots, stat,
-                 wl.tiles, wl.counts);
+    persist_grid(bk_gemm16<MODE, BatchCfg16b, TY>, tune.grid, BatchCfg16b::NT, 0, st, slots,
+                 stat, wl.tiles, wl.counts);
   else
-    persist_grid(bk_gemm16<MODE, BatchCfg16a>, tune.grid, BatchCfg16a::NT, 0, st, slots, stat,
-                 wl.tiles, wl.counts);
+    persist_grid(bk_gemm16<MODE, BatchCfg16a, TY>, tune.grid, BatchCfg16a::NT, 0, st, slots,
+                 stat, wl.tiles, wl.counts);
 }
 
 template <typename VT, typename LT, typename C, int K4, bool OUTER>
@@ -568,31 +591,45 @@ const char* batch_gemm16_name(int cfg) {
   return cfg == 1 ? "128x128 16x16x32 K64" : "128x128 32x32x16 K32";
 }
 
-void b_lambda16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
-                hipStream_t st) {
+template <typename TV>
+void lambda16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+              hipStream_t st) {
   switch (prec) {
     case RT_PREC_BF16:
-      launch_b_lambda<float, float, float, lam::K4_BF16, false>(slots, stat, wl, st);
+      launch_b_lambda<TV, float, float, lam::K4_BF16, false>(slots, stat, wl, st);
       break;
     case RT_PREC_FP16:
-      launch_b_lambda<float, float, float, lam::K4_FP16, false>(slots, stat, wl, st);
+      launch_b_lambda<TV, float, float, lam::K4_FP16, false>(slots, stat, wl, st);
       break;
     case RT_PREC_BF16X3:
-      launch_b_lambda<float, float, float, lam::K4_SPLIT, false>(slots, stat, wl, st);
+      launch_b_lambda<TV, float, float, lam::K4_SPLIT, false>(slots, stat, wl, st);
       break;
     default:
       fail(RT_E_INVALID, "b_lambda16: not a 16-bit precision");
   }
 }
 
-void b_time_gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
-                   hipStream_t st, const BatchTune& tune) {
+template <typename TV>
+void gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec, hipStream_t st,
+            const BatchTune& tune) {
   switch (prec) {
-    case RT_PREC_BF16: launch_b_gemm16<g16::MODE_BF16>(slots, stat, wl, tune, st); break;
-    case RT_PREC_FP16: launch_b_gemm16<g16::MODE_FP16>(slots, stat, wl, tune, st); break;
-    case RT_PREC_BF16X3: launch_b_gemm16<g16::MODE_SPLIT>(slots, stat, wl, tune, st); break;
+    case RT_PREC_BF16: launch_b_gemm16<g16::MODE_BF16, TV>(slots, stat, wl, tune, st); break;
+    case RT_PREC_FP16: launch_b_gemm16<g16::MODE_FP16, TV>(slots, stat, wl, tune, st); break;
+    case RT_PREC_BF16X3: launch_b_gemm16<g16::MODE_SPLIT, TV>(slots, stat, wl, tune, st); break;
     default: fail(RT_E_INVALID, "b_time_gemm16: not a 16-bit precision");
   }
+}
+
+void b_lambda16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                hipStream_t st, bool half_basis) {
+  if (half_basis) lambda16<_Float16>(slots, stat, wl, prec, st);
+  else lambda16<float>(slots, stat, wl, prec, st);
+}
+
+void b_time_gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
+                   hipStream_t st, const BatchTune& tune, bool half_basis) {
+  if (half_basis) gemm16<_Float16>(slots, stat, wl, prec, st, tune);
+  else gemm16<float>(slots, stat, wl, prec, st, tune);
 }
 
 template <typename TV>
@@ -607,6 +644,7 @@ void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl
   } else {
     switch (prec) {
       case RT_PREC_FP32: {
+        if constexpr (sizeof(TV) == 2) fail(RT_E_INVALID, "an fp16 basis needs a 16-bit operator");
         launch_b_lambda<float, float, C, -1, false>(slots, stat, wl, st);
         ProfScope prof(RT_KCLASS_SIGMA, st);
         persist(bk_gemm<float, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
@@ -615,8 +653,8 @@ void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl
       case RT_PREC_BF16:
       case RT_PREC_FP16:
       case RT_PREC_BF16X3:
-        b_lambda16(slots, stat, wl, prec, st);
-        b_time_gemm16(slots, stat, wl, prec, st, tune);
+        lambda16<TV>(slots, stat, wl, prec, st);
+        gemm16<TV>(slots, stat, wl, prec, st, tune);
         break;
       default:
         fail(RT_E_INVALID, "unknown precision");
@@ -658,5 +696,9 @@ template void b_cycle_end<double>(const SlotDev*, SlotStat*, const WorkLists&, h
 template void b_cycle_end<float>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
 template void b_start_cycle<double>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
 template void b_start_cycle<float>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
+template void b_inner_iteration<_Float16>(const SlotDev*, SlotStat*, const WorkLists&, int,
+                                          hipStream_t, const BatchTune&);
+template void b_cycle_end<_Float16>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
+template void b_start_cycle<_Float16>(const SlotDev*, SlotStat*, const WorkLists&, hipStream_t);
 
 }  // namespace rtsn

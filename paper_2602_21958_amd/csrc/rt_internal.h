@@ -120,6 +120,8 @@ void launch_lambda_k4(const Problem& p, int precision, const float* s, uint16_t*
 void launch_lambda_k4(const Problem& p, int precision, const _Float16* s, uint16_t* hi,
                       uint16_t* lo, const double* scale, hipStream_t st);
 float fp16_lambda_scale(int64_t n);
+// Power-of-two scale of an fp16 Krylov basis of vectors of n entries.
+float fp16_basis_scale(int64_t n);
 // Frequencies swept together by one box workgroup for planes of P points.
 int box_chunk(int P, int elem_bytes, int max_lds);
 // Size in elements of one part of the k4 operand; allocation of the

@@ -14,6 +14,7 @@
 // changes the speed only: every candidate accumulates each output in the same
 // k order up to the MFMA's internal order).  RTSN_GEMM16_CFG=<index> forces a
 // candidate.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 
@@ -217,12 +218,23 @@ void convert_to_k4(const Problem& p, int precision, const float* L, uint16_t* hi
   RT_HIP(hipGetLastError());
 }
 
-// Power-of-two scale applied to Lambda's fp16 output (keeps unit-norm Krylov
-// vectors of n entries near 1 in magnitude).
+// Power-of-two scale applied to Lambda's fp16 output: about sqrt(n), which
+// brings the entries of Lambda of a unit-norm vector of n entries near 1,
+// capped at 2^14.  The cap keeps every entry finite: Lambda's weights are
+// non-negative and sum to at most 1 along a ray, so |Lambda v| <= max |v| <= 1
+// and the scaled output stays below 2^14, a quarter of fp16's largest value.
 float fp16_lambda_scale(int64_t n) {
   const double e = std::ceil(0.5 * std::log2((double)(n > 1 ? n : 1)));
-  return (float)std::ldexp(1.0, (int)e);
+  return (float)std::ldexp(1.0, std::min((int)e, 14));
 }
+
+// Scale of an fp16 Krylov basis (stored vectors are 2^11 times the unit-norm
+// ones).  With non-negative scattering and transfer weights, |A|_inf <= 2, so
+// an operator output for a unit vector has entries of at most 2, and the
+// Gram-Schmidt update adds at most sum_i |h_i| <= 2 sqrt(m + 1): below 25 for
+// any restart m <= 128, so stored entries stay under 2^11 * 25 < 65504.  The
+// smallest normal fp16 value then stands for 3e-8 of a unit vector.
+float fp16_basis_scale(int64_t) { return 2048.f; }
 
 const char* gemm16_config_name(int cfg) {
   return (cfg >= 0 && cfg < kNumCfg) ? kCfgName[cfg] : "untuned";

@@ -215,17 +215,17 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
 
 // One GMRES(m) cycle of the refinement's inner solve A_lo d = r / ||r|| with
 // the basis in fp16.  Stored basis vectors are S times the FP32 basis's
-// (S = the power of two >= sqrt(n) that also scales Lambda's fp16 output), so
-// that entries of a unit vector are of order one: the cycle runs Arnoldi on
-// the operator S A with right-hand side S r / ||r||, whose Hessenberg matrix
-// is S times A's and whose least-squares solution y, and hence d = sum y_i
-// v_i, is the unscaled one.  Returns the inner iteration count.
+// (S = fp16_basis_scale: entries of a unit vector would mostly be fp16
+// subnormals otherwise): the cycle runs Arnoldi on the operator S A with
+// right-hand side S r / ||r||, whose Hessenberg matrix is S times A's and
+// whose least-squares solution y, and hence d = sum y_i v_i, is the unscaled
+// one.  Returns the inner iteration count.
 int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* d, int m,
                      double itol, int cap, Workspace& ws, hipStream_t st) {
   const int64_t n = p.n;
   _Float16* V = static_cast<_Float16*>(ws.V);   // the FP32 basis's memory, half used
   GmresState* gs = ws.gs;
-  const float S = fp16_lambda_scale(n);
+  const float S = fp16_basis_scale(n);
   k_convert<double, _Float16>(r64, V, n, (double)S / rn, st);
   RT_HIP(hipMemsetAsync(d, 0, (size_t)n * sizeof(float), st));
   k_norm_partial<_Float16>(V, n, ws.partial, st);

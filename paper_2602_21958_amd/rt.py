@@ -30,6 +30,7 @@ GEOM = {"slab": 0, "box": 1}
 KERNEL = {"dipole_prd": 0, "explicit": 1}
 FORMAL = {"linear_sc": 0, "implicit_euler": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
+RT_BATCH_BASIS_FP16 = 1
 KRYLOV = {"gmres": 0, "bicgstab": 1}
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_NOT_CONVERGED", -1: "RT_E_INVALID", -2: "RT_E_NOMEM",
@@ -88,6 +89,8 @@ _sig = {
                            C.POINTER(SolveStats), _vp]),
     "rt_batch_create": (C.c_int, [C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
                                   C.POINTER(_vp)]),
+    "rt_batch_create_ex": (C.c_int, [C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                     C.c_int, C.POINTER(_vp)]),
     "rt_batch_info": (C.c_int, [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 C.POINTER(C.c_int64)]),
     "rt_batch_footprint": (C.c_int, [_vp, _vp, C.c_int, C.POINTER(C.c_int64)]),
@@ -303,17 +306,20 @@ class Batch:
 
     def __init__(self, precision: str = "fp64", hbm_budget: int = 8 << 30,
                  max_slots: int = 512, queue_cap: int = 100000, use_graph: bool = True,
-                 device: int = 0):
+                 device: int = 0, basis_fp16: bool = False):
         h = _vp()
-        _check(_lib.rt_batch_create(int(device), PREC[precision], int(hbm_budget),
-                                    int(max_slots), int(queue_cap), int(bool(use_graph)),
-                                    C.byref(h)), "rt_batch_create")
+        _check(_lib.rt_batch_create_ex(int(device), PREC[precision], int(hbm_budget),
+                                       int(max_slots), int(queue_cap), int(bool(use_graph)),
+                                       RT_BATCH_BASIS_FP16 if basis_fp16 else 0, C.byref(h)),
+               "rt_batch_create_ex")
         self.handle = h
         self.precision = precision
+        self.basis_fp16 = bool(basis_fp16)
 
     def submit(self, problem: "Problem", x_out, **opts) -> int:
         o = default_opts()
         o.precision = PREC[self.precision]
+        o.basis_fp16 = int(self.basis_fp16)
         for k, v in opts.items():
             if k == "precision":
                 v = PREC[v] if isinstance(v, str) else v

@@ -49,13 +49,13 @@ def small_slabs(count, seed):
 
 
 def run_engine(specs, precision="fp64", order=None, graph=True, budget=1 << 30, max_slots=64,
-               late=None, restart=30):
+               late=None, restart=30, basis_fp16=False):
     """Solve all specs in one engine; returns (solutions, stats)."""
     rt = _rt()
     probs = [rt.Problem(s) for s in specs]
     xs = [torch.empty(p.n, dtype=torch.float64, device="cuda:0") for p in probs]
     eng = rt.Batch(precision=precision, hbm_budget=budget, max_slots=max_slots,
-                   use_graph=graph)
+                   use_graph=graph, basis_fp16=basis_fp16)
     order = list(range(len(specs))) if order is None else order
     late = late or {}
     tickets = {}
@@ -159,6 +159,59 @@ def test_batch_mixed_precision_reaches_fp64_residual(precision):
             # plain bf16 (8-bit significand) can be too coarse for the
             # conditioning of a slab: reported as not converged, never hidden
             assert precision == "bf16", st
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16x3"])
+def test_batch_fp16_basis_reaches_fp64_residual(precision):
+    """Engine with fp16 Krylov bases (stored times 2^11, like the
+    single-problem option).  Every solve reaches the oracle-evaluated 1e-8
+    FP64 residual.  On the slab64 and box problems the basis rounding (2^-11)
+    is far below what one inner cycle reaches and the refinement takes at
+    most two more outer steps than with FP32 bases; on the small batch-style
+    slabs (kappa(A) up to ~1e3) an inner cycle only gains about
+    kappa * 2^-11 and the refinement needs more steps, but still converges."""
+    good = [W.slab64(), W.small_box(8, 4, 8, 5), W.small_box(12, 4, 8, 9, seed=5, nz=9, ny=10)]
+    hard = small_slabs(4, 5)
+    specs = good + hard
+    say(f"batch fp16 basis {precision}")
+    sols, stats, _ = run_engine(specs, precision=precision, basis_fp16=True)
+    _, ref_stats, _ = run_engine(specs, precision=precision)
+    for i, (spec, s, st, rs) in enumerate(zip(specs, sols, stats, ref_stats)):
+        res = OProblem(spec).residual_norm(s)
+        say(f"   {i}: conv={st['converged']} iters={st['iters']} outer={st['outer_iters']} "
+            f"(FP32 basis: iters={rs['iters']} outer={rs['outer_iters']}) "
+            f"oracle residual={res:.2e}")
+        assert st["converged"], st
+        assert res <= 1.05e-8
+        if i < len(good):
+            assert st["outer_iters"] <= rs["outer_iters"] + 2, (st, rs)
+
+
+def test_batch_fp16_basis_alone_equals_in_mix_bitwise():
+    specs = small_slabs(6, 2) + [W.small_box(8, 4, 8, 5)]
+    say("alone vs mix fp16 basis")
+    mix, mstats, _ = run_engine(specs, precision="fp16", order=[6, 3, 0, 5, 1, 4, 2],
+                                basis_fp16=True)
+    for i in (0, 6):
+        alone, astats, _ = run_engine([specs[i]], precision="fp16", basis_fp16=True)
+        assert astats[0]["converged"] and mstats[i]["converged"]
+        assert astats[0]["iters"] == mstats[i]["iters"]
+        assert np.array_equal(alone[0], mix[i]), i
+
+
+def test_batch_fp16_basis_rejections():
+    rt = _rt()
+    for prec in ("fp64", "fp32"):
+        with pytest.raises(rt.RtError):
+            rt.Batch(precision=prec, hbm_budget=1 << 24, basis_fp16=True)
+    eng = rt.Batch(precision="fp16", hbm_budget=1 << 24, max_slots=2, basis_fp16=True)
+    try:
+        with rt.Problem(small_slabs(1, 9)[0]) as p:
+            x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+            with pytest.raises(rt.RtError):
+                eng.submit(p, x, basis_fp16=0)   # differs from the engine's basis
+    finally:
+        eng.close()
 
 
 @pytest.mark.parametrize("force", ["1,512", "0,2048"])
