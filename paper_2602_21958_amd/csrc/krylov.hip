@@ -150,8 +150,11 @@ __global__ __launch_bounds__(kThreads) void reduce_rows_kernel(const double* __r
 }
 
 // w -= sum_i coef_i W_i with coef_i = h_i * s_i; partial norm^2 of new w.
-// Each block owns one contiguous range (16-byte loads when the vector length
-// keeps them aligned); eight basis loads are kept in flight per thread.
+// FP64 vectors: one element per thread, grid-stride (measured fastest for
+// 8-byte elements: 1.84 ms against 1.92 ms with 16-byte groups per block
+// range and 2.00 ms with 16-byte groups grid-stride, box32).  FP32 and fp16
+// vectors: 16-byte groups (when the vector length keeps them aligned) over
+// one contiguous range per block.  Eight basis loads in flight per thread.
 template <typename TV>
 __global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__ V, int64_t n,
                                                           int cnt, const double* __restrict__ h,
@@ -165,8 +168,25 @@ __global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__
   using VT = typename Vec16<TV>::type;
   constexpr int W = Vec16<TV>::n;
   double nrm = 0.0;
-  int64_t b0, b1;
-  if (n % W == 0) {
+  if constexpr (sizeof(TV) == 8) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+      AT v = (AT)w[e];
+      int i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        AT a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = (AT)V[(size_t)(i + u) * n + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v -= coef[i + u] * a[u];
+      }
+      for (; i < cnt; ++i) v -= coef[i] * (AT)V[(size_t)i * n + e];
+      const TV vs = (TV)v;
+      w[e] = vs;
+      nrm += (double)vs * (double)vs;
+    }
+  } else if (n % W == 0) {
+    int64_t b0, b1;
     block_range(n / W, b0, b1);
     VT* wv = reinterpret_cast<VT*>(w);
     for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
@@ -198,6 +218,7 @@ __global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__
       wv[e] = r;
     }
   } else {
+    int64_t b0, b1;
     block_range(n, b0, b1);
     for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
       AT v = (AT)w[e];
@@ -211,8 +232,8 @@ __global__ __launch_bounds__(kThreads) void update_kernel(const TV* __restrict__
   block_reduce_store<1>(a, partial + blockIdx.x, 1, 1);
 }
 
-// x += sum_i coef_i W_i (coef on device, cnt <= kMaxRestart+1); same block
-// ranges and vector loads as the update.
+// x += sum_i coef_i W_i (coef on device, cnt <= kMaxRestart+1); the same
+// access pattern as the update for each basis type.
 template <typename TV, typename TX>
 __global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict__ V, int64_t n,
                                                            int cnt, const double* __restrict__ coef_d,
@@ -224,7 +245,22 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const TV* __restrict_
   constexpr int W = Vec16<TV>::n;
   using XT = typename VecN<TX, W>::type;
   int64_t b0, b1;
-  if (n % W == 0) {
+  if constexpr (sizeof(TV) == 8) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+      double v = (double)x[e];
+      int i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = (double)V[(size_t)(i + u) * n + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += coef[i + u] * a[u];
+      }
+      for (; i < cnt; ++i) v += coef[i] * (double)V[(size_t)i * n + e];
+      x[e] = (TX)v;
+    }
+  } else if (n % W == 0) {
     block_range(n / W, b0, b1);
     XT* xv = reinterpret_cast<XT*>(x);
     for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
