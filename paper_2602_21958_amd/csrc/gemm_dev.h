@@ -72,14 +72,21 @@ template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = d2_t; static constexpr int n = 2; };
 template <> struct Vec16<float> { using type = f4_t; static constexpr int n = 4; };
 
+// Stages between a K stage's global loads and its MFMAs: FP64 loads two
+// stages ahead from two register sets (one 16-stage of FP64 MFMAs does not
+// cover the load latency: 4.88 -> 4.48 ms on the 32^3 box, identical
+// results); FP32 keeps one stage, which leaves it at 4 waves per SIMD.
+template <typename T> constexpr int kPrefetch = sizeof(T) == 8 ? 2 : 1;
+
 // One 128 x 128 output tile at (m0, n0) computed by a 256-thread workgroup,
 // K staged BK at a time.  At: Mhat transposed ([k'][k], leading dimension
 // lda, zero rows up to a multiple of KPAD >= K).  xs multiplies x in the
 // epilogue (ignored when X is null).  Both operand tiles arrive [k][m] /
 // [k][n] with 16-byte loads of consecutive addresses and are stored to LDS
-// as loaded; the next K stage is loaded into registers while the current one
-// is multiplied from a double-buffered LDS ring (one barrier per stage).
-template <typename T, int BK, bool DOTS = false>
+// as loaded; later K stages are loaded into registers (PD stages ahead)
+// while the current one is multiplied from a double-buffered LDS ring (one
+// barrier per stage).
+template <typename T, int BK, bool DOTS = false, int PD = kPrefetch<T>>
 __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
                                           const T* __restrict__ B, const T* X, T* Y,
                                           const double* __restrict__ albedo, double xs, int M,
@@ -105,9 +112,10 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
   const bool b_vec = (N % VN) == 0;
   const int Kp = (K + BK - 1) / BK * BK;
 
-  V ra[A_CH], rb[B_CH];
+  static_assert(PD == 1 || PD == 2, "prefetch distance");
+  V ra[A_CH], rb[B_CH], ra2[A_CH], rb2[B_CH];
 
-  auto gload = [&](int k0) {
+  auto gload = [&](int k0, V (&ra)[A_CH], V (&rb)[B_CH]) {
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
       const int c = tid + 256 * i;
@@ -130,7 +138,7 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
       }
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const V (&ra)[A_CH], const V (&rb)[B_CH]) {
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
       const int c = tid + 256 * i;
@@ -152,14 +160,8 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
   const int nst = Kp / BK;
-  __syncthreads();   // a persistent caller may still read LDS of its previous tile
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int s = 0; s < nst; ++s) {
-    const int buf = s & 1;
-    gload(min(s + 1, nst - 1) * BK);   // the last stage reloads itself (unused)
-    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+  // MFMAs of one K stage from LDS buffer buf
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -174,9 +176,46 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ At, int lda,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = MF::mma(af[i], bf[j], acc[i][j]);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    lstore(buf ^ 1);
-    __syncthreads();
+  };
+
+  __syncthreads();   // a persistent caller may still read LDS of its previous tile
+  gload(0, ra, rb);
+  if constexpr (PD == 2) gload(min(1, nst - 1) * BK, ra2, rb2);
+  lstore(0, ra, rb);
+  __syncthreads();
+  if constexpr (PD == 1) {
+    for (int s = 0; s < nst; ++s) {
+      const int buf = s & 1;
+      gload(min(s + 1, nst - 1) * BK, ra, rb);   // the last stage reloads itself (unused)
+      __builtin_amdgcn_sched_barrier(0);         // keep the loads ahead of the MFMAs
+      stage(buf);
+      __builtin_amdgcn_sched_barrier(0);
+      lstore(buf ^ 1, ra, rb);
+      __syncthreads();
+    }
+  } else {
+    // the two register sets in turn: during stage s the set holding stage
+    // s + 1 goes to LDS while the other receives stage s + 2 (loads past the
+    // last stage reload it, unused)
+    int s = 0;
+    for (; s + 1 < nst; s += 2) {
+      gload(min(s + 2, nst - 1) * BK, ra, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      stage(0);
+      __builtin_amdgcn_sched_barrier(0);
+      lstore(1, ra2, rb2);
+      __syncthreads();
+      gload(min(s + 3, nst - 1) * BK, ra2, rb2);
+      __builtin_amdgcn_sched_barrier(0);
+      stage(1);
+      __builtin_amdgcn_sched_barrier(0);
+      lstore(0, ra, rb);
+      __syncthreads();
+    }
+    if (s < nst) {   // odd stage count: the last stage is in buffer 0
+      stage(0);
+      __syncthreads();
+    }
   }
 
   // epilogue (the final values stay in acc for the fused dots; zero outside)
