@@ -495,7 +495,7 @@ def test_operator_16bit_box(shape, prec):
 @pytest.mark.parametrize("name", ["slab64", "box8"])
 def test_mixed_refinement_per_precision(name, prec):
     """FP64 refinement around each low-precision inner operator; the result is
-    judged by the oracle-evaluated FP64 residual."""
+    checked by the oracle-evaluated FP64 residual."""
     rt = _rt()
     spec = ALL[name]()
     say(f"mixed {prec} {name}")
