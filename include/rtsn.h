@@ -205,7 +205,10 @@ typedef struct {
                              basis).  An inner cycle then gains at most about
                              kappa(A) 2^-11: on ill-conditioned problems the
                              refinement takes more outer steps.  RT_E_INVALID
-                             with any other precision.                           */
+                             with any other precision, or when a row of
+                             (1 - eps) |Mhat| sums to more than 1 (possible
+                             only with an explicit kernel), which the basis
+                             scale's overflow bound assumes.                     */
 } rt_solver_opts;
 
 typedef struct {

@@ -206,6 +206,17 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
       therm[(size_t)k * p.n_s + i] = (eps[i] * ph + d.r) * bpl[i] / fac;
   }
 
+  {
+    double amax = 0.0, rmax = 0.0;
+    for (int64_t i = 0; i < p.n_s; ++i) amax = std::max(amax, alb[i]);
+    for (int k = 0; k < p.n_r; ++k) {
+      double r = 0.0;
+      for (int kp = 0; kp < p.n_r; ++kp) r += std::fabs(p.tab.mhat[(size_t)k * p.n_r + kp]);
+      rmax = std::max(rmax, r);
+    }
+    p.scatter_inf = amax * rmax;
+  }
+
   int64_t tot = 0;
   RT_HIP(hipSetDevice(p.device));
   {
@@ -560,6 +571,8 @@ rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, do
     if (o.basis_fp16 && o.precision != RT_PREC_BF16 && o.precision != RT_PREC_FP16 &&
         o.precision != RT_PREC_BF16X3)
       fail(RT_E_INVALID, "basis_fp16 needs a 16-bit operator precision");
+    if (o.basis_fp16 && q->scatter_inf > 1.0 + 1e-9)
+      fail(RT_E_INVALID, "basis_fp16 needs max row sum of |(1-eps) Mhat| <= 1");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double* bb = b ? b : physical_rhs(*q, st);
     status = solve(*q, o, bb, x, x_is_guess, stats, st);

@@ -258,6 +258,17 @@ def test_fp16_basis_rejected_outside_16bit_operators():
                 eng.submit(p, x, basis_fp16=1)
         finally:
             eng.close()
+    # an explicit kernel whose scattering rows sum to more than 1 breaks the
+    # overflow bound of the basis scale: refused (the problem itself is valid)
+    bad = slab(nz=12, n_mu=2, n_nu=3)
+    n_r = 2 * 3
+    bad.kernel, bad.kernel_matrix = "explicit", np.full((n_r, n_r), 40.0)
+    with rt.Problem(bad) as p:
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(rt.RtError):
+            p.solve(x, precision="fp16", basis_fp16=1)
+        y = torch.empty_like(x)
+        p.apply(x.fill_(1.0), y)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
