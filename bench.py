@@ -140,7 +140,7 @@ def cpu_baseline(spec, gpu_iters, gpu_cycles):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}),
+        print(json.dumps({"error": "the solver runs on one GPU (a problem and its workspace live on one device); --gpus must be 1"}),
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch512":
