@@ -206,9 +206,9 @@ typedef struct {
                              kappa(A) 2^-11: on ill-conditioned problems the
                              refinement takes more outer steps.  RT_E_INVALID
                              with any other precision, or when a row of
-                             (1 - eps) |Mhat| sums to more than 1 (possible
-                             only with an explicit kernel), which the basis
-                             scale's overflow bound assumes.                     */
+                             (1 - eps) |Mhat| sums to more than 2 (possible
+                             only with an explicit kernel; the physical kernels
+                             give about 1), which the basis scale assumes.      */
 } rt_solver_opts;
 
 typedef struct {

@@ -571,8 +571,8 @@ rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, do
     if (o.basis_fp16 && o.precision != RT_PREC_BF16 && o.precision != RT_PREC_FP16 &&
         o.precision != RT_PREC_BF16X3)
       fail(RT_E_INVALID, "basis_fp16 needs a 16-bit operator precision");
-    if (o.basis_fp16 && q->scatter_inf > 1.0 + 1e-9)
-      fail(RT_E_INVALID, "basis_fp16 needs max row sum of |(1-eps) Mhat| <= 1");
+    if (o.basis_fp16 && q->scatter_inf > 2.0)
+      fail(RT_E_INVALID, "basis_fp16 needs max row sum of |(1-eps) Mhat| <= 2");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double* bb = b ? b : physical_rhs(*q, st);
     status = solve(*q, o, bb, x, x_is_guess, stats, st);

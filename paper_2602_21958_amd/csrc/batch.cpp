@@ -701,8 +701,8 @@ rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts, 
     if (!(o.rtol > 0)) fail(RT_E_INVALID, "rtol must be > 0");
     if ((o.basis_fp16 != 0) != e->basis16)
       fail(RT_E_INVALID, "basis_fp16 differs from the engine's basis");
-    if (e->basis16 && q->scatter_inf > 1.0 + 1e-9)
-      fail(RT_E_INVALID, "an fp16 basis needs max row sum of |(1-eps) Mhat| <= 1");
+    if (e->basis16 && q->scatter_inf > 2.0)
+      fail(RT_E_INVALID, "an fp16 basis needs max row sum of |(1-eps) Mhat| <= 2");
     if (o.max_outer < 1) o.max_outer = 1;
     std::lock_guard<std::mutex> lk(e->mu);
     if (e->footprint(*q, o.restart) > e->arena.size())

@@ -8,13 +8,19 @@ namespace rtsn {
 constexpr int kMaxRestart = 128;
 constexpr int kReduceBlocks = 1024;  // dots; the update pass uses twice as many
 
-// GMRES state kept in device memory.  The first fields are what the host
-// reads back after each step.
+// GMRES state kept in device memory.  The fields before h are what the host
+// reads back.  resid / breakdown / nonfinite describe the step at which the
+// cycle stops (stop_k, 1-based; 0 while it continues) once that step has
+// run, so steps launched past it change none of them.
 struct GmresState {
-  double resid;        // |g_{j+1}| after the last Givens step
+  double resid;        // |g_{j+1}| after the last Givens step up to the stop
   double beta;         // norm computed by finish_norm
   int breakdown;       // h_{j+1,j} vanished (lucky breakdown)
   int nonfinite;       // NaN/Inf met
+  int stop_k;          // first step whose residual estimate met the tolerance,
+                       // broke down or was not finite (0: none yet)
+  int pad;
+  double log[kMaxRestart];   // |g_{j+1}| of every step j of the cycle
   double h[kMaxRestart + 1];
   double R[(size_t)kMaxRestart * (kMaxRestart + 1)];  // column j at j*(kMaxRestart+1)
   double cs[kMaxRestart], sn[kMaxRestart];
@@ -49,7 +55,9 @@ void k_norm_partial(const T* x, int64_t n, double* partial, hipStream_t st);
 void k_finish_norm(const double* partial, int64_t n, GmresState* gs, int start_cycle,
                    hipStream_t st);
 void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStream_t st);
-void k_givens(const double* partial, int64_t n, GmresState* gs, int j, hipStream_t st);
+// Givens step j; tol: residual-estimate threshold that stops the cycle.
+void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double tol,
+              hipStream_t st);
 void k_solve_r(GmresState* gs, int k, hipStream_t st);
 template <typename T>
 void k_dots4(const T* a0, const T* b0, const T* a1, const T* b1, int cnt, int64_t n,

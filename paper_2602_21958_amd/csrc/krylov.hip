@@ -344,14 +344,16 @@ __global__ __launch_bounds__(64) void finish_norm_kernel(const double* __restric
       st->vscale[0] = beta > 0.0 ? 1.0 / beta : 0.0;
       st->g[0] = beta;
       for (int i = 1; i <= kMaxRestart; ++i) st->g[i] = 0.0;
+      st->stop_k = 0;
     }
   }
 }
 
 // Givens step j: column h[0..j] (already scaled dots), h_{j+1,j} from the
-// update's partial norms.
+// update's partial norms.  The first step whose residual estimate is <= tol,
+// breaks down or is not finite is recorded in stop_k, with its status.
 __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ partial, int nb,
-                                                    GmresState* st, int j) {
+                                                    GmresState* st, int j, double tol) {
   const int lane = threadIdx.x;
   double s = 0.0;
   for (int b = lane; b < nb; b += 64) s += partial[b];
@@ -381,9 +383,15 @@ __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ p
   st->g[j] = c * st->g[j];
   const int breakdown = !(hn > 1e-14 * fabs(raw_diag) + 1e-300);
   st->vscale[j + 1] = breakdown ? 0.0 : 1.0 / hn;
-  st->resid = fabs(st->g[j + 1]);
-  st->breakdown = breakdown;
-  st->nonfinite = !isfinite(hn) || !isfinite(st->resid);
+  const double resid = fabs(st->g[j + 1]);
+  const int nonfinite = !isfinite(hn) || !isfinite(resid);
+  st->log[j] = resid;
+  if (st->stop_k == 0) {
+    st->resid = resid;
+    st->breakdown = breakdown;
+    st->nonfinite = nonfinite;
+    if (resid <= tol || breakdown || nonfinite) st->stop_k = j + 1;
+  }
 }
 
 // Back substitution R y = g (k x k), coef_i = y_i * vscale_i.
@@ -615,8 +623,10 @@ void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStre
   RT_HIP(hipGetLastError());
 }
 
-void k_givens(const double* partial, int64_t n, GmresState* gs, int j, hipStream_t st) {
-  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j);
+void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double tol,
+              hipStream_t st) {
+  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j,
+                     tol);
   RT_HIP(hipGetLastError());
 }
 

@@ -85,8 +85,9 @@ struct Problem {
   // values each.  Zero-filled at allocation: padding rows must stay zero.
   uint16_t* d_l16 = nullptr;
   int g16_cfg[3] = {-1, -1, -1};        // tuned tile configuration per 16-bit mode
-  double scatter_inf = 0;               // max_k sum_k' |(1 - eps) Mhat[k, k']| (the
-                                        // fp16 basis scale assumes <= 1)
+  double scatter_inf = 0;               // max_k sum_k' |(1 - eps) Mhat[k, k']| (about 1
+                                        // for the physical kernels; an fp16 basis is
+                                        // refused above 2)
   double* d_albedo = nullptr;           // n_s: 1 - eps_i
   double* d_thermal = nullptr;          // n: t
   double* d_dt = nullptr;               // slab: nz-1 depth increments

@@ -229,11 +229,14 @@ float fp16_lambda_scale(int64_t n) {
 }
 
 // Scale of an fp16 Krylov basis (stored vectors are 2^11 times the unit-norm
-// ones).  With non-negative scattering and transfer weights, |A|_inf <= 2, so
-// an operator output for a unit vector has entries of at most 2, and the
-// Gram-Schmidt update adds at most sum_i |h_i| <= 2 sqrt(m + 1): below 25 for
-// any restart m <= 128, so stored entries stay under 2^11 * 25 < 65504.  The
-// smallest normal fp16 value then stands for 3e-8 of a unit vector.
+// ones).  Transfer weights are non-negative with row sums <= 1, so for the
+// physical kernels (|(1 - eps) Mhat|_inf about 1, refused above 2) an
+// operator output for a unit vector has entries of at most about 2, stored
+// below 2^12; the Gram-Schmidt update subtracts multiples h_i of unit
+// vectors, with |h_i| <= |A v_j|_2, in practice of order one, which leaves
+// a factor of about 16 below fp16's largest value.  An overflow would show
+// as a non-finite value and stop the solve with RT_E_NONFINITE.  The
+// smallest normal fp16 value stands for 3e-8 of a unit vector.
 float fp16_basis_scale(int64_t) { return 2048.f; }
 
 const char* gemm16_config_name(int cfg) {

@@ -126,6 +126,38 @@ Status read_status(Workspace& ws, hipStream_t st) {
   return Status{ws.host->resid, ws.host->beta, ws.host->breakdown, ws.host->nonfinite};
 }
 
+// Arnoldi steps launched between two status reads.  A read is a host round
+// trip, which dominates the step time of small problems; steps launched past
+// the cycle's stopping step are discarded (the cycle keeps its first stop_k
+// steps, whose basis vectors, Hessenberg columns and g entries later steps do
+// not touch), so the results are those of reading after every step.  Large
+// problems read after every step: a discarded step would cost more than the
+// read.  RTSN_STATUS_EVERY overrides.
+int status_every(int64_t n) {
+  if (const char* e = std::getenv("RTSN_STATUS_EVERY")) return std::max(1, std::atoi(e));
+  return n <= (int64_t(1) << 22) ? 4 : 1;
+}
+
+struct StepRead {
+  int k;        // steps of the cycle to keep
+  bool stop;    // the cycle met its tolerance, broke down (or hit a non-finite value)
+};
+
+// Status read after `done` steps of the cycle: the steps to keep, the new
+// residual estimates appended to hist (relative to bnorm); fails on a
+// non-finite value at or before the stopping step.
+StepRead read_steps(Workspace& ws, hipStream_t st, int done, int& logged,
+                    std::vector<double>* hist, double bnorm) {
+  const Status g = read_status(ws, st);
+  const int stop_k = ws.host->stop_k;
+  const int k = stop_k > 0 ? std::min(stop_k, done) : done;
+  if (hist)
+    for (int q = logged; q < k; ++q) hist->push_back(ws.host->log[q] / bnorm);
+  logged = k;
+  if (g.nonfinite) fail(RT_E_NONFINITE, "non-finite value in the Arnoldi process");
+  return StepRead{k, stop_k > 0};
+}
+
 double read_scalar(const double* d, hipStream_t st, Workspace& ws) {
   double* h = reinterpret_cast<double*>(ws.host);
   RT_HIP(hipMemcpyAsync(h, d, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -171,9 +203,10 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   if (!std::isfinite(s.beta)) fail(RT_E_NONFINITE, "non-finite residual");
   res.beta = s.beta;
   if (hist) hist->push_back(s.beta / bnorm);
+  const int every = status_every(n);
   while (s.beta > rtol * bnorm && res.iters < max_iters) {
     res.cycles++;
-    int k = 0;
+    int k = 0, logged = 0;
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
@@ -188,13 +221,14 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
         k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
       }
       k_update<TV>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-      k_givens(ws.partial, n, gs, j, st);
-      Status g = read_status(ws, st);
+      k_givens(ws.partial, n, gs, j, rtol * bnorm, st);
       res.iters++;
       k = j + 1;
-      if (g.nonfinite) fail(RT_E_NONFINITE, "non-finite value in the Arnoldi process");
-      if (hist) hist->push_back(g.resid / bnorm);
-      if (g.breakdown || g.resid <= rtol * bnorm || res.iters >= max_iters) break;
+      if (k < m && res.iters < max_iters && k % every != 0) continue;
+      const StepRead r = read_steps(ws, st, k, logged, hist, bnorm);
+      res.iters -= k - r.k;
+      k = r.k;
+      if (r.stop || res.iters >= max_iters) break;
     }
     k_solve_r(gs, k, st);
     k_combine<TV, TV>(V, n, k, gs->coef, x, st);
@@ -233,18 +267,20 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
   const Status s0 = read_status(ws, st);
   if (!(s0.beta > 0.0) || !std::isfinite(s0.beta))
     fail(RT_E_NONFINITE, "fp16 basis: right-hand side out of range");
-  int k = 0;
-  for (int j = 0; j < std::min(m, cap); ++j) {
+  int k = 0, logged = 0;
+  const int steps = std::min(m, cap), every = status_every(n);
+  for (int j = 0; j < steps; ++j) {
     _Float16* w = V + (size_t)(j + 1) * n;
     operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st);
     k_mdot<_Float16>(V, n, j + 1, w, ws.partial, st);
     k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
     k_update<_Float16>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-    k_givens(ws.partial, n, gs, j, st);
-    const Status g = read_status(ws, st);
+    k_givens(ws.partial, n, gs, j, itol * s0.beta, st);
     k = j + 1;
-    if (g.nonfinite) fail(RT_E_NONFINITE, "non-finite value in the fp16 Arnoldi process");
-    if (g.breakdown || g.resid <= itol * s0.beta) break;
+    if (k < steps && k % every != 0) continue;
+    const StepRead r = read_steps(ws, st, k, logged, nullptr, 1.0);
+    k = r.k;
+    if (r.stop) break;
   }
   k_solve_r(gs, k, st);
   k_combine<_Float16, float>(V, n, k, gs->coef, d, st);

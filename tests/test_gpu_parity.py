@@ -258,8 +258,8 @@ def test_fp16_basis_rejected_outside_16bit_operators():
                 eng.submit(p, x, basis_fp16=1)
         finally:
             eng.close()
-    # an explicit kernel whose scattering rows sum to more than 1 breaks the
-    # overflow bound of the basis scale: refused (the problem itself is valid)
+    # an explicit kernel whose scattering rows sum far above 1 (here ~40/phi)
+    # voids the headroom of the basis scale: refused (the problem is valid)
     bad = slab(nz=12, n_mu=2, n_nu=3)
     n_r = 2 * 3
     bad.kernel, bad.kernel_matrix = "explicit", np.full((n_r, n_r), 40.0)
@@ -286,6 +286,32 @@ def test_gmres_with_dots_fused_into_sigma(prec, monkeypatch):
         s = host(x)
     assert st["converged"]
     assert op.residual_norm(s) <= 1.05e-8
+
+
+@pytest.mark.parametrize("name,precision,basis16",
+                         [("slab64", "fp64", 0), ("box8", "fp64", 0), ("slab64", "fp16", 0),
+                          ("box8", "fp16", 1)])
+def test_batched_status_reads_give_identical_results(name, precision, basis16, monkeypatch):
+    """Reading the Arnoldi status every 4 steps (the default for small
+    problems; steps past the stop are launched and discarded) gives the same
+    bits, iteration counts and residual history as reading after every step."""
+    rt = _rt()
+    spec = ALL[name]()
+    monkeypatch.setenv("RTSN_GEMM16_CFG", "2")   # one tile shape for all three problems
+    out = {}
+    for every in ("1", "4", "7"):
+        monkeypatch.setenv("RTSN_STATUS_EVERY", every)
+        with rt.Problem(spec) as p:
+            x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+            st = p.solve(x, rtol=1e-8, restart=30, precision=precision, basis_fp16=basis16)
+            out[every] = (st, host(x))
+    say(f"status every 1/4/7 {name} {precision}: iters "
+        f"{[out[e][0]['iters'] for e in out]}")
+    for every in ("4", "7"):
+        assert out[every][0]["iters"] == out["1"][0]["iters"]
+        assert out[every][0]["outer_iters"] == out["1"][0]["outer_iters"]
+        assert out[every][0]["history"] == out["1"][0]["history"]
+        assert np.array_equal(out[every][1], out["1"][1])
 
 
 def test_gmres_tight_solution_matches_oracle():
