@@ -141,14 +141,17 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
   hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT>), dim3(grid), dim3(NT), lds, \
                      st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx,  \
                      p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
-    // planes up to 1024 points: 256 threads; larger planes: 1024 threads
-    // (FP32) or 512 threads (FP64, which needs twice the registers per point)
+    // planes up to 256 points: 256 threads; up to 1024 points: 512 threads of
+    // 2 points each (FP64: 100 VGPRs and 4 waves per SIMD, where 256 threads
+    // of 4 points need 146 VGPRs and run at 3: 0.400 against 0.443 ms on the
+    // 32^3 box; FP32 also gains); larger planes: 1024 threads (FP32) or 512
+    // threads (FP64, which needs twice the registers per point)
     if (F == 4) {
       if (P <= 256) RT_BOX_LAUNCH(4, 1, 256);
       else RT_BOX_LAUNCH(4, 1, 1024);
     } else {
       if (P <= 256) RT_BOX_LAUNCH(1, 1, 256);
-      else if (P <= 1024) RT_BOX_LAUNCH(1, 4, 256);
+      else if (P <= 1024) RT_BOX_LAUNCH(1, 2, 512);
       else if (P <= 4096 && sizeof(C) == 4) RT_BOX_LAUNCH(1, 4, 1024);
       else if (P <= 4096) RT_BOX_LAUNCH(1, 8, 512);
       else fail(RT_E_INVALID, "box plane larger than 4096 points");
