@@ -388,8 +388,9 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   for (int i = 0; i < 5; ++i) wl.h_counts[i] = hc[i];
   RT_HIP(hipMemcpyAsync(wl.counts, hc, 5 * sizeof(int), hipMemcpyHostToDevice, stream));
   wl.box_pmax = pmax;
-  wl.box_npt = pmax <= 256 ? 1 : (pmax <= 1024 ? 4 : 16);
+  wl.box_npt = pmax <= 256 ? 1 : (pmax <= 1024 ? 2 : 16);
   wl.box_f = bf;
+  wl.max_lds = max_lds;
 }
 
 // Time the grouped 16-bit GEMM's persistent grid sizes on the live work

@@ -77,9 +77,10 @@ struct WorkLists {
   int* slots = nullptr;      int cap_slots = 0;
   int* counts = nullptr;     // [lam_slab, lam_box, tiles, chunks, slots]
   int h_counts[5] = {0, 0, 0, 0, 0};
-  int box_npt = 1;           // points per thread class for box rays (1, 4, 16)
+  int box_npt = 1;           // points per thread class for box rays (1, 2, 16)
   int box_pmax = 0;          // largest box plane among the listed slots
   int box_f = 1;             // frequencies per box item (1 or 4)
+  int max_lds = 0;           // LDS bytes per workgroup of the device
   uint64_t gen = 0;          // bumped whenever a list buffer is reallocated: a graph
                              // captured with the old addresses must not be replayed
 };

@@ -110,7 +110,7 @@ __device__ __forceinline__ auto slot_outs(const SlotDev& s, int k0, size_t len) 
                            s.np16, k0};
 }
 
-template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT, bool OUTER>
+template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT, bool PP, bool OUTER>
 __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ slots,
                                                     const SlotStat* __restrict__ stat,
                                                     const Item* __restrict__ items,
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ 
 #pragma unroll
     for (int f = 0; f < F; ++f) fac[f] = f < nf ? C(s.ray_fac[k0 + f]) : C(0);
     const auto outs = slot_outs<LT, K4>(s, k0, vol);
-    lam::box_rays<VT, decltype(outs), C, F, NPT, NT>(
+    lam::box_rays<VT, decltype(outs), C, F, NPT, NT, PP>(
         src + (size_t)k0 * vol, vol, nf, outs, s.kline, s.stencil[k0 / s.n_nu], fac, s.nx,
         s.ny, s.nz, C(0), sc, om, reinterpret_cast<C*>(smem_raw));
   }
@@ -568,20 +568,27 @@ void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists
   if (wl.h_counts[0] > 0)
     persist(bk_lambda_slab<VT, LT, C, K4, OUTER>, TB, 0, st, slots, stat, wl.lam_slab, wl.counts);
   if (wl.h_counts[1] > 0) {
-    const size_t lds = (size_t)(2 * wl.box_f + 1) * wl.box_pmax * sizeof(C);
-#define RT_BBOX(FF, NPT, NT) \
-  persist(bk_lambda_box<VT, LT, C, K4, FF, NPT, NT, OUTER>, NT, lds, st, slots, stat, wl.lam_box, \
-          wl.counts)
+    // two alternating LDS sets where they fit (the kernel takes PP = true
+    // only then; PP = false needs no more than lds either way)
+    const bool pp = box_pingpong(wl.box_f, wl.box_pmax, (int)sizeof(C), wl.max_lds);
+    const size_t lds = lam::box_lds_elems(wl.box_f, wl.box_pmax, pp) * sizeof(C);
+#define RT_BBOX1(FF, NPT, NT, PPV)                                                          \
+  persist(bk_lambda_box<VT, LT, C, K4, FF, NPT, NT, PPV, OUTER>, NT, lds, st, slots, stat, \
+          wl.lam_box, wl.counts)
+#define RT_BBOX(FF, NPT, NT)         \
+  if (pp) RT_BBOX1(FF, NPT, NT, true); \
+  else RT_BBOX1(FF, NPT, NT, false)
     if (wl.box_f == 4) {
-      if (wl.box_npt <= 1) RT_BBOX(4, 1, 256);
-      else RT_BBOX(4, 1, 1024);
+      if (wl.box_npt <= 1) RT_BBOX1(4, 1, 256, false);
+      else RT_BBOX1(4, 1, 1024, false);
     } else {
-      if (wl.box_npt <= 1) RT_BBOX(1, 1, 256);
-      else if (wl.box_npt <= 4) RT_BBOX(1, 4, 256);
-      else if (sizeof(C) == 4) RT_BBOX(1, 4, 1024);
-      else RT_BBOX(1, 8, 512);
+      if (wl.box_npt <= 1) { RT_BBOX(1, 1, 256); }
+      else if (wl.box_npt <= 2) { RT_BBOX(1, 2, 512); }
+      else if (sizeof(C) == 4) { RT_BBOX(1, 4, 1024); }
+      else { RT_BBOX1(1, 8, 512, false); }
     }
 #undef RT_BBOX
+#undef RT_BBOX1
   }
 }
 

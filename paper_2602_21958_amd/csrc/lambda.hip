@@ -65,17 +65,32 @@ __device__ __forceinline__ auto rays_out(void* o0, void* o1, int k0, size_t len,
     return lam::K4Outs<K4>{static_cast<uint16_t*>(o0), static_cast<uint16_t*>(o1), Np, k0};
 }
 
+// Order of the groups when each writes one ray of the k4-interleaved 16-bit
+// operand: the four rays of a k4 group fill alternate 2-byte slots of the
+// same cache lines.  Workgroups are dealt to the 8 XCDs in turn (group b on
+// XCD b % 8), each with its own L2, so in launch order the four rays would
+// write parts of each line from four L2s.  Group b = 8 (4 m + r) + x sweeps
+// ray 4 (8 m + x) + r instead: the rays of a k4 group run on one XCD, one
+// after another in its dispatch order, and their writes meet in one L2.  A
+// tail of fewer than 32 groups keeps launch order.
+__device__ __forceinline__ int k4_xcd_order(int b, int n) {
+  if (b >= n / 32 * 32) return b;
+  const int x = b & 7, slot = b >> 3;
+  return 4 * (8 * (slot >> 2) + x) + (slot & 3);
+}
+
 // One workgroup per (ordinate, chunk of F frequencies).
-template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT>
+template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT, bool PP>
 __global__ __launch_bounds__(NT) void lambda_box_kernel(
     const VT* __restrict__ s, void* out0, void* out1, int64_t Np,
     const double* __restrict__ kline, const BoxStencil* __restrict__ stencil,
     const double* __restrict__ ray_fac, int n_nu, int nx, int ny, int nz, double i_top,
-    double i_bot, int with_bc, const double* __restrict__ scale, float out_mul) {
+    double i_bot, int with_bc, const double* __restrict__ scale, float out_mul, int xcd_order) {
   extern __shared__ unsigned char smem_raw[];
   const int nch = (n_nu + F - 1) / F;
-  const int o = blockIdx.x / nch;
-  const int nu0 = (blockIdx.x % nch) * F;
+  const int b = xcd_order ? k4_xcd_order(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int o = b / nch;
+  const int nu0 = (b % nch) * F;
   const int nf = min(F, n_nu - nu0);
   const int k0 = o * n_nu + nu0;
   const BoxStencil st = stencil[o];
@@ -86,7 +101,7 @@ __global__ __launch_bounds__(NT) void lambda_box_kernel(
 #pragma unroll
   for (int f = 0; f < F; ++f) fac[f] = f < nf ? C(ray_fac[k0 + f]) : C(0);
   const auto outs = rays_out<LT, K4>(out0, out1, k0, vol, Np);
-  lam::box_rays<VT, decltype(outs), C, F, NPT, NT>(s + (size_t)k0 * vol, vol, nf, outs, kline,
+  lam::box_rays<VT, decltype(outs), C, F, NPT, NT, PP>(s + (size_t)k0 * vol, vol, nf, outs, kline,
                                                    st, fac, nx, ny, nz, i_in, sc, out_mul,
                                                    reinterpret_cast<C*>(smem_raw));
 }
@@ -119,6 +134,20 @@ int box_chunk(int P, int elem_bytes, int max_lds) {
   return 0;
 }
 
+// Measured on the 32^3 box: FP32 sweeps 0.144 -> 0.141 ms (fp16 input 0.153
+// -> 0.126 ms) with two sets; FP64 0.247 -> 0.254 ms and FP32 on 64^2
+// planes 5.76 -> 5.86 ms, where the larger LDS footprint costs more than
+// the barrier it saves.
+bool box_pingpong(int F, int P, int elem_bytes, int max_lds) {
+  static const int env = [] {
+    const char* e = std::getenv("RTSN_LAMBDA_PP");
+    return e ? std::atoi(e) : -1;
+  }();
+  if (env == 0 || F != 1 || lam::box_lds_elems(F, P, true) * elem_bytes > (size_t)max_lds)
+    return false;
+  return env == 1 || (elem_bytes == 4 && P <= 1024);
+}
+
 template <typename VT, typename LT, int K4>
 void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int64_t Np,
                      bool with_bc, const double* scale, hipStream_t st, float out_mul) {
@@ -135,28 +164,44 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
     const int F = box_chunk(P, (int)sizeof(C), max_lds);
     if (F == 0) fail(RT_E_INVALID, "box plane too large for LDS in this precision");
-    const size_t lds = (size_t)(2 * F + 1) * P * sizeof(C);
+    // the kernel takes PP = true only where pp sized the LDS for two sets
+    const bool pp = box_pingpong(F, P, (int)sizeof(C), max_lds);
+    const size_t lds = lam::box_lds_elems(F, P, pp) * sizeof(C);
     const int grid = p.n_omega * ((p.n_nu + F - 1) / F);
-#define RT_BOX_LAUNCH(FF, NPT, NT)                                                              \
-  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT>), dim3(grid), dim3(NT), lds, \
-                     st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu, p.nx,  \
-                     p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul)
+    // one ray per group (group index = ray index) into the k4 operand
+    static const bool xcd_env = [] {
+      const char* e = std::getenv("RTSN_LAMBDA_XCD");
+      return !(e && std::atoi(e) == 0);
+    }();
+    const int xcd = (K4 >= 0 && F == 1 && xcd_env) ? 1 : 0;
+#define RT_BOX_LAUNCH1(FF, NPT, NT, PPV)                                                          \
+  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT, PPV>), dim3(grid), dim3(NT), \
+                     lds, st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu,    \
+                     p.nx, p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul, xcd)
+#define RT_BOX_LAUNCH(FF, NPT, NT)       \
+  if (pp) RT_BOX_LAUNCH1(FF, NPT, NT, true); \
+  else RT_BOX_LAUNCH1(FF, NPT, NT, false)
     // planes up to 256 points: 256 threads; up to 1024 points: 512 threads of
     // 2 points each (FP64: 100 VGPRs and 4 waves per SIMD, where 256 threads
     // of 4 points need 146 VGPRs and run at 3: 0.400 against 0.443 ms on the
     // 32^3 box; FP32 also gains); larger planes: 1024 threads (FP32) or 512
     // threads (FP64, which needs twice the registers per point)
+    // (FP64 planes over 1024 points keep one set: the kernel needs no more
+    // LDS than lds holds whatever pp is)
     if (F == 4) {
-      if (P <= 256) RT_BOX_LAUNCH(4, 1, 256);
-      else RT_BOX_LAUNCH(4, 1, 1024);
+      if (P <= 256) RT_BOX_LAUNCH1(4, 1, 256, false);
+      else RT_BOX_LAUNCH1(4, 1, 1024, false);
     } else {
-      if (P <= 256) RT_BOX_LAUNCH(1, 1, 256);
-      else if (P <= 1024) RT_BOX_LAUNCH(1, 2, 512);
-      else if (P <= 4096 && sizeof(C) == 4) RT_BOX_LAUNCH(1, 4, 1024);
-      else if (P <= 4096) RT_BOX_LAUNCH(1, 8, 512);
-      else fail(RT_E_INVALID, "box plane larger than 4096 points");
+      if (P <= 256) { RT_BOX_LAUNCH(1, 1, 256); }
+      else if (P <= 1024) { RT_BOX_LAUNCH(1, 2, 512); }
+      else if (P <= 4096 && sizeof(C) == 4) { RT_BOX_LAUNCH(1, 4, 1024); }
+      else if (P <= 4096) { RT_BOX_LAUNCH1(1, 8, 512, false); }
+      else {
+        fail(RT_E_INVALID, "box plane larger than 4096 points");
+      }
     }
 #undef RT_BOX_LAUNCH
+#undef RT_BOX_LAUNCH1
   }
   RT_HIP(hipGetLastError());
 }

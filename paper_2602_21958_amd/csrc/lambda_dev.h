@@ -29,9 +29,18 @@ static __device__ __constant__ double kInvFactN[18] = {
 // c = d phi_2(d) comes from its series (one Horner chain).  Above 1/2,
 // e = exp(-d) and q = (1 - e)/d have no cancellation.  FP32 uses the
 // hardware exponential and reciprocal (about 1 ulp each).
-template <typename C>
+//
+// BR: keep the two ranges as a branch that a wavefront whose lanes all fall
+// on one side skips the other side of (an empty volatile asm statement on
+// each side stops the compiler from evaluating both and selecting).  In FP64
+// the exponential and the division cost about twice the series, and in a
+// box sweep the 64 points of a wavefront lie in one plane of one ray, with
+// nearly equal optical steps; slab rays put the whole depth range in one
+// wavefront, and FP32 sides are a handful of instructions, so both select.
+template <typename C, bool BR = false>
 __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
   if (d < C(0.5)) {
+    if constexpr (BR) asm volatile("" : "+v"(d));
     constexpr int T = Series<C>::terms;
     C ph = C(0);
 #pragma unroll
@@ -40,6 +49,7 @@ __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
     e = (C(1) - d) + d * c;
     a = d - (C(1) + d) * c;
   } else {
+    if constexpr (BR) asm volatile("" : "+v"(d));
     C q;
     if constexpr (sizeof(C) == 8) {
       e = exp(-d);
@@ -233,7 +243,12 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
 // stencil, the interpolated opacity and the step's optical depth up to the
 // frequency factor are computed once per point and used by all F rays; the
 // previous plane's intensities and sources (per ray) and opacity sit in LDS,
-// (2F + 1) P values of type C.
+// (2F + 1) P values of type C (box_lds_elems).  PP: two such sets, written
+// by alternate planes, so that a plane needs one barrier (its writes go to
+// the set the next plane reads, while the set it reads is not written);
+// otherwise one set and two barriers per plane.  The next plane's sources
+// and opacity are loaded a plane ahead and kept as loaded (no arithmetic on
+// them before they are used, so the loads stay in flight over a plane).
 //
 // src(f): the ray's nz*P source values; fac[f]: phi_nu + r of ray f;
 // out.put(f, i, v) stores value i of ray f, out.put4(i, v0..v3) the four rays
@@ -241,15 +256,17 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
 // 16-bit operand).
 constexpr int kBoxThreads = 256;
 
-template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads>
+// LDS elements of type C that box_rays needs.
+constexpr size_t box_lds_elems(int F, int P, bool pp) { return (size_t)(pp ? 2 : 1) * (2 * F + 1) * P; }
+
+template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads,
+          bool PP = false>
 __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_stride, int nf,
                                          const OUT& out, const double* __restrict__ kline,
                                          const BoxStencil st, const C* fac, int nx, int ny,
                                          int nz, C i_in, C sc, float out_mul, C* smem) {
   const int P = nx * ny;
-  C* lK = smem;
-  C* lI = lK + P;          // [F][P]
-  C* lS = lI + F * P;      // [F][P]
+  const size_t set = (size_t)(2 * F + 1) * P;   // one set: K [P], I [F][P], S [F][P]
   const C path = C(st.path);
   const C tx = C(st.tx), ty = C(st.ty);
   const size_t plane_stride = (size_t)P;
@@ -278,8 +295,9 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
   const C w10 = ty * (C(1) - tx), w11 = ty * tx;
   const C om = C(out_mul);
 
-  // sources and opacity of the next plane are loaded one plane ahead
-  C Sn[F][kBoxMaxPts], Kn[kBoxMaxPts];
+  // sources and opacity of the next plane, loaded one plane ahead
+  VT Sn[F][kBoxMaxPts];
+  double Kn[kBoxMaxPts];
   C Sv[F][kBoxMaxPts], Iv[F][kBoxMaxPts], Kv[kBoxMaxPts];
   auto load_plane = [&](int t) {
     const int z = st.up ? t : nz - 1 - t;
@@ -289,11 +307,10 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
       if (j >= npt) break;
       const int p = threadIdx.x + j * NT;
       if (p < P) {
-        Kn[j] = C(kz[p]);
+        Kn[j] = kz[p];
 #pragma unroll
         for (int f = 0; f < F; ++f)
-          Sn[f][j] = f < nf ? sc * C(s0[(size_t)f * ray_stride + (size_t)z * plane_stride + p])
-                            : C(0);
+          Sn[f][j] = f < nf ? s0[(size_t)f * ray_stride + (size_t)z * plane_stride + p] : VT(0);
       }
     }
   };
@@ -301,12 +318,19 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
   for (int t = 0; t < nz; ++t) {
     const int z = st.up ? t : nz - 1 - t;
     const size_t oz = (size_t)z * plane_stride;
+    // the set the previous plane wrote, and the one this plane writes
+    const C* rK = smem + (PP ? (size_t)((t + 1) & 1) * set : 0);
+    const C* rI = rK + P;
+    const C* rS = rI + F * P;
+    C* wK = smem + (PP ? (size_t)(t & 1) * set : 0);
+    C* wI = wK + P;
+    C* wS = wI + F * P;
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
-      Kv[j] = Kn[j];
+      Kv[j] = C(Kn[j]);
 #pragma unroll
-      for (int f = 0; f < F; ++f) Sv[f][j] = Sn[f][j];
+      for (int f = 0; f < F; ++f) Sv[f][j] = sc * C(Sn[f][j]);
     }
     if (t + 1 < nz) load_plane(t + 1);
 #pragma unroll
@@ -319,16 +343,16 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
 #pragma unroll
         for (int f = 0; f < F; ++f) I[f] = i_in;
       } else {
-        const C ku = w00 * lK[n00[j]] + w01 * lK[n01[j]] + w10 * lK[n10[j]] + w11 * lK[n11[j]];
+        const C ku = w00 * rK[n00[j]] + w01 * rK[n01[j]] + w10 * rK[n10[j]] + w11 * rK[n11[j]];
         const C base = C(0.5) * (ku + Kv[j]) * path;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          const C* If = lI + f * P;
-          const C* Sf = lS + f * P;
+          const C* If = rI + f * P;
+          const C* Sf = rS + f * P;
           const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
           const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
           C e, a, c;
-          sc_weights<C>(base * fac[f], e, a, c);
+          sc_weights<C, sizeof(C) == 8>(base * fac[f], e, a, c);
           I[f] = e * Iu + a * Su + c * Sv[f][j];
         }
       }
@@ -348,17 +372,17 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
 #pragma unroll
       for (int f = 0; f < F; ++f) Iv[f][j] = I[f];
     }
-    __syncthreads();
+    if constexpr (!PP) __syncthreads();   // every read of the one set is done
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
       const int p = threadIdx.x + j * NT;
       if (p >= P) break;
-      lK[p] = Kv[j];
+      wK[p] = Kv[j];
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        lI[f * P + p] = Iv[f][j];
-        lS[f * P + p] = Sv[f][j];
+        wI[f * P + p] = Iv[f][j];
+        wS[f * P + p] = Sv[f][j];
       }
     }
     __syncthreads();
