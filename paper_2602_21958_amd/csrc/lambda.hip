@@ -134,10 +134,11 @@ int box_chunk(int P, int elem_bytes, int max_lds) {
   return 0;
 }
 
-// Measured on the 32^3 box: FP32 sweeps 0.144 -> 0.141 ms (fp16 input 0.153
-// -> 0.126 ms) with two sets; FP64 0.247 -> 0.254 ms and FP32 on 64^2
-// planes 5.76 -> 5.86 ms, where the larger LDS footprint costs more than
-// the barrier it saves.
+// Measured with two sets against one on the 32^3 box: FP64 0.239 -> 0.226 ms
+// (72 against 92 VGPRs: three groups per CU instead of two), FP32 0.144 ->
+// 0.141 ms, fp16 input 0.153 -> 0.126 ms; on 64^2 planes (FP32, 1024
+// threads, one group per CU either way) 5.76 -> 5.86 ms, so larger planes
+// keep one set.
 bool box_pingpong(int F, int P, int elem_bytes, int max_lds) {
   static const int env = [] {
     const char* e = std::getenv("RTSN_LAMBDA_PP");
@@ -145,7 +146,7 @@ bool box_pingpong(int F, int P, int elem_bytes, int max_lds) {
   }();
   if (env == 0 || F != 1 || lam::box_lds_elems(F, P, true) * elem_bytes > (size_t)max_lds)
     return false;
-  return env == 1 || (elem_bytes == 4 && P <= 1024);
+  return env == 1 || P <= 1024;
 }
 
 template <typename VT, typename LT, int K4>
@@ -182,10 +183,10 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
   if (pp) RT_BOX_LAUNCH1(FF, NPT, NT, true); \
   else RT_BOX_LAUNCH1(FF, NPT, NT, false)
     // planes up to 256 points: 256 threads; up to 1024 points: 512 threads of
-    // 2 points each (FP64: 100 VGPRs and 4 waves per SIMD, where 256 threads
-    // of 4 points need 146 VGPRs and run at 3: 0.400 against 0.443 ms on the
-    // 32^3 box; FP32 also gains); larger planes: 1024 threads (FP32) or 512
-    // threads (FP64, which needs twice the registers per point)
+    // 2 points each (FP64 with two LDS sets: 72 VGPRs, three groups per CU;
+    // 256 threads of 4 points or 1024 threads of 1 point measured slower on
+    // the 32^3 box); larger planes: 1024 threads (FP32) or 512 threads (FP64,
+    // which needs twice the registers per point)
     // (FP64 planes over 1024 points keep one set: the kernel needs no more
     // LDS than lds holds whatever pp is)
     if (F == 4) {

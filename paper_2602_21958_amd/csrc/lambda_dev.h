@@ -22,13 +22,46 @@ static __device__ __constant__ double kInvFactN[18] = {
     1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0,
     1.0 / 355687428096000.0};
 
+// e^{-d} in FP64 for d >= 0: Cody-Waite range reduction and a Taylor
+// series.  d = n ln2 + r with n = rint(d / ln2) and |r| <= ln2 / 2, ln2
+// split into a head whose low 12 significand bits are zero (n head is exact
+// for n < 2^12) and a tail; e^{-r} = sum_{k=0}^{13} (-r)^k / k!, whose first
+// omitted term is below 5e-18 of the sum; the result is scaled by 2^-n.  d is
+// clamped at 800, past which e^{-d} is 0 in FP64 anyway.  The coefficients
+// come from kInvFactN (scalar registers), so each Horner step is one FMA.
+__device__ __forceinline__ double exp_neg_f64(double d) {
+  constexpr double kInvLn2 = 0x1.71547652b82fep+0;
+  constexpr double kLn2Hi = 0x1.62e42fefa3000p-1;
+  constexpr double kLn2Lo = 0x1.3de6af278ece6p-42;
+  const double dc = fmin(d, 800.0);
+  const double mn = rint(dc * -kInvLn2);   // -n (rint is odd: same n)
+  double r = fma(mn, kLn2Hi, dc);
+  r = fma(mn, kLn2Lo, r);
+  double p = kInvFactN[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) p = fma(p, -r, kInvFactN[k]);
+  return ldexp(p, (int)mn);
+}
+
+// num / d in FP64 for d >= 1/2 and |num| <= 1 (no operand near the exponent
+// limits, so no scaling): the hardware reciprocal refined by two Newton
+// steps, then one residual correction of the quotient (within 1 ulp).
+__device__ __forceinline__ double div_f64_normal(double num, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double q = num * r;
+  return fma(fma(-d, q, num), r, q);
+}
+
 // Weights of one linear short-characteristics step of optical length d:
 // e = e^{-d}, a = (1 - e)/d - e, c = 1 - (1 - e)/d.  With q = (1 - e)/d the
 // three follow from c alone: q = 1 - c, e = 1 - d q = 1 - d + d c and
 // a = q - e = d - (1 + d) c, none of which cancels for d <= 1/2, where
 // c = d phi_2(d) comes from its series (one Horner chain).  Above 1/2,
-// e = exp(-d) and q = (1 - e)/d have no cancellation.  FP32 uses the
-// hardware exponential and reciprocal (about 1 ulp each).
+// e = exp(-d) and q = (1 - e)/d have no cancellation (FP64: exp_neg_f64 and
+// div_f64_normal).  FP32 uses the hardware exponential and reciprocal (about
+// 1 ulp each).
 //
 // BR: keep the two ranges as a branch that a wavefront whose lanes all fall
 // on one side skips the other side of (an empty volatile asm statement on
@@ -42,9 +75,9 @@ __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
   if (d < C(0.5)) {
     if constexpr (BR) asm volatile("" : "+v"(d));
     constexpr int T = Series<C>::terms;
-    C ph = C(0);
+    C ph = C(kInvFactN[T + 1]);
 #pragma unroll
-    for (int m = T - 1; m >= 0; --m) ph = ph * (-d) + C(kInvFactN[m + 2]);
+    for (int m = T - 2; m >= 0; --m) ph = ph * (-d) + C(kInvFactN[m + 2]);
     c = d * ph;
     e = (C(1) - d) + d * c;
     a = d - (C(1) + d) * c;
@@ -52,8 +85,8 @@ __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
     if constexpr (BR) asm volatile("" : "+v"(d));
     C q;
     if constexpr (sizeof(C) == 8) {
-      e = exp(-d);
-      q = (C(1) - e) / d;
+      e = exp_neg_f64(d);
+      q = div_f64_normal(C(1) - e, d);
     } else {
       e = __expf(-d);
       q = __fdividef(C(1) - e, d);

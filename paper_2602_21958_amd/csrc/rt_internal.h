@@ -128,9 +128,9 @@ float fp16_basis_scale(int64_t n);
 // Frequencies swept together by one box workgroup for planes of P points.
 int box_chunk(int P, int elem_bytes, int max_lds);
 // Whether box sweeps of F frequencies per group on planes of P points keep two
-// alternating LDS sets (one barrier per plane): FP32 arithmetic, F == 1,
-// P <= 1024 and 2 (2F + 1) P elements within max_lds bytes.  RTSN_LAMBDA_PP=0
-// turns it off, =1 also allows it for FP64 and larger planes.
+// alternating LDS sets (one barrier per plane): F == 1, P <= 1024 and
+// 2 (2F + 1) P elements within max_lds bytes.  RTSN_LAMBDA_PP=0 turns it off,
+// =1 also allows it for larger planes.
 bool box_pingpong(int F, int P, int elem_bytes, int max_lds);
 // Size in elements of one part of the k4 operand; allocation of the
 // problem's (zeroed) two-part buffer.

@@ -63,6 +63,10 @@ BOXES = {
     "box_12x10x9": lambda: W.small_box(12, 4, 4, 3, nz=9, ny=10),
     "box16_shallow": lambda: W.small_box(16, 8, 8, 3, nz=6),
     "box_1x1x5": lambda: W.small_box(1, 2, 4, 2, nz=5, ny=1),
+    # planes of 257..1024 points (two points per thread, two LDS sets) and of
+    # more than 1024 (FP64: eight points per thread, one set)
+    "box_24x20x5": lambda: W.small_box(24, 2, 4, 2, nz=5, ny=20),
+    "box_40x36x4": lambda: W.small_box(40, 2, 4, 2, nz=4, ny=36),
 }
 
 ALL = {**SLABS, **BOXES}
