@@ -65,11 +65,11 @@ __device__ __forceinline__ double div_f64_normal(double num, double d) {
 //
 // BR: keep the two ranges as a branch that a wavefront whose lanes all fall
 // on one side skips the other side of (an empty volatile asm statement on
-// each side stops the compiler from evaluating both and selecting).  In FP64
-// the exponential and the division cost about twice the series, and in a
+// each side stops the compiler from evaluating both and selecting).  In a
 // box sweep the 64 points of a wavefront lie in one plane of one ray, with
-// nearly equal optical steps; slab rays put the whole depth range in one
-// wavefront, and FP32 sides are a handful of instructions, so both select.
+// nearly equal optical steps, so most wavefronts run one side (32^3 box:
+// FP64 0.299 -> 0.247 ms, FP32 0.141 -> 0.130 ms).  Slab rays put the whole
+// depth range in one wavefront and evaluate both sides and select.
 template <typename C, bool BR = false>
 __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
   if (d < C(0.5)) {
@@ -385,7 +385,7 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
           const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
           const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
           C e, a, c;
-          sc_weights<C, sizeof(C) == 8>(base * fac[f], e, a, c);
+          sc_weights<C, true>(base * fac[f], e, a, c);   // branch form
           I[f] = e * Iu + a * Su + c * Sv[f][j];
         }
       }
