@@ -6,7 +6,10 @@
 
 namespace rtsn {
 
-constexpr int kChunk = 4096;          // vector elements per reduction chunk
+// Vector elements per reduction chunk (batch512: 2048 and 4096 equal within
+// 1 % for FP32 bases, 2048 6 % faster with fp16 bases; 16384 leaves too few
+// chunks for the grid, -20 %).
+constexpr int kChunk = 2048;
 constexpr int kPersistBlocks = 1024;  // grid of the persistent work-list kernels
 
 // Everything one admitted solve needs on the device.  Pointers to tables are
