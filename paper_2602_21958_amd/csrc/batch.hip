@@ -584,8 +584,7 @@ void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists
     } else {
       if (wl.box_npt <= 1) { RT_BBOX(1, 1, 256); }
       else if (wl.box_npt <= 2) { RT_BBOX(1, 2, 512); }
-      else if (sizeof(C) == 4) { RT_BBOX(1, 4, 1024); }
-      else { RT_BBOX1(1, 8, 512, false); }
+      else { RT_BBOX(1, 4, 1024); }
     }
 #undef RT_BBOX
 #undef RT_BBOX1

@@ -185,18 +185,16 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     // planes up to 256 points: 256 threads; up to 1024 points: 512 threads of
     // 2 points each (FP64 with two LDS sets: 72 VGPRs, three groups per CU;
     // 256 threads of 4 points or 1024 threads of 1 point measured slower on
-    // the 32^3 box); larger planes: 1024 threads (FP32) or 512 threads (FP64,
-    // which needs twice the registers per point)
-    // (FP64 planes over 1024 points keep one set: the kernel needs no more
-    // LDS than lds holds whatever pp is)
+    // the 32^3 box); up to 4096 points: 1024 threads of 4 points (FP64: 128
+    // VGPRs with a few spilled, 16 waves per CU, 10.6 ms on the 64^3 box
+    // against 11.7 ms for 512 threads of 8 points at 250 VGPRs)
     if (F == 4) {
       if (P <= 256) RT_BOX_LAUNCH1(4, 1, 256, false);
       else RT_BOX_LAUNCH1(4, 1, 1024, false);
     } else {
       if (P <= 256) { RT_BOX_LAUNCH(1, 1, 256); }
       else if (P <= 1024) { RT_BOX_LAUNCH(1, 2, 512); }
-      else if (P <= 4096 && sizeof(C) == 4) { RT_BOX_LAUNCH(1, 4, 1024); }
-      else if (P <= 4096) { RT_BOX_LAUNCH1(1, 8, 512, false); }
+      else if (P <= 4096) { RT_BOX_LAUNCH(1, 4, 1024); }
       else {
         fail(RT_E_INVALID, "box plane larger than 4096 points");
       }

@@ -116,6 +116,26 @@ def test_batch_alone_equals_in_mix_bitwise(precision):
         assert np.array_equal(alone[0], mix[i]), i
 
 
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_batch_boxes_of_every_sweep_shape(precision):
+    """Boxes whose planes take each launch shape of the batched sweep (64,
+    480 and 1440 points: the largest plane of the engine picks the shape for
+    every box item) reach the oracle-checked residual, and a box gives the
+    same bits alone (its own shape) and in the mix (the largest one's)."""
+    specs = small_slabs(2, 4) + [W.small_box(8, 4, 8, 5),
+                                 W.small_box(24, 2, 4, 2, nz=5, ny=20),
+                                 W.small_box(40, 2, 4, 2, nz=4, ny=36)]
+    say(f"batch box shapes {precision}")
+    mix, mstats, _ = run_engine(specs, precision=precision)
+    for spec, s, st in zip(specs, mix, mstats):
+        assert st["converged"], st
+        assert OProblem(spec).residual_norm(s) <= 1.05e-8
+    for i in (2, 4):
+        alone, astats, _ = run_engine([specs[i]], precision=precision)
+        assert astats[0]["iters"] == mstats[i]["iters"]
+        assert np.array_equal(alone[0], mix[i]), i
+
+
 def test_batch_late_arrival_and_graph_replay():
     specs = small_slabs(5, 3)
     say("late arrival")
