@@ -265,6 +265,7 @@ bool Engine::setup_slot(Request* r, int s) {
   d.partial = reinterpret_cast<double*>(q);     q += align_up((size_t)(m + 2) * d.nch * 8);
   d.gs = reinterpret_cast<GmresState*>(q);
   d.x = r->x_out;
+  // (only the fp16 k4 operand is scaled; plain outputs ignore l_scale)
   d.l_scale = precision == RT_PREC_FP16 ? fp16_lambda_scale(p.n) : 1.f;
   d.vs = basis16 ? fp16_basis_scale(p.n) : 1.f;
   h_slots[s] = d;

@@ -153,6 +153,8 @@ template <typename VT, typename LT, int K4>
 void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int64_t Np,
                      bool with_bc, const double* scale, hipStream_t st, float out_mul) {
   using C = typename ComputeOf<VT>::type;
+  // plain outputs are stored unscaled (the kernels skip the multiply)
+  if (K4 < 0 && out_mul != 1.f) fail(RT_E_INVALID, "plain Lambda output takes no output scale");
   ProfScope prof(RT_KCLASS_LAMBDA, st);
   if (p.geom == RT_GEOM_SLAB) {
     dim3 grid((p.n_r + 3) / 4);

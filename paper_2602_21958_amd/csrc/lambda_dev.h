@@ -119,6 +119,7 @@ __device__ __forceinline__ LT store_val(C v) {
 // pointers are already offset to the ray, so element i is at [4 i].
 template <typename LT>
 struct PlainOut {
+  static constexpr bool kScaled = false;   // no output scale (out_mul is 1)
   LT* o;
   template <typename C>
   __device__ __forceinline__ void put(size_t i, C v) const { o[i] = store_val<C, LT>(v); }
@@ -132,6 +133,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float v) {
 
 template <int MODE>
 struct K4Out {
+  static constexpr bool kScaled = true;    // fp16 operands carry an output scale
   uint16_t* hi;
   uint16_t* lo;   // SPLIT only: v - bf16(v), rounded to bf16
   template <typename C>
@@ -151,6 +153,7 @@ struct K4Out {
 // Outputs of F consecutive rays k0 .. k0 + F - 1.
 template <typename LT>
 struct PlainOuts {
+  static constexpr bool kScaled = false;
   LT* o;          // ray k0
   size_t stride;  // elements per ray
   __device__ __forceinline__ bool grouped() const { return false; }
@@ -164,6 +167,7 @@ struct PlainOuts {
 
 template <int MODE>
 struct K4Outs {
+  static constexpr bool kScaled = true;
   uint16_t* hi;   // k4 buffer parts (not offset)
   uint16_t* lo;
   int64_t Np;
@@ -198,6 +202,14 @@ struct K4Outs {
                                                       (uint32_t)l[2] | ((uint32_t)l[3] << 16));
   }
 };
+
+// v times the output scale om where the output type takes one (a plain
+// output is never scaled, which saves a multiply per unknown).
+template <typename OUT, typename C>
+__device__ __forceinline__ C scaled_out(C v, C om) {
+  if constexpr (OUT::kScaled) return v * om;
+  else return v;
+}
 
 // 16-bit operand of ray k inside a k4 buffer (Np points per k4 group).
 template <int MODE>
@@ -266,7 +278,7 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
     C e, b;
     elem(q, e, b);
     I = e * I + b;
-    out.put(down ? q : nz - 1 - q, I * C(out_mul));
+    out.put(down ? q : nz - 1 - q, scaled_out<OUT>(I, C(out_mul)));
   }
 }
 
@@ -300,7 +312,7 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
                                          int nz, C i_in, C sc, float out_mul, C* smem) {
   const int P = nx * ny;
   const size_t set = (size_t)(2 * F + 1) * P;   // one set: K [P], I [F][P], S [F][P]
-  const C path = C(st.path);
+  const C hpath = C(0.5) * C(st.path);   // exact: (a / 2) path = a (path / 2)
   const C tx = C(st.tx), ty = C(st.ty);
   const size_t plane_stride = (size_t)P;
 
@@ -377,7 +389,7 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
         for (int f = 0; f < F; ++f) I[f] = i_in;
       } else {
         const C ku = w00 * rK[n00[j]] + w01 * rK[n01[j]] + w10 * rK[n10[j]] + w11 * rK[n11[j]];
-        const C base = C(0.5) * (ku + Kv[j]) * path;
+        const C base = (ku + Kv[j]) * hpath;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
           const C* If = rI + f * P;
@@ -391,16 +403,17 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
       }
       if constexpr (F == 4) {
         if (nf == 4 && out.grouped()) {   // all four rays of one k4 group are here
-          out.put4(oz + p, I[0] * om, I[1] * om, I[2] * om, I[3] * om);
+          out.put4(oz + p, scaled_out<OUT>(I[0], om), scaled_out<OUT>(I[1], om),
+                   scaled_out<OUT>(I[2], om), scaled_out<OUT>(I[3], om));
         } else {
 #pragma unroll
           for (int f = 0; f < F; ++f)
-            if (f < nf) out.put(f, oz + p, I[f] * om);
+            if (f < nf) out.put(f, oz + p, scaled_out<OUT>(I[f], om));
         }
       } else {
 #pragma unroll
         for (int f = 0; f < F; ++f)
-          if (f < nf) out.put(f, oz + p, I[f] * om);
+          if (f < nf) out.put(f, oz + p, scaled_out<OUT>(I[f], om));
       }
 #pragma unroll
       for (int f = 0; f < F; ++f) Iv[f][j] = I[f];
