@@ -103,7 +103,7 @@ def test_lambda_fp64(name, with_bc):
     assert relerr(got, ref) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9", "box_24x20x5", "box_40x36x4"])
 def test_lambda_fp32(name):
     rt = _rt()
     spec = ALL[name]()
