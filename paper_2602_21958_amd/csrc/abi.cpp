@@ -332,6 +332,37 @@ void operator_apply(Problem& p, int precision, const void* x, void* y, const dou
   }
 }
 
+void operator_apply_k(Problem& p, int precision, const void* x, void* y, const double* xscale,
+                      hipStream_t st, gemm::TileDots* dots) {
+  const size_t n = (size_t)p.n;
+  switch (precision) {
+    case RT_PREC_FP64: {
+      double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
+      launch_lambda<double, double>(p, static_cast<const double*>(x), L, false, xscale, st);
+      launch_sigma_f64(p, L, nullptr, static_cast<double*>(y), xscale, +1.0, st, dots);
+      break;
+    }
+    case RT_PREC_FP32: {
+      float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
+      launch_lambda<float, float>(p, static_cast<const float*>(x), L, false, xscale, st);
+      launch_sigma_f32(p, L, nullptr, static_cast<float*>(y), xscale, +1.0, st, dots);
+      break;
+    }
+    case RT_PREC_BF16:
+    case RT_PREC_FP16:
+    case RT_PREC_BF16X3: {
+      uint16_t* L = problem_l16(p, st);
+      uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
+      launch_lambda_k4(p, precision, static_cast<const float*>(x), L, Llo, xscale, st);
+      launch_sigma_b16(p, precision, L, Llo, nullptr, static_cast<float*>(y), xscale, +1.0, st,
+                       dots);
+      break;
+    }
+    default:
+      fail(RT_E_INVALID, "unknown precision");
+  }
+}
+
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st) {
   if (precision != RT_PREC_BF16 && precision != RT_PREC_FP16 && precision != RT_PREC_BF16X3)

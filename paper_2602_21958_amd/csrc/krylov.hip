@@ -353,7 +353,8 @@ __global__ __launch_bounds__(64) void finish_norm_kernel(const double* __restric
 // update's partial norms.  The first step whose residual estimate is <= tol,
 // breaks down or is not finite is recorded in stop_k, with its status.
 __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ partial, int nb,
-                                                    GmresState* st, int j, double tol) {
+                                                    GmresState* st, int j, double tol,
+                                                    int kform) {
   const int lane = threadIdx.x;
   double s = 0.0;
   for (int b = lane; b < nb; b += 64) s += partial[b];
@@ -361,9 +362,14 @@ __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ p
   if (lane != 0) return;
   const double hn = sqrt(s);
   double* col = st->R + (size_t)j * (kMaxRestart + 1);
-  for (int i = 0; i <= j; ++i) col[i] = st->h[i];
+  if (kform) {   // A v_j = v_j - K v_j
+    for (int i = 0; i <= j; ++i) col[i] = (i == j ? 1.0 : 0.0) - st->h[i];
+    col[j + 1] = -hn;
+  } else {
+    for (int i = 0; i <= j; ++i) col[i] = st->h[i];
+    col[j + 1] = hn;
+  }
   const double raw_diag = col[j];
-  col[j + 1] = hn;
   for (int i = 0; i < j; ++i) {
     const double t1 = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
     col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
@@ -624,9 +630,9 @@ void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStre
 }
 
 void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double tol,
-              hipStream_t st) {
+              hipStream_t st, int kform) {
   hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j,
-                     tol);
+                     tol, kform);
   RT_HIP(hipGetLastError());
 }
 

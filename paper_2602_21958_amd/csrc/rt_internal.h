@@ -168,6 +168,11 @@ int sigma_dot_slots(const Problem& p, int precision);
 void operator_apply(Problem& p, int precision, const void* x, void* y,
                     const double* xscale, hipStream_t st,
                     gemm::TileDots* dots = nullptr);
+// The scattering part alone, y = K (xs x) with K = (1 - eps) Mhat Lambda =
+// I - A (no x term: the GEMM epilogue reads no x).
+void operator_apply_k(Problem& p, int precision, const void* x, void* y,
+                      const double* xscale, hipStream_t st,
+                      gemm::TileDots* dots = nullptr);
 // 16-bit operator precisions on an fp16 basis: y = ymul A (xs x).
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st);

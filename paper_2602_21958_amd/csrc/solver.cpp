@@ -75,6 +75,17 @@ bool fuse_dots() {
   return e && e[0] == '1';
 }
 
+// Arnoldi on K = I - A instead of A (same Krylov space; A's Hessenberg
+// column follows as e_j - h and -beta): the operator then needs no x term,
+// so the GEMM epilogue reads no x.  RTSN_KFORM=0 runs Arnoldi on A.
+bool kform() {
+  static const bool k = [] {
+    const char* e = std::getenv("RTSN_KFORM");
+    return !(e && e[0] == '0');
+  }();
+  return k;
+}
+
 // basis_elem: bytes per basis element (8 FP64, 4 FP32, 2 fp16)
 Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab, int basis_elem) {
   Workspace* ws = p.ws;
@@ -210,18 +221,21 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
+      const bool kf = kform();
       if (fuse_dots()) {
         // h_q = vscale_q V_q . w, summed over the GEMM's output tiles in its epilogue
         gemm::TileDots d{V, n, j + 1, ws.partial, ws.dot_slots};
-        operator_apply(p, prec, vj, w, gs->vscale + j, st, &d);   // sets d.ldp = tiles
+        if (kf) operator_apply_k(p, prec, vj, w, gs->vscale + j, st, &d);   // sets d.ldp
+        else operator_apply(p, prec, vj, w, gs->vscale + j, st, &d);
         k_reduce_rows_nb(ws.partial, d.ldp, j + 1, gs->vscale, gs->h, st);
       } else {
-        operator_apply(p, prec, vj, w, gs->vscale + j, st);
+        if (kf) operator_apply_k(p, prec, vj, w, gs->vscale + j, st);
+        else operator_apply(p, prec, vj, w, gs->vscale + j, st);
         k_mdot<TV>(V, n, j + 1, w, ws.partial, st);
         k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
       }
       k_update<TV>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-      k_givens(ws.partial, n, gs, j, rtol * bnorm, st);
+      k_givens(ws.partial, n, gs, j, rtol * bnorm, st, kf ? 1 : 0);
       res.iters++;
       k = j + 1;
       if (k < m && res.iters < max_iters && k % every != 0) continue;
