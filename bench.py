@@ -38,11 +38,13 @@ PEAK_BF16_TFLOPS = 2500.0
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the dispatches of
 # one solve), scaled by what the same counters read for a 2 GiB device copy
 # (read x2.000, write x1.000).  Each entry holds a hash of the kernel's
-# sources at the time of measurement: once they change the figure is stale
-# and the bench reports null.
+# sources and of the code that chooses its launches (the solver decides
+# whether a GEMM reads x) at the time of measurement: once they change the
+# figure is stale and the bench reports null.
 TRAFFIC = {
-    "sigma_f64_box32": {"files": ("gemm_dev.h", "sigma_gemm.hip"), "sha": "1a9b6a2d5487372d",
-                        "fetch_kib": 1.924e6, "write_kib": 5.243e5,
+    "sigma_f64_box32": {"files": ("gemm_dev.h", "sigma_gemm.hip", "solver.cpp", "abi.cpp"),
+                        "sha": "6df6d412e297230b",
+                        "fetch_kib": 1.339e6, "write_kib": 5.243e5,
                         "fetch_scale": 2.000, "write_scale": 1.000,
                         "profile": "profiles/sigma_gemm_f64_box32_counters.md"},
 }

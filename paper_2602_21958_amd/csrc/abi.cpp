@@ -364,13 +364,16 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y, const d
 }
 
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
-                      const double* xscale, float ymul, hipStream_t st) {
+                      const double* xscale, float ymul, hipStream_t st, bool kform) {
   if (precision != RT_PREC_BF16 && precision != RT_PREC_FP16 && precision != RT_PREC_BF16X3)
     fail(RT_E_INVALID, "an fp16 basis needs a 16-bit operator precision");
   uint16_t* L = problem_l16(p, st);
   uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
   launch_lambda_k4(p, precision, x, L, Llo, xscale, st);
-  launch_sigma_b16_h(p, precision, L, Llo, x, y, ymul, xscale, -1.0, st);
+  if (kform)
+    launch_sigma_b16_h(p, precision, L, Llo, nullptr, y, ymul, xscale, +1.0, st);
+  else
+    launch_sigma_b16_h(p, precision, L, Llo, x, y, ymul, xscale, -1.0, st);
 }
 
 const double* physical_rhs(Problem& p, hipStream_t st) {

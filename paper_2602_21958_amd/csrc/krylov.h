@@ -56,10 +56,11 @@ void k_finish_norm(const double* partial, int64_t n, GmresState* gs, int start_c
                    hipStream_t st);
 void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStream_t st);
 // Givens step j; tol: residual-estimate threshold that stops the cycle.
-// kform: h and the norm are those of Arnoldi on K = I - A (K v_j =
-// sum_i h_i v_i + beta v_{j+1}); the step uses A's column e_j - h, -beta.
+// kdiag != 0: h and the norm are those of Arnoldi on c K where c A =
+// c I - c K and kdiag = c (K v_j = sum_i h_i v_i + beta v_{j+1}); the step
+// uses the column kdiag e_j - h, -beta of c A.
 void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double tol,
-              hipStream_t st, int kform = 0);
+              hipStream_t st, double kdiag = 0.0);
 void k_solve_r(GmresState* gs, int k, hipStream_t st);
 template <typename T>
 void k_dots4(const T* a0, const T* b0, const T* a1, const T* b1, int cnt, int64_t n,

@@ -354,7 +354,7 @@ __global__ __launch_bounds__(64) void finish_norm_kernel(const double* __restric
 // breaks down or is not finite is recorded in stop_k, with its status.
 __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ partial, int nb,
                                                     GmresState* st, int j, double tol,
-                                                    int kform) {
+                                                    double kdiag) {
   const int lane = threadIdx.x;
   double s = 0.0;
   for (int b = lane; b < nb; b += 64) s += partial[b];
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ p
   if (lane != 0) return;
   const double hn = sqrt(s);
   double* col = st->R + (size_t)j * (kMaxRestart + 1);
-  if (kform) {   // A v_j = v_j - K v_j
-    for (int i = 0; i <= j; ++i) col[i] = (i == j ? 1.0 : 0.0) - st->h[i];
+  if (kdiag != 0.0) {   // c A v_j = c v_j - c K v_j
+    for (int i = 0; i <= j; ++i) col[i] = (i == j ? kdiag : 0.0) - st->h[i];
     col[j + 1] = -hn;
   } else {
     for (int i = 0; i <= j; ++i) col[i] = st->h[i];
@@ -630,9 +630,9 @@ void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStre
 }
 
 void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double tol,
-              hipStream_t st, int kform) {
+              hipStream_t st, double kdiag) {
   hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j,
-                     tol, kform);
+                     tol, kdiag);
   RT_HIP(hipGetLastError());
 }
 

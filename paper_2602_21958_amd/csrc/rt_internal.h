@@ -173,9 +173,10 @@ void operator_apply(Problem& p, int precision, const void* x, void* y,
 void operator_apply_k(Problem& p, int precision, const void* x, void* y,
                       const double* xscale, hipStream_t st,
                       gemm::TileDots* dots = nullptr);
-// 16-bit operator precisions on an fp16 basis: y = ymul A (xs x).
+// 16-bit operator precisions on an fp16 basis: y = ymul A (xs x), or with
+// kform y = ymul K (xs x) (no x term).
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
-                      const double* xscale, float ymul, hipStream_t st);
+                      const double* xscale, float ymul, hipStream_t st, bool kform = false);
 size_t lambda_elem_bytes(int precision);
 const double* physical_rhs(Problem& p, hipStream_t st);
 

@@ -235,7 +235,7 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
         k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
       }
       k_update<TV>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-      k_givens(ws.partial, n, gs, j, rtol * bnorm, st, kf ? 1 : 0);
+      k_givens(ws.partial, n, gs, j, rtol * bnorm, st, kf ? 1.0 : 0.0);
       res.iters++;
       k = j + 1;
       if (k < m && res.iters < max_iters && k % every != 0) continue;
@@ -285,11 +285,12 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
   const int steps = std::min(m, cap), every = status_every(n);
   for (int j = 0; j < steps; ++j) {
     _Float16* w = V + (size_t)(j + 1) * n;
-    operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st);
+    const bool kf = kform();   // Arnoldi on S K: S A = S I - S K
+    operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, kf);
     k_mdot<_Float16>(V, n, j + 1, w, ws.partial, st);
     k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
     k_update<_Float16>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-    k_givens(ws.partial, n, gs, j, itol * s0.beta, st);
+    k_givens(ws.partial, n, gs, j, itol * s0.beta, st, kf ? (double)S : 0.0);
     k = j + 1;
     if (k < steps && k % every != 0) continue;
     const StepRead r = read_steps(ws, st, k, logged, nullptr, 1.0);
