@@ -168,6 +168,8 @@ int sigma_dot_slots(const Problem& p, int precision);
 void operator_apply(Problem& p, int precision, const void* x, void* y,
                     const double* xscale, hipStream_t st,
                     gemm::TileDots* dots = nullptr);
+// Whether GMRES runs Arnoldi on K = I - A (default) rather than on A.
+bool kform();
 // The scattering part alone, y = K (xs x) with K = (1 - eps) Mhat Lambda =
 // I - A (no x term: the GEMM epilogue reads no x).
 void operator_apply_k(Problem& p, int precision, const void* x, void* y,

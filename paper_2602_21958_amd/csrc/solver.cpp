@@ -21,6 +21,17 @@
 
 namespace rtsn {
 
+// Arnoldi on K = I - A instead of A (same Krylov space; A's Hessenberg
+// column follows as e_j - h and -beta): the operator then needs no x term,
+// so the GEMM epilogue reads no x.  RTSN_KFORM=0 runs Arnoldi on A.
+bool kform() {
+  static const bool k = [] {
+    const char* e = std::getenv("RTSN_KFORM");
+    return !(e && e[0] == '0');
+  }();
+  return k;
+}
+
 Workspace::~Workspace() {
   hipFree(V);
   hipFree(partial);
@@ -75,16 +86,7 @@ bool fuse_dots() {
   return e && e[0] == '1';
 }
 
-// Arnoldi on K = I - A instead of A (same Krylov space; A's Hessenberg
-// column follows as e_j - h and -beta): the operator then needs no x term,
-// so the GEMM epilogue reads no x.  RTSN_KFORM=0 runs Arnoldi on A.
-bool kform() {
-  static const bool k = [] {
-    const char* e = std::getenv("RTSN_KFORM");
-    return !(e && e[0] == '0');
-  }();
-  return k;
-}
+
 
 // basis_elem: bytes per basis element (8 FP64, 4 FP32, 2 fp16)
 Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab, int basis_elem) {
