@@ -209,6 +209,15 @@ typedef struct {
                              (1 - eps) |Mhat| sums to more than 2 (possible
                              only with an explicit kernel; the physical kernels
                              give about 1), which the basis scale assumes.      */
+  int two_step;           /* FP64 GMRES: take the Arnoldi steps in pairs, u1 = K v_j
+                             and u2 = K u1 with K = I - A, orthogonalised together
+                             with one pass over the basis for the dots and one
+                             for the update instead of two each (default 0).
+                             Same Krylov spaces and iterates in exact
+                             arithmetic; in floating point the residual
+                             estimates drift from the one-step ones by up to
+                             a few 1e-8 relative after 20 steps (monomial pair
+                             basis).  Ignored in mixed precision and BiCGStab.  */
 } rt_solver_opts;
 
 typedef struct {

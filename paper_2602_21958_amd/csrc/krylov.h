@@ -6,6 +6,7 @@
 namespace rtsn {
 
 constexpr int kMaxRestart = 128;
+constexpr int kPairRows = kMaxRestart + 2;   // two-step Arnoldi: rows per dot block
 constexpr int kReduceBlocks = 1024;  // dots; the update pass uses twice as many
 
 // GMRES state kept in device memory.  The fields before h are what the host
@@ -62,6 +63,19 @@ void k_finish_norm_simple(const double* partial, int64_t n, double* out, hipStre
 void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double tol,
               hipStream_t st, double kdiag = 0.0);
 void k_solve_r(GmresState* gs, int k, hipStream_t st);
+// Two Arnoldi steps on K at once (FP64 basis): u1 = K v_j in slot j + 1 and
+// u2 = K u1 in slot j + 2 become v_{j+1}, v_{j+2} (stored unnormalised with
+// their scales) with one dots pass and one update pass over v_0..v_j.
+// pair: 8 + 4 kPairRows doubles; hk: kPairRows^2 doubles (K's Hessenberg
+// columns of the cycle).
+void k_mdot2(const double* V, int64_t n, int cnt, const double* u1, const double* u2,
+             double* partial, hipStream_t st);
+void k_pair_coef(const double* partial, int64_t n, int j, const double* vscale, double* pair,
+                 hipStream_t st);
+void k_update2(const double* V, int64_t n, int cnt, const double* pair, double* u1, double* u2,
+               double* partial, hipStream_t st);
+void k_givens2(const double* partial, int64_t n, GmresState* gs, int j, double tol,
+               const double* pair, double* hk, hipStream_t st);
 template <typename T>
 void k_dots4(const T* a0, const T* b0, const T* a1, const T* b1, int cnt, int64_t n,
              double* partial, hipStream_t st);
@@ -97,6 +111,8 @@ struct Workspace {
   float* d32 = nullptr;         // n: inner correction (mixed)
   float* t32 = nullptr;         // n: scaled residual, inner right-hand side (mixed)
   float* a32 = nullptr;         // n: inner operator output (mixed)
+  double* pair = nullptr;       // two-step Arnoldi coefficients (8 + 4 kPairRows)
+  double* hk = nullptr;         // K's Hessenberg columns of a cycle (kPairRows^2)
   GmresState* host = nullptr;   // pinned status mirror
   ~Workspace();
 };

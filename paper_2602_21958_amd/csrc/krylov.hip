@@ -349,26 +349,14 @@ __global__ __launch_bounds__(64) void finish_norm_kernel(const double* __restric
   }
 }
 
-// Givens step j: column h[0..j] (already scaled dots), h_{j+1,j} from the
-// update's partial norms.  The first step whose residual estimate is <= tol,
-// breaks down or is not finite is recorded in stop_k, with its status.
-__global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ partial, int nb,
-                                                    GmresState* st, int j, double tol,
-                                                    double kdiag) {
-  const int lane = threadIdx.x;
-  double s = 0.0;
-  for (int b = lane; b < nb; b += 64) s += partial[b];
-  s = wave_sum(s);
-  if (lane != 0) return;
-  const double hn = sqrt(s);
+// Givens step j on the Hessenberg column already in R's column j (rows
+// 0..j+1; hn = |h_{j+1,j}|, the norm of the new basis vector before
+// scaling): rotations, g, 1/hn as the new vector's scale, the residual
+// estimate and the stop record.  The first step whose residual estimate is
+// <= tol, breaks down or is not finite is recorded in stop_k, with its
+// status.
+__device__ void givens_step(GmresState* st, int j, double hn, double tol) {
   double* col = st->R + (size_t)j * (kMaxRestart + 1);
-  if (kdiag != 0.0) {   // c A v_j = c v_j - c K v_j
-    for (int i = 0; i <= j; ++i) col[i] = (i == j ? kdiag : 0.0) - st->h[i];
-    col[j + 1] = -hn;
-  } else {
-    for (int i = 0; i <= j; ++i) col[i] = st->h[i];
-    col[j + 1] = hn;
-  }
   const double raw_diag = col[j];
   for (int i = 0; i < j; ++i) {
     const double t1 = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
@@ -398,6 +386,232 @@ __global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ p
     st->nonfinite = nonfinite;
     if (resid <= tol || breakdown || nonfinite) st->stop_k = j + 1;
   }
+}
+
+// Givens step j: column h[0..j] (already scaled dots), h_{j+1,j} from the
+// update's partial norms.
+__global__ __launch_bounds__(64) void givens_kernel(const double* __restrict__ partial, int nb,
+                                                    GmresState* st, int j, double tol,
+                                                    double kdiag) {
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += partial[b];
+  s = wave_sum(s);
+  if (lane != 0) return;
+  const double hn = sqrt(s);
+  double* col = st->R + (size_t)j * (kMaxRestart + 1);
+  if (kdiag != 0.0) {   // c A v_j = c v_j - c K v_j
+    for (int i = 0; i <= j; ++i) col[i] = (i == j ? kdiag : 0.0) - st->h[i];
+    col[j + 1] = -hn;
+  } else {
+    for (int i = 0; i <= j; ++i) col[i] = st->h[i];
+    col[j + 1] = hn;
+  }
+  givens_step(st, j, hn, tol);
+}
+
+// ------------------------------------------------- two Arnoldi steps at once
+// Steps j and j + 1 on K from u1 = K v_j and u2 = K u1 (in basis slots j + 1
+// and j + 2), with one pass over the basis for the dots and one for the
+// update instead of two each.  With c1 = V^T u1, c2 = V^T u2 (V = v_0..v_j,
+// unit vectors), g11 = |u1|^2 and g12 = u1 . u2:
+//   P1 = u1 - V c1,            v_{j+1} = P1 / |P1|,
+//   nu = (g12 - c1 . c2) / (g11 - |c1|^2)     (the P1 component of u2 - V c2),
+//   Z  = u2 - nu u1 - V (c2 - nu c1) = u2 - V c2 - nu P1,   v_{j+2} = Z / |Z|.
+// K P1 = u2 - K V c1 = u2 - V p - c1_j P1 with p = t + c1_j c1 and
+// t_l = sum_{i<j} c1_i Hk_{l,i} (K's earlier Hessenberg columns), so
+//   K v_j     = V c1 + |P1| v_{j+1},
+//   K v_{j+1} = V (c2 - p) / |P1| + (nu - c1_j) v_{j+1} + |Z| / |P1| v_{j+2},
+// an exact identity whatever rounding nu carries; |P1| and |Z| are the
+// norms of the stored vectors, summed by the update pass.  Hk is kept per
+// cycle for the t of later pairs.
+
+template <typename TV, int G>
+__global__ __launch_bounds__(kThreads) void mdot2_kernel(const TV* __restrict__ V, int64_t n,
+                                                         int i0, int cnt,
+                                                         const TV* __restrict__ u1,
+                                                         const TV* __restrict__ u2,
+                                                         double* __restrict__ partial) {
+  using VT = typename Vec16<TV>::type;
+  constexpr int W = Vec16<TV>::n;
+  double a1[G], a2[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) a1[g] = a2[g] = 0.0;
+  if (n % W == 0) {
+    int64_t b0, b1;
+    block_range(n / W, b0, b1);
+    const VT* x1v = reinterpret_cast<const VT*>(u1);
+    const VT* x2v = reinterpret_cast<const VT*>(u2);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const VT x1 = x1v[e], x2 = x2v[e];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (g < cnt) {
+          const VT v = reinterpret_cast<const VT*>(V + (size_t)(i0 + g) * n)[e];
+          a1[g] += Vec16<TV>::dot(v, x1);
+          a2[g] += Vec16<TV>::dot(v, x2);
+        }
+    }
+  } else {
+    int64_t b0, b1;
+    block_range(n, b0, b1);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const double x1 = (double)u1[e], x2 = (double)u2[e];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (g < cnt) {
+          const double v = (double)V[(size_t)(i0 + g) * n + e];
+          a1[g] += v * x1;
+          a2[g] += v * x2;
+        }
+    }
+  }
+  block_reduce_store<G>(a1, partial + (size_t)i0 * gridDim.x + blockIdx.x, gridDim.x, cnt);
+  block_reduce_store<G>(a2, partial + (size_t)(kPairRows + i0) * gridDim.x + blockIdx.x,
+                        gridDim.x, cnt);
+}
+
+// pair[] layout: [0] nu, then c1, c2, the update coefficients k1 = c1 s,
+// k2 = (c2 - nu c1) s (s: the basis scales), kPairRows each.
+constexpr int kPairC1 = 8, kPairC2 = kPairC1 + kPairRows, kPairK1 = kPairC2 + kPairRows,
+              kPairK2 = kPairK1 + kPairRows;
+
+__global__ __launch_bounds__(kThreads) void pair_coef_kernel(const double* __restrict__ partial,
+                                                             int nb, int j,
+                                                             const double* __restrict__ vscale,
+                                                             double* __restrict__ pair) {
+  __shared__ double c1[kPairRows], c2[kPairRows];
+  __shared__ double nu_s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q <= j + 1; q += kThreads / 64) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = lane; b < nb; b += 64) {
+      s1 += partial[(size_t)q * nb + b];
+      s2 += partial[(size_t)(kPairRows + q) * nb + b];
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      const double sc = q <= j ? vscale[q] : 1.0;   // row j + 1: u1 itself
+      c1[q] = sc * s1;
+      c2[q] = sc * s2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double n1 = 0.0, d12 = 0.0;
+    for (int q = 0; q <= j; ++q) {
+      n1 += c1[q] * c1[q];
+      d12 += c1[q] * c2[q];
+    }
+    const double b2 = c1[j + 1] - n1;   // |P1|^2 by Pythagoras (only for nu)
+    const double nu = b2 > 0.0 ? (c2[j + 1] - d12) / b2 : 0.0;
+    nu_s = nu;
+    pair[0] = nu;
+  }
+  __syncthreads();
+  const double nu = nu_s;
+  for (int q = threadIdx.x; q <= j; q += kThreads) {
+    pair[kPairC1 + q] = c1[q];
+    pair[kPairC2 + q] = c2[q];
+    pair[kPairK1 + q] = c1[q] * vscale[q];
+    pair[kPairK2 + q] = (c2[q] - nu * c1[q]) * vscale[q];
+  }
+}
+
+// u1 <- P1 = u1 - sum k1_q W_q, u2 <- Z = u2 - nu u1 - sum k2_q W_q in one
+// pass over W_0..W_j; partial[b] = block b's |P1|^2, partial[nb + b] its |Z|^2.
+// FP64: one element per thread, grid-stride, eight basis loads in flight.
+__global__ __launch_bounds__(kThreads) void update2_kernel(const double* __restrict__ V,
+                                                           int64_t n, int cnt,
+                                                           const double* __restrict__ pair,
+                                                           double* __restrict__ u1,
+                                                           double* __restrict__ u2,
+                                                           double* __restrict__ partial) {
+  __shared__ double k1[kMaxRestart + 1], k2[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+    k1[i] = pair[kPairK1 + i];
+    k2[i] = pair[kPairK2 + i];
+  }
+  __syncthreads();
+  const double nu = pair[0];
+  double n1 = 0.0, nz = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const double a = u1[e], b = u2[e];
+    double s1 = 0.0, s2 = 0.0;
+    int i = 0;
+    for (; i + 8 <= cnt; i += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(i + u) * n + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s1 += k1[i + u] * v[u];
+        s2 += k2[i + u] * v[u];
+      }
+    }
+    for (; i < cnt; ++i) {
+      const double v = V[(size_t)i * n + e];
+      s1 += k1[i] * v;
+      s2 += k2[i] * v;
+    }
+    const double p1 = a - s1;
+    const double z = (b - nu * a) - s2;
+    u1[e] = p1;
+    u2[e] = z;
+    n1 += p1 * p1;
+    nz += z * z;
+  }
+  double acc[2] = {n1, nz};
+  block_reduce_store<2>(acc, partial + blockIdx.x, gridDim.x, 2);
+}
+
+// Hessenberg columns j and j + 1 of K (kept in hk, column i at i * kPairRows)
+// from the pair's dots and norms, turned into A's (e_i - h, -h_sub) and
+// given to two Givens steps; the second is skipped once the first stopped.
+__global__ __launch_bounds__(64) void givens2_kernel(const double* __restrict__ partial, int nb,
+                                                     GmresState* st, int j, double tol,
+                                                     const double* __restrict__ pair,
+                                                     double* __restrict__ hk) {
+  const int lane = threadIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    s1 += partial[b];
+    s2 += partial[nb + b];
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane != 0) return;
+  const double np1 = sqrt(s1), nz = sqrt(s2);
+  const double nu = pair[0];
+  const double* c1 = pair + kPairC1;
+  const double* c2 = pair + kPairC2;
+  double* h0 = hk + (size_t)j * kPairRows;         // K's column j
+  double* h1 = hk + (size_t)(j + 1) * kPairRows;   // K's column j + 1
+  for (int i = 0; i <= j; ++i) h0[i] = c1[i];
+  h0[j + 1] = np1;
+  double* col = st->R + (size_t)j * (kMaxRestart + 1);
+  for (int i = 0; i <= j; ++i) col[i] = (i == j ? 1.0 : 0.0) - h0[i];
+  col[j + 1] = -np1;
+  const int stopped_before = st->stop_k != 0;
+  givens_step(st, j, np1, tol);
+  // p = t + c1_j c1, t_l = sum_{i<j} c1_i hk_{l,i} (column i has rows 0..i+1)
+  const double inv = np1 > 0.0 ? 1.0 / np1 : 0.0;
+  for (int l = 0; l <= j; ++l) {
+    double t = 0.0;
+    for (int i = (l > 0 ? l - 1 : 0); i < j; ++i) t += c1[i] * hk[(size_t)i * kPairRows + l];
+    h1[l] = (c2[l] - (t + c1[j] * c1[l])) * inv;
+  }
+  h1[j + 1] = nu - c1[j];
+  h1[j + 2] = nz * inv;
+  if (!stopped_before && st->stop_k != 0) return;   // the pair's first step ended the cycle
+  col = st->R + (size_t)(j + 1) * (kMaxRestart + 1);
+  for (int i = 0; i <= j + 1; ++i) col[i] = (i == j + 1 ? 1.0 : 0.0) - h1[i];
+  col[j + 2] = -h1[j + 2];
+  givens_step(st, j + 1, h1[j + 2], tol);
+  // v_{j+2} = Z / |Z|: givens_step stored 1 / h_{j+2,j+1} = |P1| / |Z|
+  st->vscale[j + 2] = st->vscale[j + 2] == 0.0 ? 0.0 : 1.0 / nz;
 }
 
 // Back substitution R y = g (k x k), coef_i = y_i * vscale_i.
@@ -633,6 +847,40 @@ void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double to
               hipStream_t st, double kdiag) {
   hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j,
                      tol, kdiag);
+  RT_HIP(hipGetLastError());
+}
+
+void k_mdot2(const double* V, int64_t n, int cnt, const double* u1, const double* u2,
+             double* partial, hipStream_t st) {
+  const int nb = grid_for(n);
+  ProfScope prof(RT_KCLASS_ARNOLDI, st);
+  for (int i0 = 0; i0 < cnt; i0 += 8) {
+    const int c = cnt - i0 < 8 ? cnt - i0 : 8;
+    hipLaunchKernelGGL((mdot2_kernel<double, 8>), dim3(nb), dim3(kThreads), 0, st, V, n, i0, c,
+                       u1, u2, partial);
+  }
+  RT_HIP(hipGetLastError());
+}
+
+void k_pair_coef(const double* partial, int64_t n, int j, const double* vscale, double* pair,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(pair_coef_kernel, dim3(1), dim3(kThreads), 0, st, partial, grid_for(n), j,
+                     vscale, pair);
+  RT_HIP(hipGetLastError());
+}
+
+void k_update2(const double* V, int64_t n, int cnt, const double* pair, double* u1, double* u2,
+               double* partial, hipStream_t st) {
+  ProfScope prof(RT_KCLASS_ARNOLDI, st);
+  hipLaunchKernelGGL(update2_kernel, dim3(grid_update(n)), dim3(kThreads), 0, st, V, n, cnt,
+                     pair, u1, u2, partial);
+  RT_HIP(hipGetLastError());
+}
+
+void k_givens2(const double* partial, int64_t n, GmresState* gs, int j, double tol,
+               const double* pair, double* hk, hipStream_t st) {
+  hipLaunchKernelGGL(givens2_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j,
+                     tol, pair, hk);
   RT_HIP(hipGetLastError());
 }
 

@@ -11,6 +11,7 @@
 //   the inner basis is kept in fp16, scaled to entries of order one.
 // * BiCGStab (van der Vorst), FP64, scalars kept on the device.
 #include <algorithm>
+#include <type_traits>
 #include <cstdlib>
 #include <chrono>
 #include <cmath>
@@ -28,6 +29,16 @@ bool kform() {
   static const bool k = [] {
     const char* e = std::getenv("RTSN_KFORM");
     return !(e && e[0] == '0');
+  }();
+  return k;
+}
+
+// Two Arnoldi steps per pass over the basis (FP64 GMRES on K) for every
+// solve: RTSN_SSTEP=2 (otherwise per solve with rt_solver_opts.two_step).
+bool two_step() {
+  static const bool k = [] {
+    const char* e = std::getenv("RTSN_SSTEP");
+    return e && std::atoi(e) == 2;
   }();
   return k;
 }
@@ -109,10 +120,13 @@ Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab, 
   // the dots fused into the Sigma GEMM one slot per output tile and basis
   // vector (the 16-bit GEMM's smallest tile gives the most slots)
   ws->dot_slots = sigma_dot_slots(p, RT_PREC_BF16);
-  ws->partial_elems = std::max((size_t)(kMaxRestart + 1) * 2 * kReduceBlocks,
-                               (size_t)(restart + 1) * ws->dot_slots);
+  ws->partial_elems = std::max({(size_t)(kMaxRestart + 1) * 2 * kReduceBlocks,
+                                (size_t)2 * kPairRows * kReduceBlocks,
+                                (size_t)(restart + 1) * ws->dot_slots});
   ws->partial = dalloc<double>(ws->partial_elems, tot);
   ws->gs = dalloc<GmresState>(1, tot);
+  ws->pair = dalloc<double>(8 + 4 * kPairRows, tot);
+  ws->hk = dalloc<double>((size_t)kPairRows * kPairRows, tot);
   ws->bs = dalloc<BicgState>(1, tot);
   ws->scal = dalloc<double>(64, tot);
   ws->r64 = dalloc<double>(n, tot);
@@ -199,7 +213,8 @@ struct CoreResult {
 template <typename TV>
 rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int m, double rtol,
                      int max_iters, double bnorm, Workspace& ws, TV* tmp, hipStream_t st,
-                     std::vector<double>* hist, CoreResult& res, bool single_cycle = false) {
+                     std::vector<double>* hist, CoreResult& res, bool single_cycle = false,
+                     bool two = false) {
   const int64_t n = p.n;
   TV* V = static_cast<TV*>(ws.V);
   GmresState* gs = ws.gs;
@@ -220,9 +235,32 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   while (s.beta > rtol * bnorm && res.iters < max_iters) {
     res.cycles++;
     int k = 0, logged = 0;
+    const bool pairs = std::is_same<TV, double>::value && kform() && (two || two_step()) &&
+                       !fuse_dots();
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
+      if (pairs && j + 1 < m && res.iters + 2 <= max_iters) {
+        // steps j and j + 1: u1 = K v_j, u2 = K u1, one dots and one update pass
+        double* Vd = reinterpret_cast<double*>(V);
+        double* u1 = Vd + (size_t)(j + 1) * n;
+        double* u2 = Vd + (size_t)(j + 2) * n;
+        operator_apply_k(p, prec, Vd + (size_t)j * n, u1, gs->vscale + j, st);
+        operator_apply_k(p, prec, u1, u2, nullptr, st);
+        k_mdot2(Vd, n, j + 2, u1, u2, ws.partial, st);
+        k_pair_coef(ws.partial, n, j, gs->vscale, ws.pair, st);
+        k_update2(Vd, n, j + 1, ws.pair, u1, u2, ws.partial, st);
+        k_givens2(ws.partial, n, gs, j, rtol * bnorm, ws.pair, ws.hk, st);
+        res.iters += 2;
+        ++j;
+        k = j + 1;
+        if (k < m && res.iters < max_iters && k % every != 0 && (k - 1) % every != 0) continue;
+        const StepRead r = read_steps(ws, st, k, logged, hist, bnorm);
+        res.iters -= k - r.k;
+        k = r.k;
+        if (r.stop || res.iters >= max_iters) break;
+        continue;
+      }
       const bool kf = kform();
       if (fuse_dots()) {
         // h_q = vscale_q V_q . w, summed over the GEMM's output tiles in its epilogue
@@ -402,7 +440,8 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
     if (hist) hist->push_back(0.0);
   } else if (!mixed && !bicg) {
     status = gmres_core<double>(p, RT_PREC_FP64, b, x, !x_is_guess, o.restart, o.rtol,
-                                o.max_iters, bnorm, ws, ws.ax64, st, hist, res);
+                                o.max_iters, bnorm, ws, ws.ax64, st, hist, res, false,
+                                o.two_step != 0);
     outer = res.cycles;
   } else if (!mixed && bicg) {
     status = bicgstab_fp64(p, b, x, !x_is_guess, o.rtol, o.max_iters, bnorm, ws, st, hist, res);

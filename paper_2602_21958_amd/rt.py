@@ -64,7 +64,8 @@ class ProblemInfo(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("krylov", C.c_int), ("restart", C.c_int), ("max_iters", C.c_int),
                 ("rtol", C.c_double), ("precision", C.c_int), ("inner_rtol", C.c_double),
-                ("max_outer", C.c_int), ("record_history", C.c_int), ("basis_fp16", C.c_int)]
+                ("max_outer", C.c_int), ("record_history", C.c_int), ("basis_fp16", C.c_int),
+                ("two_step", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -264,7 +265,7 @@ class Problem:
     def solve(self, x, b=None, x_is_guess: bool = False, stream=None, **opts):
         """Solve A s = b (b None: physical rhs).  opts: krylov, restart,
         max_iters, rtol, precision, inner_rtol, max_outer, record_history,
-        basis_fp16.
+        basis_fp16, two_step.
         Returns a dict of solve statistics; raises on errors other than
         RT_NOT_CONVERGED."""
         o = default_opts()
