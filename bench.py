@@ -43,8 +43,8 @@ PEAK_BF16_TFLOPS = 2500.0
 # figure is stale and the bench reports null.
 TRAFFIC = {
     "sigma_f64_box32": {"files": ("gemm_dev.h", "sigma_gemm.hip", "solver.cpp", "abi.cpp"),
-                        "sha": "ad1bb04673c9d01d",
-                        "fetch_kib": 1.339e6, "write_kib": 5.243e5,
+                        "sha": "2c541f070fc6db98",
+                        "fetch_kib": 1.335e6, "write_kib": 5.243e5,
                         "fetch_scale": 2.000, "write_scale": 1.000,
                         "profile": "profiles/sigma_gemm_f64_box32_counters.md"},
 }
@@ -238,24 +238,24 @@ def main():
         "arnoldi": {"launches": arn_n, "total_ms_per_solve": arn_ms / args.steps},
     }
 
-    # the same FP64 solve with the Arnoldi steps in pairs (two_step: one dots
-    # and one update pass over the basis per two steps)
+    # the same FP64 solve with one Arnoldi step per pass over the basis (the
+    # library's default takes them in pairs: one dots and one update pass
+    # over the basis per two steps)
     x2 = torch.empty_like(x)
-    p.solve(x2, rtol=1e-8, restart=30, two_step=1, stream=stream)  # warm
+    p.solve(x2, rtol=1e-8, restart=30, two_step=0, stream=stream)  # warm
     torch.cuda.synchronize()
     rt.profile_enable(True)
     rt.profile_read("arnoldi", reset=True)
     t2a = time.perf_counter()
     st2 = None
     for _ in range(args.steps):
-        st2 = p.solve(x2, rtol=1e-8, restart=30, two_step=1, stream=stream)
+        st2 = p.solve(x2, rtol=1e-8, restart=30, two_step=0, stream=stream)
     torch.cuda.synchronize()
     t2b = time.perf_counter()
     rt.profile_enable(False)
     a2_n, a2_ms = rt.profile_read("arnoldi", reset=True)
-    out["fp64_two_step"] = {
+    out["fp64_one_step"] = {
         "value": args.steps / (t2b - t2a), "unit": "solves/s",
-        "speedup_vs_fp64": (args.steps / (t2b - t2a)) / value,
         "converged": st2["converged"], "relres": st2["relres"], "iters": st2["iters"],
         "rel_diff_vs_fp64_solution":
             (torch.linalg.vector_norm(x2 - x) / torch.linalg.vector_norm(x)).item(),

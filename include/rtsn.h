@@ -212,12 +212,12 @@ typedef struct {
   int two_step;           /* FP64 GMRES: take the Arnoldi steps in pairs, u1 = K v_j
                              and u2 = K u1 with K = I - A, orthogonalised together
                              with one pass over the basis for the dots and one
-                             for the update instead of two each (default 0).
-                             Same Krylov spaces and iterates in exact
-                             arithmetic; in floating point the residual
-                             estimates drift from the one-step ones by up to
-                             a few 1e-8 relative after 20 steps (monomial pair
-                             basis).  Ignored in mixed precision and BiCGStab.  */
+                             for the update instead of two each, plus one pass
+                             over the pair that removes the new vector's
+                             component along the first (default 1; 0: one
+                             step per pass).  Same Krylov spaces and iterates
+                             in exact arithmetic.  Ignored in mixed precision
+                             and BiCGStab.                                        */
 } rt_solver_opts;
 
 typedef struct {

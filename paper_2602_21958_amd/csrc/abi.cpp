@@ -583,6 +583,7 @@ void rt_solver_opts_default(rt_solver_opts* o) {
   o->inner_rtol = 1e-3;
   o->max_outer = 50;
   o->record_history = 1;
+  o->two_step = 1;
 }
 
 rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, double* x,

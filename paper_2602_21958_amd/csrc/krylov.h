@@ -74,6 +74,10 @@ void k_pair_coef(const double* partial, int64_t n, int j, const double* vscale, 
                  hipStream_t st);
 void k_update2(const double* V, int64_t n, int cnt, const double* pair, double* u1, double* u2,
                double* partial, hipStream_t st);
+// Z <- Z - rho P1 with rho = P1 . Z / |P1|^2 from the update's sums (the
+// P1 component that nu's rounding leaves); |Z|^2 recomputed.
+void k_pair_fix(double* p1, double* z, int64_t n, double* pair, double* partial,
+                hipStream_t st);
 void k_givens2(const double* partial, int64_t n, GmresState* gs, int j, double tol,
                const double* pair, double* hk, hipStream_t st);
 template <typename T>

@@ -520,7 +520,8 @@ __global__ __launch_bounds__(kThreads) void pair_coef_kernel(const double* __res
 }
 
 // u1 <- P1 = u1 - sum k1_q W_q, u2 <- Z = u2 - nu u1 - sum k2_q W_q in one
-// pass over W_0..W_j; partial[b] = block b's |P1|^2, partial[nb + b] its |Z|^2.
+// pass over W_0..W_j; partial[b] = block b's |P1|^2, partial[nb + b] its
+// |Z|^2, partial[2 nb + b] its P1 . Z.
 // FP64: one element per thread, grid-stride, eight basis loads in flight.
 __global__ __launch_bounds__(kThreads) void update2_kernel(const double* __restrict__ V,
                                                            int64_t n, int cnt,
@@ -535,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void update2_kernel(const double* __restr
   }
   __syncthreads();
   const double nu = pair[0];
-  double n1 = 0.0, nz = 0.0;
+  double n1 = 0.0, nz = 0.0, pz = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
     const double a = u1[e], b = u2[e];
@@ -562,9 +563,44 @@ __global__ __launch_bounds__(kThreads) void update2_kernel(const double* __restr
     u2[e] = z;
     n1 += p1 * p1;
     nz += z * z;
+    pz += p1 * z;
   }
-  double acc[2] = {n1, nz};
-  block_reduce_store<2>(acc, partial + blockIdx.x, gridDim.x, 2);
+  double acc[3] = {n1, nz, pz};
+  block_reduce_store<3>(acc, partial + blockIdx.x, gridDim.x, 3);
+}
+
+// rho = (P1 . Z) / |P1|^2 from the update's sums into pair[1]: nu carries the
+// rounding of |u1|^2 - |c1|^2, and Z then keeps a P1 component that one-step
+// Gram-Schmidt would not leave (in NumPy on the 8^3 test box: orthogonality
+// 1e-4 against 3e-9 once it is removed).
+__global__ __launch_bounds__(64) void pair_rho_kernel(const double* __restrict__ partial,
+                                                      int nb, double* __restrict__ pair) {
+  const int lane = threadIdx.x;
+  double a = 0.0, c = 0.0;
+  for (int b = lane; b < nb; b += 64) {
+    a += partial[b];
+    c += partial[2 * nb + b];
+  }
+  a = wave_sum(a);
+  c = wave_sum(c);
+  if (lane == 0) pair[1] = a > 0.0 ? c / a : 0.0;
+}
+
+// Z <- Z - rho P1 and partial[nb + b] = block b's |Z|^2 afterwards.
+__global__ __launch_bounds__(kThreads) void pair_fix_kernel(const double* __restrict__ p1,
+                                                            double* __restrict__ z, int64_t n,
+                                                            const double* __restrict__ pair,
+                                                            double* __restrict__ partial) {
+  const double rho = pair[1];
+  double nz = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+    const double v = z[e] - rho * p1[e];
+    z[e] = v;
+    nz += v * v;
+  }
+  double acc[1] = {nz};
+  block_reduce_store<1>(acc, partial + gridDim.x + blockIdx.x, 1, 1);
 }
 
 // Hessenberg columns j and j + 1 of K (kept in hk, column i at i * kPairRows)
@@ -603,7 +639,7 @@ __global__ __launch_bounds__(64) void givens2_kernel(const double* __restrict__ 
     for (int i = (l > 0 ? l - 1 : 0); i < j; ++i) t += c1[i] * hk[(size_t)i * kPairRows + l];
     h1[l] = (c2[l] - (t + c1[j] * c1[l])) * inv;
   }
-  h1[j + 1] = nu - c1[j];
+  h1[j + 1] = nu + pair[1] - c1[j];   // Z's P1 part rho moved into the column
   h1[j + 2] = nz * inv;
   if (!stopped_before && st->stop_k != 0) return;   // the pair's first step ended the cycle
   col = st->R + (size_t)(j + 1) * (kMaxRestart + 1);
@@ -874,6 +910,15 @@ void k_update2(const double* V, int64_t n, int cnt, const double* pair, double* 
   ProfScope prof(RT_KCLASS_ARNOLDI, st);
   hipLaunchKernelGGL(update2_kernel, dim3(grid_update(n)), dim3(kThreads), 0, st, V, n, cnt,
                      pair, u1, u2, partial);
+  RT_HIP(hipGetLastError());
+}
+
+void k_pair_fix(double* p1, double* z, int64_t n, double* pair, double* partial,
+                hipStream_t st) {
+  ProfScope prof(RT_KCLASS_ARNOLDI, st);
+  hipLaunchKernelGGL(pair_rho_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), pair);
+  hipLaunchKernelGGL(pair_fix_kernel, dim3(grid_update(n)), dim3(kThreads), 0, st, p1, z, n,
+                     pair, partial);
   RT_HIP(hipGetLastError());
 }
 

@@ -33,12 +33,13 @@ bool kform() {
   return k;
 }
 
-// Two Arnoldi steps per pass over the basis (FP64 GMRES on K) for every
-// solve: RTSN_SSTEP=2 (otherwise per solve with rt_solver_opts.two_step).
-bool two_step() {
-  static const bool k = [] {
+// Two Arnoldi steps per pass over the basis (FP64 GMRES on K): per solve
+// with rt_solver_opts.two_step; RTSN_SSTEP=2 / =1 forces pairs / single
+// steps for every solve.
+int two_step_env() {
+  static const int k = [] {
     const char* e = std::getenv("RTSN_SSTEP");
-    return e && std::atoi(e) == 2;
+    return e ? std::atoi(e) : 0;
   }();
   return k;
 }
@@ -235,8 +236,9 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   while (s.beta > rtol * bnorm && res.iters < max_iters) {
     res.cycles++;
     int k = 0, logged = 0;
-    const bool pairs = std::is_same<TV, double>::value && kform() && (two || two_step()) &&
-                       !fuse_dots();
+    const int env = two_step_env();
+    const bool pairs = std::is_same<TV, double>::value && kform() && !fuse_dots() &&
+                       (env == 2 || (env != 1 && two));
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
@@ -250,6 +252,7 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
         k_mdot2(Vd, n, j + 2, u1, u2, ws.partial, st);
         k_pair_coef(ws.partial, n, j, gs->vscale, ws.pair, st);
         k_update2(Vd, n, j + 1, ws.pair, u1, u2, ws.partial, st);
+        k_pair_fix(u1, u2, n, ws.pair, ws.partial, st);
         k_givens2(ws.partial, n, gs, j, rtol * bnorm, ws.pair, ws.hk, st);
         res.iters += 2;
         ++j;
