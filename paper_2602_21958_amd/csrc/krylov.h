@@ -68,16 +68,18 @@ void k_solve_r(GmresState* gs, int k, hipStream_t st);
 // their scales) with one dots pass and one update pass over v_0..v_j.
 // pair: 8 + 4 kPairRows doubles; hk: kPairRows^2 doubles (K's Hessenberg
 // columns of the cycle).
-void k_mdot2(const double* V, int64_t n, int cnt, const double* u1, const double* u2,
-             double* partial, hipStream_t st);
+template <typename TV>
+void k_mdot2(const TV* V, int64_t n, int cnt, const TV* u1, const TV* u2, double* partial,
+             hipStream_t st);
 void k_pair_coef(const double* partial, int64_t n, int j, const double* vscale, double* pair,
                  hipStream_t st);
-void k_update2(const double* V, int64_t n, int cnt, const double* pair, double* u1, double* u2,
+template <typename TV>
+void k_update2(const TV* V, int64_t n, int cnt, const double* pair, TV* u1, TV* u2,
                double* partial, hipStream_t st);
 // Z <- Z - rho P1 with rho = P1 . Z / |P1|^2 from the update's sums (the
 // P1 component that nu's rounding leaves); |Z|^2 recomputed.
-void k_pair_fix(double* p1, double* z, int64_t n, double* pair, double* partial,
-                hipStream_t st);
+template <typename TV>
+void k_pair_fix(TV* p1, TV* z, int64_t n, double* pair, double* partial, hipStream_t st);
 void k_givens2(const double* partial, int64_t n, GmresState* gs, int j, double tol,
                const double* pair, double* hk, hipStream_t st);
 template <typename T>

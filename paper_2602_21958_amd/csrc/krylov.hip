@@ -521,13 +521,16 @@ __global__ __launch_bounds__(kThreads) void pair_coef_kernel(const double* __res
 
 // u1 <- P1 = u1 - sum k1_q W_q, u2 <- Z = u2 - nu u1 - sum k2_q W_q in one
 // pass over W_0..W_j; partial[b] = block b's |P1|^2, partial[nb + b] its
-// |Z|^2, partial[2 nb + b] its P1 . Z.
-// FP64: one element per thread, grid-stride, eight basis loads in flight.
-__global__ __launch_bounds__(kThreads) void update2_kernel(const double* __restrict__ V,
+// |Z|^2, partial[2 nb + b] its P1 . Z (norms of the stored, rounded values).
+// FP64: one element per thread, grid-stride, eight basis loads in flight;
+// FP32: 16-byte groups over one contiguous range per block, FP64
+// accumulation (the one-step update's access pattern for each type).
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void update2_kernel(const TV* __restrict__ V,
                                                            int64_t n, int cnt,
                                                            const double* __restrict__ pair,
-                                                           double* __restrict__ u1,
-                                                           double* __restrict__ u2,
+                                                           TV* __restrict__ u1,
+                                                           TV* __restrict__ u2,
                                                            double* __restrict__ partial) {
   __shared__ double k1[kMaxRestart + 1], k2[kMaxRestart + 1];
   for (int i = threadIdx.x; i < cnt; i += kThreads) {
@@ -537,33 +540,92 @@ __global__ __launch_bounds__(kThreads) void update2_kernel(const double* __restr
   __syncthreads();
   const double nu = pair[0];
   double n1 = 0.0, nz = 0.0, pz = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-    const double a = u1[e], b = u2[e];
-    double s1 = 0.0, s2 = 0.0;
-    int i = 0;
-    for (; i + 8 <= cnt; i += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(i + u) * n + e];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        s1 += k1[i + u] * v[u];
-        s2 += k2[i + u] * v[u];
-      }
-    }
-    for (; i < cnt; ++i) {
-      const double v = V[(size_t)i * n + e];
-      s1 += k1[i] * v;
-      s2 += k2[i] * v;
-    }
-    const double p1 = a - s1;
-    const double z = (b - nu * a) - s2;
-    u1[e] = p1;
-    u2[e] = z;
+  auto finish = [&](double a, double b, double s1, double s2, TV& o1, TV& o2) {
+    o1 = (TV)(a - s1);
+    o2 = (TV)((b - nu * a) - s2);
+    const double p1 = (double)o1, z = (double)o2;
     n1 += p1 * p1;
     nz += z * z;
     pz += p1 * z;
+  };
+  using VT = typename Vec16<TV>::type;
+  constexpr int W = Vec16<TV>::n;
+  if constexpr (sizeof(TV) == 8) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+      double s1 = 0.0, s2 = 0.0;
+      int i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(i + u) * n + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          s1 += k1[i + u] * v[u];
+          s2 += k2[i + u] * v[u];
+        }
+      }
+      for (; i < cnt; ++i) {
+        const double v = V[(size_t)i * n + e];
+        s1 += k1[i] * v;
+        s2 += k2[i] * v;
+      }
+      finish((double)u1[e], (double)u2[e], s1, s2, u1[e], u2[e]);
+    }
+  } else if (n % W == 0) {
+    int64_t b0, b1;
+    block_range(n / W, b0, b1);
+    VT* x1v = reinterpret_cast<VT*>(u1);
+    VT* x2v = reinterpret_cast<VT*>(u2);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      const VT x1 = x1v[e], x2 = x2v[e];
+      double s1[W], s2[W];
+#pragma unroll
+      for (int q = 0; q < W; ++q) s1[q] = s2[q] = 0.0;
+      int i = 0;
+      for (; i + 8 <= cnt; i += 8) {
+        VT a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = reinterpret_cast<const VT*>(V + (size_t)(i + u) * n)[e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < W; ++q) {
+            s1[q] += k1[i + u] * (double)a[u][q];
+            s2[q] += k2[i + u] * (double)a[u][q];
+          }
+      }
+      for (; i < cnt; ++i) {
+        const VT a = reinterpret_cast<const VT*>(V + (size_t)i * n)[e];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          s1[q] += k1[i] * (double)a[q];
+          s2[q] += k2[i] * (double)a[q];
+        }
+      }
+      VT r1, r2;
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        TV o1, o2;
+        finish((double)x1[q], (double)x2[q], s1[q], s2[q], o1, o2);
+        r1[q] = o1;
+        r2[q] = o2;
+      }
+      x1v[e] = r1;
+      x2v[e] = r2;
+    }
+  } else {
+    int64_t b0, b1;
+    block_range(n, b0, b1);
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kThreads) {
+      double s1 = 0.0, s2 = 0.0;
+      for (int i = 0; i < cnt; ++i) {
+        const double v = (double)V[(size_t)i * n + e];
+        s1 += k1[i] * v;
+        s2 += k2[i] * v;
+      }
+      finish((double)u1[e], (double)u2[e], s1, s2, u1[e], u2[e]);
+    }
   }
   double acc[3] = {n1, nz, pz};
   block_reduce_store<3>(acc, partial + blockIdx.x, gridDim.x, 3);
@@ -586,18 +648,20 @@ __global__ __launch_bounds__(64) void pair_rho_kernel(const double* __restrict__
   if (lane == 0) pair[1] = a > 0.0 ? c / a : 0.0;
 }
 
-// Z <- Z - rho P1 and partial[nb + b] = block b's |Z|^2 afterwards.
-__global__ __launch_bounds__(kThreads) void pair_fix_kernel(const double* __restrict__ p1,
-                                                            double* __restrict__ z, int64_t n,
+// Z <- Z - rho P1 and partial[nb + b] = block b's |Z|^2 afterwards (of the
+// stored values).
+template <typename TV>
+__global__ __launch_bounds__(kThreads) void pair_fix_kernel(const TV* __restrict__ p1,
+                                                            TV* __restrict__ z, int64_t n,
                                                             const double* __restrict__ pair,
                                                             double* __restrict__ partial) {
   const double rho = pair[1];
   double nz = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-    const double v = z[e] - rho * p1[e];
+    const TV v = (TV)((double)z[e] - rho * (double)p1[e]);
     z[e] = v;
-    nz += v * v;
+    nz += (double)v * (double)v;
   }
   double acc[1] = {nz};
   block_reduce_store<1>(acc, partial + gridDim.x + blockIdx.x, 1, 1);
@@ -886,14 +950,15 @@ void k_givens(const double* partial, int64_t n, GmresState* gs, int j, double to
   RT_HIP(hipGetLastError());
 }
 
-void k_mdot2(const double* V, int64_t n, int cnt, const double* u1, const double* u2,
-             double* partial, hipStream_t st) {
+template <typename TV>
+void k_mdot2(const TV* V, int64_t n, int cnt, const TV* u1, const TV* u2, double* partial,
+             hipStream_t st) {
   const int nb = grid_for(n);
   ProfScope prof(RT_KCLASS_ARNOLDI, st);
   for (int i0 = 0; i0 < cnt; i0 += 8) {
     const int c = cnt - i0 < 8 ? cnt - i0 : 8;
-    hipLaunchKernelGGL((mdot2_kernel<double, 8>), dim3(nb), dim3(kThreads), 0, st, V, n, i0, c,
-                       u1, u2, partial);
+    hipLaunchKernelGGL((mdot2_kernel<TV, 8>), dim3(nb), dim3(kThreads), 0, st, V, n, i0, c, u1,
+                       u2, partial);
   }
   RT_HIP(hipGetLastError());
 }
@@ -905,20 +970,21 @@ void k_pair_coef(const double* partial, int64_t n, int j, const double* vscale, 
   RT_HIP(hipGetLastError());
 }
 
-void k_update2(const double* V, int64_t n, int cnt, const double* pair, double* u1, double* u2,
+template <typename TV>
+void k_update2(const TV* V, int64_t n, int cnt, const double* pair, TV* u1, TV* u2,
                double* partial, hipStream_t st) {
   ProfScope prof(RT_KCLASS_ARNOLDI, st);
-  hipLaunchKernelGGL(update2_kernel, dim3(grid_update(n)), dim3(kThreads), 0, st, V, n, cnt,
-                     pair, u1, u2, partial);
+  hipLaunchKernelGGL((update2_kernel<TV>), dim3(grid_update(n)), dim3(kThreads), 0, st, V, n,
+                     cnt, pair, u1, u2, partial);
   RT_HIP(hipGetLastError());
 }
 
-void k_pair_fix(double* p1, double* z, int64_t n, double* pair, double* partial,
-                hipStream_t st) {
+template <typename TV>
+void k_pair_fix(TV* p1, TV* z, int64_t n, double* pair, double* partial, hipStream_t st) {
   ProfScope prof(RT_KCLASS_ARNOLDI, st);
   hipLaunchKernelGGL(pair_rho_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), pair);
-  hipLaunchKernelGGL(pair_fix_kernel, dim3(grid_update(n)), dim3(kThreads), 0, st, p1, z, n,
-                     pair, partial);
+  hipLaunchKernelGGL((pair_fix_kernel<TV>), dim3(grid_update(n)), dim3(kThreads), 0, st, p1, z,
+                     n, pair, partial);
   RT_HIP(hipGetLastError());
 }
 
@@ -985,6 +1051,16 @@ int reduce_blocks(int64_t n) { return grid_for(n); }
 
 // explicit instantiations
 template void k_mdot<double>(const double*, int64_t, int, const double*, double*, hipStream_t);
+template void k_mdot2<double>(const double*, int64_t, int, const double*, const double*, double*,
+                              hipStream_t);
+template void k_mdot2<float>(const float*, int64_t, int, const float*, const float*, double*,
+                             hipStream_t);
+template void k_update2<double>(const double*, int64_t, int, const double*, double*, double*,
+                                double*, hipStream_t);
+template void k_update2<float>(const float*, int64_t, int, const double*, float*, float*,
+                               double*, hipStream_t);
+template void k_pair_fix<double>(double*, double*, int64_t, double*, double*, hipStream_t);
+template void k_pair_fix<float>(float*, float*, int64_t, double*, double*, hipStream_t);
 template void k_mdot<float>(const float*, int64_t, int, const float*, double*, hipStream_t);
 template void k_update<double>(const double*, int64_t, int, const double*, const double*, double*,
                                double*, hipStream_t);

@@ -237,22 +237,21 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
     res.cycles++;
     int k = 0, logged = 0;
     const int env = two_step_env();
-    const bool pairs = std::is_same<TV, double>::value && kform() && !fuse_dots() &&
-                       (env == 2 || (env != 1 && two));
+    const bool pairs = (std::is_same<TV, double>::value || std::is_same<TV, float>::value) &&
+                       kform() && !fuse_dots() && (env == 2 || (env != 1 && two));
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
       if (pairs && j + 1 < m && res.iters + 2 <= max_iters) {
         // steps j and j + 1: u1 = K v_j, u2 = K u1, one dots and one update pass
-        double* Vd = reinterpret_cast<double*>(V);
-        double* u1 = Vd + (size_t)(j + 1) * n;
-        double* u2 = Vd + (size_t)(j + 2) * n;
-        operator_apply_k(p, prec, Vd + (size_t)j * n, u1, gs->vscale + j, st);
+        TV* u1 = V + (size_t)(j + 1) * n;
+        TV* u2 = V + (size_t)(j + 2) * n;
+        operator_apply_k(p, prec, vj, u1, gs->vscale + j, st);
         operator_apply_k(p, prec, u1, u2, nullptr, st);
-        k_mdot2(Vd, n, j + 2, u1, u2, ws.partial, st);
+        k_mdot2<TV>(V, n, j + 2, u1, u2, ws.partial, st);
         k_pair_coef(ws.partial, n, j, gs->vscale, ws.pair, st);
-        k_update2(Vd, n, j + 1, ws.pair, u1, u2, ws.partial, st);
-        k_pair_fix(u1, u2, n, ws.pair, ws.partial, st);
+        k_update2<TV>(V, n, j + 1, ws.pair, u1, u2, ws.partial, st);
+        k_pair_fix<TV>(u1, u2, n, ws.pair, ws.partial, st);
         k_givens2(ws.partial, n, gs, j, rtol * bnorm, ws.pair, ws.hk, st);
         res.iters += 2;
         ++j;
@@ -480,7 +479,7 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
       } else {
         CoreResult ir;
         gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
-                          nullptr, st, nullptr, ir, /*single_cycle=*/true);
+                          nullptr, st, nullptr, ir, /*single_cycle=*/true, o.two_step != 0);
         total_inner += ir.iters;
       }
       RT_HIP(hipMemcpyAsync(ws.scal + 1, &rn, sizeof(double), hipMemcpyHostToDevice, st));

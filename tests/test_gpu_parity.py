@@ -569,18 +569,20 @@ def test_operator_16bit_box(shape, prec):
     assert np.all(err <= bound), float(np.max(err / bound))
 
 
+@pytest.mark.parametrize("two_step", [1, 0])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16", "bf16"])
 @pytest.mark.parametrize("name", ["slab64", "box8"])
-def test_mixed_refinement_per_precision(name, prec):
-    """FP64 refinement around each low-precision inner operator; the result is
+def test_mixed_refinement_per_precision(name, prec, two_step):
+    """FP64 refinement around each low-precision inner operator, the inner
+    Arnoldi steps in pairs (the default) and one at a time; the result is
     checked by the oracle-evaluated FP64 residual."""
     rt = _rt()
     spec = ALL[name]()
-    say(f"mixed {prec} {name}")
+    say(f"mixed {prec} {name} two_step={two_step}")
     op = OProblem(spec)
     with rt.Problem(spec) as p:
         x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
-        st = p.solve(x, rtol=1e-8, precision=prec, max_outer=30)
+        st = p.solve(x, rtol=1e-8, precision=prec, max_outer=30, two_step=two_step)
         s = host(x)
     res = op.residual_norm(s)
     say(f"   {prec} {name}: converged={st['converged']} outer={st['outer_iters']} "
