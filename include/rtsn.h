@@ -209,9 +209,9 @@ typedef struct {
                              (1 - eps) |Mhat| sums to more than 2 (possible
                              only with an explicit kernel; the physical kernels
                              give about 1), which the basis scale assumes.      */
-  int two_step;           /* GMRES on FP64 or FP32 Krylov vectors (the FP64
-                             solve, and the inner cycles of mixed precision with
-                             an FP32 basis): take the Arnoldi steps in pairs,
+  int two_step;           /* GMRES (the FP64 solve, and the inner cycles of
+                             mixed precision on FP32 or fp16 bases): take the
+                             Arnoldi steps in pairs,
                              u1 = K v_j and u2 = K u1 with K = I - A,
                              orthogonalised together with one pass over the
                              basis for the dots and one for the update instead
@@ -219,7 +219,7 @@ typedef struct {
                              removes the new vector's component along the first
                              (default 1; 0: one step per pass).  Same Krylov
                              spaces and iterates in exact arithmetic.  Ignored
-                             with an fp16 basis and in BiCGStab.                  */
+                             in BiCGStab.                                         */
 } rt_solver_opts;
 
 typedef struct {

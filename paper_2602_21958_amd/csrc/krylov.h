@@ -68,6 +68,9 @@ void k_solve_r(GmresState* gs, int k, hipStream_t st);
 // their scales) with one dots pass and one update pass over v_0..v_j.
 // pair: 8 + 4 kPairRows doubles; hk: kPairRows^2 doubles (K's Hessenberg
 // columns of the cycle).
+// Slot of the pair workspace (8 + 4 kPairRows doubles) that the pair kernels
+// leave alone (they use 0, 1 and 8 on): a caller's device scalar.
+constexpr int kPairUser = 2;
 template <typename TV>
 void k_mdot2(const TV* V, int64_t n, int cnt, const TV* u1, const TV* u2, double* partial,
              hipStream_t st);
@@ -81,7 +84,8 @@ void k_update2(const TV* V, int64_t n, int cnt, const double* pair, TV* u1, TV* 
 template <typename TV>
 void k_pair_fix(TV* p1, TV* z, int64_t n, double* pair, double* partial, hipStream_t st);
 void k_givens2(const double* partial, int64_t n, GmresState* gs, int j, double tol,
-               const double* pair, double* hk, hipStream_t st);
+               const double* pair, double* hk, hipStream_t st, double kdiag = 1.0,
+               double sigma = 1.0);
 template <typename T>
 void k_dots4(const T* a0, const T* b0, const T* a1, const T* b1, int cnt, int64_t n,
              double* partial, hipStream_t st);

@@ -668,12 +668,17 @@ __global__ __launch_bounds__(kThreads) void pair_fix_kernel(const TV* __restrict
 }
 
 // Hessenberg columns j and j + 1 of K (kept in hk, column i at i * kPairRows)
-// from the pair's dots and norms, turned into A's (e_i - h, -h_sub) and
-// given to two Givens steps; the second is skipped once the first stopped.
+// from the pair's dots and norms, turned into A's (kdiag e_i - h, -h_sub)
+// and given to two Givens steps; the second is skipped once the first
+// stopped.  sigma: the Arnoldi operator is sigma times the one that made u2
+// from u1 (an fp16 basis runs Arnoldi on S K but forms u2 = K u1, which
+// keeps u2 at the basis's scale): K v_{j+1} then carries sigma on c2, on
+// nu + rho and on |Z|.
 __global__ __launch_bounds__(64) void givens2_kernel(const double* __restrict__ partial, int nb,
                                                      GmresState* st, int j, double tol,
                                                      const double* __restrict__ pair,
-                                                     double* __restrict__ hk) {
+                                                     double* __restrict__ hk, double kdiag,
+                                                     double sigma) {
   const int lane = threadIdx.x;
   double s1 = 0.0, s2 = 0.0;
   for (int b = lane; b < nb; b += 64) {
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(64) void givens2_kernel(const double* __restrict__ 
   for (int i = 0; i <= j; ++i) h0[i] = c1[i];
   h0[j + 1] = np1;
   double* col = st->R + (size_t)j * (kMaxRestart + 1);
-  for (int i = 0; i <= j; ++i) col[i] = (i == j ? 1.0 : 0.0) - h0[i];
+  for (int i = 0; i <= j; ++i) col[i] = (i == j ? kdiag : 0.0) - h0[i];
   col[j + 1] = -np1;
   const int stopped_before = st->stop_k != 0;
   givens_step(st, j, np1, tol);
@@ -701,13 +706,13 @@ __global__ __launch_bounds__(64) void givens2_kernel(const double* __restrict__ 
   for (int l = 0; l <= j; ++l) {
     double t = 0.0;
     for (int i = (l > 0 ? l - 1 : 0); i < j; ++i) t += c1[i] * hk[(size_t)i * kPairRows + l];
-    h1[l] = (c2[l] - (t + c1[j] * c1[l])) * inv;
+    h1[l] = (sigma * c2[l] - (t + c1[j] * c1[l])) * inv;
   }
-  h1[j + 1] = nu + pair[1] - c1[j];   // Z's P1 part rho moved into the column
-  h1[j + 2] = nz * inv;
+  h1[j + 1] = sigma * (nu + pair[1]) - c1[j];   // Z's P1 part rho moved into the column
+  h1[j + 2] = sigma * nz * inv;
   if (!stopped_before && st->stop_k != 0) return;   // the pair's first step ended the cycle
   col = st->R + (size_t)(j + 1) * (kMaxRestart + 1);
-  for (int i = 0; i <= j + 1; ++i) col[i] = (i == j + 1 ? 1.0 : 0.0) - h1[i];
+  for (int i = 0; i <= j + 1; ++i) col[i] = (i == j + 1 ? kdiag : 0.0) - h1[i];
   col[j + 2] = -h1[j + 2];
   givens_step(st, j + 1, h1[j + 2], tol);
   // v_{j+2} = Z / |Z|: givens_step stored 1 / h_{j+2,j+1} = |P1| / |Z|
@@ -989,9 +994,9 @@ void k_pair_fix(TV* p1, TV* z, int64_t n, double* pair, double* partial, hipStre
 }
 
 void k_givens2(const double* partial, int64_t n, GmresState* gs, int j, double tol,
-               const double* pair, double* hk, hipStream_t st) {
+               const double* pair, double* hk, hipStream_t st, double kdiag, double sigma) {
   hipLaunchKernelGGL(givens2_kernel, dim3(1), dim3(64), 0, st, partial, grid_update(n), gs, j,
-                     tol, pair, hk);
+                     tol, pair, hk, kdiag, sigma);
   RT_HIP(hipGetLastError());
 }
 
@@ -1061,6 +1066,11 @@ template void k_update2<float>(const float*, int64_t, int, const double*, float*
                                double*, hipStream_t);
 template void k_pair_fix<double>(double*, double*, int64_t, double*, double*, hipStream_t);
 template void k_pair_fix<float>(float*, float*, int64_t, double*, double*, hipStream_t);
+template void k_mdot2<_Float16>(const _Float16*, int64_t, int, const _Float16*, const _Float16*,
+                                double*, hipStream_t);
+template void k_update2<_Float16>(const _Float16*, int64_t, int, const double*, _Float16*,
+                                  _Float16*, double*, hipStream_t);
+template void k_pair_fix<_Float16>(_Float16*, _Float16*, int64_t, double*, double*, hipStream_t);
 template void k_mdot<float>(const float*, int64_t, int, const float*, double*, hipStream_t);
 template void k_update<double>(const double*, int64_t, int, const double*, const double*, double*,
                                double*, hipStream_t);

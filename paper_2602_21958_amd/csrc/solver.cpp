@@ -311,7 +311,7 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
 // whose least-squares solution y, and hence d = sum y_i v_i, is the unscaled
 // one.  Returns the inner iteration count.
 int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* d, int m,
-                     double itol, int cap, Workspace& ws, hipStream_t st) {
+                     double itol, int cap, Workspace& ws, hipStream_t st, bool two) {
   const int64_t n = p.n;
   _Float16* V = static_cast<_Float16*>(ws.V);   // the FP32 basis's memory, half used
   GmresState* gs = ws.gs;
@@ -320,13 +320,41 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
   RT_HIP(hipMemsetAsync(d, 0, (size_t)n * sizeof(float), st));
   k_norm_partial<_Float16>(V, n, ws.partial, st);
   k_finish_norm(ws.partial, n, gs, 1, st);
+  // 1 / S on the device for the pairs' second application (read_status
+  // below waits for the copy while inv_s lives)
+  const double inv_s = 1.0 / (double)S;
+  RT_HIP(hipMemcpyAsync(ws.pair + kPairUser, &inv_s, sizeof(double), hipMemcpyHostToDevice, st));
   const Status s0 = read_status(ws, st);
   if (!(s0.beta > 0.0) || !std::isfinite(s0.beta))
     fail(RT_E_NONFINITE, "fp16 basis: right-hand side out of range");
   int k = 0, logged = 0;
   const int steps = std::min(m, cap), every = status_every(n);
+  const int env = two_step_env();
+  const bool pairs = kform() && (env == 2 || (env != 1 && two));
   for (int j = 0; j < steps; ++j) {
     _Float16* w = V + (size_t)(j + 1) * n;
+    if (pairs && j + 1 < steps) {
+      // steps j and j + 1: u1 = S K v_j as in a single step, u2 = K u1 (not
+      // S K u1, which would leave fp16's range), so the pair's second
+      // Hessenberg column carries the factor S (sigma of k_givens2).  u2 is
+      // formed as S K (u1 / S): the 16-bit Lambda output's scale assumes an
+      // input of unit size, which u1 / S has and u1 does not.
+      _Float16* u2 = V + (size_t)(j + 2) * n;
+      operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, true);
+      operator_apply_h(p, prec, w, u2, ws.pair + kPairUser, S, st, true);
+      k_mdot2<_Float16>(V, n, j + 2, w, u2, ws.partial, st);
+      k_pair_coef(ws.partial, n, j, gs->vscale, ws.pair, st);
+      k_update2<_Float16>(V, n, j + 1, ws.pair, w, u2, ws.partial, st);
+      k_pair_fix<_Float16>(w, u2, n, ws.pair, ws.partial, st);
+      k_givens2(ws.partial, n, gs, j, itol * s0.beta, ws.pair, ws.hk, st, (double)S, (double)S);
+      ++j;
+      k = j + 1;
+      if (k < steps && k % every != 0 && (k - 1) % every != 0) continue;
+      const StepRead r = read_steps(ws, st, k, logged, nullptr, 1.0);
+      k = r.k;
+      if (r.stop) break;
+      continue;
+    }
     const bool kf = kform();   // Arnoldi on S K: S A = S I - S K
     operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, kf);
     k_mdot<_Float16>(V, n, j + 1, w, ws.partial, st);
@@ -475,7 +503,7 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
       const int cap = std::min(o.restart, o.max_iters - total_inner);
       if (o.basis_fp16) {
         total_inner += inner_cycle_fp16(p, o.precision, ws.r64, rn, ws.d32, o.restart, itol, cap,
-                                        ws, st);
+                                        ws, st, o.two_step != 0);
       } else {
         CoreResult ir;
         gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,

@@ -257,19 +257,22 @@ def test_gmres_two_step_matches_oracle(name, restart):
     assert diff < (1e-6 if st["iters"] == ref["iters"] else 1e-5)
 
 
+@pytest.mark.parametrize("two_step", [1, 0])
 @pytest.mark.parametrize("prec", ["fp16", "bf16x3", "bf16"])
 @pytest.mark.parametrize("name", ["slab64", "box8", "small_box_ragged"])
-def test_mixed_refinement_fp16_basis(name, prec):
-    """Refinement whose inner GMRES keeps its basis in (scaled) fp16 reaches
-    the same oracle-evaluated FP64 residual as with the FP32 basis."""
+def test_mixed_refinement_fp16_basis(name, prec, two_step):
+    """Refinement whose inner GMRES keeps its basis in (scaled) fp16, with the
+    inner Arnoldi steps in pairs (the default) or one at a time, reaches the
+    same oracle-evaluated FP64 residual as with the FP32 basis."""
     rt = _rt()
     spec = (W.small_box(12, 4, 8, 9, seed=5, nz=9, ny=10) if name == "small_box_ragged"
             else ALL[name]())
-    say(f"mixed {prec} fp16 basis {name}")
+    say(f"mixed {prec} fp16 basis {name} two_step={two_step}")
     op = OProblem(spec)
     with rt.Problem(spec) as p:
         x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
-        st = p.solve(x, rtol=1e-8, precision=prec, max_outer=30, basis_fp16=1)
+        st = p.solve(x, rtol=1e-8, precision=prec, max_outer=30, basis_fp16=1,
+                     two_step=two_step)
         s = host(x)
         ref = p.solve(torch.empty_like(x), rtol=1e-8, precision=prec, max_outer=30)
     res = op.residual_norm(s)
