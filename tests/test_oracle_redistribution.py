@@ -75,3 +75,72 @@ def test_kernel_photon_conservation_and_thermal_rows(make):
     assert np.allclose(p.psi, p.psi.T)
     # rows of Mhat reproduce the line albedo: a Planckian field scatters to B
     assert np.allclose(p.mhat.sum(axis=1), p.phi_ray / p.fac_ray, rtol=1e-13)
+
+
+# Continuum limit of the coherent kernel (pins the width convention).  With
+# w2 = 0.5 the symmetric kernel c(x) exp(-2 (x - x')^2) c(x') whose marginals
+# are the Doppler profile exp(-x^2)/sqrt(pi) has c(x) = A exp(-beta x^2):
+# integrating over x' gives the exponent -(2 + beta) x^2 + 4 x^2 / (2 + beta),
+# which equals -x^2 when alpha = 2 + beta solves alpha^2 - alpha - 4 = 0, and
+# the prefactor A^2 sqrt(pi / alpha) = 1 / sqrt(pi).
+_ALPHA = (1.0 + math.sqrt(17.0)) / 2.0
+_BETA = _ALPHA - 2.0
+
+
+def _coherent_continuum(x):
+    a, b = x[:, None], x[None, :]
+    return (math.sqrt(_ALPHA) / math.pi) * np.exp(-2.0 * (a - b) ** 2) \
+        * np.exp(-_BETA * (a * a + b * b))
+
+
+def _coherent_discrete(n_nu, x_max, width2):
+    x, w, phi = frequency_grid(n_nu, x_max)
+    # coherent part alone: with c = 1 the kernel is P_coh
+    return x, prd_frequency_kernel(x, w, phi, 1.0, width2)
+
+
+def test_coherent_continuum_kernel_has_doppler_marginals():
+    # the closed form itself, by a fine quadrature of its marginal
+    x = np.linspace(-9.0, 9.0, 3601)
+    h = x[1] - x[0]
+    k = _coherent_continuum(x)
+    marg = k.sum(axis=1) * h
+    phi = np.exp(-x * x) / math.sqrt(math.pi)
+    inner = np.abs(x) < 4.0
+    assert np.max(np.abs(marg[inner] - phi[inner]) / phi[inner]) < 1e-12
+
+
+def test_prd_coherent_part_converges_to_continuum_kernel():
+    # [-8, 8]: the discrete Sinkhorn-scaled kernel approaches the continuum
+    # one at a rate that keeps rising under refinement (the trapezoid rule is
+    # spectrally accurate for these Gaussians), down to rounding
+    errs, hs = [], []
+    for n_nu in (11, 16, 21, 31):
+        x, p = _coherent_discrete(n_nu, 8.0, 0.5)
+        c = _coherent_continuum(x)
+        errs.append(np.max(np.abs(p - c)) / np.max(c))
+        hs.append(16.0 / (n_nu - 1))
+    orders = [math.log(errs[i] / errs[i + 1]) / math.log(hs[i] / hs[i + 1])
+              for i in range(len(errs) - 1)]
+    assert all(o > 4.0 for o in orders), orders
+    assert orders[-1] > orders[0]
+    for n_nu in (51, 101, 201):
+        x, p = _coherent_discrete(n_nu, 8.0, 0.5)
+        c = _coherent_continuum(x)
+        assert np.max(np.abs(p - c)) / np.max(c) < 1e-13
+    # the workloads' grids on [-5, 5]: 21 frequencies to 1e-6, finer ones to
+    # the truncation of the profile's tails
+    for n_nu, tol in ((21, 1e-6), (32, 1e-11), (48, 1e-11), (64, 1e-11)):
+        x, p = _coherent_discrete(n_nu, 5.0, 0.5)
+        c = _coherent_continuum(x)
+        assert np.max(np.abs(p - c)) / np.max(c) < tol, n_nu
+
+
+def test_prd_width_convention_is_pinned():
+    # reading exp(-(x-x')^2 / w2) as exp(-(x-x')^2 / (2 w2)) (i.e. w2 = 1)
+    # gives a different kernel with the same marginals: it misses the
+    # continuum limit by 20 %
+    for n_nu in (51, 101):
+        x, p = _coherent_discrete(n_nu, 8.0, 1.0)
+        c = _coherent_continuum(x)
+        assert np.max(np.abs(p - c)) / np.max(c) > 0.1

@@ -7,6 +7,7 @@ weights summing to 1 with gamma = (1 - t)/2 as the per-point albedo, and the
 count |lambda| in [0.999, 1.001] (an exact eigenvalue 1 computes as 1 +- 1e-16).
 """
 import os
+from decimal import Decimal, ROUND_HALF_UP
 
 import numpy as np
 import pytest
@@ -49,15 +50,30 @@ def _cluster_pct(a):
     return 100.0 * np.mean((lam >= 0.999) & (lam <= 1.001)), lam.min()
 
 
+def _printed_pct(a):
+    """Clustered share as the table prints it: the exact count over N rounded
+    half up to one decimal (1927 of 2000 eigenvalues is 96.35 %, printed
+    96.4), and the smallest |lambda|."""
+    lam = np.abs(np.linalg.eigvals(a))
+    cnt = int(np.sum((lam >= 0.999) & (lam <= 1.001)))
+    pct = (Decimal(100 * cnt) / Decimal(lam.size)).quantize(Decimal("0.1"),
+                                                             rounding=ROUND_HALF_UP)
+    return float(pct), lam.min()
+
+
 # entries whose reading reproduces the printed value to the printed digit
-REPRODUCED = [(10, 12), (10, 24), (20, 12), (20, 24), (40, 12), (100, 12), (10, 100)]
+# (12 of the 17 whose dense operator has at most 5000 rows; the five others,
+# (10,50), (20,50), (40,24), (40,50) and (100,50), come out 0.4-1.1 points
+# high and are checked for the trend only)
+REPRODUCED = [(10, 12), (10, 24), (10, 100), (20, 12), (20, 24), (20, 100), (40, 12),
+              (40, 100), (100, 12), (100, 24), (200, 12), (200, 24)]
 
 
 @pytest.mark.parametrize("ns,nom", REPRODUCED)
 def test_table1_entries(ns, nom):
     gold = _load_table1()[(ns, nom)]
-    pct, lmin = _cluster_pct(mono_operator(ns, nom).dense())
-    assert round(pct, 1) == gold
+    pct, lmin = _printed_pct(mono_operator(ns, nom).dense())
+    assert pct == gold
     assert lmin > 0.815                   # paper: |lambda|_min > 0.82 (printed to 2 digits)
 
 
