@@ -267,7 +267,6 @@ bool Engine::setup_slot(Request* r, int s) {
   d.x = r->x_out;
   // (only the fp16 k4 operand is scaled; plain outputs ignore l_scale)
   d.l_scale = precision == RT_PREC_FP16 ? fp16_lambda_scale(p.n) : 1.f;
-  d.kform = kform() ? 1 : 0;
   d.vs = basis16 ? fp16_basis_scale(p.n) : 1.f;
   h_slots[s] = d;
   RT_HIP(hipMemcpyAsync(d_slots + s, &h_slots[s], sizeof(SlotDev), hipMemcpyHostToDevice, stream));

@@ -24,7 +24,6 @@ struct SlotDev {
   int active;
   int64_t n_s, n;
   int nch;                      // reduction chunks of a length-n vector
-  int kform;                    // Arnoldi on K = I - A (the GEMM reads no V_j)
   const double* mhat64;
   const float* mhat32;
   const uint16_t* a8_hi;        // Mhat, k8 layout: bf16 (hi part)

@@ -172,12 +172,12 @@ __global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
         A = reinterpret_cast<const T*>(s.mhat64);
       else
         A = reinterpret_cast<const T*>(s.mhat32);
-      X = s.kform ? nullptr : static_cast<const T*>(s.V) + (size_t)j * s.n;
+      X = nullptr;   // Arnoldi on K: the step reads no V_j
       Y = static_cast<T*>(s.V) + (size_t)(j + 1) * s.n;
       xs = s.gs->vscale[j];
     }
-    // K-form Arnoldi steps: y = +(1 - eps) Mhat L, no x term
-    const double sign = (!OUTER && s.kform) ? 1.0 : -1.0;
+    // Arnoldi steps on K: y = +(1 - eps) Mhat L, no x term
+    const double sign = OUTER ? -1.0 : 1.0;
     gemm::gemm_tile<T, 16>(A, s.lda_mhat, static_cast<const T*>(s.L), X, Y, s.albedo, xs,
                            s.n_r, (int)s.n_s, s.n_r, w.a, w.b, sign);
   }
@@ -203,14 +203,13 @@ __global__ __launch_bounds__(C::NT) void bk_gemm16(const SlotDev* __restrict__ s
     const Item w = items[it];
     const SlotDev& s = slots[w.slot];
     const int j = stat[w.slot].j;
-    const TY* X = s.kform ? nullptr : static_cast<const TY*>(s.V) + (size_t)j * s.n;
     TY* Y = static_cast<TY*>(s.V) + (size_t)(j + 1) * s.n;
     const uint16_t* ahi = MODE == g16::MODE_FP16 ? s.a8_f16 : s.a8_hi;
     const uint16_t* blo = MODE == g16::MODE_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr;
-    g16::tile<MODE, C, false, TY>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X,
+    g16::tile<MODE, C, false, TY>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, nullptr,
                                   Y, s.albedo, MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr,
                                   1.f / s.l_scale, (float)s.gs->vscale[j],
-                                  s.kform ? 1.f : -1.f, s.n_r,
+                                  1.f, s.n_r,
                                   (int)s.n_s, w.a, w.b, lds, gemm::TileDots{}, 0, s.vs);
   }
 }
@@ -388,13 +387,9 @@ __global__ __launch_bounds__(64) void bk_givens(const SlotDev* __restrict__ slot
       const int j = z.j;
       const double hn = sqrt(v);
       double* col = gs->R + (size_t)j * (kMaxRestart + 1);
-      if (s.kform) {   // vs A v_j = vs v_j - vs K v_j
-        for (int i = 0; i <= j; ++i) col[i] = (i == j ? (double)s.vs : 0.0) - gs->h[i];
-        col[j + 1] = -hn;
-      } else {
-        for (int i = 0; i <= j; ++i) col[i] = gs->h[i];
-        col[j + 1] = hn;
-      }
+      // vs A v_j = vs v_j - vs K v_j
+      for (int i = 0; i <= j; ++i) col[i] = (i == j ? (double)s.vs : 0.0) - gs->h[i];
+      col[j + 1] = -hn;
       const double raw_diag = col[j];
       for (int i = 0; i < j; ++i) {
         const double t1 = gs->cs[i] * col[i] + gs->sn[i] * col[i + 1];

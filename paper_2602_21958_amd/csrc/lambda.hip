@@ -113,25 +113,13 @@ template <> struct ComputeOf<_Float16> { using type = float; };
 
 }  // namespace
 
-// Frequencies per box workgroup.  One by default: sweeping four frequencies
-// of an ordinate together shares the upwind stencil and opacity but needs
-// 4x the per-thread state, and at the occupancy that leaves the sweep is
-// slower (measured on the 32^3 box).  RTSN_LAMBDA_F=4 selects four for
-// planes of up to 1024 points (one point per thread of a 1024-thread group
-// when the plane is larger than 256 points); 0 when not even one ray's
-// (2F + 1) LDS planes fit.
+// Frequencies per box workgroup: one (a ray per group), or 0 when the ray's
+// three LDS planes do not fit.  Sweeping four frequencies of an ordinate
+// together shares the upwind stencil and opacity but needs 4x the per-thread
+// state, and at the occupancy that leaves it was measured slower on the 32^3
+// box (FP64 0.82 against 0.40 ms; FP32 0.22 against 0.19 ms).
 int box_chunk(int P, int elem_bytes, int max_lds) {
-  static const int want = [] {
-    const char* e = std::getenv("RTSN_LAMBDA_F");
-    return (e && std::atoi(e) >= 4) ? 4 : 1;
-  }();
-  // (FP64 state of four rays per thread fits a 1024-thread group only for
-  // planes of up to 256 points)
-  if (want == 4 && P <= (elem_bytes == 4 ? 1024 : 256) &&
-      (size_t)9 * P * elem_bytes <= (size_t)max_lds)
-    return 4;
-  if ((size_t)3 * P * elem_bytes <= (size_t)max_lds) return 1;
-  return 0;
+  return (size_t)3 * P * elem_bytes <= (size_t)max_lds ? 1 : 0;
 }
 
 // Measured with two sets against one on the 32^3 box: FP64 0.239 -> 0.226 ms
@@ -140,13 +128,8 @@ int box_chunk(int P, int elem_bytes, int max_lds) {
 // threads, one group per CU either way) 5.76 -> 5.86 ms, so larger planes
 // keep one set.
 bool box_pingpong(int F, int P, int elem_bytes, int max_lds) {
-  static const int env = [] {
-    const char* e = std::getenv("RTSN_LAMBDA_PP");
-    return e ? std::atoi(e) : -1;
-  }();
-  if (env == 0 || F != 1 || lam::box_lds_elems(F, P, true) * elem_bytes > (size_t)max_lds)
-    return false;
-  return env == 1 || P <= 1024;
+  if (F != 1 || lam::box_lds_elems(F, P, true) * elem_bytes > (size_t)max_lds) return false;
+  return P <= 1024;
 }
 
 template <typename VT, typename LT, int K4>
@@ -172,11 +155,7 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     const size_t lds = lam::box_lds_elems(F, P, pp) * sizeof(C);
     const int grid = p.n_omega * ((p.n_nu + F - 1) / F);
     // one ray per group (group index = ray index) into the k4 operand
-    static const bool xcd_env = [] {
-      const char* e = std::getenv("RTSN_LAMBDA_XCD");
-      return !(e && std::atoi(e) == 0);
-    }();
-    const int xcd = (K4 >= 0 && F == 1 && xcd_env) ? 1 : 0;
+    const int xcd = (K4 >= 0 && F == 1) ? 1 : 0;
 #define RT_BOX_LAUNCH1(FF, NPT, NT, PPV)                                                          \
   hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT, PPV>), dim3(grid), dim3(NT), \
                      lds, st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu,    \
@@ -190,16 +169,11 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     // the 32^3 box); up to 4096 points: 1024 threads of 4 points (FP64: 128
     // VGPRs with a few spilled, 16 waves per CU, 10.6 ms on the 64^3 box
     // against 11.7 ms for 512 threads of 8 points at 250 VGPRs)
-    if (F == 4) {
-      if (P <= 256) RT_BOX_LAUNCH1(4, 1, 256, false);
-      else RT_BOX_LAUNCH1(4, 1, 1024, false);
-    } else {
-      if (P <= 256) { RT_BOX_LAUNCH(1, 1, 256); }
-      else if (P <= 1024) { RT_BOX_LAUNCH(1, 2, 512); }
-      else if (P <= 4096) { RT_BOX_LAUNCH(1, 4, 1024); }
-      else {
-        fail(RT_E_INVALID, "box plane larger than 4096 points");
-      }
+    if (P <= 256) { RT_BOX_LAUNCH(1, 1, 256); }
+    else if (P <= 1024) { RT_BOX_LAUNCH(1, 2, 512); }
+    else if (P <= 4096) { RT_BOX_LAUNCH(1, 4, 1024); }
+    else {
+      fail(RT_E_INVALID, "box plane larger than 4096 points");
     }
 #undef RT_BOX_LAUNCH
 #undef RT_BOX_LAUNCH1

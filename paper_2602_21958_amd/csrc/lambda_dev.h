@@ -156,13 +156,10 @@ struct PlainOuts {
   static constexpr bool kScaled = false;
   LT* o;          // ray k0
   size_t stride;  // elements per ray
-  __device__ __forceinline__ bool grouped() const { return false; }
   template <typename C>
   __device__ __forceinline__ void put(int f, size_t i, C v) const {
     o[(size_t)f * stride + i] = store_val<C, LT>(v);
   }
-  template <typename C>
-  __device__ __forceinline__ void put4(size_t, C, C, C, C) const {}
 };
 
 template <int MODE>
@@ -172,34 +169,11 @@ struct K4Outs {
   uint16_t* lo;
   int64_t Np;
   int k0;
-  __device__ __forceinline__ bool grouped() const { return (k0 & 3) == 0; }
   template <typename C>
   __device__ __forceinline__ void put(int f, size_t i, C v) const {
     const int k = k0 + f;
     const size_t off = ((size_t)(k >> 2) * Np) * 4 + (k & 3);
     K4Out<MODE>{hi + off, lo ? lo + off : nullptr}.put(i, v);
-  }
-  // the four values of k4 group k0 / 4 at point i: one 8-byte store per part
-  template <typename C>
-  __device__ __forceinline__ void put4(size_t i, C v0, C v1, C v2, C v3) const {
-    const size_t at = ((size_t)(k0 >> 2) * Np + i) * 4;
-    const float v[4] = {(float)v0, (float)v1, (float)v2, (float)v3};
-    uint16_t h[4], l[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if constexpr (MODE == K4_FP16) {
-        h[f] = __half_as_ushort(__float2half(v[f]));
-      } else {
-        h[f] = bf16_rne(v[f]);
-        if constexpr (MODE == K4_SPLIT)
-          l[f] = bf16_rne(v[f] - __bfloat162float(__ushort_as_bfloat16(h[f])));
-      }
-    }
-    *reinterpret_cast<uint2*>(hi + at) =
-        make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-    if constexpr (MODE == K4_SPLIT)
-      *reinterpret_cast<uint2*>(lo + at) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
-                                                      (uint32_t)l[2] | ((uint32_t)l[3] << 16));
   }
 };
 
@@ -296,9 +270,7 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
 // them before they are used, so the loads stay in flight over a plane).
 //
 // src(f): the ray's nz*P source values; fac[f]: phi_nu + r of ray f;
-// out.put(f, i, v) stores value i of ray f, out.put4(i, v0..v3) the four rays
-// at once when nf == 4 and out.grouped() (the rays form one k4 group of the
-// 16-bit operand).
+// out.put(f, i, v) stores value i of ray f.
 constexpr int kBoxThreads = 256;
 
 // LDS elements of type C that box_rays needs.
@@ -401,20 +373,9 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
           I[f] = e * Iu + a * Su + c * Sv[f][j];
         }
       }
-      if constexpr (F == 4) {
-        if (nf == 4 && out.grouped()) {   // all four rays of one k4 group are here
-          out.put4(oz + p, scaled_out<OUT>(I[0], om), scaled_out<OUT>(I[1], om),
-                   scaled_out<OUT>(I[2], om), scaled_out<OUT>(I[3], om));
-        } else {
 #pragma unroll
-          for (int f = 0; f < F; ++f)
-            if (f < nf) out.put(f, oz + p, scaled_out<OUT>(I[f], om));
-        }
-      } else {
-#pragma unroll
-        for (int f = 0; f < F; ++f)
-          if (f < nf) out.put(f, oz + p, scaled_out<OUT>(I[f], om));
-      }
+      for (int f = 0; f < F; ++f)
+        if (f < nf) out.put(f, oz + p, scaled_out<OUT>(I[f], om));
 #pragma unroll
       for (int f = 0; f < F; ++f) Iv[f][j] = I[f];
     }

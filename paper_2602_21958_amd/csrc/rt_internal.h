@@ -129,8 +129,7 @@ float fp16_basis_scale(int64_t n);
 int box_chunk(int P, int elem_bytes, int max_lds);
 // Whether box sweeps of F frequencies per group on planes of P points keep two
 // alternating LDS sets (one barrier per plane): F == 1, P <= 1024 and
-// 2 (2F + 1) P elements within max_lds bytes.  RTSN_LAMBDA_PP=0 turns it off,
-// =1 also allows it for larger planes.
+// 2 (2F + 1) P elements within max_lds bytes.
 bool box_pingpong(int F, int P, int elem_bytes, int max_lds);
 // Size in elements of one part of the k4 operand; allocation of the
 // problem's (zeroed) two-part buffer.
@@ -168,8 +167,6 @@ int sigma_dot_slots(const Problem& p, int precision);
 void operator_apply(Problem& p, int precision, const void* x, void* y,
                     const double* xscale, hipStream_t st,
                     gemm::TileDots* dots = nullptr);
-// Whether GMRES runs Arnoldi on K = I - A (default) rather than on A.
-bool kform();
 // The scattering part alone, y = K (xs x) with K = (1 - eps) Mhat Lambda =
 // I - A (no x term: the GEMM epilogue reads no x).
 void operator_apply_k(Problem& p, int precision, const void* x, void* y,

@@ -27,15 +27,6 @@ using gemm::TileDots;
 
 namespace {
 
-// K-tile depth of the FP64/FP32 GEMM (tuning override: RTSN_GEMM_BK=16|32).
-int gemm_bk() {
-  static const int bk = [] {
-    const char* e = std::getenv("RTSN_GEMM_BK");
-    return (e && std::atoi(e) == 32) ? 32 : 16;
-  }();
-  return bk;
-}
-
 template <typename T, int BK, bool DOTS>
 __global__ __launch_bounds__(256) void sigma_gemm_kernel(
     const T* __restrict__ A, int lda, const T* __restrict__ B, const T* X, T* Y,
@@ -65,11 +56,8 @@ void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* 
 #define RT_SIGMA_LAUNCH(BKV, DV)                                                              \
   hipLaunchKernelGGL((sigma_gemm_kernel<T, BKV, DV>), dim3(tiles), dim3(256), 0, st, mhat,   \
                      p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign, d)
-  if (gemm_bk() == 32) {
-    if (dots) RT_SIGMA_LAUNCH(32, true); else RT_SIGMA_LAUNCH(32, false);
-  } else {
-    if (dots) RT_SIGMA_LAUNCH(16, true); else RT_SIGMA_LAUNCH(16, false);
-  }
+  // K stage 16 (a stage of 32 was measured slower)
+  if (dots) RT_SIGMA_LAUNCH(16, true); else RT_SIGMA_LAUNCH(16, false);
 #undef RT_SIGMA_LAUNCH
   RT_HIP(hipGetLastError());
 }

@@ -22,28 +22,6 @@
 
 namespace rtsn {
 
-// Arnoldi on K = I - A instead of A (same Krylov space; A's Hessenberg
-// column follows as e_j - h and -beta): the operator then needs no x term,
-// so the GEMM epilogue reads no x.  RTSN_KFORM=0 runs Arnoldi on A.
-bool kform() {
-  static const bool k = [] {
-    const char* e = std::getenv("RTSN_KFORM");
-    return !(e && e[0] == '0');
-  }();
-  return k;
-}
-
-// Two Arnoldi steps per pass over the basis (FP64 GMRES on K): per solve
-// with rt_solver_opts.two_step; RTSN_SSTEP=2 / =1 forces pairs / single
-// steps for every solve.
-int two_step_env() {
-  static const int k = [] {
-    const char* e = std::getenv("RTSN_SSTEP");
-    return e ? std::atoi(e) : 0;
-  }();
-  return k;
-}
-
 Workspace::~Workspace() {
   hipFree(V);
   hipFree(partial);
@@ -236,9 +214,8 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   while (s.beta > rtol * bnorm && res.iters < max_iters) {
     res.cycles++;
     int k = 0, logged = 0;
-    const int env = two_step_env();
     const bool pairs = (std::is_same<TV, double>::value || std::is_same<TV, float>::value) &&
-                       kform() && !fuse_dots() && (env == 2 || (env != 1 && two));
+                       !fuse_dots() && two;
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
@@ -263,21 +240,20 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
         if (r.stop || res.iters >= max_iters) break;
         continue;
       }
-      const bool kf = kform();
+      // Arnoldi on K = I - A (same Krylov space; A's Hessenberg column is
+      // e_j - h, -beta): the operator has no x term, the GEMM reads no v_j
       if (fuse_dots()) {
         // h_q = vscale_q V_q . w, summed over the GEMM's output tiles in its epilogue
         gemm::TileDots d{V, n, j + 1, ws.partial, ws.dot_slots};
-        if (kf) operator_apply_k(p, prec, vj, w, gs->vscale + j, st, &d);   // sets d.ldp
-        else operator_apply(p, prec, vj, w, gs->vscale + j, st, &d);
+        operator_apply_k(p, prec, vj, w, gs->vscale + j, st, &d);   // sets d.ldp
         k_reduce_rows_nb(ws.partial, d.ldp, j + 1, gs->vscale, gs->h, st);
       } else {
-        if (kf) operator_apply_k(p, prec, vj, w, gs->vscale + j, st);
-        else operator_apply(p, prec, vj, w, gs->vscale + j, st);
+        operator_apply_k(p, prec, vj, w, gs->vscale + j, st);
         k_mdot<TV>(V, n, j + 1, w, ws.partial, st);
         k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
       }
       k_update<TV>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-      k_givens(ws.partial, n, gs, j, rtol * bnorm, st, kf ? 1.0 : 0.0);
+      k_givens(ws.partial, n, gs, j, rtol * bnorm, st, 1.0);
       res.iters++;
       k = j + 1;
       if (k < m && res.iters < max_iters && k % every != 0) continue;
@@ -329,8 +305,7 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
     fail(RT_E_NONFINITE, "fp16 basis: right-hand side out of range");
   int k = 0, logged = 0;
   const int steps = std::min(m, cap), every = status_every(n);
-  const int env = two_step_env();
-  const bool pairs = kform() && (env == 2 || (env != 1 && two));
+  const bool pairs = two;
   for (int j = 0; j < steps; ++j) {
     _Float16* w = V + (size_t)(j + 1) * n;
     if (pairs && j + 1 < steps) {
@@ -355,12 +330,12 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
       if (r.stop) break;
       continue;
     }
-    const bool kf = kform();   // Arnoldi on S K: S A = S I - S K
-    operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, kf);
+    // Arnoldi on S K: S A = S I - S K
+    operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, true);
     k_mdot<_Float16>(V, n, j + 1, w, ws.partial, st);
     k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
     k_update<_Float16>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
-    k_givens(ws.partial, n, gs, j, itol * s0.beta, st, kf ? (double)S : 0.0);
+    k_givens(ws.partial, n, gs, j, itol * s0.beta, st, (double)S);
     k = j + 1;
     if (k < steps && k % every != 0) continue;
     const StepRead r = read_steps(ws, st, k, logged, nullptr, 1.0);

@@ -116,7 +116,12 @@ def test_lambda_fp32(name):
         got = host(out)
     ref = op.lam(s.astype(np.float32).astype(np.float64).reshape(op.n_r, op.n_s),
                  with_bc=False).ravel()
-    assert relerr(got, ref) < 2e-5
+    # per entry: the source is positive, so every term of the recurrence is
+    # positive and each intensity carries a few FP32 roundings of its own size
+    assert np.all(ref > 0)
+    rel = np.abs(got - ref) / ref
+    say(f"   worst per-entry relative error {rel.max():.2e}")
+    assert rel.max() < 2e-5
 
 
 @pytest.mark.parametrize("name", list(ALL))
@@ -192,11 +197,21 @@ def test_box32_operator_full_size():
     assert relerr(got, ref) < 1e-12
 
 
+def oracle_at_step(op, b, restart, iters):
+    """The oracle's GMRES(restart) iterate after exactly `iters` Arnoldi
+    steps (no stopping test): the iterate a library solve that took `iters`
+    steps computes in exact arithmetic, whatever step each side's rounding
+    let cross the tolerance."""
+    return gmres(op.apply, b, restart=restart, tol=0.0, maxiter=iters)["x"]
+
+
 @pytest.mark.parametrize("two_step", [1, 0])
 @pytest.mark.parametrize("name", ["slab64", "box8"])
 def test_gmres_fp64_matches_oracle(name, two_step):
     """FP64 GMRES(30) against the oracle's: Arnoldi steps in pairs (the
-    default) and one at a time."""
+    default) and one at a time.  Residual estimates follow the oracle's to
+    1e-8 over 20 steps; the solution is the oracle's iterate at the same
+    step to 1e-9 (Gram-Schmidt rounding only)."""
     rt = _rt()
     spec = ALL[name]()
     say(f"gmres fp64 {name} two_step={two_step}")
@@ -213,14 +228,12 @@ def test_gmres_fp64_matches_oracle(name, two_step):
     h = np.array(st["history"][:20])
     hr = np.array(ref["history"][:20])
     assert np.max(np.abs(h - hr) / hr) < 1e-8
-    assert op.residual_norm(s) <= 1.0e-8
-    diff = np.linalg.norm(s - ref["x"]) / np.linalg.norm(ref["x"])
-    if st["iters"] == ref["iters"]:
-        # same Krylov step: iterates differ by Gram-Schmidt rounding only
-        assert diff < 1e-9
-    else:
-        # one step apart: both satisfy the 1e-8 residual bound
-        assert diff < 1e-5
+    assert op.residual_norm(s) <= 1e-8
+    xr = ref["x"] if st["iters"] == ref["iters"] else oracle_at_step(op, b, 30, st["iters"])
+    diff = np.linalg.norm(s - xr) / np.linalg.norm(xr)
+    say(f"   iters {st['iters']} (oracle {ref['iters']}), diff to the same-step iterate "
+        f"{diff:.2e}")
+    assert diff < 1e-9
 
 
 @pytest.mark.parametrize("restart", [30, 7])
@@ -228,33 +241,61 @@ def test_gmres_fp64_matches_oracle(name, two_step):
 def test_gmres_two_step_matches_oracle(name, restart):
     """FP64 GMRES with the Arnoldi steps taken in pairs (two_step: u1 = K v_j,
     u2 = K u1 orthogonalised together; an odd restart ends each cycle with
-    one single step), also with short restarts.  Same Krylov iterates in
-    exact arithmetic: the iteration count is within 2 % (at least one) of
-    the oracle's (many short cycles compound rounding differences), the
-    oracle-evaluated residual meets 1e-8 and the residual estimates follow
-    the oracle's to 1e-8 relative over 20 steps."""
+    one single step), also with short restarts, beside the one-step form.
+    Same Krylov iterates in exact arithmetic: the iteration counts are within
+    2 % (at least one) of the oracle's (many short cycles compound rounding
+    differences near the tolerance), the oracle-evaluated residual meets
+    1e-8, the residual estimates follow the oracle's to 1e-8 relative over 20
+    steps, and each solution is the oracle's iterate at its own step count
+    to 1e-9."""
     rt = _rt()
     spec = ALL[name]()
     say(f"gmres two-step {name} m={restart}")
     op = OProblem(spec)
     b = op.rhs().ravel()
     ref = gmres(op.apply, b, restart=restart, tol=1e-8)
+    out = {}
+    with rt.Problem(spec) as p:
+        for two in (1, 0):
+            x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+            out[two] = (p.solve(x, rtol=1e-8, restart=restart, two_step=two), host(x))
+    say(f"   iters: pairs {out[1][0]['iters']}, one step {out[0][0]['iters']}, "
+        f"oracle {ref['iters']}")
+    tol_it = max(1, ref["iters"] // 50)
+    for two, (st, s) in out.items():
+        assert st["converged"]
+        assert abs(st["iters"] - ref["iters"]) <= tol_it, (two, st["iters"], ref["iters"])
+        h = np.array(st["history"][:20])
+        hr = np.array(ref["history"][:20])
+        assert np.max(np.abs(h - hr) / hr) < 1e-8
+        assert op.residual_norm(s) <= 1e-8
+        xr = ref["x"] if st["iters"] == ref["iters"] else oracle_at_step(op, b, restart,
+                                                                         st["iters"])
+        diff = np.linalg.norm(s - xr) / np.linalg.norm(xr)
+        say(f"   two_step={two}: diff to the oracle iterate at step {st['iters']}: {diff:.2e}")
+        assert diff < 1e-9
+
+
+@pytest.mark.parametrize("two_step", [1, 0])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_24x20x5"])
+def test_gmres_tight_solution_matches_oracle(name, two_step):
+    """Solves at rtol 1e-13 agree with the oracle's to 1e-10 (2-norm
+    relative), with the Arnoldi steps in pairs and one at a time."""
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"gmres tight {name} two_step={two_step}")
+    op = OProblem(spec)
+    ref = gmres(op.apply, op.rhs().ravel(), restart=30, tol=1e-13)
+    assert ref["converged"]
     with rt.Problem(spec) as p:
         x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
-        st = p.solve(x, rtol=1e-8, restart=restart, two_step=1)
+        st = p.solve(x, rtol=1e-13, restart=30, two_step=two_step, max_iters=3000)
         s = host(x)
-    assert st["converged"]
-    # many short cycles compound the rounding difference (GMRES(7) on the
-    # 24x20 box: 206 steps against the oracle's 203)
-    assert abs(st["iters"] - ref["iters"]) <= max(1, ref["iters"] // 50), (st["iters"],
-                                                                          ref["iters"])
-    h = np.array(st["history"][:20])
-    hr = np.array(ref["history"][:20])
-    assert np.max(np.abs(h - hr) / hr) < 1e-8
-    assert op.residual_norm(s) <= 1.0e-8
     diff = np.linalg.norm(s - ref["x"]) / np.linalg.norm(ref["x"])
-    say(f"   iters {st['iters']} (oracle {ref['iters']}), solution diff {diff:.2e}")
-    assert diff < (1e-6 if st["iters"] == ref["iters"] else 1e-5)
+    say(f"   iters {st['iters']} (oracle {ref['iters']}), relres {st['relres']:.2e}, "
+        f"solution diff {diff:.2e}")
+    assert st["converged"]
+    assert diff < 1e-10
 
 
 @pytest.mark.parametrize("two_step", [1, 0])
@@ -280,7 +321,7 @@ def test_mixed_refinement_fp16_basis(name, prec, two_step):
         f"inner={st['iters']} (FP32 basis: outer={ref['outer_iters']}) residual={res:.3e}")
     if ref["converged"]:
         assert st["converged"], st
-        assert res <= 1.05e-8
+        assert res <= 1e-8
         # the basis rounding (2^-11) must not cost the refinement extra steps
         # beyond a small margin
         assert st["outer_iters"] <= ref["outer_iters"] + 2, (st, ref)
@@ -329,7 +370,7 @@ def test_gmres_with_dots_fused_into_sigma(prec, monkeypatch):
         st = p.solve(x, rtol=1e-8, restart=30, precision=prec)
         s = host(x)
     assert st["converged"]
-    assert op.residual_norm(s) <= 1.05e-8
+    assert op.residual_norm(s) <= 1e-8
 
 
 @pytest.mark.parametrize("name,precision,basis16",
@@ -358,20 +399,6 @@ def test_batched_status_reads_give_identical_results(name, precision, basis16, m
         assert np.array_equal(out[every][1], out["1"][1])
 
 
-def test_gmres_tight_solution_matches_oracle():
-    rt = _rt()
-    spec = W.slab64()
-    say("gmres tight slab64")
-    op = OProblem(spec)
-    ref = gmres(op.apply, op.rhs().ravel(), restart=30, tol=1e-13)
-    with rt.Problem(spec) as p:
-        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
-        st = p.solve(x, rtol=1e-13, restart=30)
-        s = host(x)
-    assert st["converged"]
-    assert np.linalg.norm(s - ref["x"]) / np.linalg.norm(ref["x"]) < 1e-10
-
-
 def test_eps_one_is_one_iteration():
     rt = _rt()
     spec = W.slab64()
@@ -397,10 +424,11 @@ def test_zero_rhs_gives_zero():
         assert not torch.any(x).item()
 
 
-def test_bicgstab_fp64():
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
+def test_bicgstab_fp64(name):
     rt = _rt()
-    spec = W.slab64()
-    say("bicgstab slab64")
+    spec = ALL[name]()
+    say(f"bicgstab {name}")
     op = OProblem(spec)
     ref = bicgstab(op.apply, op.rhs().ravel(), tol=1e-8)
     with rt.Problem(spec) as p:
@@ -451,7 +479,7 @@ def test_mixed_fp32_refinement_reaches_fp64_residual(name):
         s = host(x)
     assert st["converged"], st
     assert st["outer_iters"] >= 2
-    assert op.residual_norm(s) <= 1.05e-8
+    assert op.residual_norm(s) <= 1e-8
 
 
 def test_profile_counts_launches():
@@ -540,9 +568,9 @@ def test_sigma_16bit_every_tile_shape(cfg, prec, monkeypatch):
                                    (40, 40, 6, 2, 4, 4)])
 def test_operator_16bit_box(shape, prec):
     """Whole 16-bit operator y = x - (1-eps) Mhat Lambda x on boxes whose
-    frequency count is a multiple of 4 (one k4 group per workgroup, 8-byte
-    stores) or not (groups straddle ordinates; partial last chunk), and a plane
-    larger than 1024 points (one frequency per workgroup).  Bound: 16-bit
+    frequency count is a multiple of 4 (a k4 group of rays is one ordinate's)
+    or not (k4 groups straddle two ordinates; partial last group), with planes
+    of up to 1024 points (two LDS sets) and of more (one set).  Bound: 16-bit
     operand rounding of Mhat and of the FP32 Lambda output, plus the FP32
     Lambda itself."""
     rt = _rt()
@@ -591,7 +619,7 @@ def test_mixed_refinement_per_precision(name, prec, two_step):
     say(f"   {prec} {name}: converged={st['converged']} outer={st['outer_iters']} "
         f"inner={st['iters']} oracle residual={res:.3e}")
     if st["converged"]:
-        assert res <= 1.05e-8
+        assert res <= 1e-8
     else:
         # a precision too coarse for this conditioning: reported, not hidden
         assert prec == "bf16", st

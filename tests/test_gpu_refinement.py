@@ -65,7 +65,7 @@ def test_slab_counts_flat_under_depth_refinement(precision):
         say(f"slab nz={nz} {precision}")
         st, s = _solve(spec, precision)
         assert st["converged"], st
-        assert OProblem(spec).residual_norm(s) <= 1.05e-8
+        assert OProblem(spec).residual_norm(s) <= 1e-8
         counts[nz] = st["iters"]
     say(f"   slab {precision} iterations by N_z: {counts}")
     assert _within(counts, 0.1), counts
@@ -88,7 +88,7 @@ def test_counts_flat_under_angle_and_frequency_refinement():
         say(f"slab mu={n_mu} nu={n_nu}")
         st, s = _solve(spec)
         assert st["converged"], st
-        assert OProblem(spec).residual_norm(s) <= 1.05e-8
+        assert OProblem(spec).residual_norm(s) <= 1e-8
         counts[(n_mu, n_nu)] = st["iters"]
     say(f"   slab iterations by (mu, nu): {counts}")
     assert _within(counts, 0.1), counts
@@ -103,7 +103,24 @@ def test_box_counts_under_spatial_refinement():
         assert st["converged"], st
         if n <= 16:   # oracle FP64 residual (larger grids: the device FP64
             # operator, checked against the oracle by the parity tests)
-            assert OProblem(spec).residual_norm(s) <= 1.05e-8
+            assert OProblem(spec).residual_norm(s) <= 1e-8
         counts[n] = st["iters"]
     say(f"   box iterations by n: {counts}")
     assert counts[48] - counts[16] <= 5, counts
+
+
+def test_config_recipe_counts_flat_from_32_to_64():
+    """The box workloads' own recipe (vertical line-centre depth 1e4, 20 %
+    log-normal horizontal fluctuations, 8 mu x 8 azimuths) with 8 instead
+    of 32-48 frequencies: GMRES(30) counts at 32^3, 48^3 and 64^3 within
+    10 % of the finest grid's, the regime the benchmark boxes run in."""
+    counts = {}
+    for n in (32, 48, 64):
+        spec = W.box(n, 8, 8, 8, W.SEED_BASE + 1)
+        say(f"config-recipe box {n}^3 (8 mu x 8 az x 8 nu)")
+        st, s = _solve(spec)
+        assert st["converged"], st
+        counts[n] = st["iters"]
+        del s
+    say(f"   config-recipe iterations by n: {counts}")
+    assert _within(counts, 0.1), counts
