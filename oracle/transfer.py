@@ -4,7 +4,7 @@ Paper Sec. 3.2: along each ray r = (mu, nu) the transfer equation
 dI/dtau = I - S is integrated from the incoming boundary; different rays are
 independent, so Lambda is block diagonal in ray order (eq. lambda_block).
 
-Two schemes:
+Three schemes:
 
 * implicit Euler, exactly eqs. ie_1 / ie_2: for mu < 0 (entering at the
   surface, index 0) I_{i+1} = (I_i + dtau_i S_{i+1}) / (1 + dtau_i); for mu > 0
@@ -17,6 +17,16 @@ Two schemes:
   For D < 0.5 a and c are summed from their Taylor series
   a = sum_{n>=1} (-1)^{n+1} n D^n/(n+1)!,  c = sum_{n>=1} (-1)^{n+1} D^n/(n+1)!
   (25 terms), avoiding the cancellation of the closed forms.
+* quadratic short characteristics: the same integral with S the parabola
+  through the upwind, local and downwind values.  With t the optical depth
+  measured back from the local point (t = D_u at the upwind point, -D_d at
+  the downwind one) and the moments w_k = int_0^{D_u} t^k e^{-t} dt,
+  integrating each Lagrange basis polynomial against e^{-t} gives
+  I_0 = e^{-D_u} I_u + psi_u s_u + psi_0 s_0 + psi_d s_d,
+  psi_u = (w2 + D_d w1) / (D_u (D_u + D_d)),
+  psi_0 = (w2 - (D_u - D_d) w1 - D_u D_d w0) / (-D_u D_d),
+  psi_d = (w2 - D_u w1) / (D_d (D_u + D_d)).
+  The last point of a ray has no downwind point and takes the linear step.
 
 Optical depths: slab, dtau_i(mu, nu) = (t_{i+1} - t_i)(phi_nu + r)/|mu| with t
 the frequency-integrated line optical depth (Sec. 5: tau = phi t / mu, with |mu|
@@ -65,6 +75,44 @@ def exp_weights(d: np.ndarray):
     return e, a, c
 
 
+def exp_moments(d: np.ndarray):
+    """(w0, w1, w2), w_k(D) = int_0^D t^k e^{-t} dt.
+
+    Closed forms from integration by parts, w_k = k w_{k-1} - D^k e^{-D}
+    (w0 = 1 - e^{-D}); for D < 0.5 the Taylor series of e^{-t} integrated
+    term by term, w_k = sum_m (-1)^m D^{k+m+1} / (m! (k+m+1)) (30 terms)."""
+    d = np.asarray(d, dtype=np.float64)
+    small = d < _SERIES_BELOW
+    ds = np.where(small, d, 0.0)
+    ser = [np.zeros_like(d) for _ in range(3)]
+    for k in range(3):
+        fact = 1.0
+        for m in range(30):
+            if m:
+                fact *= m
+            sign = 1.0 if m % 2 == 0 else -1.0
+            ser[k] = ser[k] + sign * ds ** (k + m + 1) / (fact * (k + m + 1))
+    dl = np.where(small, 1.0, d)
+    e = np.exp(-dl)
+    w0 = -np.expm1(-dl)
+    w1 = w0 - dl * e
+    w2 = 2.0 * w1 - dl * dl * e
+    return (np.where(small, ser[0], w0), np.where(small, ser[1], w1),
+            np.where(small, ser[2], w2))
+
+
+def quad_weights(du: np.ndarray, dd: np.ndarray):
+    """(e^{-D_u}, psi_u, psi_0, psi_d) of the quadratic short-characteristics
+    step with upwind interval D_u and downwind interval D_d."""
+    du = np.asarray(du, dtype=np.float64)
+    dd = np.asarray(dd, dtype=np.float64)
+    w0, w1, w2 = exp_moments(du)
+    psi_u = (w2 + dd * w1) / (du * (du + dd))
+    psi_0 = (w2 - (du - dd) * w1 - du * dd * w0) / (-du * dd)
+    psi_d = (w2 - du * w1) / (dd * (du + dd))
+    return np.exp(-du), psi_u, psi_0, psi_d
+
+
 def sweep_slab(depth, mu_ray, fac_ray, s, i_top=0.0, i_bot=0.0,
                scheme: str = "linear_sc"):
     """Formal solution on a slab for every ray.
@@ -102,6 +150,26 @@ def sweep_slab(depth, mu_ray, fac_ray, s, i_top=0.0, i_bot=0.0,
         for i in range(nz - 2, -1, -1):
             e, a, c = exp_weights(dtau[up, i])
             out[up, i] = e * out[up, i + 1] + a * s[up, i + 1] + c * s[up, i]
+    elif scheme == "quadratic_sc":
+        # downgoing rays: upwind i-1, downwind i+1; the last point (i = nz-1)
+        # takes the linear step
+        for i in range(1, nz):
+            if i + 1 < nz:
+                e, pu, p0, pd = quad_weights(dtau[down, i - 1], dtau[down, i])
+                out[down, i] = (e * out[down, i - 1] + pu * s[down, i - 1] + p0 * s[down, i]
+                                + pd * s[down, i + 1])
+            else:
+                e, a, c = exp_weights(dtau[down, i - 1])
+                out[down, i] = e * out[down, i - 1] + a * s[down, i - 1] + c * s[down, i]
+        # upgoing rays: upwind i+1, downwind i-1; the last point is i = 0
+        for i in range(nz - 2, -1, -1):
+            if i > 0:
+                e, pu, p0, pd = quad_weights(dtau[up, i], dtau[up, i - 1])
+                out[up, i] = (e * out[up, i + 1] + pu * s[up, i + 1] + p0 * s[up, i]
+                              + pd * s[up, i - 1])
+            else:
+                e, a, c = exp_weights(dtau[up, i])
+                out[up, i] = e * out[up, i + 1] + a * s[up, i + 1] + c * s[up, i]
     else:
         raise ValueError(scheme)
     return out

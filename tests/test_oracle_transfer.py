@@ -11,12 +11,13 @@ from oracle import (exp_weights, sweep_slab, sweep_box, directions_3d,
 
 
 def _weights_decimal(d):
-    """a(D), c(D) in 50-digit arithmetic from e^{-D} (closed forms)."""
-    ctx = decimal.Context(prec=50)
-    D = ctx.create_decimal_from_float(float(d))
-    e = ctx.exp(-D)
-    q = ctx.divide(1 - e, D)
-    return float(q - e), float(1 - q)
+    """a(D), c(D) in 50-digit arithmetic from e^{-D} (closed forms; every
+    operation in the 50-digit context)."""
+    with decimal.localcontext(decimal.Context(prec=50)):
+        D = decimal.Decimal(float(d))
+        e = (-D).exp()
+        q = (1 - e) / D
+        return float(q - e), float(1 - q)
 
 
 @pytest.mark.parametrize("d", [1e-12, 1e-8, 1e-4, 1e-2, 0.1, 0.3, 0.4999, 0.5,
