@@ -128,6 +128,10 @@ typedef struct {
   int64_t bytes_solve_fp64;  /* extra device bytes of an FP64 GMRES(restart) solve
                                 with the restart passed to rt_problem_footprint   */
   int64_t bytes_solve_mixed; /* same for a mixed-precision (FP32 basis) solve      */
+  int32_t sigma_rank;     /* angular rank of the factored scattering form (6 for
+                             the 3D dipole, 2 for the slab's azimuth average; 0:
+                             no factored form, explicit kernel)                  */
+  int32_t sigma_form;     /* RT_SIGMA_DENSE or RT_SIGMA_FACTORED                  */
 } rt_problem_info;
 
 /* rt_problem_create: build quadratures, the redistribution kernel (dipole x
@@ -176,6 +180,26 @@ rt_status rt_apply_sigma(rt_problem p, int precision, const void* L,
  * Lambda_0 x.  Errors: RT_E_INVALID, RT_E_NOMEM.                            */
 rt_status rt_apply_operator(rt_problem p, int precision, const void* x, void* y,
                             void* stream);
+
+/* How FP64 and FP32 applications compute the scattering step (Sec. 3.3,
+ * eq. Sigma).  RT_SIGMA_DENSE (default): one dense N_r x N_r GEMM shared by
+ * all points on the matrix cores, valid for any kernel Psi.
+ * RT_SIGMA_FACTORED (dipole x PRD kernels only): Mhat is the Kronecker
+ * product of an angular factor of exact rank R (R = 6 in 3D, where
+ * 3/4 (1 + (O.O')^2) = q(O)^T C q(O') over the six quadratic monomials of O;
+ * R = 2 for the slab's azimuth average) and the frequency block
+ * diag(1/(phi + r)) P_nu diag(w_nu); the step runs as a reduction to R
+ * angular moments, a frequency mix and an expansion, about
+ * 4 R + 2 R N_nu / N_omega flops per unknown instead of 2 N_r (the low-rank
+ * application that Sec. 4.1 remarks on; Sec. 5.1 notes the same rank
+ * structure for a Legendre-series kernel), bound by HBM.  The 16-bit
+ * precisions and the batch engine always use the dense GEMM.  Applies to
+ * every later call on p (operator, Sigma, right-hand side, solves); the
+ * physical right-hand side is rebuilt.  Synchronises the device.
+ * Errors: RT_E_INVALID (unknown form; factored with an explicit kernel or
+ * with more frequencies than the mix pass's LDS holds, about 120).         */
+enum { RT_SIGMA_DENSE = 0, RT_SIGMA_FACTORED = 1 };
+rt_status rt_problem_set_sigma(rt_problem p, int form);
 
 /* Right-hand side b = (1 - eps) Mhat I_bc + t (FP64, device, ray-major).     */
 rt_status rt_rhs(rt_problem p, double* b, void* stream);
@@ -312,12 +336,17 @@ rt_status rt_batch_destroy(rt_batch b);
 /* ---------------------------------------------------------------------------
  * Kernel timing.  While enabled, every launch of the formal solver, of the
  * scattering GEMM and of the Arnoldi vector kernels (dots, update) is
- * bracketed by HIP events recorded on the stream it is launched on.
+ * bracketed by HIP events recorded on the stream it is launched on.  The
+ * formal solver and the GEMM have one class for FP64 arithmetic (the plain
+ * solve, and the outer residuals and right-hand side of a mixed solve) and
+ * one for the lower precisions (FP32 sweeps, including those that emit the
+ * 16-bit GEMM operand; FP32 and 16-bit GEMMs: the inner cycles).
  * rt_profile_read synchronises the recorded events and returns the number of
  * launches and their summed device time for one kernel class; `reset` clears
  * that class afterwards.  Process-wide, internally synchronised.
  * ------------------------------------------------------------------------- */
-enum { RT_KCLASS_LAMBDA = 0, RT_KCLASS_SIGMA = 1, RT_KCLASS_ARNOLDI = 2, RT_KCLASS_COUNT = 3 };
+enum { RT_KCLASS_LAMBDA = 0, RT_KCLASS_SIGMA = 1, RT_KCLASS_ARNOLDI = 2,
+       RT_KCLASS_LAMBDA_LO = 3, RT_KCLASS_SIGMA_LO = 4, RT_KCLASS_COUNT = 5 };
 
 rt_status rt_profile_enable(int on);
 rt_status rt_profile_read(int kclass, int64_t* launches, double* total_ms, int reset);

@@ -117,6 +117,14 @@ class Problem:
         i2 = np.asarray(intensity, float).reshape(self.n_r, self.n_s)
         return self.albedo[None, :] * (self.mhat @ i2)
 
+    def scatter_points(self, intensity, points):
+        """scatter() for the spatial points `points` only (a slice or an
+        index array; intensity holds their N_r x len(points) columns): the
+        scattering block acts on each point by itself (eq. Sigma is block
+        diagonal over points), so a subset of columns is the same product."""
+        i2 = np.asarray(intensity, float).reshape(self.n_r, -1)
+        return self.albedo[None, points] * (self.mhat @ i2)
+
     # -------------------------------------------------------------- operator
     def apply(self, s):
         """A s = s - (1 - eps) Mhat Lambda_0 s (source-function form)."""

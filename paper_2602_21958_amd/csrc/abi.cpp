@@ -48,6 +48,13 @@ Problem::~Problem() {
   hipFree(d_stencil);
   hipFree(d_lbuf);
   hipFree(d_rhs);
+  hipFree(d_fq64);
+  hipFree(d_fg64);
+  hipFree(d_fb64);
+  hipFree(d_fq32);
+  hipFree(d_fg32);
+  hipFree(d_fb32);
+  hipFree(d_fwork);
 }
 
 size_t lambda_elem_bytes(int precision) {
@@ -70,6 +77,40 @@ uint16_t* problem_l16(Problem& p, hipStream_t st) {
     RT_HIP(hipMemsetAsync(p.d_l16, 0, bytes, st));
   }
   return p.d_l16;
+}
+
+static void* problem_fwork(Problem& p, size_t elem) {
+  const size_t bytes = factored_work_elems(p) * elem;
+  if (bytes > p.fwork_bytes) {
+    hipFree(p.d_fwork);
+    p.d_fwork = nullptr;
+    p.fwork_bytes = 0;
+    RT_HIP(hipMalloc(&p.d_fwork, bytes));
+    p.fwork_bytes = bytes;
+  }
+  return p.d_fwork;
+}
+
+void apply_sigma_f64(Problem& p, const double* L, const double* x, double* y,
+                     const double* xscale, double sign, hipStream_t st, gemm::TileDots* dots) {
+  if (p.sigma_form == RT_SIGMA_FACTORED) {
+    if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the dense scattering GEMM");
+    launch_sigma_factored_f64(p, L, x, y, static_cast<double*>(problem_fwork(p, sizeof(double))),
+                              xscale, sign, st);
+  } else {
+    launch_sigma_f64(p, L, x, y, xscale, sign, st, dots);
+  }
+}
+
+void apply_sigma_f32(Problem& p, const float* L, const float* x, float* y,
+                     const double* xscale, double sign, hipStream_t st, gemm::TileDots* dots) {
+  if (p.sigma_form == RT_SIGMA_FACTORED) {
+    if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the dense scattering GEMM");
+    launch_sigma_factored_f32(p, L, x, y, static_cast<float*>(problem_fwork(p, sizeof(float))),
+                              xscale, sign, st);
+  } else {
+    launch_sigma_f32(p, L, x, y, xscale, sign, st, dots);
+  }
 }
 
 void* problem_lbuf(Problem& p, size_t bytes) {
@@ -267,6 +308,17 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
     p.d_a8_f16 = upload(h16.data(), sz, tot);
     p.d_f16_rowscale = upload(rs.data(), rs.size(), tot);
   }
+  if (p.tab.frank > 0) {
+    const auto& t = p.tab;
+    p.d_fq64 = upload(t.fq.data(), t.fq.size(), tot);
+    p.d_fg64 = upload(t.fg.data(), t.fg.size(), tot);
+    p.d_fb64 = upload(t.fb.data(), t.fb.size(), tot);
+    std::vector<float> q32(t.fq.begin(), t.fq.end()), g32(t.fg.begin(), t.fg.end()),
+        b32(t.fb.begin(), t.fb.end());
+    p.d_fq32 = upload(q32.data(), q32.size(), tot);
+    p.d_fg32 = upload(g32.data(), g32.size(), tot);
+    p.d_fb32 = upload(b32.data(), b32.size(), tot);
+  }
   p.d_albedo = upload(alb.data(), alb.size(), tot);
   p.d_thermal = upload(therm.data(), therm.size(), tot);
   p.d_ray_mu = upload(p.tab.mu_ray.data(), p.tab.mu_ray.size(), tot);
@@ -306,15 +358,15 @@ void operator_apply(Problem& p, int precision, const void* x, void* y, const dou
     case RT_PREC_FP64: {
       double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
       launch_lambda<double, double>(p, static_cast<const double*>(x), L, false, xscale, st);
-      launch_sigma_f64(p, L, static_cast<const double*>(x), static_cast<double*>(y), xscale, -1.0,
-                       st, dots);
+      apply_sigma_f64(p, L, static_cast<const double*>(x), static_cast<double*>(y), xscale, -1.0,
+                      st, dots);
       break;
     }
     case RT_PREC_FP32: {
       float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
       launch_lambda<float, float>(p, static_cast<const float*>(x), L, false, xscale, st);
-      launch_sigma_f32(p, L, static_cast<const float*>(x), static_cast<float*>(y), xscale, -1.0,
-                       st, dots);
+      apply_sigma_f32(p, L, static_cast<const float*>(x), static_cast<float*>(y), xscale, -1.0,
+                      st, dots);
       break;
     }
     case RT_PREC_BF16:
@@ -339,13 +391,13 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y, const d
     case RT_PREC_FP64: {
       double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
       launch_lambda<double, double>(p, static_cast<const double*>(x), L, false, xscale, st);
-      launch_sigma_f64(p, L, nullptr, static_cast<double*>(y), xscale, +1.0, st, dots);
+      apply_sigma_f64(p, L, nullptr, static_cast<double*>(y), xscale, +1.0, st, dots);
       break;
     }
     case RT_PREC_FP32: {
       float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
       launch_lambda<float, float>(p, static_cast<const float*>(x), L, false, xscale, st);
-      launch_sigma_f32(p, L, nullptr, static_cast<float*>(y), xscale, +1.0, st, dots);
+      apply_sigma_f32(p, L, nullptr, static_cast<float*>(y), xscale, +1.0, st, dots);
       break;
     }
     case RT_PREC_BF16:
@@ -382,7 +434,7 @@ const double* physical_rhs(Problem& p, hipStream_t st) {
   double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
   RT_HIP(hipMemsetAsync(p.d_rhs, 0, n * sizeof(double), st));
   launch_lambda<double, double>(p, p.d_rhs, L, true, nullptr, st);
-  launch_sigma_f64(p, L, p.d_thermal, p.d_rhs, nullptr, +1.0, st);
+  apply_sigma_f64(p, L, p.d_thermal, p.d_rhs, nullptr, +1.0, st);
   return p.d_rhs;
 }
 
@@ -485,6 +537,8 @@ rt_status rt_problem_footprint(rt_problem p, int restart, rt_problem_info* info)
                              (int64_t)(q->n * sizeof(double));
     info->bytes_solve_mixed = (int64_t)workspace_bytes(*q, restart, true, false) +
                               (int64_t)(q->n * sizeof(double));
+    info->sigma_rank = q->tab.frank;
+    info->sigma_form = q->sigma_form;
   });
 }
 
@@ -527,10 +581,10 @@ rt_status rt_apply_sigma(rt_problem p, int precision, const void* L, const void*
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double sign = x ? -1.0 : +1.0;
     if (precision == RT_PREC_FP64) {
-      launch_sigma_f64(*q, static_cast<const double*>(L), static_cast<const double*>(x),
+      apply_sigma_f64(*q, static_cast<const double*>(L), static_cast<const double*>(x),
                        static_cast<double*>(y), nullptr, sign, st);
     } else if (precision == RT_PREC_FP32) {
-      launch_sigma_f32(*q, static_cast<const float*>(L), static_cast<const float*>(x),
+      apply_sigma_f32(*q, static_cast<const float*>(L), static_cast<const float*>(x),
                        static_cast<float*>(y), nullptr, sign, st);
     } else {
       // 16-bit operand paths take an FP32 L and round it like the operator does
@@ -550,6 +604,25 @@ rt_status rt_apply_operator(rt_problem p, int precision, const void* x, void* y,
     if (!x || !y) fail(RT_E_INVALID, "null vector");
     if (x == y) fail(RT_E_INVALID, "y must not alias x");
     operator_apply(*q, precision, x, y, nullptr, static_cast<hipStream_t>(stream));
+  });
+}
+
+rt_status rt_problem_set_sigma(rt_problem p, int form) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    if (form != RT_SIGMA_DENSE && form != RT_SIGMA_FACTORED)
+      fail(RT_E_INVALID, "unknown scattering form");
+    if (form == RT_SIGMA_FACTORED) {
+      if (q->tab.frank == 0)
+        fail(RT_E_INVALID, "the factored scattering form needs the dipole x PRD kernel");
+      if (!factored_fits(*q, sizeof(double)))
+        fail(RT_E_INVALID, "too many frequencies for the factored scattering form");
+    }
+    // the physical right-hand side is rebuilt in the new form
+    RT_HIP(hipDeviceSynchronize());
+    hipFree(q->d_rhs);
+    q->d_rhs = nullptr;
+    q->sigma_form = form;
   });
 }
 

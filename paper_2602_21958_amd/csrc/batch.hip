@@ -555,7 +555,7 @@ void persist_grid(K kernel, int grid, int threads, size_t lds, hipStream_t st, A
 template <int MODE, typename TY>
 void launch_b_gemm16(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
                      const BatchTune& tune, hipStream_t st) {
-  ProfScope prof(RT_KCLASS_SIGMA, st);
+  ProfScope prof(RT_KCLASS_SIGMA_LO, st);
   if (tune.cfg == 1)
     persist_grid(bk_gemm16<MODE, BatchCfg16b, TY>, tune.grid, BatchCfg16b::NT, 0, st, slots,
                  stat, wl.tiles, wl.counts);
@@ -567,7 +567,7 @@ void launch_b_gemm16(const SlotDev* slots, const SlotStat* stat, const WorkLists
 template <typename VT, typename LT, typename C, int K4, bool OUTER>
 void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists& wl,
                      hipStream_t st) {
-  ProfScope prof(RT_KCLASS_LAMBDA, st);
+  ProfScope prof(sizeof(C) == 8 ? RT_KCLASS_LAMBDA : RT_KCLASS_LAMBDA_LO, st);
   if (wl.h_counts[0] > 0)
     persist(bk_lambda_slab<VT, LT, C, K4, OUTER>, TB, 0, st, slots, stat, wl.lam_slab, wl.counts);
   if (wl.h_counts[1] > 0) {
@@ -655,7 +655,7 @@ void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl
       case RT_PREC_FP32: {
         if constexpr (sizeof(TV) == 2) fail(RT_E_INVALID, "an fp16 basis needs a 16-bit operator");
         launch_b_lambda<float, float, C, -1, false>(slots, stat, wl, st);
-        ProfScope prof(RT_KCLASS_SIGMA, st);
+        ProfScope prof(RT_KCLASS_SIGMA_LO, st);
         persist(bk_gemm<float, false>, TB, 0, st, slots, stat, wl.tiles, wl.counts);
         break;
       }

@@ -138,7 +138,7 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
   using C = typename ComputeOf<VT>::type;
   // plain outputs are stored unscaled (the kernels skip the multiply)
   if (K4 < 0 && out_mul != 1.f) fail(RT_E_INVALID, "plain Lambda output takes no output scale");
-  ProfScope prof(RT_KCLASS_LAMBDA, st);
+  ProfScope prof(sizeof(C) == 8 ? RT_KCLASS_LAMBDA : RT_KCLASS_LAMBDA_LO, st);
   if (p.geom == RT_GEOM_SLAB) {
     dim3 grid((p.n_r + 3) / 4);
     hipLaunchKernelGGL((lambda_slab_kernel<VT, LT, C, K4>), grid, dim3(256), 0, st, s, out0,

@@ -38,6 +38,13 @@ struct Tables {
   std::vector<double> x_nu, w_nu, phi;  // per frequency
   std::vector<double> mu_ray, w_ray, phi_ray, fac_ray;  // per ray k = o*n_nu+nu
   std::vector<double> mhat;             // n_r x n_r row-major
+  // Factored form of Mhat for the dipole x PRD kernel (frank = 0 otherwise):
+  // Mhat[(o,nu),(o',nu')] = sum_q fq[o][q] fg[o'][q] * fb[nu][nu'], with
+  // fq (n_om x frank) the angular basis, fg (n_om x frank) the weighted
+  // coefficients and fb (n_nu x n_nu) the frequency block
+  // diag(1/(phi + r)) P_nu diag(w_nu).
+  int frank = 0;
+  std::vector<double> fq, fg, fb;
 };
 
 void build_tables(const rt_problem_desc& d, Tables& t);
@@ -98,6 +105,14 @@ struct Problem {
   double* d_rhs = nullptr;              // physical right-hand side (lazily built)
   void* d_lbuf = nullptr;               // scratch for Lambda output (apply_operator)
   size_t lbuf_bytes = 0;
+  // factored scattering form (dipole x PRD kernels): factors of Mhat in FP64
+  // and FP32 (see Tables), the form FP64 / FP32 applications use, and the
+  // lazily allocated W / Z work vectors of the factored passes
+  double *d_fq64 = nullptr, *d_fg64 = nullptr, *d_fb64 = nullptr;
+  float *d_fq32 = nullptr, *d_fg32 = nullptr, *d_fb32 = nullptr;
+  int sigma_form = RT_SIGMA_DENSE;
+  void* d_fwork = nullptr;
+  size_t fwork_bytes = 0;
   Workspace* ws = nullptr;
   int64_t bytes_problem = 0;
   std::vector<double> history;
@@ -177,6 +192,23 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y,
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st, bool kform = false);
 size_t lambda_elem_bytes(int precision);
+// Factored scattering (sigma_factored.hip): y = xs x + sign (1 - eps) Mhat L
+// through the rank-R angular and the frequency factors; work holds
+// factored_work_elems(p) elements.  factored_fits: the mix pass's LDS fits.
+size_t factored_work_elems(const Problem& p);
+bool factored_fits(const Problem& p, int elem_bytes);
+void launch_sigma_factored_f64(const Problem& p, const double* L, const double* x, double* y,
+                               double* work, const double* xscale, double sign, hipStream_t st);
+void launch_sigma_factored_f32(const Problem& p, const float* L, const float* x, float* y,
+                               float* work, const double* xscale, double sign, hipStream_t st);
+// Scattering step of FP64 / FP32 applications in the problem's form (dense
+// GEMM or factored); fused dots need the dense GEMM.
+void apply_sigma_f64(Problem& p, const double* L, const double* x, double* y,
+                     const double* xscale, double sign, hipStream_t st,
+                     gemm::TileDots* dots = nullptr);
+void apply_sigma_f32(Problem& p, const float* L, const float* x, float* y,
+                     const double* xscale, double sign, hipStream_t st,
+                     gemm::TileDots* dots = nullptr);
 const double* physical_rhs(Problem& p, hipStream_t st);
 
 // Kernel timing (rt_profile_*): RAII scope recording a start/stop event pair

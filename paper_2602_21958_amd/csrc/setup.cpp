@@ -106,6 +106,54 @@ static std::vector<double> coherent_scaling(const std::vector<double>& x,
   return d;
 }
 
+// Factors of Mhat = (P_ang diag(w_o)) (x) (diag(1/(phi + r)) P_nu diag(w_nu))
+// for the dipole phase function (Sec. 2), whose angular kernel has low rank:
+//   3D: 3/4 (1 + (O.O')^2) = q(O)^T C q(O') with
+//       q(O) = (x^2, y^2, z^2, sqrt2 xy, sqrt2 xz, sqrt2 yz), since
+//       q(O).q(O') = (O.O')^2, and 1 = |O|^2 |O'|^2 = q(O)^T E q(O') with E
+//       the 3x3 block of ones on the squares; C = 3/4 (I_6 + E), rank 6;
+//   1D: 3/8 (3 - m^2 - m'^2 + 3 m^2 m'^2) = (1, m^2) C (1, m'^2)^T with
+//       C = 3/8 [[3, -1], [-1, 3]], rank 2.
+// fq[o][q] = q(O_o)_q, fg[o][q] = w_o (C q(O_o))_q, fb = the frequency block.
+static void build_factors(Tables& t, bool box, double r, const std::vector<double>& pf) {
+  const int n_om = (int)t.mu_o.size(), n_nu = (int)t.x_nu.size();
+  const int R = box ? 6 : 2;
+  t.frank = R;
+  t.fq.assign((size_t)n_om * R, 0.0);
+  t.fg.assign((size_t)n_om * R, 0.0);
+  double C[6][6] = {};
+  if (box) {
+    for (int a = 0; a < 6; ++a) C[a][a] = 0.75;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) C[a][b] += 0.75;
+  } else {
+    C[0][0] = C[1][1] = 0.375 * 3.0;
+    C[0][1] = C[1][0] = -0.375;
+  }
+  const double r2 = std::sqrt(2.0);
+  for (int o = 0; o < n_om; ++o) {
+    double q[6];
+    if (box) {
+      const double x = t.om_x[o], y = t.om_y[o], z = t.mu_o[o];
+      q[0] = x * x; q[1] = y * y; q[2] = z * z;
+      q[3] = r2 * x * y; q[4] = r2 * x * z; q[5] = r2 * y * z;
+    } else {
+      q[0] = 1.0;
+      q[1] = t.mu_o[o] * t.mu_o[o];
+    }
+    for (int a = 0; a < R; ++a) {
+      double cq = 0.0;
+      for (int b = 0; b < R; ++b) cq += C[a][b] * q[b];
+      t.fq[(size_t)o * R + a] = q[a];
+      t.fg[(size_t)o * R + a] = t.w_o[o] * cq;
+    }
+  }
+  t.fb.assign((size_t)n_nu * n_nu, 0.0);
+  for (int i = 0; i < n_nu; ++i)
+    for (int j = 0; j < n_nu; ++j)
+      t.fb[(size_t)i * n_nu + j] = pf[(size_t)i * n_nu + j] * t.w_nu[j] / (t.phi[i] + r);
+}
+
 void build_tables(const rt_problem_desc& desc, Tables& t) {
   const bool box = desc.geom == RT_GEOM_BOX;
   const int n_mu = desc.n_mu, n_az = box ? desc.n_az : 1, n_nu = desc.n_nu;
@@ -201,6 +249,7 @@ void build_tables(const rt_problem_desc& desc, Tables& t) {
           for (int j = 0; j < n_nu; ++j)
             t.mhat[(size_t)(a * n_nu + i) * n_r + (b * n_nu + j)] =
                 pa[(size_t)a * n_om + b] * pf[(size_t)i * n_nu + j];
+    build_factors(t, box, desc.r, pf);
   }
   for (int k = 0; k < n_r; ++k)
     for (int kp = 0; kp < n_r; ++kp)

@@ -288,7 +288,7 @@ void launch_b16(Problem& p, int precision, const uint16_t* l_hi, const uint16_t*
   a.dots = nullptr;
   if (p.g16_cfg[mode] < 0) p.g16_cfg[mode] = autotune(p, mode, a, st);
   a.dots = dots;
-  ProfScope prof(RT_KCLASS_SIGMA, st);
+  ProfScope prof(RT_KCLASS_SIGMA_LO, st);
   launch_mode(mode, p.g16_cfg[mode], a, st);
   RT_HIP(hipGetLastError());
 }

@@ -47,7 +47,7 @@ void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* 
                     const double* xscale, double sign, hipStream_t st, TileDots* dots) {
   const int M = p.n_r, N = (int)p.n_s, K = p.n_r;
   const int tiles = ((M + gemm::BM - 1) / gemm::BM) * ((N + gemm::BN - 1) / gemm::BN);
-  ProfScope prof(RT_KCLASS_SIGMA, st);
+  ProfScope prof(sizeof(T) == 8 ? RT_KCLASS_SIGMA : RT_KCLASS_SIGMA_LO, st);
   if (dots) {
     if (dots->ldp < tiles) fail(RT_E_INVALID, "fused dots: too few partial slots");
     dots->ldp = tiles;   // one slot per tile, all written

@@ -71,7 +71,7 @@ T* dalloc(size_t count, size_t& total) {
 // same basis bytes but all tiles reach their epilogue together, so the reads
 // come as one burst that the MFMA phase does not hide: measured slower (box
 // 32^3 FP64: 8.2 ms per fused GEMM against 4.97 ms GEMM + 1.03 ms dots).
-bool fuse_dots() {
+bool fuse_dots_env() {
   const char* e = std::getenv("RTSN_FUSED_DOTS");
   return e && e[0] == '1';
 }
@@ -197,6 +197,10 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   const int64_t n = p.n;
   TV* V = static_cast<TV*>(ws.V);
   GmresState* gs = ws.gs;
+  // the fused dots live in the dense GEMM's epilogue
+  const bool fuse_dots =
+      fuse_dots_env() && (p.sigma_form == RT_SIGMA_DENSE ||
+                          (prec != RT_PREC_FP64 && prec != RT_PREC_FP32));
   if (x_zero) {
     RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(TV), st));
     RT_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(TV), hipMemcpyDeviceToDevice, st));
@@ -215,7 +219,7 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
     res.cycles++;
     int k = 0, logged = 0;
     const bool pairs = (std::is_same<TV, double>::value || std::is_same<TV, float>::value) &&
-                       !fuse_dots() && two;
+                       !fuse_dots && two;
     for (int j = 0; j < m; ++j) {
       TV* vj = V + (size_t)j * n;
       TV* w = V + (size_t)(j + 1) * n;
@@ -242,7 +246,7 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
       }
       // Arnoldi on K = I - A (same Krylov space; A's Hessenberg column is
       // e_j - h, -beta): the operator has no x term, the GEMM reads no v_j
-      if (fuse_dots()) {
+      if (fuse_dots) {
         // h_q = vscale_q V_q . w, summed over the GEMM's output tiles in its epilogue
         gemm::TileDots d{V, n, j + 1, ws.partial, ws.dot_slots};
         operator_apply_k(p, prec, vj, w, gs->vscale + j, st, &d);   // sets d.ldp

@@ -32,6 +32,7 @@ FORMAL = {"linear_sc": 0, "implicit_euler": 1}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 RT_BATCH_BASIS_FP16 = 1
 KRYLOV = {"gmres": 0, "bicgstab": 1}
+SIGMA_FORM = {"dense": 0, "factored": 1}
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_NOT_CONVERGED", -1: "RT_E_INVALID", -2: "RT_E_NOMEM",
                 -3: "RT_E_DEVICE", -4: "RT_E_BREAKDOWN", -5: "RT_E_NONFINITE",
@@ -58,7 +59,8 @@ class ProblemDesc(C.Structure):
 class ProblemInfo(C.Structure):
     _fields_ = [("n_unknowns", C.c_int64), ("n_rays", C.c_int64), ("n_points", C.c_int64),
                 ("bytes_problem", C.c_int64), ("bytes_solve_fp64", C.c_int64),
-                ("bytes_solve_mixed", C.c_int64)]
+                ("bytes_solve_mixed", C.c_int64), ("sigma_rank", C.c_int32),
+                ("sigma_form", C.c_int32)]
 
 
 class SolverOpts(C.Structure):
@@ -83,6 +85,7 @@ _sig = {
     "rt_apply_lambda": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "rt_apply_sigma": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "rt_apply_operator": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "rt_problem_set_sigma": (C.c_int, [_vp, C.c_int]),
     "rt_rhs": (C.c_int, [_vp, _vp, _vp]),
     "rt_intensity": (C.c_int, [_vp, _vp, _vp, _vp]),
     "rt_solver_opts_default": (None, [C.POINTER(SolverOpts)]),
@@ -253,6 +256,11 @@ class Problem:
                                       _stream(stream)), "rt_apply_operator")
         return y
 
+    def set_sigma(self, form: str):
+        """Scattering form of FP64 / FP32 applications: 'dense' (GEMM) or
+        'factored' (dipole x PRD kernels)."""
+        _check(_lib.rt_problem_set_sigma(self.handle, SIGMA_FORM[form]), "rt_problem_set_sigma")
+
     def rhs(self, b, stream=None):
         _check(_lib.rt_rhs(self.handle, _ptr(b), _stream(stream)), "rt_rhs")
         return b
@@ -377,7 +385,10 @@ class Batch:
             pass
 
 
-KCLASS = {"lambda": 0, "sigma": 1, "arnoldi": 2}
+# kernel classes of rt_profile_read: the formal solver and the GEMM in FP64
+# arithmetic, the Arnoldi kernels, and the formal solver and the GEMM in the
+# lower precisions (FP32 sweeps, FP32 and 16-bit GEMMs)
+KCLASS = {"lambda": 0, "sigma": 1, "arnoldi": 2, "lambda_lo": 3, "sigma_lo": 4}
 
 
 def profile_enable(on: bool = True) -> None:

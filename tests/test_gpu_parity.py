@@ -117,9 +117,13 @@ def test_lambda_fp32(name):
     ref = op.lam(s.astype(np.float32).astype(np.float64).reshape(op.n_r, op.n_s),
                  with_bc=False).ravel()
     # per entry: the source is positive, so every term of the recurrence is
-    # positive and each intensity carries a few FP32 roundings of its own size
-    assert np.all(ref > 0)
-    rel = np.abs(got - ref) / ref
+    # positive and each intensity carries a few FP32 roundings of its own size;
+    # the first node of every ray (zero incoming radiation) is exactly zero
+    edge = ref == 0
+    assert np.all(ref[~edge] > 0)
+    assert edge.sum() == op.n_r * (op.n_s // spec.nz)
+    assert np.all(got[edge] == 0)
+    rel = np.abs(got[~edge] - ref[~edge]) / ref[~edge]
     say(f"   worst per-entry relative error {rel.max():.2e}")
     assert rel.max() < 2e-5
 
@@ -247,7 +251,14 @@ def test_gmres_two_step_matches_oracle(name, restart):
     differences near the tolerance), the oracle-evaluated residual meets
     1e-8, the residual estimates follow the oracle's to 1e-8 relative over 20
     steps, and each solution is the oracle's iterate at its own step count
-    to 1e-9."""
+    to 1e-9 on slab64 and box8.  Two iterates whose relative residuals are
+    both at most 1e-8 differ by at most 2e-8 kappa(A) relative to x; the
+    24x20x5 box (GMRES(30) needs 94 steps, GMRES(7) 203) is the worst
+    conditioned case here, and there the library's iterates (classical
+    Gram-Schmidt, in pairs or one step at a time) differ from the oracle's
+    (modified Gram-Schmidt) by 1.5e-8 .. 6.8e-8, held to 2e-7.  Solved to
+    rtol 1e-13 both forms agree with the oracle to 1e-10 on the same box
+    (test_gmres_tight_solution_matches_oracle)."""
     rt = _rt()
     spec = ALL[name]()
     say(f"gmres two-step {name} m={restart}")
@@ -273,7 +284,7 @@ def test_gmres_two_step_matches_oracle(name, restart):
                                                                          st["iters"])
         diff = np.linalg.norm(s - xr) / np.linalg.norm(xr)
         say(f"   two_step={two}: diff to the oracle iterate at step {st['iters']}: {diff:.2e}")
-        assert diff < 1e-9
+        assert diff < (2e-7 if name == "box_24x20x5" else 1e-9)
 
 
 @pytest.mark.parametrize("two_step", [1, 0])
@@ -488,15 +499,21 @@ def test_profile_counts_launches():
     with rt.Problem(spec) as p:
         x = dev(W.random_field(p.n, 3))
         y = torch.empty_like(x)
+        x32 = x.float()
+        y32 = torch.empty_like(x32)
         rt.profile_enable(True)
-        for k in ("lambda", "sigma", "arnoldi"):
+        for k in rt.KCLASS:
             rt.profile_read(k)
         for _ in range(3):
             p.apply(x, y)
+        for prec in ("fp32", "fp16"):
+            p.apply(x32, y32, precision=prec)
         rt.profile_enable(False)
-        n_l, ms_l = rt.profile_read("lambda")
-        n_s, ms_s = rt.profile_read("sigma")
-    assert n_l == 3 and n_s == 3 and ms_l > 0 and ms_s > 0
+        got = {k: rt.profile_read(k) for k in rt.KCLASS}
+    # FP64 arithmetic and the lower precisions are counted apart
+    assert got["lambda"][0] == 3 and got["sigma"][0] == 3
+    assert got["lambda_lo"][0] == 2 and got["sigma_lo"][0] == 2
+    assert all(ms > 0 for k, (n, ms) in got.items() if k != "arnoldi")
 
 
 # 16-bit scattering GEMM: bound from operand rounding.  With unit roundoff u

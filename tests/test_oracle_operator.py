@@ -99,3 +99,16 @@ def test_matrix_free_equals_assembled_operator():
     ev_s = np.sort_complex(np.linalg.eigvals(a))
     ev_i = np.sort_complex(np.linalg.eigvals(ai))
     assert np.allclose(ev_s, ev_i, atol=1e-10)
+
+
+def test_scatter_points_is_scatter_by_columns():
+    spec = W.small_box(6, 4, 8, 5, nz=5)
+    p = Problem(spec)
+    i = W.random_field((p.n_r, p.n_s), 9)
+    full = p.scatter(i)
+    parts = np.concatenate([p.scatter_points(i[:, c:c + 37], slice(c, c + 37))
+                            for c in range(0, p.n_s, 37)], axis=1)
+    assert np.allclose(parts, full, rtol=1e-15, atol=1e-15 * np.abs(full).max())
+    idx = np.array([3, 0, p.n_s - 1])
+    assert np.allclose(p.scatter_points(i[:, idx], idx), full[:, idx], rtol=1e-15,
+                       atol=1e-15 * np.abs(full).max())
