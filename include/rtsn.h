@@ -181,6 +181,24 @@ rt_status rt_apply_sigma(rt_problem p, int precision, const void* L,
 rt_status rt_apply_operator(rt_problem p, int precision, const void* x, void* y,
                             void* stream);
 
+/* rt_apply_operator without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arithmetic, kernels and result as
+ * rt_apply_operator; Lambda_0 x is held in a fixed 64 MiB device array of the
+ * library instead of the problem's buffer.  One such array exists per GPU
+ * for the life of the process and every call on that GPU shares it: calls
+ * that overlap on one GPU (other streams, other threads, other problems)
+ * race and must be serialised by the caller.  No entry of the array needs to
+ * be cleared between calls (Lambda writes all n entries before the GEMM
+ * reads them).  precision: RT_PREC_FP64 or RT_PREC_FP32 only, with the dense
+ * scattering form (rt_problem_set_sigma).
+ * Errors: RT_E_INVALID for other precisions or the factored form, for
+ * n_unknowns * element size above 64 MiB (8 388 608 FP64 / 16 777 216 FP32
+ * unknowns), null or aliased vectors; RT_E_DEVICE if the array's address
+ * cannot be taken.                                                          */
+rt_status rt_apply_operator_noalloc(rt_problem p, int precision, const void* x, void* y,
+                                    void* stream);
+
 /* How FP64 and FP32 applications compute the scattering step (Sec. 3.3,
  * eq. Sigma).  RT_SIGMA_DENSE (default): one dense N_r x N_r GEMM shared by
  * all points on the matrix cores, valid for any kernel Psi.

@@ -607,6 +607,17 @@ rt_status rt_apply_operator(rt_problem p, int precision, const void* x, void* y,
   });
 }
 
+rt_status rt_apply_operator_noalloc(rt_problem p, int precision, const void* x, void* y,
+                                    void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    check_prec(precision);
+    if (!x || !y) fail(RT_E_INVALID, "null vector");
+    if (x == y) fail(RT_E_INVALID, "y must not alias x");
+    operator_apply_noalloc(*q, precision, x, y, static_cast<hipStream_t>(stream));
+  });
+}
+
 rt_status rt_problem_set_sigma(rt_problem p, int form) {
   return guarded([&] {
     Problem* q = as_problem(p);

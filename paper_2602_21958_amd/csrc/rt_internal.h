@@ -191,6 +191,10 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y,
 // kform y = ymul K (xs x) (no x term).
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st, bool kform = false);
+// rt_apply_operator's arithmetic (FP64 / FP32, dense scattering form) with
+// the formal solution held in a fixed device array instead of the problem's
+// buffer; no device memory is allocated.
+void operator_apply_noalloc(Problem& p, int precision, const void* x, void* y, hipStream_t st);
 size_t lambda_elem_bytes(int precision);
 // Factored scattering (sigma_factored.hip): y = xs x + sign (1 - eps) Mhat L
 // through the rank-R angular and the frequency factors; work holds

@@ -85,6 +85,7 @@ _sig = {
     "rt_apply_lambda": (C.c_int, [_vp, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "rt_apply_sigma": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "rt_apply_operator": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "rt_apply_operator_noalloc": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "rt_problem_set_sigma": (C.c_int, [_vp, C.c_int]),
     "rt_rhs": (C.c_int, [_vp, _vp, _vp]),
     "rt_intensity": (C.c_int, [_vp, _vp, _vp, _vp]),
@@ -254,6 +255,14 @@ class Problem:
     def apply(self, x, y, precision: str = "fp64", stream=None):
         _check(_lib.rt_apply_operator(self.handle, PREC[precision], _ptr(x), _ptr(y),
                                       _stream(stream)), "rt_apply_operator")
+        return y
+
+    def apply_noalloc(self, x, y, precision: str = "fp64", stream=None):
+        """y = A x through rt_apply_operator_noalloc (FP64 / FP32, dense
+        scattering form; no device allocation: the library's fixed per-GPU
+        array holds Lambda x)."""
+        _check(_lib.rt_apply_operator_noalloc(self.handle, PREC[precision], _ptr(x), _ptr(y),
+                                              _stream(stream)), "rt_apply_operator_noalloc")
         return y
 
     def set_sigma(self, form: str):
