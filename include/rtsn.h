@@ -66,7 +66,7 @@ typedef struct rt_batch_s* rt_batch;
 
 enum { RT_GEOM_SLAB = 0, RT_GEOM_BOX = 1 };
 enum { RT_KERNEL_DIPOLE_PRD = 0, RT_KERNEL_EXPLICIT = 1 };
-enum { RT_FORMAL_LINEAR_SC = 0, RT_FORMAL_IMPLICIT_EULER = 1 };
+enum { RT_FORMAL_LINEAR_SC = 0, RT_FORMAL_IMPLICIT_EULER = 1, RT_FORMAL_QUADRATIC_SC = 2 };
 
 /* Arithmetic of one operator application.
  *   FP64  : vectors double; Lambda and Sigma in FP64 (Sigma on FP64 MFMA).
@@ -116,8 +116,15 @@ typedef struct {
                              in ray order (Sec. 3.3, the block Psi_[i])            */
   double coh_frac;        /* DIPOLE_PRD: weight c of the coherent part            */
   double coh_width2;      /* DIPOLE_PRD: w2 in exp(-(x - x')^2 / w2)               */
-  int formal;             /* RT_FORMAL_LINEAR_SC (box and slab) or
-                             RT_FORMAL_IMPLICIT_EULER (slab only, eqs. ie_1/ie_2)  */
+  int formal;             /* RT_FORMAL_LINEAR_SC (box and slab),
+                             RT_FORMAL_IMPLICIT_EULER (slab only, eqs. ie_1/ie_2)
+                             or RT_FORMAL_QUADRATIC_SC: the integral form of the
+                             transfer equation (Sec. 2, eq. rt_integral) with the
+                             source taken as the parabola through the upwind,
+                             local and downwind values (Sec. 5.3: the production
+                             code's quadratic integrator); the last node of a
+                             ray, which has no downwind node, takes the linear
+                             step                                                 */
 } rt_problem_desc;
 
 typedef struct {
@@ -219,11 +226,20 @@ rt_status rt_apply_operator_noalloc(rt_problem p, int precision, const void* x, 
 enum { RT_SIGMA_DENSE = 0, RT_SIGMA_FACTORED = 1 };
 rt_status rt_problem_set_sigma(rt_problem p, int form);
 
-/* Right-hand side b = (1 - eps) Mhat I_bc + t (FP64, device, ray-major).     */
+/* Right-hand side of the source-function system, b = (1 - eps) Mhat I_bc + t:
+ * the scattering (Sec. 3.3, eq. Sigma) of the boundary radiation propagated
+ * through the medium (the I_in vector of Sec. 3.1, eq. RT_sys_algebraic)
+ * plus the thermal part of the source (Sec. 2, eq. S).  b: device, FP64,
+ * ray-major, n_unknowns entries, caller-owned.  Built on the first call (or
+ * solve) and kept with the problem; asynchronous on the stream.
+ * Errors: RT_E_INVALID (null), RT_E_NOMEM.                                   */
 rt_status rt_rhs(rt_problem p, double* b, void* stream);
 
-/* Full intensity I = Lambda_0 s + I_bc for a source function s (FP64 device
- * arrays), e.g. the emergent spectrum of a solution.                         */
+/* Full intensity I = Lambda_0 s + I_bc of a source function s: the formal
+ * solution with the boundary radiation (Sec. 3.2, eq. lambda_block, plus the
+ * I_in vector of Sec. 3.1), e.g. the emergent spectrum of a solution.
+ * s, I: device, FP64, ray-major, n_unknowns entries; I must not alias s.
+ * Errors: RT_E_INVALID.                                                     */
 rt_status rt_intensity(rt_problem p, const double* s, double* I, void* stream);
 
 enum { RT_KRYLOV_GMRES = 0, RT_KRYLOV_BICGSTAB = 1 };

@@ -105,10 +105,10 @@ class Problem:
         ib = sp.i_bot if with_bc else 0.0
         if self.geom == "slab":
             return sweep_slab(sp.depth, self.mu_ray, self.fac_ray, s, it, ib, sp.formal)
-        if sp.formal != "linear_sc":
-            raise ValueError("box supports linear_sc only")
+        if sp.formal not in ("linear_sc", "quadratic_sc"):
+            raise ValueError("box supports linear_sc and quadratic_sc")
         out = sweep_box(sp.k_line, self.omega, self.phi + sp.r,
-                        s.reshape(self.n_r, sp.nz, sp.ny, sp.nx), it, ib)
+                        s.reshape(self.n_r, sp.nz, sp.ny, sp.nx), it, ib, sp.formal)
         return out.reshape(self.n_r, self.n_s)
 
     # ----------------------------------------------------------------- Sigma

@@ -195,13 +195,17 @@ def _interp(plane, i0, tx, j0, ty):
             + ty * (1 - tx) * shifted(j0 + 1, i0) + ty * tx * shifted(j0 + 1, i0 + 1))
 
 
-def sweep_box(k_line, omega, fac_nu, s, i_top=0.0, i_bot=0.0):
-    """Plane-to-plane linear short-characteristics sweep in the periodic box.
+def sweep_box(k_line, omega, fac_nu, s, i_top=0.0, i_bot=0.0, scheme: str = "linear_sc"):
+    """Plane-to-plane short-characteristics sweep in the periodic box.
 
     k_line (nz, ny, nx), z index 0 = bottom; omega (n_omega, 3); fac_nu (n_nu,)
     = phi_nu + r; s (n_omega*n_nu, nz, ny, nx) with ray k = o*n_nu + nu.
     Incoming intensities: i_bot enters at the bottom plane (mu > 0), i_top at
     the top plane (mu < 0).
+    scheme 'linear_sc', or 'quadratic_sc': the source is also taken at the
+    downwind point, on the next plane downstream displaced by +Omega_xy dz/|mu|
+    (bilinear, periodic, like the upwind point), over the downwind interval
+    D_d = (k_0 + k_d)/2 (phi + r) dz/|mu|; the last plane takes the linear step.
     """
     k_line = np.asarray(k_line, float)
     nz, ny, nx = k_line.shape
@@ -212,6 +216,8 @@ def sweep_box(k_line, omega, fac_nu, s, i_top=0.0, i_bot=0.0):
     fac = np.asarray(fac_nu, float)[:, None, None]
     for o in range(n_om):
         i0, tx, j0, ty, path = _upwind_stencil(omega[o], nx, ny, nz)
+        # the downwind point: the same displacement in the opposite direction
+        d0, dtx, e0, dty, _ = _upwind_stencil(-omega[o], nx, ny, nz)
         if omega[o, 2] > 0:
             first, planes, step = 0, range(1, nz), -1
             out[o, :, first] = i_bot
@@ -220,10 +226,20 @@ def sweep_box(k_line, omega, fac_nu, s, i_top=0.0, i_bot=0.0):
             out[o, :, first] = i_top
         for z in planes:
             zu = z + step
+            zd = z - step
             k_up = _interp(k_line[zu], i0, tx, j0, ty)
             d = 0.5 * (k_up + k_line[z])[None] * path * fac
-            e, a, c = exp_weights(d)
             i_up = _interp(out[o, :, zu], i0, tx, j0, ty)
             s_up = _interp(s[o, :, zu], i0, tx, j0, ty)
-            out[o, :, z] = e * i_up + a * s_up + c * s[o, :, z]
+            if scheme == "quadratic_sc" and 0 <= zd < nz:
+                k_dn = _interp(k_line[zd], d0, dtx, e0, dty)
+                dd = 0.5 * (k_dn + k_line[z])[None] * path * fac
+                s_dn = _interp(s[o, :, zd], d0, dtx, e0, dty)
+                e, pu, p0, pd = quad_weights(d, dd)
+                out[o, :, z] = e * i_up + pu * s_up + p0 * s[o, :, z] + pd * s_dn
+            elif scheme in ("linear_sc", "quadratic_sc"):
+                e, a, c = exp_weights(d)
+                out[o, :, z] = e * i_up + a * s_up + c * s[o, :, z]
+            else:
+                raise ValueError(scheme)
     return out.reshape(n_om * n_nu, nz, ny, nx)

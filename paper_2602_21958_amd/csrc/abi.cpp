@@ -187,9 +187,11 @@ void validate(const rt_problem_desc& d) {
     for (size_t i = 0; i < ns; ++i)
       if (!(d.k_line[i] > 0)) fail(RT_E_INVALID, "k_line must be > 0");
     if ((int64_t)d.nx * d.ny > 4096) fail(RT_E_INVALID, "box plane larger than 4096 points");
-    if (d.formal != RT_FORMAL_LINEAR_SC) fail(RT_E_INVALID, "box supports linear SC only");
+    if (d.formal == RT_FORMAL_IMPLICIT_EULER)
+      fail(RT_E_INVALID, "implicit Euler is a slab scheme");
   }
-  if (d.formal != RT_FORMAL_LINEAR_SC && d.formal != RT_FORMAL_IMPLICIT_EULER)
+  if (d.formal != RT_FORMAL_LINEAR_SC && d.formal != RT_FORMAL_IMPLICIT_EULER &&
+      d.formal != RT_FORMAL_QUADRATIC_SC)
     fail(RT_E_INVALID, "unknown formal solver");
   if (d.kernel == RT_KERNEL_EXPLICIT) {
     if (!d.kernel_matrix) fail(RT_E_INVALID, "explicit kernel needs kernel_matrix");
@@ -344,6 +346,13 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
       s.ty = sy - fy;
       s.path = path;
       s.up = mu > 0 ? 1 : 0;
+      const double dx = p.tab.om_x[o] * path * p.nx;
+      const double dy = p.tab.om_y[o] * path * p.ny;
+      const double gx = std::floor(dx), gy = std::floor(dy);
+      s.di0 = (int)(((long long)gx % p.nx + p.nx) % p.nx);
+      s.dj0 = (int)(((long long)gy % p.ny + p.ny) % p.ny);
+      s.dtx = dx - gx;
+      s.dty = dy - gy;
       p.stencil[o] = s;
     }
     p.d_stencil = upload(p.stencil.data(), p.stencil.size(), tot);

@@ -80,7 +80,8 @@ __device__ __forceinline__ int k4_xcd_order(int b, int n) {
 }
 
 // One workgroup per (ordinate, chunk of F frequencies).
-template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT, bool PP>
+template <typename VT, typename LT, typename C, int K4, int F, int NPT, int NT, bool PP,
+          bool QUAD>
 __global__ __launch_bounds__(NT) void lambda_box_kernel(
     const VT* __restrict__ s, void* out0, void* out1, int64_t Np,
     const double* __restrict__ kline, const BoxStencil* __restrict__ stencil,
@@ -101,9 +102,9 @@ __global__ __launch_bounds__(NT) void lambda_box_kernel(
 #pragma unroll
   for (int f = 0; f < F; ++f) fac[f] = f < nf ? C(ray_fac[k0 + f]) : C(0);
   const auto outs = rays_out<LT, K4>(out0, out1, k0, vol, Np);
-  lam::box_rays<VT, decltype(outs), C, F, NPT, NT, PP>(s + (size_t)k0 * vol, vol, nf, outs, kline,
-                                                   st, fac, nx, ny, nz, i_in, sc, out_mul,
-                                                   reinterpret_cast<C*>(smem_raw));
+  lam::box_rays<VT, decltype(outs), C, F, NPT, NT, PP, QUAD>(
+      s + (size_t)k0 * vol, vol, nf, outs, kline, st, fac, nx, ny, nz, i_in, sc, out_mul,
+      reinterpret_cast<C*>(smem_raw));
 }
 
 template <typename VT> struct ComputeOf;
@@ -156,13 +157,17 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     const int grid = p.n_omega * ((p.n_nu + F - 1) / F);
     // one ray per group (group index = ray index) into the k4 operand
     const int xcd = (K4 >= 0 && F == 1) ? 1 : 0;
-#define RT_BOX_LAUNCH1(FF, NPT, NT, PPV)                                                          \
-  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT, PPV>), dim3(grid), dim3(NT), \
-                     lds, st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, p.n_nu,    \
-                     p.nx, p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale, out_mul, xcd)
+#define RT_BOX_LAUNCH2(FF, NPT, NT, PPV, QV)                                                    \
+  hipLaunchKernelGGL((lambda_box_kernel<VT, LT, C, K4, FF, NPT, NT, PPV, QV>), dim3(grid),      \
+                     dim3(NT), lds, st, s, out0, out1, Np, p.d_kline, p.d_stencil, p.d_ray_fac, \
+                     p.n_nu, p.nx, p.ny, p.nz, p.i_top, p.i_bot, with_bc ? 1 : 0, scale,        \
+                     out_mul, xcd)
+#define RT_BOX_LAUNCH1(FF, NPT, NT, PPV)                                \
+  if (p.formal == RT_FORMAL_QUADRATIC_SC) RT_BOX_LAUNCH2(FF, NPT, NT, PPV, true); \
+  else RT_BOX_LAUNCH2(FF, NPT, NT, PPV, false)
 #define RT_BOX_LAUNCH(FF, NPT, NT)       \
-  if (pp) RT_BOX_LAUNCH1(FF, NPT, NT, true); \
-  else RT_BOX_LAUNCH1(FF, NPT, NT, false)
+  if (pp) { RT_BOX_LAUNCH1(FF, NPT, NT, true); } \
+  else { RT_BOX_LAUNCH1(FF, NPT, NT, false); }
     // planes up to 256 points: 256 threads; up to 1024 points: 512 threads of
     // 2 points each (FP64 with two LDS sets: 72 VGPRs, three groups per CU;
     // 256 threads of 4 points or 1024 threads of 1 point measured slower on
@@ -177,6 +182,7 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     }
 #undef RT_BOX_LAUNCH
 #undef RT_BOX_LAUNCH1
+#undef RT_BOX_LAUNCH2
   }
   RT_HIP(hipGetLastError());
 }

@@ -96,6 +96,62 @@ __device__ __forceinline__ void sc_weights(C d, C& e, C& a, C& c) {
   }
 }
 
+// Quadratic short characteristics: with the source the parabola through the
+// upwind (s_u), local (s_0) and downwind (s_d) values, the integral form of
+// the transfer equation over the upwind interval of optical length du gives
+// I_0 = e^{-du} I_u + pu s_u + p0 s_0 + pd s_d, where integrating each Lagrange
+// basis polynomial (abscissa t = optical depth back from the local point:
+// du upwind, -dd downwind) against e^{-t} over [0, du] gives
+//   pu = (w2 + dd w1) / (du (du + dd)),
+//   p0 = (w2 - (du - dd) w1 - du dd w0) / (-du dd),
+//   pd = (w2 - du w1) / (dd (du + dd)),
+// with the moments w_k = int_0^du t^k e^{-t} dt.  Above du = 1/2 the moments
+// follow from e^{-du} by integration by parts (w0 = 1 - e, w1 = w0 - du e,
+// w2 = 2 w1 - du^2 e); below, from their Taylor series
+// w_k = du^{k+1} sum_m (-du)^m / (m! (k + m + 1)), whose first omitted term
+// (m = 16 in FP64, 9 in FP32) is below the unit roundoff of the sum.
+constexpr double mom_coef(int k, int m) {
+  double f = 1.0;
+  for (int j = 2; j <= m; ++j) f *= j;
+  return 1.0 / (f * (k + m + 1));
+}
+#define RT_MC(k) {mom_coef(k, 0), mom_coef(k, 1), mom_coef(k, 2), mom_coef(k, 3), \
+  mom_coef(k, 4), mom_coef(k, 5), mom_coef(k, 6), mom_coef(k, 7), mom_coef(k, 8), \
+  mom_coef(k, 9), mom_coef(k, 10), mom_coef(k, 11), mom_coef(k, 12), mom_coef(k, 13), \
+  mom_coef(k, 14), mom_coef(k, 15)}
+static __device__ __constant__ double kMomCoef[3][16] = {RT_MC(0), RT_MC(1), RT_MC(2)};
+#undef RT_MC
+
+template <typename C>
+__device__ __forceinline__ void qsc_weights(C du, C dd, C& e, C& pu, C& p0, C& pd) {
+  C w0, w1, w2;
+  if (du < C(0.5)) {
+    constexpr int T = sizeof(C) == 8 ? 16 : 9;
+    C s0 = C(kMomCoef[0][T - 1]), s1 = C(kMomCoef[1][T - 1]), s2 = C(kMomCoef[2][T - 1]);
+#pragma unroll
+    for (int m = T - 2; m >= 0; --m) {
+      s0 = s0 * (-du) + C(kMomCoef[0][m]);
+      s1 = s1 * (-du) + C(kMomCoef[1][m]);
+      s2 = s2 * (-du) + C(kMomCoef[2][m]);
+    }
+    const C d2 = du * du;
+    w0 = du * s0;
+    w1 = d2 * s1;
+    w2 = d2 * du * s2;
+    e = C(1) - w0;
+  } else {
+    if constexpr (sizeof(C) == 8) e = exp_neg_f64(du);
+    else e = __expf(-du);
+    w0 = C(1) - e;
+    w1 = w0 - du * e;
+    w2 = C(2) * w1 - du * du * e;
+  }
+  const C sum = du + dd;
+  pu = (w2 + dd * w1) / (du * sum);
+  p0 = (w2 - (du - dd) * w1 - du * dd * w0) / (-du * dd);
+  pd = (w2 - du * w1) / (dd * sum);
+}
+
 template <typename T> __device__ __forceinline__ T to_out(double v);
 template <> __device__ __forceinline__ double to_out<double>(double v) { return v; }
 template <> __device__ __forceinline__ float to_out<float>(double v) { return (float)v; }
@@ -218,6 +274,13 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
       const C inv = C(1) / (C(1) + d);
       e = inv;
       b = d * s0 * inv;
+    } else if (scheme == RT_FORMAL_QUADRATIC_SC && q + 1 < nz) {
+      const int md = down ? q + 1 : m - 1;      // memory index of the downwind node
+      const int ivd = down ? q : m - 1;         // downwind interval index
+      const C dd = C(dt[ivd] * g);
+      C pu, p0, pd;
+      qsc_weights<C>(d, dd, e, pu, p0, pd);
+      b = pu * (sc * C(sk[mp])) + p0 * s0 + pd * (sc * C(sk[md]));
     } else {
       C a, c;
       sc_weights<C>(d, e, a, c);
@@ -276,8 +339,15 @@ constexpr int kBoxThreads = 256;
 // LDS elements of type C that box_rays needs.
 constexpr size_t box_lds_elems(int F, int P, bool pp) { return (size_t)(pp ? 2 : 1) * (2 * F + 1) * P; }
 
+//
+// QUAD: quadratic short characteristics (qsc_weights): every plane but the
+// last also takes the source at the downwind point, on the next plane
+// downstream at the opposite displacement (st.di0, st.dj0, st.dtx, st.dty),
+// and the opacity there for the downwind interval; both are bilinear
+// interpolations read from global memory (the plane was just read into the
+// L2 as the next plane's local values).
 template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads,
-          bool PP = false>
+          bool PP = false, bool QUAD = false>
 __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_stride, int nf,
                                          const OUT& out, const double* __restrict__ kline,
                                          const BoxStencil st, const C* fac, int nx, int ny,
@@ -311,6 +381,32 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
   const C w00 = (C(1) - ty) * (C(1) - tx), w01 = (C(1) - ty) * tx;
   const C w10 = ty * (C(1) - tx), w11 = ty * tx;
   const C om = C(out_mul);
+  // downwind stencil (QUAD)
+  int d00[QUAD ? kBoxMaxPts : 1], d01[QUAD ? kBoxMaxPts : 1];
+  int d10[QUAD ? kBoxMaxPts : 1], d11[QUAD ? kBoxMaxPts : 1];
+  C v00 = C(0), v01 = C(0), v10 = C(0), v11 = C(0);
+  if constexpr (QUAD) {
+    const C dtx = C(st.dtx), dty = C(st.dty);
+    v00 = (C(1) - dty) * (C(1) - dtx);
+    v01 = (C(1) - dty) * dtx;
+    v10 = dty * (C(1) - dtx);
+    v11 = dty * dtx;
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      if (j >= npt) break;
+      const int p = threadIdx.x + j * NT;
+      const int x = p % nx, y = p / nx;
+      int xa = x + st.di0; if (xa >= nx) xa -= nx;
+      int xb = xa + 1;     if (xb >= nx) xb -= nx;
+      int ya = y + st.dj0; if (ya >= ny) ya -= ny;
+      int yb = ya + 1;     if (yb >= ny) yb -= ny;
+      const bool in = p < P;
+      d00[j] = in ? ya * nx + xa : 0;
+      d01[j] = in ? ya * nx + xb : 0;
+      d10[j] = in ? yb * nx + xa : 0;
+      d11[j] = in ? yb * nx + xb : 0;
+    }
+  }
 
   // sources and opacity of the next plane, loaded one plane ahead
   VT Sn[F][kBoxMaxPts];
@@ -362,15 +458,36 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
       } else {
         const C ku = w00 * rK[n00[j]] + w01 * rK[n01[j]] + w10 * rK[n10[j]] + w11 * rK[n11[j]];
         const C base = (ku + Kv[j]) * hpath;
+        if (QUAD && t + 1 < nz) {
+          const int zd = st.up ? z + 1 : z - 1;
+          const double* kd = kline + (size_t)zd * plane_stride;
+          const C kdn = v00 * C(kd[d00[j]]) + v01 * C(kd[d01[j]]) + v10 * C(kd[d10[j]]) +
+                        v11 * C(kd[d11[j]]);
+          const C based = (kdn + Kv[j]) * hpath;
 #pragma unroll
-        for (int f = 0; f < F; ++f) {
-          const C* If = rI + f * P;
-          const C* Sf = rS + f * P;
-          const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
-          const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
-          C e, a, c;
-          sc_weights<C, true>(base * fac[f], e, a, c);   // branch form
-          I[f] = e * Iu + a * Su + c * Sv[f][j];
+          for (int f = 0; f < F; ++f) {
+            const C* If = rI + f * P;
+            const C* Sf = rS + f * P;
+            const VT* sd = s0 + (size_t)f * ray_stride + (size_t)zd * plane_stride;
+            const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
+            const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
+            const C Sd = sc * (v00 * C(sd[d00[j]]) + v01 * C(sd[d01[j]]) + v10 * C(sd[d10[j]]) +
+                               v11 * C(sd[d11[j]]));
+            C e, pu, p0, pd;
+            qsc_weights<C>(base * fac[f], based * fac[f], e, pu, p0, pd);
+            I[f] = e * Iu + pu * Su + p0 * Sv[f][j] + pd * Sd;
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            const C* If = rI + f * P;
+            const C* Sf = rS + f * P;
+            const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
+            const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
+            C e, a, c;
+            sc_weights<C, true>(base * fac[f], e, a, c);   // branch form
+            I[f] = e * Iu + a * Su + c * Sv[f][j];
+          }
         }
       }
 #pragma unroll

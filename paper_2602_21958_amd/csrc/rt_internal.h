@@ -57,6 +57,10 @@ struct BoxStencil {
   int pad;
   double tx, ty;    // bilinear fractions
   double path;      // dz / |mu|
+  // downwind point (quadratic short characteristics): the opposite
+  // displacement on the next plane downstream
+  int di0, dj0;
+  double dtx, dty;
 };
 
 // --------------------------------------------------------------------------

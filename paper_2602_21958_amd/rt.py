@@ -28,7 +28,7 @@ RT_E_INVALID, RT_E_NOMEM, RT_E_DEVICE = -1, -2, -3
 RT_E_BREAKDOWN, RT_E_NONFINITE, RT_E_BUSY = -4, -5, -6
 GEOM = {"slab": 0, "box": 1}
 KERNEL = {"dipole_prd": 0, "explicit": 1}
-FORMAL = {"linear_sc": 0, "implicit_euler": 1}
+FORMAL = {"linear_sc": 0, "implicit_euler": 1, "quadratic_sc": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 RT_BATCH_BASIS_FP16 = 1
 KRYLOV = {"gmres": 0, "bicgstab": 1}

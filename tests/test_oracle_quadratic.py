@@ -139,3 +139,82 @@ def test_quadratic_step_converges_at_third_order():
     assert all(o > 2.7 for o in oq), oq
     assert all(1.7 < o < 2.3 for o in ol), ol
     assert e_q[-1] < 0.1 * e_l[-1]
+
+
+# ------------------------------------------------------------------ box
+def test_quadratic_box_with_uniform_layers_equals_slab():
+    # the box's quadratic sweep of a horizontally uniform problem is the
+    # slab's quadratic sweep on the trapezoid-cumulated depths (both ends of
+    # every ray, including the linear last step)
+    import workloads as W
+    from oracle import Problem
+    from test_oracle_transfer import _uniform_box_and_slab
+    spec, slab = _uniform_box_and_slab()
+    spec.formal = slab.formal = "quadratic_sc"
+    pb, ps = Problem(spec), Problem(slab)
+    n_nu, nz = spec.n_nu, spec.nz
+    s_slab = W.random_field((ps.n_r, nz), 3, positive=True)
+    s_box = np.zeros((spec.n_mu, spec.n_az, n_nu, nz, spec.ny, spec.nx))
+    s_box[:] = s_slab.reshape(spec.n_mu, n_nu, nz)[:, :, ::-1][:, None, :, :, None, None]
+    ib = pb.lam(s_box.reshape(pb.n_r, pb.n_s), with_bc=True)
+    i_slab = ps.lam(s_slab, with_bc=True).reshape(spec.n_mu, n_nu, nz)[:, :, ::-1]
+    ib = ib.reshape(spec.n_mu, spec.n_az, n_nu, nz, spec.ny, spec.nx)
+    assert np.allclose(ib, np.broadcast_to(i_slab[:, None, :, :, None, None], ib.shape),
+                       rtol=1e-12, atol=1e-14)
+    # and it differs from the linear sweep (the downwind values enter)
+    spec.formal = "linear_sc"
+    il = Problem(spec).lam(s_box.reshape(pb.n_r, pb.n_s), with_bc=True)
+    assert np.max(np.abs(il.reshape(ib.shape) - ib)) > 1e-4
+
+
+def test_quadratic_box_translation_and_quarter_turn():
+    import workloads as W
+    from oracle import Problem
+    n_az = 8
+    spec = W.small_box(6, 4, n_az, 3, nz=7)
+    spec.formal = "quadratic_sc"
+    p = Problem(spec)
+    shape = (spec.n_mu, n_az, spec.n_nu, spec.nz, spec.ny, spec.nx)
+    s = W.random_field(shape, 9)
+    out = p.lam(s.reshape(p.n_r, -1), with_bc=True).reshape(shape)
+    spec2 = W.small_box(6, 4, n_az, 3, nz=7)
+    spec2.formal = "quadratic_sc"
+    spec2.k_line = np.roll(spec.k_line, (3, 5), axis=(1, 2))
+    out2 = Problem(spec2).lam(np.roll(s, (3, 5), axis=(4, 5)).reshape(p.n_r, -1),
+                              with_bc=True).reshape(shape)
+    assert np.allclose(out2, np.roll(out, (3, 5), axis=(4, 5)), rtol=1e-13, atol=1e-14)
+    perm = [(n_az // 4 - 1 - b) % n_az for b in range(n_az)]
+    spec3 = W.small_box(6, 4, n_az, 3, nz=7)
+    spec3.formal = "quadratic_sc"
+    spec3.k_line = spec.k_line.transpose(0, 2, 1).copy()
+    s3 = s[:, perm].transpose(0, 1, 2, 3, 5, 4)
+    out3 = Problem(spec3).lam(s3.reshape(p.n_r, -1), with_bc=True).reshape(shape)
+    assert np.allclose(out3, out[:, perm].transpose(0, 1, 2, 3, 5, 4), rtol=1e-13, atol=1e-14)
+
+
+def test_quadratic_box_reads_the_downwind_point():
+    # A point source on plane z0 + 1 reaches plane z0 of an up-going ray only
+    # through the downwind term: the node whose downwind point is the source
+    # lies upstream, at the source displaced by -Omega_xy dz/mu (bilinear
+    # interpolation keeps that first moment); the linear sweep gives zero.
+    from oracle import directions_3d
+    from oracle.transfer import sweep_box
+    n, nz = 16, 9
+    k = np.full((nz, n, n), 3.0)
+    om, _ = directions_3d(4, 8)
+    o = [i for i in range(len(om)) if om[i, 2] > 0.5][1]
+    fac = np.array([1.0])
+    s = np.zeros((len(om), nz, n, n))
+    z0, y0, x0 = 4, 8, 8
+    s[o, z0 + 1, y0, x0] = 1.0
+    lin = sweep_box(k, om, fac, s)[o, z0]
+    assert np.all(lin == 0)
+    out = sweep_box(k, om, fac, s, scheme="quadratic_sc")[o, z0]
+    dz = 1.0 / (nz - 1)
+    shift = om[o, :2] * dz / om[o, 2] * n
+    ys, xs = np.mgrid[0:n, 0:n]
+    wsum = out.sum()
+    assert wsum < 0          # the downwind weight is negative
+    cx = (out * xs).sum() / wsum - x0
+    cy = (out * ys).sum() / wsum - y0
+    assert abs(cx + shift[0]) < 1e-12 and abs(cy + shift[1]) < 1e-12

@@ -60,7 +60,8 @@ class ProblemSpec:
     kernel_matrix  explicit N_r x N_r symmetric kernel (only for 'explicit')
     coh_frac    weight of the coherent part of the PRD kernel
     coh_width2  squared width of the coherent Gaussian exp(-(x-x')^2/w2)
-    formal      'linear_sc' (exponential integrator) or 'implicit_euler'
+    formal      'linear_sc' (exponential integrator), 'implicit_euler' or
+                'quadratic_sc' (parabolic source through upwind, local, downwind)
     """
 
     geom: str = "slab"
