@@ -27,8 +27,14 @@ index [k, i] with ray k = o * N_nu + nu (frequency fastest) and point i; in the
 box i = (z * ny + y) * nx + x with z = 0 the bottom plane, in the slab i is the
 depth index from the top.
 
+Per-point kernels: Sec. 3.3 allows a different (possibly full) block
+Psi_[i] at every point i.  With spec.point_class the points fall into classes,
+each with its own kernel (a coherent fraction of the dipole x PRD recipe, or
+an explicit matrix), and the scattering of point i uses its class's block.
+
 Pins: eps = 1 identity, thermal equilibrium s = B, sqrt(eps) surface law,
-matrix-free columns = dense assembly (tests/test_oracle_operator.py).
+matrix-free columns = dense assembly (tests/test_oracle_operator.py); classes
+in tests/test_oracle_classes.py.
 """
 from __future__ import annotations
 
@@ -78,16 +84,35 @@ class Problem:
         self.fac_ray = self.phi_ray + spec.r
         self.mu_ray = np.repeat(self.mu_o, n_nu)
 
-        if spec.kernel == "dipole_prd":
-            p_ang = dipole_1d(self.mu_o) if self.geom == "slab" else dipole_3d(self.omega)
-            p_nu = prd_frequency_kernel(x, w_x, phi, spec.coh_frac, spec.coh_width2)
-            self.psi = np.kron(p_ang, p_nu)
-        elif spec.kernel == "explicit":
-            self.psi = np.asarray(spec.kernel_matrix, float)
-            assert self.psi.shape == (self.n_r, self.n_r)
-        else:
+        def kernel_block(coh_frac=None, matrix=None):
+            if spec.kernel == "dipole_prd":
+                p_ang = dipole_1d(self.mu_o) if self.geom == "slab" else dipole_3d(self.omega)
+                p_nu = prd_frequency_kernel(x, w_x, phi, coh_frac, spec.coh_width2)
+                return np.kron(p_ang, p_nu)
+            if spec.kernel == "explicit":
+                psi = np.asarray(matrix, float)
+                assert psi.shape == (self.n_r, self.n_r)
+                return psi
             raise ValueError(spec.kernel)
-        self.mhat = (1.0 / self.fac_ray)[:, None] * self.psi * self.w_ray[None, :]
+
+        def mhat_of(psi):
+            return (1.0 / self.fac_ray)[:, None] * psi * self.w_ray[None, :]
+
+        self.psi = kernel_block(spec.coh_frac, spec.kernel_matrix)
+        self.mhat = mhat_of(self.psi)
+        # per-point classes: self.point_class (n_s) and one Mhat per class
+        self.point_class = None
+        self.mhat_classes = None
+        if getattr(spec, "point_class", None) is not None:
+            pc = np.asarray(spec.point_class, dtype=np.int64).reshape(-1)
+            assert pc.shape == (spec.n_s,)
+            if spec.kernel == "dipole_prd":
+                blocks = [kernel_block(coh_frac=c) for c in spec.class_coh_frac]
+            else:
+                blocks = [kernel_block(matrix=m) for m in spec.class_kernels]
+            assert pc.min() >= 0 and pc.max() < len(blocks)
+            self.point_class = pc
+            self.mhat_classes = [mhat_of(b) for b in blocks]
 
         eps = np.broadcast_to(np.asarray(spec.eps, float), (self.n_s,)).copy()
         bpl = np.broadcast_to(np.asarray(spec.planck, float), (self.n_s,)).copy()
@@ -113,9 +138,10 @@ class Problem:
 
     # ----------------------------------------------------------------- Sigma
     def scatter(self, intensity):
-        """(1 - eps_i) * Mhat @ I: the scattering part of the source function."""
+        """(1 - eps_i) * Mhat_[i] @ I: the scattering part of the source
+        function (Mhat_[i] the block of point i's class, or the one Mhat)."""
         i2 = np.asarray(intensity, float).reshape(self.n_r, self.n_s)
-        return self.albedo[None, :] * (self.mhat @ i2)
+        return self.scatter_points(i2, slice(None))
 
     def scatter_points(self, intensity, points):
         """scatter() for the spatial points `points` only (a slice or an
@@ -123,7 +149,14 @@ class Problem:
         scattering block acts on each point by itself (eq. Sigma is block
         diagonal over points), so a subset of columns is the same product."""
         i2 = np.asarray(intensity, float).reshape(self.n_r, -1)
-        return self.albedo[None, points] * (self.mhat @ i2)
+        if self.point_class is None:
+            return self.albedo[None, points] * (self.mhat @ i2)
+        pc = self.point_class[points]
+        out = np.empty_like(i2)
+        for c, m in enumerate(self.mhat_classes):
+            sel = pc == c
+            out[:, sel] = m @ i2[:, sel]
+        return self.albedo[None, points] * out
 
     # -------------------------------------------------------------- operator
     def apply(self, s):

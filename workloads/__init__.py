@@ -62,6 +62,10 @@ class ProblemSpec:
     coh_width2  squared width of the coherent Gaussian exp(-(x-x')^2/w2)
     formal      'linear_sc' (exponential integrator), 'implicit_euler' or
                 'quadratic_sc' (parabolic source through upwind, local, downwind)
+    point_class optional per-point scattering class (n_s ints in
+                [0, n_classes)); each class has its own kernel block
+    class_coh_frac   dipole_prd: coherent fraction of each class
+    class_kernels    explicit: (n_classes, N_r, N_r) symmetric kernel per class
     """
 
     geom: str = "slab"
@@ -84,6 +88,17 @@ class ProblemSpec:
     coh_frac: float = 0.5
     coh_width2: float = 0.5
     formal: str = "linear_sc"
+    point_class: Optional[np.ndarray] = None
+    class_coh_frac: Optional[np.ndarray] = None
+    class_kernels: Optional[np.ndarray] = None
+
+    @property
+    def n_classes(self) -> int:
+        if self.point_class is None:
+            return 1
+        if self.class_kernels is not None:
+            return len(self.class_kernels)
+        return len(self.class_coh_frac)
 
     @property
     def n_s(self) -> int:
