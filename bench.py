@@ -1,7 +1,7 @@
 """Benchmark of the S_N radiative-transfer Krylov path on one GPU.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                [--workload box32|batch512|serve|box64]
+                [--no-box64] [--workload box32|batch512|serve|box64|slab64]
 
 Default workload (box32): FP64 GMRES(30) solves of the 32^3 periodic box.
 
@@ -14,8 +14,14 @@ dominant kernel), the formal solver and the Arnoldi kernels are measured with
 HIP events on the stream they run on, over the timed region.  A mixed-
 precision leg (FP64 iterative refinement around an inner solve with FP32
 vectors and a low-precision operator) runs on the same workload after the
-timed FP64 region, and the FP64 oracle is timed on the host cores on a
-bounded sample of the workload.  Prints one JSON line.
+timed FP64 region, then the same FP64 solve with the scattering step in
+factored form (dipole rank 6 x frequency block, bound by HBM), and the FP64
+oracle is timed on the host cores on a bounded sample of the workload.  A
+second leg solves the 64^3 box (1.61e9 unknowns) in mixed precision
+(16-bit or factored FP32 scattering, FP64 refinement): one timed solve per
+variant, the kernel rates of its 16-bit GEMM and FP32 sweep, and the
+oracle's FP64 residual of its solution (host processes, a few minutes).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -79,9 +85,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-box64", action="store_true",
+                    help="default run: skip the 64^3 mixed-precision leg")
+    ap.add_argument("--oracle-procs", type=int, default=12,
+                    help="host processes of the oracle's box64 sweeps (cpu_baseline leg)")
     ap.add_argument("--mixed-precision", default="fp16")
     ap.add_argument("--workload", default="box32",
-                    choices=["box32", "batch512", "serve", "box64", "slab64"])
+                    choices=["box32", "batch512", "serve", "box64", "slab64", "apply"])
+    ap.add_argument("--problem", default="box64", choices=["box32", "box64", "slab64"],
+                    help="apply: the problem whose operator is applied")
+    ap.add_argument("--sigma-form", default="dense", choices=["dense", "factored"],
+                    help="apply: scattering form of FP64 / FP32 applications")
     ap.add_argument("--precision", default=None,
                     help="operator precision for batch512 / serve / box64")
     ap.add_argument("--duration", type=float, default=60.0, help="serve: stream length (s)")
@@ -153,6 +167,8 @@ def main():
         return bench_box64(args)
     if args.workload == "slab64":
         return bench_slab64(args)
+    if args.workload == "apply":
+        return bench_apply(args)
     import torch
     import workloads as W
     from paper_2602_21958_amd import rt
@@ -175,7 +191,7 @@ def main():
     torch.cuda.synchronize()
 
     rt.profile_enable(True)
-    for k in ("lambda", "sigma", "arnoldi"):
+    for k in rt.KCLASS:
         rt.profile_read(k, reset=True)
     lat, stats = [], []
     torch.cuda.synchronize()
@@ -188,7 +204,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rt.profile_enable(False)
-    prof = {k: rt.profile_read(k, reset=True) for k in ("lambda", "sigma", "arnoldi")}
+    prof = {k: rt.profile_read(k, reset=True) for k in rt.KCLASS}
 
     elapsed = t1 - t0
     value = args.steps / elapsed
@@ -267,7 +283,7 @@ def main():
         p.solve(xm, rtol=1e-8, restart=30, precision=prec, stream=stream)  # warm
         torch.cuda.synchronize()
         rt.profile_enable(True)
-        rt.profile_read("sigma", reset=True)
+        _profile_summary(rt)
         m_steps = max(1, args.steps)
         tm0 = time.perf_counter()
         mst = None
@@ -276,17 +292,26 @@ def main():
         torch.cuda.synchronize()
         tm1 = time.perf_counter()
         rt.profile_enable(False)
-        ms_n, ms_ms = rt.profile_read("sigma", reset=True)
+        mprof = _profile_summary(rt)
+        lo_n, lo_ms = mprof["sigma_lo"]["launches"], mprof["sigma_lo"]["total_ms"]
+        hi_n, hi_ms = mprof["sigma"]["launches"], mprof["sigma"]["total_ms"]
         diff = (torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x)).item()
         out["mixed"] = {"precision": prec, "value": m_steps / (tm1 - tm0), "unit": "solves/s",
                         "speedup_vs_fp64": (m_steps / (tm1 - tm0)) / value,
                         "relres_fp64": mst["relres"], "converged": mst["converged"],
                         "inner_iters": mst["iters"], "outer_iters": mst["outer_iters"],
                         "rel_diff_vs_fp64_solution": diff,
-                        "sigma_avg_ms": ms_ms / max(ms_n, 1),
-                        "sigma_tflops": sig_flops / (ms_ms / max(ms_n, 1) * 1e-3) / 1e12,
-                        "sigma_tile": p.gemm16_tile(prec) if prec in ("bf16", "fp16", "bf16x3")
-                        else "FP32 MFMA 128x128"}
+                        "inner_sigma": {
+                            "kernel": (f"sigma16 {prec} " + p.gemm16_tile(prec))
+                            if prec in ("bf16", "fp16", "bf16x3") else "FP32 MFMA 128x128",
+                            "launches": lo_n, "avg_ms": lo_ms / max(lo_n, 1),
+                            "TFLOP/s": sig_flops / (lo_ms / max(lo_n, 1) * 1e-3) / 1e12},
+                        "outer_sigma_fp64": {
+                            "launches": hi_n, "avg_ms": hi_ms / max(hi_n, 1),
+                            "TFLOP/s": sig_flops / (hi_ms / max(hi_n, 1) * 1e-3) / 1e12
+                            if hi_n else None},
+                        "kernel_ms_per_solve": {k: v["total_ms"] / m_steps
+                                                for k, v in mprof.items()}}
         if prec in ("bf16", "fp16", "bf16x3"):
             # the same refinement with the inner Krylov basis kept in fp16
             p.solve(xm, rtol=1e-8, restart=30, precision=prec, basis_fp16=1, stream=stream)
@@ -305,15 +330,82 @@ def main():
                 "inner_iters": hst["iters"], "outer_iters": hst["outer_iters"],
                 "rel_diff_vs_fp64_solution": diff}
 
+    # the same FP64 solve with the scattering step in factored form (dipole
+    # rank 6 x frequency block: HBM-bound passes instead of the dense GEMM)
+    print("box32: factored FP64 leg", file=sys.stderr, flush=True)
+    p.set_sigma("factored")
+    xf = torch.empty_like(x)
+    p.solve(xf, rtol=1e-8, restart=30, stream=stream)  # warm
+    torch.cuda.synchronize()
+    rt.profile_enable(True)
+    _profile_summary(rt)
+    tf0 = time.perf_counter()
+    stf = None
+    for _ in range(args.steps):
+        stf = p.solve(xf, rtol=1e-8, restart=30, stream=stream)
+    torch.cuda.synchronize()
+    tf1 = time.perf_counter()
+    rt.profile_enable(False)
+    fprof = _profile_summary(rt)
+    # the factored passes alone, y = (1 - eps) Mhat L (no x term, as in the
+    # Arnoldi steps): read L, write y, and W, Z of R x N_nu x N_s each
+    # written once and read once
+    yf = torch.empty_like(x)
+    for _ in range(2):
+        p.apply_sigma(x, None, yf, stream=stream)
+    torch.cuda.synchronize()
+    rt.profile_enable(True)
+    _profile_summary(rt)
+    for _ in range(5):
+        p.apply_sigma(x, None, yf, stream=stream)
+    torch.cuda.synchronize()
+    rt.profile_enable(False)
+    aprof = _profile_summary(rt)
+    del yf
+    p.set_sigma("dense")
+    rank = p.footprint().sigma_rank
+    n_nu_b, n_om_b = spec.n_nu, spec.n_omega
+    f_n, f_ms = aprof["sigma"]["launches"], aprof["sigma"]["total_ms"]
+    f_avg = f_ms / max(f_n, 1)
+    wz = rank * n_nu_b * n_s
+    f_bytes = 8.0 * (2 * n + 4 * wz)
+    out["fp64_factored_sigma"] = {
+        "value": args.steps / (tf1 - tf0), "unit": "solves/s",
+        "speedup_vs_dense": (args.steps / (tf1 - tf0)) / value,
+        "converged": stf["converged"], "relres": stf["relres"], "iters": stf["iters"],
+        "rel_diff_vs_dense_solution":
+            (torch.linalg.vector_norm(xf - x) / torch.linalg.vector_norm(x)).item(),
+        "sigma_ms_per_solve_in_solves": fprof["sigma"]["total_ms"] / args.steps,
+        "kernel_ms_per_solve": {k: v["total_ms"] / args.steps for k, v in fprof.items()},
+        "flop_per_apply": {"dense": sig_flops,
+                           "factored": 4.0 * rank * n + 2.0 * rank * n_nu_b * n_nu_b * n_s},
+        "roofline": {"kernel": "fsig_reduce + fsig_mix + fsig_expand <double>", "bound": "hbm",
+                     "achieved": f_bytes / (f_avg * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": f_bytes / (f_avg * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "avg_ms": f_avg, "launches": f_n,
+                     "algorithmic_per_launch": f"read L, write y (16 B x N) + W and Z "
+                                               f"({rank} x N_nu x N_s doubles each, written "
+                                               f"and read) = {f_bytes:.4g} B"},
+    }
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, stats[-1]["iters"], stats[-1]["outer_iters"])
-
     p.close()
+    del x, x2
+    if not args.no_mixed:
+        del xm
+    del xf
+    torch.cuda.empty_cache()
+
+    if not args.no_box64:
+        out["box64"] = box64_leg(BOX64_DEFAULT, oracle_check=not args.no_cpu_baseline,
+                                 procs=args.oracle_procs)
     print(json.dumps(out), flush=True)
 
 
 # --------------------------------------------------------------------------
-def _profile_summary(rt, names=("lambda", "sigma", "arnoldi")):
+def _profile_summary(rt, names=None):
+    names = rt.KCLASS if names is None else names
     return {k: dict(zip(("launches", "total_ms"), rt.profile_read(k, reset=True))) for k in names}
 
 
@@ -386,7 +478,7 @@ def bench_batch512(args):
         probs[i].solve(xs[i], rtol=1e-8, restart=30, record_history=0)
     torch.cuda.synchronize()
     loop_per_slab = (time.perf_counter() - t0) / len(sample)
-    sig = prof["sigma"]
+    sig = prof["sigma" if prec == "fp64" else "sigma_lo"]
     out = {
         "metric": "solves/s to 1e-8 residual (512 heterogeneous slabs, one engine)",
         "value": 512 / el, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -578,114 +670,286 @@ def _blas_threads():
         return 1
 
 
-def box64_cpu_baseline(spec, n_apply):
-    """Oracle on a bounded sample of box64: Lambda for 2 of the 128 ordinates
-    (all 48 frequencies) and the Sigma product for 4096 of the 262 144 points,
-    each scaled to the full operator; an FP64 oracle solve at this size would
-    hold a 30-vector basis of 12.9 GB vectors in host memory, so the solve time
-    is extrapolated as n_apply operator applications."""
+# ---------------------------------------------------------------- box64
+# (label, operator precision, inner restart, fp16 basis, scattering form):
+# the default run's box64 leg, then the rest of the variants that
+# --workload box64 times.  An fp16 basis leaves room for GMRES(30) inner
+# cycles; an FP32 GMRES(30) basis would not fit 288 GB beside the FP64
+# vectors, so FP32-basis variants take GMRES(20).
+BOX64_DEFAULT = [("fp16/basis16/m30", "fp16", 30, 1, "dense"),
+                 ("bf16/basis16/m30", "bf16", 30, 1, "dense"),
+                 ("fp32/factored/m20", "fp32", 20, 0, "factored")]
+BOX64_MORE = [("fp16/m20", "fp16", 20, 0, "dense"), ("bf16/m20", "bf16", 20, 0, "dense"),
+              ("bf16x3/m20", "bf16x3", 20, 0, "dense"), ("fp32/m20", "fp32", 20, 0, "dense")]
+
+
+_SWEEP = {}
+
+
+def _sweep_init(k_line, omega, fac_nu, i_top, i_bot):
+    _SWEEP.update(k_line=k_line, omega=omega, fac_nu=fac_nu, i_top=i_top, i_bot=i_bot)
+
+
+def _sweep_worker(job):
+    """Oracle sweeps of one ordinate (spawned host process): the intensity
+    with boundary radiation for the source s_o (Lambda_0 s + I_bc) and for a
+    zero source (I_bc)."""
+    import numpy as np
+    from oracle.transfer import sweep_box
+    o, s_o = job
+    g = _SWEEP
+    om = g["omega"][o:o + 1]
+    i_x = sweep_box(g["k_line"], om, g["fac_nu"], s_o[None], g["i_top"], g["i_bot"])
+    i_0 = sweep_box(g["k_line"], om, g["fac_nu"], np.zeros_like(s_o)[None], g["i_top"],
+                    g["i_bot"])
+    return o, i_x, i_0
+
+
+def oracle_residual_box(spec, x_host, procs):
+    """FP64 relative residual ||b - A x|| / ||b|| of a box solution, evaluated
+    by the oracle: its sweeps (one ordinate per task over `procs` spawned
+    host processes, which never touch the GPU) and its scattering block,
+    chunked over points.  With I_x = Lambda_0 x + I_bc and I_bc the sweeps of
+    x and of a zero source with boundary radiation, b = (1 - eps) Mhat I_bc
+    + t and b - A x = (1 - eps) Mhat I_x + t - x (the sweep is linear in the
+    source).  Returns the residual and the host seconds of the sweeps and of
+    the products."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import Problem as OProblem
-    from oracle.transfer import sweep_box
     op = OProblem(spec)
-    n_om = op.omega.shape[0]
-    n_nu = spec.n_nu
-    sub_o, sub_p = 2, 4096
-    s = np.random.default_rng(0).standard_normal((sub_o * n_nu, spec.nz, spec.ny, spec.nx))
+    n_om, n_nu = op.n_omega, op.n_nu
+    shape = (n_om, n_nu * spec.nz * spec.ny * spec.nx)
+    src = np.asarray(x_host, dtype=np.float64).reshape(shape)
+    i_x = np.empty(shape)
+    i_0 = np.empty(shape)
+    sub = (n_nu, spec.nz, spec.ny, spec.nx)
     t0 = time.perf_counter()
-    sweep_box(spec.k_line, op.omega[:sub_o], op.phi + spec.r, s)
-    t_lam = (time.perf_counter() - t0) * n_om / sub_o
-    L = np.random.default_rng(1).standard_normal((op.n_r, sub_p))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs, initializer=_sweep_init,
+                      initargs=(np.asarray(spec.k_line, float), op.omega, op.phi + spec.r,
+                                spec.i_top, spec.i_bot)) as pool:
+            jobs = ((o, src[o].reshape(sub)) for o in range(n_om))
+            done = 0
+            for o, a, b in pool.imap_unordered(_sweep_worker, jobs):
+                i_x[o] = a.reshape(-1)
+                i_0[o] = b.reshape(-1)
+                done += 1
+                if done % 16 == 0:
+                    print(f"oracle residual: {done}/{n_om} ordinates swept "
+                          f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    assert done == n_om
+    t_sweep = time.perf_counter() - t0
+    ix = i_x.reshape(op.n_r, op.n_s)
+    i0 = i_0.reshape(op.n_r, op.n_s)
+    xs = src.reshape(op.n_r, op.n_s)
     t0 = time.perf_counter()
-    op.albedo[None, :sub_p] * (op.mhat @ L)
-    t_sig = (time.perf_counter() - t0) * op.n_s / sub_p
-    t_solve = n_apply * (t_lam + t_sig)
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": _blas_threads(),
-            "kind": "oracle",
-            "sample": f"Lambda of 2/{n_om} ordinates and Sigma on {sub_p}/{op.n_s} points, "
-                      f"scaled to one operator application (Lambda {t_lam:.1f} s + Sigma "
-                      f"{t_sig:.1f} s) and extrapolated to {n_apply} applications (the GPU "
-                      f"solve's inner + outer iterations)"}
+    rr = bb = 0.0
+    step = 16384
+    for c in range(0, op.n_s, step):
+        sl = slice(c, min(op.n_s, c + step))
+        t_c = op.t[:, sl]
+        b_c = op.scatter_points(i0[:, sl], sl) + t_c
+        r_c = op.scatter_points(ix[:, sl], sl) + t_c - xs[:, sl]
+        rr += float(np.sum(r_c * r_c))
+        bb += float(np.sum(b_c * b_c))
+        if (c // step) % 4 == 3:
+            print(f"oracle residual: Sigma over {sl.stop}/{op.n_s} points "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    t_sig = time.perf_counter() - t0
+    return float(np.sqrt(rr / bb)), t_sweep, t_sig
 
 
-def bench_box64(args):
+def box64_leg(variants, oracle_check=True, procs=12):
     """The 64^3 box (128 ordinates x 48 frequencies, N = 1.61e9) in mixed
-    precision: FP32 Lambda, 16-bit Sigma, FP64 refinement.  Inner cycles are
-    GMRES(20) with an FP32 basis (an FP32 GMRES(30) basis would not leave
-    room for the FP64 vectors in 288 GB) or GMRES(20) / GMRES(30) with an
-    fp16 basis."""
+    precision: FP32 Lambda, 16-bit (or factored FP32) Sigma, FP64
+    refinement with FP64 outer residuals.  One timed solve per variant after
+    an untimed one-iteration solve that sizes the workspace and tunes the
+    16-bit tile; kernel classes from HIP events; then single applications
+    of the 16-bit operator for its kernel rates, and the oracle's FP64
+    residual of the first variant's solution."""
+    import numpy as np
     import torch
     import workloads as W
     from paper_2602_21958_amd import rt
 
     spec = W.box64()
+    t0 = time.perf_counter()
     p = rt.Problem(spec)
+    t_create = time.perf_counter() - t0
     n, n_r, n_s = p.n, p.n_r, p.n_s
+    flops = 2.0 * n_r * n_r * n_s
     x = torch.empty(n, dtype=torch.float64, device="cuda:0")
-    res = {}
-    # (label, operator precision, inner restart, fp16 basis); an fp16 basis
-    # leaves room for GMRES(30) cycles
-    all_variants = [("fp16", "fp16", 20, 0), ("fp16/basis16", "fp16", 20, 1),
-                    ("fp16/basis16/m30", "fp16", 30, 1), ("bf16x3", "bf16x3", 20, 0),
-                    ("bf16", "bf16", 20, 0), ("fp32", "fp32", 20, 0)]
-    variants = ([v for v in all_variants if v[1] == args.precision] if args.precision
-                else all_variants)
-    for label, prec, m, b16 in variants:
-        # untimed: size the workspace for this restart / basis and tune the
-        # 16-bit tile (one refinement step of one inner iteration)
+    res, x_check = {}, None
+    for label, prec, m, b16, form in variants:
+        p.set_sigma(form)
         p.solve(x, rtol=1e-8, restart=m, precision=prec, max_outer=1, max_iters=1,
-                basis_fp16=b16)
+                basis_fp16=b16, record_history=0)
         rt.profile_enable(True)
         _profile_summary(rt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = p.solve(x, rtol=1e-8, restart=m, precision=prec, max_outer=40, max_iters=2000,
-                     basis_fp16=b16)
+                     basis_fp16=b16, record_history=0)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rt.profile_enable(False)
         prof = _profile_summary(rt)
-        res[label] = {"s_per_solve": el, "converged": st["converged"],
+        sig64 = prof["sigma"]
+        res[label] = {"s_per_solve": el, "solves_per_s": 1.0 / el, "converged": st["converged"],
                       "relres_fp64": st["relres"], "precision": prec, "restart": m,
-                      "basis": "fp16" if b16 else "fp32",
+                      "basis": "fp16" if b16 else "fp32", "sigma_form": form,
                       "inner_iters": st["iters"], "outer_iters": st["outer_iters"],
                       "kernel_ms": {k: v["total_ms"] for k, v in prof.items()},
-                      "sigma_launches": prof["sigma"]["launches"],
-                      "sigma_tile": p.gemm16_tile(prec) if prec != "fp32" else "FP32 MFMA"}
+                      "kernel_launches": {k: v["launches"] for k, v in prof.items()},
+                      "sigma16_tile": p.gemm16_tile(prec) if prec in ("bf16", "fp16", "bf16x3")
+                      else None}
+        if form == "dense" and sig64["launches"]:
+            a = sig64["total_ms"] / sig64["launches"]
+            res[label]["outer_sigma_fp64"] = {"avg_ms": a, "TFLOP/s": flops / a / 1e9,
+                                              "frac_of_78.6TF": flops / a / 1e9 / PEAK_FP64_TFLOPS}
         print(json.dumps({"box64_variant": label, **res[label]}), file=sys.stderr, flush=True)
-    best = min((v["s_per_solve"], k) for k, v in res.items() if v["converged"])
-    best_prec = res[best[1]]["precision"]
-    # single-apply kernel rates at full size
+        if x_check is None and st["converged"]:
+            x_check = (label, x.cpu().numpy())
+    p.set_sigma("dense")
+    conv = [(v["s_per_solve"], k) for k, v in res.items() if v["converged"]]
+    best = min(conv) if conv else (float("nan"), None)
+    dense = [c for c in conv if res[c[1]]["sigma_form"] == "dense"]
+    best_dense = min(dense) if dense else (float("nan"), None)
+    # single applications at full size: FP32 vector -> FP32 Lambda emitting
+    # the k4 fp16 operand (4 B read + 2 B written per unknown) -> fp16 Sigma
     xf = torch.randn(n, dtype=torch.float32, device="cuda:0")
     yf = torch.empty_like(xf)
+    kern = {}
+    for prec in ("fp16", "bf16"):
+        p.apply(xf, yf, precision=prec)
+        torch.cuda.synchronize()
+        rt.profile_enable(True)
+        _profile_summary(rt)
+        for _ in range(3):
+            p.apply(xf, yf, precision=prec)
+        torch.cuda.synchronize()
+        rt.profile_enable(False)
+        pr = _profile_summary(rt)
+        sig_ms = pr["sigma_lo"]["total_ms"] / max(pr["sigma_lo"]["launches"], 1)
+        lam_ms = pr["lambda_lo"]["total_ms"] / max(pr["lambda_lo"]["launches"], 1)
+        kern[prec] = {
+            "sigma16": {"kernel": f"sigma16 {prec} " + p.gemm16_tile(prec), "bound": "mfma",
+                        "avg_ms": sig_ms, "achieved": flops / sig_ms / 1e9,
+                        "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                        "frac": flops / sig_ms / 1e9 / PEAK_BF16_TFLOPS,
+                        "algorithmic_per_launch": f"2*N_r^2*N_s = {flops:.4g} flop"},
+            "lambda_k4": {"kernel": "lambda_box_kernel<float -> k4 16-bit>", "bound": "hbm",
+                          "avg_ms": lam_ms, "achieved": 6.0 * n / lam_ms / 1e6,
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": 6.0 * n / lam_ms / 1e6 / PEAK_HBM_GBS,
+                          "algorithmic_per_launch": f"6 B x N = {6.0 * n:.4g} B"}}
+    del xf, yf, x
+    p.close()
+    torch.cuda.empty_cache()
+    out = {"workload": "box64: 64^3 box, 128 ordinates (8 mu x 16 az), 48 frequencies, "
+                       "N = 1.61e9; FP32 Lambda + 16-bit or factored FP32 Sigma + FP64 "
+                       "refinement to 1e-8",
+           "n_unknowns": n, "create_s": t_create,
+           "value": 1.0 / best[0], "unit": "solves/s", "best_variant": best[1],
+           "best_dense_variant": best_dense[1], "best_dense_solves_per_s": 1.0 / best_dense[0],
+           "variants": res, "kernels_single_apply": kern,
+           "roofline": kern["fp16"]["sigma16"], "lambda": kern["fp16"]["lambda_k4"]}
+    if oracle_check and x_check is not None:
+        label, xh = x_check
+        rel, t_sw, t_sig = oracle_residual_box(spec, xh, procs)
+        del xh
+        v = res[label]
+        n_apply = v["inner_iters"] + v["outer_iters"]
+        t_apply = 0.5 * t_sw + 0.5 * t_sig    # one sweep and one product of the two
+        out["oracle_residual"] = {"variant": label, "relres_fp64_oracle": rel,
+                                  "host_s": t_sw + t_sig}
+        out["cpu_baseline"] = {
+            "value": 1.0 / (n_apply * t_apply), "unit": "solves/s",
+            "cores": max(procs, _blas_threads()), "kind": "oracle",
+            "sample": f"one oracle operator application timed while evaluating the FP64 "
+                      f"residual of the {label} solution (sweeps of {spec.n_mu * spec.n_az} "
+                      f"ordinates over {procs} host processes: {0.5 * t_sw:.1f} s per sweep; "
+                      f"Sigma chunked over points with {_blas_threads()} BLAS threads: "
+                      f"{0.5 * t_sig:.1f} s per product), extrapolated to {n_apply} "
+                      f"applications (the GPU solve's inner + outer iterations); an oracle "
+                      f"GMRES at this size would hold 12.9 GB per basis vector"}
+    return out
+
+
+def bench_apply(args):
+    """--workload apply: K operator applications y = A x of one problem in
+    one precision (a short, fixed program for kernel traces and memory
+    counters); reports the kernel classes' mean durations and rates."""
+    import torch
+    import workloads as W
+    from paper_2602_21958_amd import rt
+
+    spec = {"box32": W.box32, "box64": W.box64, "slab64": W.slab64}[args.problem]()
+    prec = args.precision or "fp64"
+    p = rt.Problem(spec)
+    p.set_sigma(args.sigma_form)
+    n, n_r, n_s = p.n, p.n_r, p.n_s
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x = torch.randn(n, dtype=dt, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(max(1, args.warmup)):
+        p.apply(x, y, precision=prec)
+    torch.cuda.synchronize()
     rt.profile_enable(True)
     _profile_summary(rt)
-    for _ in range(3):
-        p.apply(xf, yf, precision=best_prec)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p.apply(x, y, precision=prec)
     torch.cuda.synchronize()
+    el = time.perf_counter() - t0
     rt.profile_enable(False)
     pr = _profile_summary(rt)
-    sig_ms = pr["sigma"]["total_ms"] / max(pr["sigma"]["launches"], 1)
-    lam_ms = pr["lambda"]["total_ms"] / max(pr["lambda"]["launches"], 1)
+    lam_k = "lambda" if prec == "fp64" else "lambda_lo"
+    sig_k = "sigma" if prec == "fp64" else "sigma_lo"
+    lam_ms = pr[lam_k]["total_ms"] / max(pr[lam_k]["launches"], 1)
+    sig_ms = pr[sig_k]["total_ms"] / max(pr[sig_k]["launches"], 1)
+    lam_b = {"fp64": 16.0, "fp32": 8.0}.get(prec, 6.0) * n
     flops = 2.0 * n_r * n_r * n_s
+    out = {"metric": "operator applications per second", "value": args.steps / el,
+           "unit": "applies/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": prec, "data": "synthetic",
+           "config": {"workload": f"apply: {args.problem}, {prec}, {args.sigma_form} Sigma",
+                      "n_unknowns": n},
+           "lambda": {"avg_ms": lam_ms, "GB/s": lam_b / lam_ms / 1e6,
+                      "frac_of_8TB/s": lam_b / lam_ms / 1e6 / PEAK_HBM_GBS,
+                      "algorithmic_bytes": lam_b},
+           "sigma": {"avg_ms": sig_ms, "TFLOP/s_dense_equivalent": flops / sig_ms / 1e9}}
+    p.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_box64(args):
+    """--workload box64: every variant; one JSON line."""
+    variants = BOX64_DEFAULT + BOX64_MORE
+    if args.precision:
+        variants = [v for v in variants if v[1] == args.precision]
+    leg = box64_leg(variants, oracle_check=not args.no_cpu_baseline, procs=args.oracle_procs)
     out = {
         "metric": "solves/s to 1e-8 residual (64^3 box, mixed precision)",
-        "value": 1.0 / best[0], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": best[0] * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": best_prec, "data": "synthetic",
-        "config": {"workload": "box64: 64^3 box, 128 ordinates (8 mu x 16 az), 48 frequencies, "
-                               "N = 1.61e9; FP32 Lambda + 16-bit Sigma + FP64 refinement; "
-                               "value from the fastest variant", "variant": best[1],
-                   "n_unknowns": n},
-        "variants": res,
-        "sigma": {"precision": best_prec, "avg_ms": sig_ms, "TFLOP/s": flops / sig_ms / 1e9,
-                  "frac_of_2.5PF": flops / sig_ms / 1e9 / PEAK_BF16_TFLOPS},
-        "lambda": {"avg_ms": lam_ms, "GB/s_at_6B_per_unknown": 6.0 * n / lam_ms / 1e6},
+        "value": leg["value"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 / leg["value"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": leg["variants"][leg["best_variant"]]["precision"],
+        "data": "synthetic",
+        "config": {"workload": leg["workload"], "variant": leg["best_variant"],
+                   "n_unknowns": leg["n_unknowns"]},
+        **{k: v for k, v in leg.items() if k not in ("value", "unit", "workload")},
     }
-    p.close()
-    if not args.no_cpu_baseline:
-        v = res[best[1]]
-        out["cpu_baseline"] = box64_cpu_baseline(spec, v["inner_iters"] + v["outer_iters"])
     print(json.dumps(out), flush=True)
 
 
