@@ -125,6 +125,18 @@ typedef struct {
                              code's quadratic integrator); the last node of a
                              ray, which has no downwind node, takes the linear
                              step                                                 */
+  /* Per-point scattering classes (Sec. 3.3: the block Psi_[i] of eq. Sigma may
+   * differ from point to point).  n_classes <= 1: one kernel for every point
+   * (the fields below are ignored).  n_classes > 1: point i scatters with the
+   * block of class point_class[i]; DIPOLE_PRD kernels take the coherent
+   * fraction class_coh_frac[c] per class (coh_width2 shared), EXPLICIT ones
+   * the symmetric matrix class_kernels[c * n_rays^2 ...] (row-major; then
+   * kernel_matrix is ignored).  FP64 and FP32 applications only, dense
+   * scattering form; not in the batch engine.                               */
+  int n_classes;
+  const int32_t* point_class;   /* n_points ids in [0, n_classes)              */
+  const double* class_coh_frac; /* DIPOLE_PRD: n_classes values in [0, 1]      */
+  const double* class_kernels;  /* EXPLICIT: n_classes * n_rays * n_rays       */
 } rt_problem_desc;
 
 typedef struct {

@@ -98,7 +98,10 @@ class Problem:
         def mhat_of(psi):
             return (1.0 / self.fac_ray)[:, None] * psi * self.w_ray[None, :]
 
-        self.psi = kernel_block(spec.coh_frac, spec.kernel_matrix)
+        base = spec.kernel_matrix
+        if base is None and getattr(spec, "class_kernels", None) is not None:
+            base = spec.class_kernels[0]       # classes without a kernel_matrix
+        self.psi = kernel_block(spec.coh_frac, base)
         self.mhat = mhat_of(self.psi)
         # per-point classes: self.point_class (n_s) and one Mhat per class
         self.point_class = None

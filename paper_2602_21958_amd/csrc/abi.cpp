@@ -55,6 +55,11 @@ Problem::~Problem() {
   hipFree(d_fg32);
   hipFree(d_fb32);
   hipFree(d_fwork);
+  hipFree(d_cmhat64);
+  hipFree(d_cmhat32);
+  hipFree(d_cidx);
+  hipFree(d_calb);
+  hipFree(d_cwork);
 }
 
 size_t lambda_elem_bytes(int precision) {
@@ -91,9 +96,30 @@ static void* problem_fwork(Problem& p, size_t elem) {
   return p.d_fwork;
 }
 
+static void* problem_cwork(Problem& p, size_t elem) {
+  const size_t bytes = classes_work_elems(p) * elem;
+  if (bytes > p.cwork_bytes) {
+    hipFree(p.d_cwork);
+    p.d_cwork = nullptr;
+    p.cwork_bytes = 0;
+    RT_HIP(hipMalloc(&p.d_cwork, bytes));
+    p.cwork_bytes = bytes;
+  }
+  return p.d_cwork;
+}
+
+void require_one_kernel(const Problem& p, const char* what) {
+  if (p.n_classes > 1)
+    fail(RT_E_INVALID, std::string(what) + " is not available with per-point scattering classes");
+}
+
 void apply_sigma_f64(Problem& p, const double* L, const double* x, double* y,
                      const double* xscale, double sign, hipStream_t st, gemm::TileDots* dots) {
-  if (p.sigma_form == RT_SIGMA_FACTORED) {
+  if (p.n_classes > 1) {
+    if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the one-kernel scattering GEMM");
+    launch_sigma_classes_f64(p, L, x, y, static_cast<double*>(problem_cwork(p, sizeof(double))),
+                             xscale, sign, st);
+  } else if (p.sigma_form == RT_SIGMA_FACTORED) {
     if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the dense scattering GEMM");
     launch_sigma_factored_f64(p, L, x, y, static_cast<double*>(problem_fwork(p, sizeof(double))),
                               xscale, sign, st);
@@ -104,7 +130,11 @@ void apply_sigma_f64(Problem& p, const double* L, const double* x, double* y,
 
 void apply_sigma_f32(Problem& p, const float* L, const float* x, float* y,
                      const double* xscale, double sign, hipStream_t st, gemm::TileDots* dots) {
-  if (p.sigma_form == RT_SIGMA_FACTORED) {
+  if (p.n_classes > 1) {
+    if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the one-kernel scattering GEMM");
+    launch_sigma_classes_f32(p, L, x, y, static_cast<float*>(problem_cwork(p, sizeof(float))),
+                             xscale, sign, st);
+  } else if (p.sigma_form == RT_SIGMA_FACTORED) {
     if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the dense scattering GEMM");
     launch_sigma_factored_f32(p, L, x, y, static_cast<float*>(problem_fwork(p, sizeof(float))),
                               xscale, sign, st);
@@ -194,7 +224,8 @@ void validate(const rt_problem_desc& d) {
       d.formal != RT_FORMAL_QUADRATIC_SC)
     fail(RT_E_INVALID, "unknown formal solver");
   if (d.kernel == RT_KERNEL_EXPLICIT) {
-    if (!d.kernel_matrix) fail(RT_E_INVALID, "explicit kernel needs kernel_matrix");
+    if (!d.kernel_matrix && d.n_classes <= 1)
+      fail(RT_E_INVALID, "explicit kernel needs kernel_matrix");
   } else if (d.kernel == RT_KERNEL_DIPOLE_PRD) {
     if (!(d.coh_frac >= 0 && d.coh_frac <= 1)) fail(RT_E_INVALID, "coh_frac must be in [0,1]");
     if (!(d.coh_width2 > 0)) fail(RT_E_INVALID, "coh_width2 must be > 0");
@@ -204,12 +235,35 @@ void validate(const rt_problem_desc& d) {
   if (!std::isfinite(d.i_top) || !std::isfinite(d.i_bot) || !std::isfinite(d.eps) ||
       !std::isfinite(d.planck))
     fail(RT_E_NONFINITE, "non-finite scalar input");
+  if (d.n_classes > 1) {
+    if (d.n_classes > 256) fail(RT_E_INVALID, "at most 256 scattering classes");
+    if (!d.point_class) fail(RT_E_INVALID, "n_classes > 1 needs point_class");
+    const size_t ns = (size_t)d.nx * d.ny * d.nz;
+    for (size_t i = 0; i < ns; ++i)
+      if (d.point_class[i] < 0 || d.point_class[i] >= d.n_classes)
+        fail(RT_E_INVALID, "point_class out of range");
+    if (d.kernel == RT_KERNEL_DIPOLE_PRD) {
+      if (!d.class_coh_frac) fail(RT_E_INVALID, "dipole x PRD classes need class_coh_frac");
+      for (int c = 0; c < d.n_classes; ++c)
+        if (!(d.class_coh_frac[c] >= 0 && d.class_coh_frac[c] <= 1))
+          fail(RT_E_INVALID, "class_coh_frac must be in [0,1]");
+    } else if (!d.class_kernels) {
+      fail(RT_E_INVALID, "explicit classes need class_kernels");
+    }
+  }
 }
 
 }  // namespace
 
-void problem_build(Problem& p, const rt_problem_desc& d) {
-  validate(d);
+void problem_build(Problem& p, const rt_problem_desc& d_in) {
+  validate(d_in);
+  // with classes, the problem's own tables (and rt_problem_tables) are class 0's
+  rt_problem_desc d = d_in;
+  const bool classes = d_in.n_classes > 1;
+  if (classes) {
+    if (d.kernel == RT_KERNEL_EXPLICIT) d.kernel_matrix = d_in.class_kernels;
+    else d.coh_frac = d_in.class_coh_frac[0];
+  }
   p.geom = d.geom;
   p.nx = d.nx;
   p.ny = d.ny;
@@ -227,8 +281,8 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
   p.i_bot = d.i_bot;
   if (p.n_r > 16384) fail(RT_E_INVALID, "too many rays (n_mu*n_az*n_nu > 16384)");
   if (d.kernel == RT_KERNEL_EXPLICIT &&
-      !all_finite(d.kernel_matrix, (size_t)p.n_r * p.n_r))
-    fail(RT_E_NONFINITE, "kernel_matrix has NaN/Inf");
+      !all_finite(d.kernel_matrix, (size_t)p.n_r * p.n_r * (classes ? d_in.n_classes : 1)))
+    fail(RT_E_NONFINITE, "kernel matrix has NaN/Inf");
 
   build_tables(d, p.tab);
 
@@ -280,6 +334,53 @@ void problem_build(Problem& p, const rt_problem_desc& d) {
       }
     p.d_mhat64 = upload(m64.data(), sz, tot);
     p.d_mhat32 = upload(m32.data(), sz, tot);
+    if (classes) {
+      // one transposed Mhat per class (the same layout), the points sorted
+      // by class with their albedo in that order
+      const int nc = d_in.n_classes;
+      p.n_classes = nc;
+      p.class_mhat_stride = sz;
+      std::vector<double> c64((size_t)nc * sz, 0.0);
+      std::vector<float> c32((size_t)nc * sz, 0.f);
+      for (int c = 0; c < nc; ++c) {
+        rt_problem_desc dc = d_in;
+        if (d.kernel == RT_KERNEL_EXPLICIT)
+          dc.kernel_matrix = d_in.class_kernels + (size_t)c * p.n_r * p.n_r;
+        else
+          dc.coh_frac = d_in.class_coh_frac[c];
+        Tables tc;
+        build_tables(dc, tc);
+        double rmax = 0.0;
+        for (int k = 0; k < p.n_r; ++k) {
+          double r = 0.0;
+          for (int kp2 = 0; kp2 < p.n_r; ++kp2) {
+            const double m = tc.mhat[(size_t)k * p.n_r + kp2];
+            c64[(size_t)c * sz + (size_t)kp2 * lda + k] = m;
+            c32[(size_t)c * sz + (size_t)kp2 * lda + k] = (float)m;
+            r += std::fabs(m);
+          }
+          rmax = std::max(rmax, r);
+        }
+        double amax = 0.0;
+        for (int64_t i = 0; i < p.n_s; ++i) amax = std::max(amax, alb[i]);
+        p.scatter_inf = std::max(p.scatter_inf, amax * rmax);
+      }
+      p.d_cmhat64 = upload(c64.data(), c64.size(), tot);
+      p.d_cmhat32 = upload(c32.data(), c32.size(), tot);
+      p.class_off.assign(nc + 1, 0);
+      for (int64_t i = 0; i < p.n_s; ++i) p.class_off[d_in.point_class[i] + 1]++;
+      for (int c = 0; c < nc; ++c) p.class_off[c + 1] += p.class_off[c];
+      std::vector<int32_t> idx(p.n_s);
+      std::vector<double> calb(p.n_s);
+      std::vector<int64_t> fill(p.class_off.begin(), p.class_off.end() - 1);
+      for (int64_t i = 0; i < p.n_s; ++i) {
+        const int64_t at = fill[d_in.point_class[i]]++;
+        idx[at] = (int32_t)i;
+        calb[at] = alb[i];
+      }
+      p.d_cidx = upload(idx.data(), idx.size(), tot);
+      p.d_calb = upload(calb.data(), calb.size(), tot);
+    }
   }
   {
     // 16-bit copies in the k8 layout of the MFMA GEMM (see gemm16_dev.h):
@@ -381,6 +482,7 @@ void operator_apply(Problem& p, int precision, const void* x, void* y, const dou
     case RT_PREC_BF16:
     case RT_PREC_FP16:
     case RT_PREC_BF16X3: {
+      require_one_kernel(p, "a 16-bit operator");
       uint16_t* L = problem_l16(p, st);
       uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
       launch_lambda_k4(p, precision, static_cast<const float*>(x), L, Llo, xscale, st);
@@ -412,6 +514,7 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y, const d
     case RT_PREC_BF16:
     case RT_PREC_FP16:
     case RT_PREC_BF16X3: {
+      require_one_kernel(p, "a 16-bit operator");
       uint16_t* L = problem_l16(p, st);
       uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
       launch_lambda_k4(p, precision, static_cast<const float*>(x), L, Llo, xscale, st);
@@ -428,6 +531,7 @@ void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st, bool kform) {
   if (precision != RT_PREC_BF16 && precision != RT_PREC_FP16 && precision != RT_PREC_BF16X3)
     fail(RT_E_INVALID, "an fp16 basis needs a 16-bit operator precision");
+  require_one_kernel(p, "a 16-bit operator");
   uint16_t* L = problem_l16(p, st);
   uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
   launch_lambda_k4(p, precision, x, L, Llo, xscale, st);
@@ -546,7 +650,7 @@ rt_status rt_problem_footprint(rt_problem p, int restart, rt_problem_info* info)
                              (int64_t)(q->n * sizeof(double));
     info->bytes_solve_mixed = (int64_t)workspace_bytes(*q, restart, true, false) +
                               (int64_t)(q->n * sizeof(double));
-    info->sigma_rank = q->tab.frank;
+    info->sigma_rank = q->n_classes > 1 ? 0 : q->tab.frank;
     info->sigma_form = q->sigma_form;
   });
 }
@@ -597,6 +701,7 @@ rt_status rt_apply_sigma(rt_problem p, int precision, const void* L, const void*
                        static_cast<float*>(y), nullptr, sign, st);
     } else {
       // 16-bit operand paths take an FP32 L and round it like the operator does
+      require_one_kernel(*q, "a 16-bit operator");
       uint16_t* lb = problem_l16(*q, st);
       uint16_t* lo = precision == RT_PREC_BF16X3 ? lb + l16_part_elems(*q) : nullptr;
       convert_to_k4(*q, precision, static_cast<const float*>(L), lb, lo, st);
@@ -633,6 +738,7 @@ rt_status rt_problem_set_sigma(rt_problem p, int form) {
     if (form != RT_SIGMA_DENSE && form != RT_SIGMA_FACTORED)
       fail(RT_E_INVALID, "unknown scattering form");
     if (form == RT_SIGMA_FACTORED) {
+      require_one_kernel(*q, "the factored scattering form");
       if (q->tab.frank == 0)
         fail(RT_E_INVALID, "the factored scattering form needs the dipole x PRD kernel");
       if (!factored_fits(*q, sizeof(double)))

@@ -698,6 +698,7 @@ rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts, 
     rt_solver_opts o;
     if (opts) o = *opts; else rt_solver_opts_default(&o);
     if (o.krylov != RT_KRYLOV_GMRES) fail(RT_E_INVALID, "the batch engine runs GMRES");
+    require_one_kernel(*q, "the batch engine");
     if (q->geom == RT_GEOM_BOX && q->formal != RT_FORMAL_LINEAR_SC)
       fail(RT_E_INVALID, "the batch engine sweeps boxes with linear SC only");
     if (o.precision != e->precision) fail(RT_E_INVALID, "precision differs from the engine's");

@@ -51,6 +51,7 @@ void operator_apply_noalloc(Problem& p, int precision, const void* x, void* y, h
     fail(RT_E_INVALID,
          "rt_apply_operator_noalloc: only RT_PREC_FP64 and RT_PREC_FP32 (the 16-bit operand "
          "buffer and tile tuner of the other precisions allocate on first use)");
+  require_one_kernel(p, "rt_apply_operator_noalloc");
   if (p.sigma_form != RT_SIGMA_DENSE)
     fail(RT_E_INVALID,
          "rt_apply_operator_noalloc: the factored scattering form allocates its work vectors; "

@@ -117,6 +117,19 @@ struct Problem {
   int sigma_form = RT_SIGMA_DENSE;
   void* d_fwork = nullptr;
   size_t fwork_bytes = 0;
+  // per-point scattering classes (n_classes > 1): one transposed Mhat per
+  // class (class_mhat_stride elements apart), the points sorted by class
+  // (d_cidx, class c at class_off[c] .. class_off[c + 1]) with their albedo
+  // in that order (d_calb), and the gathered operand / product work buffer
+  int n_classes = 1;
+  size_t class_mhat_stride = 0;
+  double* d_cmhat64 = nullptr;
+  float* d_cmhat32 = nullptr;
+  int32_t* d_cidx = nullptr;
+  double* d_calb = nullptr;
+  std::vector<int64_t> class_off;
+  void* d_cwork = nullptr;
+  size_t cwork_bytes = 0;
   Workspace* ws = nullptr;
   int64_t bytes_problem = 0;
   std::vector<double> history;
@@ -209,6 +222,25 @@ void launch_sigma_factored_f64(const Problem& p, const double* L, const double* 
                                double* work, const double* xscale, double sign, hipStream_t st);
 void launch_sigma_factored_f32(const Problem& p, const float* L, const float* x, float* y,
                                float* work, const double* xscale, double sign, hipStream_t st);
+// Scattering with per-point classes (sigma_classes.hip): for each class,
+// gather its points' columns of L, one GEMM with the class's Mhat and
+// albedo, and scatter y = xs x + sign (result) to the class's columns.
+// work holds 2 n_r max_c(class size) elements.
+void launch_sigma_classes_f64(const Problem& p, const double* L, const double* x, double* y,
+                              double* work, const double* xscale, double sign, hipStream_t st);
+void launch_sigma_classes_f32(const Problem& p, const float* L, const float* x, float* y,
+                              float* work, const double* xscale, double sign, hipStream_t st);
+size_t classes_work_elems(const Problem& p);
+// RT_E_INVALID naming `what` when the problem has per-point classes.
+void require_one_kernel(const Problem& p, const char* what);
+// Dense GEMM y = xs x + sign albedo .* (A L) with explicit operands: A
+// transposed (lda), L and y N columns wide (sigma_gemm.hip).
+void launch_gemm_f64(const Problem& p, const double* A, const double* L, int N,
+                     const double* x, double* y, const double* albedo, const double* xscale,
+                     double sign, hipStream_t st);
+void launch_gemm_f32(const Problem& p, const float* A, const float* L, int N, const float* x,
+                     float* y, const double* albedo, const double* xscale, double sign,
+                     hipStream_t st);
 // Scattering step of FP64 / FP32 applications in the problem's form (dense
 // GEMM or factored); fused dots need the dense GEMM.
 void apply_sigma_f64(Problem& p, const double* L, const double* x, double* y,

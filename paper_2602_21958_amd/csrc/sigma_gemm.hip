@@ -43,11 +43,10 @@ __global__ __launch_bounds__(256) void sigma_gemm_kernel(
 }
 
 template <typename T>
-void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* y,
-                    const double* xscale, double sign, hipStream_t st, TileDots* dots) {
-  const int M = p.n_r, N = (int)p.n_s, K = p.n_r;
+void launch_gemm_core(const T* mhat, int lda, const T* L, const T* x, T* y,
+                      const double* albedo, const double* xscale, int M, int N, int K,
+                      double sign, hipStream_t st, TileDots* dots) {
   const int tiles = ((M + gemm::BM - 1) / gemm::BM) * ((N + gemm::BN - 1) / gemm::BN);
-  ProfScope prof(sizeof(T) == 8 ? RT_KCLASS_SIGMA : RT_KCLASS_SIGMA_LO, st);
   if (dots) {
     if (dots->ldp < tiles) fail(RT_E_INVALID, "fused dots: too few partial slots");
     dots->ldp = tiles;   // one slot per tile, all written
@@ -55,14 +54,36 @@ void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* 
   const TileDots d = dots ? *dots : TileDots{};
 #define RT_SIGMA_LAUNCH(BKV, DV)                                                              \
   hipLaunchKernelGGL((sigma_gemm_kernel<T, BKV, DV>), dim3(tiles), dim3(256), 0, st, mhat,   \
-                     p.lda_mhat, L, x, y, p.d_albedo, xscale, M, N, K, sign, d)
+                     lda, L, x, y, albedo, xscale, M, N, K, sign, d)
   // K stage 16 (a stage of 32 was measured slower)
   if (dots) RT_SIGMA_LAUNCH(16, true); else RT_SIGMA_LAUNCH(16, false);
 #undef RT_SIGMA_LAUNCH
   RT_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_sigma_t(const Problem& p, const T* mhat, const T* L, const T* x, T* y,
+                    const double* xscale, double sign, hipStream_t st, TileDots* dots) {
+  ProfScope prof(sizeof(T) == 8 ? RT_KCLASS_SIGMA : RT_KCLASS_SIGMA_LO, st);
+  launch_gemm_core<T>(mhat, p.lda_mhat, L, x, y, p.d_albedo, xscale, p.n_r, (int)p.n_s,
+                      p.n_r, sign, st, dots);
+}
+
 }  // namespace
+
+void launch_gemm_f64(const Problem& p, const double* A, const double* L, int N,
+                     const double* x, double* y, const double* albedo, const double* xscale,
+                     double sign, hipStream_t st) {
+  launch_gemm_core<double>(A, p.lda_mhat, L, x, y, albedo, xscale, p.n_r, N, p.n_r, sign, st,
+                           nullptr);
+}
+
+void launch_gemm_f32(const Problem& p, const float* A, const float* L, int N, const float* x,
+                     float* y, const double* albedo, const double* xscale, double sign,
+                     hipStream_t st) {
+  launch_gemm_core<float>(A, p.lda_mhat, L, x, y, albedo, xscale, p.n_r, N, p.n_r, sign, st,
+                          nullptr);
+}
 
 void launch_sigma_f64(const Problem& p, const double* L, const double* x, double* y,
                       const double* xscale, double sign, hipStream_t st, TileDots* dots) {

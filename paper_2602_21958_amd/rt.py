@@ -53,6 +53,8 @@ class ProblemDesc(C.Structure):
         ("kernel", C.c_int), ("kernel_matrix", _dp),
         ("coh_frac", C.c_double), ("coh_width2", C.c_double),
         ("formal", C.c_int),
+        ("n_classes", C.c_int), ("point_class", C.POINTER(C.c_int32)),
+        ("class_coh_frac", _dp), ("class_kernels", _dp),
     ]
 
 
@@ -168,7 +170,8 @@ class Problem:
     """Device-resident problem built from a spec object with the fields of
     ``rt_problem_desc`` (geom, nx, ny, nz, depth, k_line, n_mu, n_az, n_nu,
     x_max, r, eps, planck, i_top, i_bot, kernel, kernel_matrix, coh_frac,
-    coh_width2, formal).  eps / planck may be scalars or per-point arrays."""
+    coh_width2, formal; optional point_class with class_coh_frac or
+    class_kernels).  eps / planck may be scalars or per-point arrays."""
 
     def __init__(self, spec, device: int = 0):
         self._keep = []
@@ -207,6 +210,21 @@ class Problem:
             d.kernel_matrix = p
         d.coh_frac, d.coh_width2 = float(spec.coh_frac), float(spec.coh_width2)
         d.formal = FORMAL[spec.formal]
+        pc = getattr(spec, "point_class", None)
+        if pc is not None:
+            pcl = np.ascontiguousarray(np.asarray(pc).reshape(-1), dtype=np.int32)
+            self._keep.append(pcl)
+            d.point_class = pcl.ctypes.data_as(C.POINTER(C.c_int32))
+            if spec.kernel == "explicit":
+                arr, p = _darr(np.asarray(spec.class_kernels).reshape(-1))
+                d.n_classes = int(np.asarray(spec.class_kernels).shape[0])
+                self._keep.append(arr)
+                d.class_kernels = p
+            else:
+                arr, p = _darr(np.asarray(spec.class_coh_frac).reshape(-1))
+                d.n_classes = int(arr.size)
+                self._keep.append(arr)
+                d.class_coh_frac = p
         h = _vp()
         _check(_lib.rt_problem_create(C.byref(d), int(device), C.byref(h)), "rt_problem_create")
         self._keep = []
