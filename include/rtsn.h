@@ -257,8 +257,14 @@ rt_status rt_intensity(rt_problem p, const double* s, double* I, void* stream);
 enum { RT_KRYLOV_GMRES = 0, RT_KRYLOV_BICGSTAB = 1 };
 
 typedef struct {
-  int krylov;             /* RT_KRYLOV_GMRES (default) or RT_KRYLOV_BICGSTAB        */
-  int restart;            /* GMRES restart length m (1..200; default 30)            */
+  int krylov;             /* RT_KRYLOV_GMRES (default) or RT_KRYLOV_BICGSTAB (van der
+                             Vorst; FP64 vectors in FP64 precision; in the mixed
+                             precisions the inner solve of each refinement step,
+                             on FP32 vectors with FP64 dot products; keeps no
+                             basis)                                                */
+  int restart;            /* GMRES restart length m (1..128; default 30); with
+                             BiCGStab in a mixed precision, the iteration cap of
+                             each inner solve                                     */
   int max_iters;          /* total inner iterations cap (default 10000)             */
   double rtol;            /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual,
                              FP64)                                                   */

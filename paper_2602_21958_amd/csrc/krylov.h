@@ -93,8 +93,8 @@ template <typename T>
 void k_bicg_p(const T* r, const T* v, T* p, int64_t n, const BicgState* bs, hipStream_t st);
 template <typename T>
 void k_bicg_s(T* r, const T* v, int64_t n, const BicgState* bs, double* partial, hipStream_t st);
-template <typename T>
-void k_bicg_xr(double* x, const T* p, T* r, const T* t, int64_t n, const BicgState* bs,
+template <typename T, typename TX>
+void k_bicg_xr(TX* x, const T* p, T* r, const T* t, int64_t n, const BicgState* bs,
                int only_alpha, double* partial, hipStream_t st);
 void k_bicg_scalar(const double* partial, int64_t n, int stage, BicgState* bs, hipStream_t st);
 template <typename TS, typename TD>

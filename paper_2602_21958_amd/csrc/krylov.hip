@@ -777,8 +777,8 @@ __global__ __launch_bounds__(kThreads) void bicg_s_kernel(T* __restrict__ r, con
 }
 
 // x += alpha p + omega s ; r = s - omega t (s stored in r), partial ||r||^2
-template <typename T>
-__global__ __launch_bounds__(kThreads) void bicg_xr_kernel(double* __restrict__ x,
+template <typename T, typename TX>
+__global__ __launch_bounds__(kThreads) void bicg_xr_kernel(TX* __restrict__ x,
                                                            const T* __restrict__ p,
                                                            T* __restrict__ r,
                                                            const T* __restrict__ t, int64_t n,
@@ -789,7 +789,7 @@ __global__ __launch_bounds__(kThreads) void bicg_xr_kernel(double* __restrict__ 
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
     const double s = (double)r[e];
-    x[e] += alpha * (double)p[e] + omega * s;
+    x[e] = (TX)((double)x[e] + alpha * (double)p[e] + omega * s);
     if (!only_alpha) {
       const T rn = (T)(s - omega * (double)t[e]);
       r[e] = rn;
@@ -1026,11 +1026,11 @@ void k_bicg_s(T* r, const T* v, int64_t n, const BicgState* bs, double* partial,
   RT_HIP(hipGetLastError());
 }
 
-template <typename T>
-void k_bicg_xr(double* x, const T* p, T* r, const T* t, int64_t n, const BicgState* bs,
+template <typename T, typename TX>
+void k_bicg_xr(TX* x, const T* p, T* r, const T* t, int64_t n, const BicgState* bs,
                int only_alpha, double* partial, hipStream_t st) {
-  hipLaunchKernelGGL((bicg_xr_kernel<T>), dim3(grid_for(n)), dim3(kThreads), 0, st, x, p, r, t, n,
-                     bs, only_alpha, partial);
+  hipLaunchKernelGGL((bicg_xr_kernel<T, TX>), dim3(grid_for(n)), dim3(kThreads), 0, st, x, p, r,
+                     t, n, bs, only_alpha, partial);
   RT_HIP(hipGetLastError());
 }
 
@@ -1094,8 +1094,16 @@ template void k_bicg_p<double>(const double*, const double*, double*, int64_t, c
                                hipStream_t);
 template void k_bicg_s<double>(double*, const double*, int64_t, const BicgState*, double*,
                                hipStream_t);
-template void k_bicg_xr<double>(double*, const double*, double*, const double*, int64_t,
-                                const BicgState*, int, double*, hipStream_t);
+template void k_bicg_xr<double, double>(double*, const double*, double*, const double*, int64_t,
+                                        const BicgState*, int, double*, hipStream_t);
+template void k_bicg_xr<float, float>(float*, const float*, float*, const float*, int64_t,
+                                      const BicgState*, int, double*, hipStream_t);
+template void k_dots4<float>(const float*, const float*, const float*, const float*, int,
+                             int64_t, double*, hipStream_t);
+template void k_bicg_p<float>(const float*, const float*, float*, int64_t, const BicgState*,
+                              hipStream_t);
+template void k_bicg_s<float>(float*, const float*, int64_t, const BicgState*, double*,
+                              hipStream_t);
 template void k_mdot<_Float16>(const _Float16*, int64_t, int, const _Float16*, double*,
                                hipStream_t);
 template void k_update<_Float16>(const _Float16*, int64_t, int, const double*, const double*,

@@ -16,7 +16,10 @@
 // candidate.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <mutex>
+#include <string>
 
 #include "gemm16_dev.h"
 #include "lambda_dev.h"
@@ -123,6 +126,52 @@ void launch_mode(int mode, int cfg, const Args& a, hipStream_t st) {
   else launch_index<MODE_SPLIT>(cfg, a, st);
 }
 
+// Persistent tuning cache (RTSN_TUNE_CACHE=<file>): one line per tuned
+// problem shape, "<arch> <mode> <M> <N> <cfg>", read before timing and
+// appended after; a shape found there is not timed again (no stream
+// synchronisation, no scratch allocation).  Unset: nothing is read or
+// written.
+std::mutex g_cache_mu;
+
+std::string cache_key(int device, int mode, int M, int N) {
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "";
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "%s %d %d %d", prop.gcnArchName, mode, M, N);
+  return buf;
+}
+
+int cache_lookup(const std::string& key) {
+  const char* path = std::getenv("RTSN_TUNE_CACHE");
+  if (!path || key.empty()) return -1;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -1;
+  char line[256];
+  int found = -1;
+  while (std::fgets(line, sizeof line, f)) {
+    std::string s(line);
+    const size_t sp = s.find_last_of(' ');
+    if (sp == std::string::npos) continue;
+    if (s.compare(0, sp, key) == 0 && sp == key.size()) {
+      const int c = std::atoi(s.c_str() + sp + 1);
+      if (c >= 0 && c < kNumCfg) found = c;   // the last entry wins
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const std::string& key, int cfg) {
+  const char* path = std::getenv("RTSN_TUNE_CACHE");
+  if (!path || key.empty()) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d\n", key.c_str(), cfg);
+    std::fclose(f);
+  }
+}
+
 // Time every candidate on a column slice of the real operands and epilogue
 // input (scratch output) and keep the fastest.
 int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
@@ -130,6 +179,8 @@ int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
     const int c = std::atoi(e);
     if (c >= 0 && c < kNumCfg) return c;
   }
+  const std::string key = cache_key(p.device, mode, full.M, full.N);
+  if (const int c = cache_lookup(key); c >= 0) return c;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   RT_HIP(hipStreamIsCapturing(st, &cs));
   if (cs != hipStreamCaptureStatusNone) return 2;   // cannot time inside a capture
@@ -177,7 +228,7 @@ int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   RT_HIP(hipEventDestroy(e0));
   RT_HIP(hipEventDestroy(e1));
   RT_HIP(hipFree(scratch));
-  (void)p;
+  cache_store(key, best);
   return best;
 }
 

@@ -43,7 +43,7 @@ size_t workspace_bytes(const Problem& p, int restart, bool mixed, bool bicgstab,
   if (basis_elem <= 0) basis_elem = mixed ? 4 : 8;
   size_t b = sizeof(double) * (size_t)(kMaxRestart + 1) * 2 * kReduceBlocks + sizeof(GmresState) +
              sizeof(BicgState) + 64 * sizeof(double);
-  b += (size_t)(restart + 1) * n * basis_elem;
+  b += (size_t)(bicgstab ? 1 : restart + 1) * n * basis_elem;   // BiCGStab keeps no basis
   b += (mixed ? 1 : 2) * n * sizeof(double);  // r64 (+ ax64 for FP64 GMRES)
   if (mixed) b += 2 * n * sizeof(float);
   if (bicgstab) b += 4 * n * sizeof(double);
@@ -81,7 +81,7 @@ bool fuse_dots_env() {
 // basis_elem: bytes per basis element (8 FP64, 4 FP32, 2 fp16)
 Workspace& ensure_workspace(Problem& p, int restart, bool mixed, bool bicgstab, int basis_elem) {
   Workspace* ws = p.ws;
-  const size_t vbytes = (size_t)(restart + 1) * (size_t)p.n * basis_elem;
+  const size_t vbytes = (size_t)(bicgstab ? 1 : restart + 1) * (size_t)p.n * basis_elem;
   const bool ok = ws && ws->restart >= restart && ws->mixed == mixed && ws->vbytes >= vbytes &&
                   (!bicgstab || ws->bic != nullptr);
   if (ok) return *ws;
@@ -397,7 +397,7 @@ rt_status bicgstab_fp64(Problem& p, const double* b, double* x, bool x_zero, dou
     it++;
     if (hs.breakdown) return RT_E_BREAKDOWN;
     if (sn <= rtol * bnorm) {
-      k_bicg_xr<double>(x, pv, r, t, n, bs, 1, ws.partial, st);
+      k_bicg_xr<double, double>(x, pv, r, t, n, bs, 1, ws.partial, st);
       rn = sn;
       if (hist) hist->push_back(rn / bnorm);
       break;
@@ -405,7 +405,7 @@ rt_status bicgstab_fp64(Problem& p, const double* b, double* x, bool x_zero, dou
     operator_apply(p, RT_PREC_FP64, r, t, nullptr, st);
     k_dots4<double>(t, r, t, t, 2, n, ws.partial, st);
     k_bicg_scalar(ws.partial, n, 2, bs, st);
-    k_bicg_xr<double>(x, pv, r, t, n, bs, 0, ws.partial, st);
+    k_bicg_xr<double, double>(x, pv, r, t, n, bs, 0, ws.partial, st);
     k_finish_norm_simple(ws.partial, n, ws.scal, st);
     rn = read_scalar(ws.scal, st, ws);
     read_bs();
@@ -423,6 +423,64 @@ rt_status bicgstab_fp64(Problem& p, const double* b, double* x, bool x_zero, dou
   k_finish_norm_simple(ws.partial, n, ws.scal, st);
   res.beta = read_scalar(ws.scal, st, ws);
   return res.beta <= rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
+}
+
+// Inner solve of the refinement with BiCGStab (van der Vorst 1992) in FP32
+// vectors and the low-precision operator, FP64 dot products: A_lo d = r32
+// (r32 of unit norm on entry; overwritten) from d = 0 until the recursive
+// residual estimate is below itol or after cap iterations, or at a
+// breakdown (d then holds the last iterate, which the outer FP64 residual
+// judges).  Returns the iterations taken.
+int bicgstab_inner_f32(Problem& p, int prec, float* r, float* d, double itol, int cap,
+                       Workspace& ws, hipStream_t st) {
+  const int64_t n = p.n;
+  float* rhat = reinterpret_cast<float*>(ws.bic);
+  float* pv = rhat + n;
+  float* v = rhat + 2 * n;
+  float* t = rhat + 3 * n;
+  BicgState* bs = ws.bs;
+  RT_HIP(hipMemsetAsync(d, 0, (size_t)n * sizeof(float), st));
+  RT_HIP(hipMemcpyAsync(rhat, r, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  RT_HIP(hipMemsetAsync(pv, 0, (size_t)n * sizeof(float), st));
+  RT_HIP(hipMemsetAsync(v, 0, (size_t)n * sizeof(float), st));
+  BicgState init{1.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0, 0};
+  RT_HIP(hipMemcpyAsync(bs, &init, sizeof(init), hipMemcpyHostToDevice, st));
+  BicgState hs{};
+  auto read_bs = [&]() {
+    RT_HIP(hipMemcpyAsync(ws.host, bs, sizeof(BicgState), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    std::memcpy(&hs, ws.host, sizeof(BicgState));
+  };
+  int it = 0;
+  while (it < cap) {
+    k_dots4<float>(rhat, r, nullptr, nullptr, 1, n, ws.partial, st);
+    k_bicg_scalar(ws.partial, n, 0, bs, st);
+    k_bicg_p<float>(r, v, pv, n, bs, st);
+    operator_apply(p, prec, pv, v, nullptr, st);
+    k_dots4<float>(rhat, v, nullptr, nullptr, 1, n, ws.partial, st);
+    k_bicg_scalar(ws.partial, n, 1, bs, st);
+    k_bicg_s<float>(r, v, n, bs, ws.partial, st);   // r now holds s
+    k_finish_norm_simple(ws.partial, n, ws.scal, st);
+    const double sn = read_scalar(ws.scal, st, ws);
+    read_bs();
+    it++;
+    if (hs.breakdown || !std::isfinite(sn)) break;
+    if (sn <= itol) {
+      k_bicg_xr<float, float>(d, pv, r, t, n, bs, 1, ws.partial, st);
+      break;
+    }
+    operator_apply(p, prec, r, t, nullptr, st);
+    k_dots4<float>(t, r, t, t, 2, n, ws.partial, st);
+    k_bicg_scalar(ws.partial, n, 2, bs, st);
+    k_bicg_xr<float, float>(d, pv, r, t, n, bs, 0, ws.partial, st);
+    k_finish_norm_simple(ws.partial, n, ws.scal, st);
+    const double rn = read_scalar(ws.scal, st, ws);
+    read_bs();
+    if (hs.breakdown || !std::isfinite(rn) || rn <= itol) break;
+    int one = 1;
+    RT_HIP(hipMemcpyAsync(&bs->iter, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  return it;
 }
 
 }  // namespace
@@ -455,7 +513,7 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
   } else if (!mixed && bicg) {
     status = bicgstab_fp64(p, b, x, !x_is_guess, o.rtol, o.max_iters, bnorm, ws, st, hist, res);
   } else {
-    if (bicg) fail(RT_E_INVALID, "BiCGStab is available in FP64 precision only");
+    if (bicg && o.basis_fp16) fail(RT_E_INVALID, "an fp16 basis is a GMRES option");
     // FP64 iterative refinement: r = b - A_64 x; inner A_lo d = r/||r|| (one
     // GMRES(m) cycle); x += ||r|| d.  Stops at rtol, at max_outer, or after
     // three steps without residual reduction.
@@ -480,13 +538,22 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
       const double need = o.rtol * bnorm / rn;
       if (need > itol) itol = need;
       const int cap = std::min(o.restart, o.max_iters - total_inner);
-      if (o.basis_fp16) {
+      if (bicg) {
+        // inner BiCGStab on the FP32 residual, at most `restart` iterations
+        total_inner += bicgstab_inner_f32(p, o.precision, r32, ws.d32, itol, cap, ws, st);
+      } else if (o.basis_fp16) {
         total_inner += inner_cycle_fp16(p, o.precision, ws.r64, rn, ws.d32, o.restart, itol, cap,
                                         ws, st, o.two_step != 0);
       } else {
+        // a pair's second application takes u1 = K v_j unnormalised; the
+        // 16-bit operators' fp16 Lambda scale assumes entries of at most
+        // about one, which |(1 - eps) Mhat|_inf <= 2 keeps (the physical
+        // kernels give about 1); above that the steps go one at a time
+        const bool pairs = o.two_step != 0 &&
+                           (o.precision == RT_PREC_FP32 || p.scatter_inf <= 2.0);
         CoreResult ir;
         gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
-                          nullptr, st, nullptr, ir, /*single_cycle=*/true, o.two_step != 0);
+                          nullptr, st, nullptr, ir, /*single_cycle=*/true, pairs);
         total_inner += ir.iters;
       }
       RT_HIP(hipMemcpyAsync(ws.scal + 1, &rn, sizeof(double), hipMemcpyHostToDevice, st));

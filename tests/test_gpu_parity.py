@@ -640,3 +640,56 @@ def test_mixed_refinement_per_precision(name, prec, two_step):
     else:
         # a precision too coarse for this conditioning: reported, not hidden
         assert prec == "bf16", st
+
+
+def test_gemm16_tuning_cache(monkeypatch, tmp_path):
+    """RTSN_TUNE_CACHE: the first tuned shape is appended to the file; a new
+    problem of the same shape takes the file's entry (the last one wins)
+    instead of timing the candidates again."""
+    rt = _rt()
+    names = ["256x256 32x32x16 K64", "256x128 16x16x32 K32", "128x128 32x32x16 K32",
+             "128x128 16x16x32 K64"]
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("RTSN_TUNE_CACHE", str(path))
+    monkeypatch.delenv("RTSN_GEMM16_CFG", raising=False)
+    spec = W.small_box(8, 4, 8, 5)
+    with rt.Problem(spec) as p:
+        x = torch.tensor(W.random_field(p.n, 91), dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        p.apply(x, y, precision="fp16")
+        torch.cuda.synchronize()
+        tuned = p.gemm16_tile("fp16")
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    key, cfg = lines[0].rsplit(" ", 1)
+    assert names[int(cfg)] == tuned and key.split()[0].startswith("gfx")
+    other = (int(cfg) + 1) % 4
+    with open(path, "a") as f:
+        f.write(f"{key} {other}\n")
+    with rt.Problem(spec) as p:
+        x = torch.tensor(W.random_field(p.n, 92), dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        p.apply(x, y, precision="fp16")
+        torch.cuda.synchronize()
+        assert p.gemm16_tile("fp16") == names[other]
+    assert len(path.read_text().splitlines()) == 2     # nothing timed, nothing appended
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16x3"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
+def test_bicgstab_mixed_refinement(name, prec):
+    """BiCGStab as the inner solver of FP64 refinement (FP32 vectors, FP64
+    dot products, the low-precision operator): the oracle-evaluated FP64
+    residual meets 1e-8."""
+    rt = _rt()
+    spec = ALL[name]()
+    say(f"bicgstab mixed {prec} {name}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        st = p.solve(x, rtol=1e-8, precision=prec, krylov="bicgstab", max_outer=40,
+                     restart=60)
+        s = host(x)
+    res = op.residual_norm(s)
+    say(f"   outer {st['outer_iters']} inner {st['iters']} residual {res:.2e}")
+    assert st["converged"] and res <= 1e-8
