@@ -25,24 +25,37 @@ namespace {
 constexpr int kMaxRank = 6;
 constexpr int kMixTile = 64;     // points per mix workgroup
 
-// W = fg^T L over the ordinates; one thread per (nu', i), grid-stride.  The
-// ordinate loop walks rays nu' + o' N_nu, so a wave's loads are 64
+// Vectors of V consecutive points: one 16-byte load or store per lane when
+// V = 16 / sizeof(T) (the problem's point count a multiple of V, so that every
+// ray's row starts 16-byte aligned), else single elements.
+template <typename T, int V> struct VecOf;
+template <> struct VecOf<double, 2> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct VecOf<float, 4> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <> struct VecOf<double, 1> { typedef double type; };
+template <> struct VecOf<float, 1> { typedef float type; };
+
+// W = fg^T L over the ordinates; one thread per (nu', V points), grid-stride.
+// The ordinate loop walks rays nu' + o' N_nu, so a wave's loads are 64 V
 // consecutive points of one ray; fg is wave-uniform (scalar loads).
-template <typename T, int R>
+template <typename T, int R, int V>
 __global__ __launch_bounds__(256) void fsig_reduce(const T* __restrict__ L,
                                                    const T* __restrict__ fg, T* __restrict__ W,
                                                    int n_om, int n_nu, int64_t n_s) {
+  using VT = typename VecOf<T, V>::type;
   const int64_t m = (int64_t)n_nu * n_s;
-  const int64_t ray_stride = (int64_t)n_nu * n_s;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+  const int64_t mv = m / V;
+  const int64_t ray_stride = m / V;    // in vectors
+  const VT* Lv = reinterpret_cast<const VT*>(L);
+  VT* Wv = reinterpret_cast<VT*>(W);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mv;
        e += (int64_t)gridDim.x * blockDim.x) {
-    T acc[R];
+    VT acc[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = T(0);
-    const T* src = L + e;
+    for (int q = 0; q < R; ++q) acc[q] = VT(0);
+    const VT* src = Lv + e;
     int o = 0;
     for (; o + 4 <= n_om; o += 4) {
-      T v[4];
+      VT v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[u] = src[(int64_t)(o + u) * ray_stride];
 #pragma unroll
@@ -51,12 +64,12 @@ __global__ __launch_bounds__(256) void fsig_reduce(const T* __restrict__ L,
         for (int q = 0; q < R; ++q) acc[q] += fg[(o + u) * R + q] * v[u];
     }
     for (; o < n_om; ++o) {
-      const T v = src[(int64_t)o * ray_stride];
+      const VT v = src[(int64_t)o * ray_stride];
 #pragma unroll
       for (int q = 0; q < R; ++q) acc[q] += fg[o * R + q] * v;
     }
 #pragma unroll
-    for (int q = 0; q < R; ++q) W[(int64_t)q * m + e] = acc[q];
+    for (int q = 0; q < R; ++q) Wv[(int64_t)q * mv + e] = acc[q];
   }
 }
 
@@ -91,30 +104,41 @@ __global__ __launch_bounds__(256) void fsig_mix(const T* __restrict__ W, const T
   }
 }
 
-// y = xs x + sign (1 - eps_i) fq Z, one thread per (nu, i), looping over the
-// ordinates (fq wave-uniform).
-template <typename T, int R>
+// y = xs x + sign (1 - eps_i) fq Z, one thread per (nu, V points), looping
+// over the ordinates (fq wave-uniform).
+template <typename T, int R, int V>
 __global__ __launch_bounds__(256) void fsig_expand(const T* __restrict__ Z,
                                                    const T* __restrict__ fq,
                                                    const double* __restrict__ albedo,
                                                    const T* x, T* y,
                                                    const double* __restrict__ xscale, T sign,
                                                    int n_om, int n_nu, int64_t n_s) {
+  using VT = typename VecOf<T, V>::type;
   const int64_t m = (int64_t)n_nu * n_s;
+  const int64_t mv = m / V;
   const T xs = (x != nullptr && xscale != nullptr) ? T(*xscale) : T(1);
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+  const VT* Zv = reinterpret_cast<const VT*>(Z);
+  const VT* xv = reinterpret_cast<const VT*>(x);
+  VT* yv = reinterpret_cast<VT*>(y);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mv;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % n_s;
-    const T a = sign * T(albedo[i]);
-    T z[R];
+    const int64_t i0 = (e * V) % n_s;     // V points of one ray row
+    VT a;
+    if constexpr (V == 1) {
+      a = sign * T(albedo[i0]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < R; ++q) z[q] = a * Z[(int64_t)q * m + e];
+      for (int u = 0; u < V; ++u) a[u] = sign * T(albedo[i0 + u]);
+    }
+    VT z[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) z[q] = a * Zv[(int64_t)q * mv + e];
     for (int o = 0; o < n_om; ++o) {
-      T s = T(0);
+      VT s = VT(0);
 #pragma unroll
       for (int q = 0; q < R; ++q) s += fq[o * R + q] * z[q];
-      const int64_t at = (int64_t)o * m + e;
-      y[at] = x ? xs * x[at] + s : s;
+      const int64_t at = (int64_t)o * mv + e;
+      yv[at] = x ? xs * xv[at] + s : s;
     }
   }
 }
@@ -134,23 +158,29 @@ void launch_factored(const Problem& p, const T* fq, const T* fg, const T* fb, co
   T* W = work;
   T* Z = work + (size_t)R * m;
   ProfScope prof(sizeof(T) == 8 ? RT_KCLASS_SIGMA : RT_KCLASS_SIGMA_LO, st);
-  const int g = stream_grid(m);
-  if (R == 6)
-    hipLaunchKernelGGL((fsig_reduce<T, 6>), dim3(g), dim3(256), 0, st, L, fg, W, n_om, n_nu, n_s);
-  else if (R == 2)
-    hipLaunchKernelGGL((fsig_reduce<T, 2>), dim3(g), dim3(256), 0, st, L, fg, W, n_om, n_nu, n_s);
-  else
+  constexpr int VV = 16 / sizeof(T);
+  const bool vec = n_s % VV == 0;
+  const int g = stream_grid(vec ? m / VV : m);
+#define RT_FSIG(KER, RR, ...)                                                              \
+  if (vec) hipLaunchKernelGGL((KER<T, RR, VV>), dim3(g), dim3(256), 0, st, __VA_ARGS__); \
+  else hipLaunchKernelGGL((KER<T, RR, 1>), dim3(g), dim3(256), 0, st, __VA_ARGS__)
+  if (R == 6) {
+    RT_FSIG(fsig_reduce, 6, L, fg, W, n_om, n_nu, n_s);
+  } else if (R == 2) {
+    RT_FSIG(fsig_reduce, 2, L, fg, W, n_om, n_nu, n_s);
+  } else {
     fail(RT_E_INVALID, "factored scattering: unsupported angular rank");
+  }
   const int64_t tiles = (n_s + kMixTile - 1) / kMixTile;
   const size_t lds = ((size_t)n_nu * kMixTile + (size_t)n_nu * n_nu) * sizeof(T);
   hipLaunchKernelGGL((fsig_mix<T>), dim3((unsigned)(R * tiles)), dim3(256), lds, st, W, fb, Z,
                      n_nu, n_s, tiles);
-  if (R == 6)
-    hipLaunchKernelGGL((fsig_expand<T, 6>), dim3(g), dim3(256), 0, st, Z, fq, p.d_albedo, x, y,
-                       xscale, T(sign), n_om, n_nu, n_s);
-  else
-    hipLaunchKernelGGL((fsig_expand<T, 2>), dim3(g), dim3(256), 0, st, Z, fq, p.d_albedo, x, y,
-                       xscale, T(sign), n_om, n_nu, n_s);
+  if (R == 6) {
+    RT_FSIG(fsig_expand, 6, Z, fq, p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s);
+  } else {
+    RT_FSIG(fsig_expand, 2, Z, fq, p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s);
+  }
+#undef RT_FSIG
   RT_HIP(hipGetLastError());
 }
 
