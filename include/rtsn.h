@@ -233,9 +233,20 @@ rt_status rt_apply_operator_noalloc(rt_problem p, int precision, const void* x, 
  * precisions and the batch engine always use the dense GEMM.  Applies to
  * every later call on p (operator, Sigma, right-hand side, solves); the
  * physical right-hand side is rebuilt.  Synchronises the device.
+ * RT_SIGMA_OZAKI (any kernel): FP64 applications emulate the dense FP64
+ * GEMM with exact int8 matrix-core products (error-free splitting in the
+ * integer-modular form of Ozaki, Uchino and Imamura, a published method, not
+ * the paper's): M-hat's rows and L's columns scaled to 51-bit integers, their
+ * residues modulo 15 pairwise coprime moduli <= 256 multiplied exactly in
+ * int32, the product rebuilt by the Chinese remainder theorem; error about
+ * 2^-51 of the largest entries of a row of M-hat and a column of L.  FP32
+ * applications use the dense FP32 GEMM.  Work memory per problem:
+ * 4 n_points + 30 ceil(n_rays / 128) 64 n_points_padded + 15 n_rays n_points
+ * bytes (box64: 48 GB).
  * Errors: RT_E_INVALID (unknown form; factored with an explicit kernel or
- * with more frequencies than the mix pass's LDS holds, about 120).         */
-enum { RT_SIGMA_DENSE = 0, RT_SIGMA_FACTORED = 1 };
+ * with more frequencies than the mix pass's LDS holds, about 120; factored
+ * or emulated with per-point classes).                                      */
+enum { RT_SIGMA_DENSE = 0, RT_SIGMA_FACTORED = 1, RT_SIGMA_OZAKI = 2 };
 rt_status rt_problem_set_sigma(rt_problem p, int form);
 
 /* Right-hand side of the source-function system, b = (1 - eps) Mhat I_bc + t:

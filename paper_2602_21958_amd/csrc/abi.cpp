@@ -60,6 +60,9 @@ Problem::~Problem() {
   hipFree(d_cidx);
   hipFree(d_calb);
   hipFree(d_cwork);
+  hipFree(d_oz_a);
+  hipFree(d_oz_ea);
+  hipFree(d_ozwork);
 }
 
 size_t lambda_elem_bytes(int precision) {
@@ -108,6 +111,18 @@ static void* problem_cwork(Problem& p, size_t elem) {
   return p.d_cwork;
 }
 
+static void* problem_ozwork(Problem& p) {
+  const size_t bytes = ozaki_work_bytes(p);
+  if (bytes > p.ozwork_bytes) {
+    hipFree(p.d_ozwork);
+    p.d_ozwork = nullptr;
+    p.ozwork_bytes = 0;
+    RT_HIP(hipMalloc(&p.d_ozwork, bytes));
+    p.ozwork_bytes = bytes;
+  }
+  return p.d_ozwork;
+}
+
 void require_one_kernel(const Problem& p, const char* what) {
   if (p.n_classes > 1)
     fail(RT_E_INVALID, std::string(what) + " is not available with per-point scattering classes");
@@ -123,6 +138,9 @@ void apply_sigma_f64(Problem& p, const double* L, const double* x, double* y,
     if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the dense scattering GEMM");
     launch_sigma_factored_f64(p, L, x, y, static_cast<double*>(problem_fwork(p, sizeof(double))),
                               xscale, sign, st);
+  } else if (p.sigma_form == RT_SIGMA_OZAKI) {
+    if (dots) fail(RT_E_INVALID, "fused Arnoldi dots need the dense scattering GEMM");
+    launch_sigma_ozaki(p, L, x, y, problem_ozwork(p), xscale, sign, st);
   } else {
     launch_sigma_f64(p, L, x, y, xscale, sign, st, dots);
   }
@@ -735,8 +753,12 @@ rt_status rt_apply_operator_noalloc(rt_problem p, int precision, const void* x, 
 rt_status rt_problem_set_sigma(rt_problem p, int form) {
   return guarded([&] {
     Problem* q = as_problem(p);
-    if (form != RT_SIGMA_DENSE && form != RT_SIGMA_FACTORED)
+    if (form != RT_SIGMA_DENSE && form != RT_SIGMA_FACTORED && form != RT_SIGMA_OZAKI)
       fail(RT_E_INVALID, "unknown scattering form");
+    if (form == RT_SIGMA_OZAKI) {
+      require_one_kernel(*q, "the emulated FP64 scattering GEMM");
+      ozaki_prepare(*q);
+    }
     if (form == RT_SIGMA_FACTORED) {
       require_one_kernel(*q, "the factored scattering form");
       if (q->tab.frank == 0)

@@ -19,7 +19,16 @@
 // MFMA: v_mfma_f32_16x16x32 (F32 = false) or v_mfma_f32_32x32x16 (F32 =
 // true) on bf16 or fp16.  A lane's 8 operand values are 8 consecutive k for
 // both A and B, so the k order inside an instruction is the natural one.
+//
+// MODE_I8 (exact integer products for the error-free split of an FP64
+// GEMM): the same layouts and tile with each 16-bit element holding two
+// consecutive int8 values (k even in the low byte), on
+// v_mfma_i32_16x16x64_i8 / v_mfma_i32_32x32x32_i8, whose lane operands are
+// the same 16 bytes (16 consecutive k); accumulation in int32 is exact while
+// K * 128^2 < 2^31.  The epilogue writes acc mod imod in [0, imod) as bytes.
 #pragma once
+
+#include <type_traits>
 
 #include "gemm_dev.h"
 #include "rt_internal.h"
@@ -33,7 +42,9 @@ typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
-enum { MODE_BF16 = 0, MODE_FP16 = 1, MODE_SPLIT = 2 };
+enum { MODE_BF16 = 0, MODE_FP16 = 1, MODE_SPLIT = 2, MODE_I8 = 3 };
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+typedef int i32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kMAlign = 256;   // Mp, Np multiple of this
 constexpr int kKAlign = 64;    // Kp multiple of this
@@ -67,6 +78,22 @@ template <> struct Mma<false, true> {
   static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a),
                                                   __builtin_bit_cast(f16x8_t, b), c, 0, 0, 0);
+  }
+};
+
+template <bool BIG> struct MmaI8;
+template <> struct MmaI8<false> {
+  using acc_t = i32x4_t;
+  static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i32x4_t, a),
+                                                 __builtin_bit_cast(i32x4_t, b), c, 0, 0, 0);
+  }
+};
+template <> struct MmaI8<true> {
+  using acc_t = i32x16_t;
+  static __device__ __forceinline__ acc_t run(u32x4_t a, u32x4_t b, acc_t c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4_t, a),
+                                                 __builtin_bit_cast(i32x4_t, b), c, 0, 0, 0);
   }
 };
 
@@ -108,11 +135,13 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
                                      const TY* X, TY* Y, const double* __restrict__ albedo,
                                      const float* __restrict__ rowscale, float colmul, float xs,
                                      float sign, int M, int N, int m0, int n0, uint8_t* lds,
-                                     gemm::TileDots dots = {}, int slot = 0, float ymul = 1.f) {
+                                     gemm::TileDots dots = {}, int slot = 0, float ymul = 1.f,
+                                     int imod = 0) {
   static_assert(!DOTS || sizeof(TY) == 4, "fused dots need an FP32 output");
   constexpr bool SPLIT = MODE == MODE_SPLIT;
   constexpr int NP = SPLIT ? 2 : 1;   // operand parts (hi, lo)
-  using MM = Mma<MODE != MODE_FP16, C::BIG>;
+  using MM = typename std::conditional<MODE == MODE_I8, MmaI8<C::BIG>,
+                                       Mma<MODE != MODE_FP16, C::BIG>>::type;
   using acc_t = typename MM::acc_t;
   constexpr int NR = C::BIG ? 16 : 4;
   constexpr int STAGE = NP * (C::ASB + C::BSB);
@@ -170,7 +199,7 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
 #pragma unroll
     for (int j = 0; j < C::TJ; ++j)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[i][j][r] = 0.f;
+      for (int r = 0; r < NR; ++r) acc[i][j][r] = 0;
 
   // lane roles: 16x16x32 -> 4 groups of 16 lanes (k8 chunk q, row/col r16);
   // 32x32x16 -> 2 groups of 32 lanes (k8 chunk p, row/col r32)
@@ -188,13 +217,17 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
     const int buf = st & 1;
     gload(min(st + 1, nst - 1) * (C::BK / 4));   // the last stage reloads itself (unused)
     __builtin_amdgcn_sched_barrier(0);           // keep the loads ahead of the MFMAs
-#pragma unroll
-    for (int h = 0; h < C::BK / KSTEP; ++h) {
+    // fragments of instruction step h, read one step ahead into two
+    // alternating register sets, so that the MFMAs of step h run while the
+    // LDS reads of step h + 1 are in flight
+    constexpr int H = C::BK / KSTEP;
+    u32x4_t bfr[2][NP][C::TJ], afr[2][NP][C::TI];
+    auto read_frags = [&](int h, u32x4_t (&bf)[NP][C::TJ], u32x4_t (&af)[NP][C::TI]) {
       const int c8 = KCH * h + kgrp;             // k8 chunk of this lane within the stage
-      u32x4_t bf[NP][C::TJ];
 #pragma unroll
       for (int s = 0; s < NP; ++s) {
-        const uint8_t* Bs = lds + buf * STAGE + s * (C::ASB + C::BSB) + C::ASB;
+        const uint8_t* As = lds + buf * STAGE + s * (C::ASB + C::BSB);
+        const uint8_t* Bs = As + C::ASB;
 #pragma unroll
         for (int j = 0; j < C::TJ; ++j) {
           const int n = wn * C::WN + C::MI * j + rc;
@@ -203,23 +236,28 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
           const uint2 hi = *reinterpret_cast<const uint2*>(p0 + C::BLKB);
           bf[s][j] = u32x4_t{lo.x, lo.y, hi.x, hi.y};
         }
+#pragma unroll
+        for (int i = 0; i < C::TI; ++i) {
+          const int m = wm * C::WM + C::MI * i + rc;
+          af[s][i] = *reinterpret_cast<const u32x4_t*>(As + (c8 * C::RB + (m >> 6)) * C::BLKA +
+                                                      (m & 63) * 16);
+        }
       }
+    };
+    read_frags(0, bfr[0], afr[0]);
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      if (h + 1 < H) read_frags(h + 1, bfr[(h + 1) & 1], afr[(h + 1) & 1]);
+      const auto& bf = bfr[h & 1];
+      const auto& af = afr[h & 1];
 #pragma unroll
       for (int i = 0; i < C::TI; ++i) {
-        const int m = wm * C::WM + C::MI * i + rc;
-        u32x4_t af[NP];
-#pragma unroll
-        for (int s = 0; s < NP; ++s) {
-          const uint8_t* As = lds + buf * STAGE + s * (C::ASB + C::BSB);
-          af[s] = *reinterpret_cast<const u32x4_t*>(As + (c8 * C::RB + (m >> 6)) * C::BLKA +
-                                                   (m & 63) * 16);
-        }
 #pragma unroll
         for (int j = 0; j < C::TJ; ++j) {
-          acc[i][j] = MM::run(af[0], bf[0][j], acc[i][j]);
+          acc[i][j] = MM::run(af[0][i], bf[0][j], acc[i][j]);
           if constexpr (SPLIT) {
-            acc[i][j] = MM::run(af[0], bf[1][j], acc[i][j]);
-            acc[i][j] = MM::run(af[1], bf[0][j], acc[i][j]);
+            acc[i][j] = MM::run(af[0][i], bf[1][j], acc[i][j]);
+            acc[i][j] = MM::run(af[1][i], bf[0][j], acc[i][j]);
           }
         }
       }
@@ -229,6 +267,27 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
     __syncthreads();
   }
 
+  if constexpr (MODE == MODE_I8) {
+    // residues of the exact integer products
+#pragma unroll
+    for (int j = 0; j < C::TJ; ++j) {
+      const int col = n0 + wn * C::WN + C::MI * j + rc;
+#pragma unroll
+      for (int i = 0; i < C::TI; ++i) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const int row = m0 + wm * C::WM + C::MI * i +
+                          (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
+          if (row < M && col < N) {
+            int v = acc[i][j][r] % imod;
+            v += v < 0 ? imod : 0;
+            Y[(size_t)row * N + col] = (TY)v;
+          }
+        }
+      }
+    }
+    return;
+  } else {
   // epilogue (the final values stay in acc for the fused dots; zero outside)
 #pragma unroll
   for (int j = 0; j < C::TJ; ++j) {
@@ -285,6 +344,7 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
       for (int w = 0; w < C::NW; ++w) t += red[q * C::NW + w];
       dots.part[(size_t)q * dots.ldp + slot] = t;
     }
+  }
   }
 }
 

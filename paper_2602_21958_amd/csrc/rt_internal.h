@@ -130,6 +130,13 @@ struct Problem {
   std::vector<int64_t> class_off;
   void* d_cwork = nullptr;
   size_t cwork_bytes = 0;
+  // emulated FP64 scattering (RT_SIGMA_OZAKI): residues of the scaled Mhat
+  // for every modulus in the 16-bit GEMM's A layout, the row scales, and the
+  // per-call work (column scales, B and C residues)
+  uint16_t* d_oz_a = nullptr;
+  int* d_oz_ea = nullptr;
+  void* d_ozwork = nullptr;
+  size_t ozwork_bytes = 0;
   Workspace* ws = nullptr;
   int64_t bytes_problem = 0;
   std::vector<double> history;
@@ -231,6 +238,13 @@ void launch_sigma_classes_f64(const Problem& p, const double* L, const double* x
 void launch_sigma_classes_f32(const Problem& p, const float* L, const float* x, float* y,
                               float* work, const double* xscale, double sign, hipStream_t st);
 size_t classes_work_elems(const Problem& p);
+// Emulated FP64 scattering (sigma_ozaki.hip): ozaki_prepare builds the Mhat
+// residues once; launch_sigma_ozaki computes y = xs x + sign (1 - eps) Mhat L
+// with work of ozaki_work_bytes(p) bytes.
+void ozaki_prepare(Problem& p);
+size_t ozaki_work_bytes(const Problem& p);
+void launch_sigma_ozaki(const Problem& p, const double* L, const double* x, double* y,
+                        void* work, const double* xscale, double sign, hipStream_t st);
 // RT_E_INVALID naming `what` when the problem has per-point classes.
 void require_one_kernel(const Problem& p, const char* what);
 // Dense GEMM y = xs x + sign albedo .* (A L) with explicit operands: A

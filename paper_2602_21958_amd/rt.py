@@ -32,7 +32,7 @@ FORMAL = {"linear_sc": 0, "implicit_euler": 1, "quadratic_sc": 2}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 RT_BATCH_BASIS_FP16 = 1
 KRYLOV = {"gmres": 0, "bicgstab": 1}
-SIGMA_FORM = {"dense": 0, "factored": 1}
+SIGMA_FORM = {"dense": 0, "factored": 1, "ozaki": 2}
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_NOT_CONVERGED", -1: "RT_E_INVALID", -2: "RT_E_NOMEM",
                 -3: "RT_E_DEVICE", -4: "RT_E_BREAKDOWN", -5: "RT_E_NONFINITE",
@@ -284,8 +284,9 @@ class Problem:
         return y
 
     def set_sigma(self, form: str):
-        """Scattering form of FP64 / FP32 applications: 'dense' (GEMM) or
-        'factored' (dipole x PRD kernels)."""
+        """Scattering form of FP64 / FP32 applications: 'dense' (GEMM),
+        'factored' (dipole x PRD kernels) or 'ozaki' (FP64 GEMM emulated
+        with exact int8 products)."""
         _check(_lib.rt_problem_set_sigma(self.handle, SIGMA_FORM[form]), "rt_problem_set_sigma")
 
     def rhs(self, b, stream=None):
