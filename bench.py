@@ -94,7 +94,7 @@ def parse():
                     choices=["box32", "batch512", "serve", "box64", "slab64", "apply"])
     ap.add_argument("--problem", default="box64", choices=["box32", "box64", "slab64"],
                     help="apply: the problem whose operator is applied")
-    ap.add_argument("--sigma-form", default="dense", choices=["dense", "factored"],
+    ap.add_argument("--sigma-form", default="dense", choices=["dense", "factored", "ozaki"],
                     help="apply: scattering form of FP64 / FP32 applications")
     ap.add_argument("--precision", default=None,
                     help="operator precision for batch512 / serve / box64")
@@ -671,13 +671,17 @@ def _blas_threads():
 
 
 # ---------------------------------------------------------------- box64
-# (label, operator precision, inner restart, fp16 basis, scattering form):
+# (label, operator precision, inner restart, fp16 basis, scattering form of
+# the FP64 / FP32 applications; the 16-bit inner operators are always the
+# dense GEMM, so "factored" with a 16-bit precision factors only the FP64
+# outer residuals):
 # the default run's box64 leg, then the rest of the variants that
 # --workload box64 times.  An fp16 basis leaves room for GMRES(30) inner
 # cycles; an FP32 GMRES(30) basis would not fit 288 GB beside the FP64
 # vectors, so FP32-basis variants take GMRES(20).
 BOX64_DEFAULT = [("fp16/basis16/m30", "fp16", 30, 1, "dense"),
                  ("bf16/basis16/m30", "bf16", 30, 1, "dense"),
+                 ("fp16/basis16/m30/factored-outer", "fp16", 30, 1, "factored"),
                  ("fp32/factored/m20", "fp32", 20, 0, "factored")]
 BOX64_MORE = [("fp16/m20", "fp16", 20, 0, "dense"), ("bf16/m20", "bf16", 20, 0, "dense"),
               ("bf16x3/m20", "bf16x3", 20, 0, "dense"), ("fp32/m20", "fp32", 20, 0, "dense")]
@@ -823,7 +827,8 @@ def box64_leg(variants, oracle_check=True, procs=12):
     p.set_sigma("dense")
     conv = [(v["s_per_solve"], k) for k, v in res.items() if v["converged"]]
     best = min(conv) if conv else (float("nan"), None)
-    dense = [c for c in conv if res[c[1]]["sigma_form"] == "dense"]
+    dense = [c for c in conv if res[c[1]]["sigma_form"] == "dense" or
+             res[c[1]]["precision"] in ("bf16", "fp16", "bf16x3")]
     best_dense = min(dense) if dense else (float("nan"), None)
     # single applications at full size: FP32 vector -> FP32 Lambda emitting
     # the k4 fp16 operand (4 B read + 2 B written per unknown) -> fp16 Sigma
@@ -861,7 +866,8 @@ def box64_leg(variants, oracle_check=True, procs=12):
                        "refinement to 1e-8",
            "n_unknowns": n, "create_s": t_create,
            "value": 1.0 / best[0], "unit": "solves/s", "best_variant": best[1],
-           "best_dense_variant": best_dense[1], "best_dense_solves_per_s": 1.0 / best_dense[0],
+           "best_dense_inner_variant": best_dense[1],
+           "best_dense_inner_solves_per_s": 1.0 / best_dense[0],
            "variants": res, "kernels_single_apply": kern,
            "roofline": kern["fp16"]["sigma16"], "lambda": kern["fp16"]["lambda_k4"]}
     if oracle_check and x_check is not None:
