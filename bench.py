@@ -673,13 +673,14 @@ def _blas_threads():
 # ---------------------------------------------------------------- box64
 # (label, operator precision, inner restart, fp16 basis, scattering form of
 # the FP64 / FP32 applications; the 16-bit inner operators are always the
-# dense GEMM, so "factored" with a 16-bit precision factors only the FP64
-# outer residuals):
+# dense GEMM, so "factored" or "ozaki" (the FP64 GEMM emulated with int8
+# products) with a 16-bit precision changes only the FP64 outer residuals):
 # the default run's box64 leg, then the rest of the variants that
 # --workload box64 times.  An fp16 basis leaves room for GMRES(30) inner
 # cycles; an FP32 GMRES(30) basis would not fit 288 GB beside the FP64
 # vectors, so FP32-basis variants take GMRES(20).
 BOX64_DEFAULT = [("fp16/basis16/m30", "fp16", 30, 1, "dense"),
+                 ("fp16/basis16/m30/ozaki-outer", "fp16", 30, 1, "ozaki"),
                  ("bf16/basis16/m30", "bf16", 30, 1, "dense"),
                  ("fp16/basis16/m30/factored-outer", "fp16", 30, 1, "factored"),
                  ("fp32/factored/m20", "fp32", 20, 0, "factored")]
@@ -817,10 +818,18 @@ def box64_leg(variants, oracle_check=True, procs=12):
                       "kernel_launches": {k: v["launches"] for k, v in prof.items()},
                       "sigma16_tile": p.gemm16_tile(prec) if prec in ("bf16", "fp16", "bf16x3")
                       else None}
-        if form == "dense" and sig64["launches"]:
+        if form in ("dense", "ozaki") and sig64["launches"]:
+            # FP64 outer residuals: the MFMA GEMM, or its int8 emulation
+            # priced at the dense GEMM's flops
             a = sig64["total_ms"] / sig64["launches"]
-            res[label]["outer_sigma_fp64"] = {"avg_ms": a, "TFLOP/s": flops / a / 1e9,
-                                              "frac_of_78.6TF": flops / a / 1e9 / PEAK_FP64_TFLOPS}
+            if form == "dense":
+                res[label]["outer_sigma_fp64"] = {
+                    "avg_ms": a, "TFLOP/s": flops / a / 1e9,
+                    "frac_of_78.6TF": flops / a / 1e9 / PEAK_FP64_TFLOPS}
+            else:
+                res[label]["outer_sigma_fp64"] = {
+                    "avg_ms": a, "kernel": "int8 emulation (15 int8 GEMMs + CRT)",
+                    "TFLOP/s_dense_equivalent": flops / a / 1e9}
         print(json.dumps({"box64_variant": label, **res[label]}), file=sys.stderr, flush=True)
         if x_check is None and st["converged"]:
             x_check = (label, x.cpu().numpy())

@@ -145,7 +145,9 @@ typedef struct {
   int64_t n_points;       /* nx * ny * nz                                          */
   int64_t bytes_problem;  /* device bytes held by the problem itself               */
   int64_t bytes_solve_fp64;  /* extra device bytes of an FP64 GMRES(restart) solve
-                                with the restart passed to rt_problem_footprint   */
+                                with the restart passed to rt_problem_footprint,
+                                including the work buffer of the problem's
+                                current scattering form (rt_problem_set_sigma) */
   int64_t bytes_solve_mixed; /* same for a mixed-precision (FP32 basis) solve      */
   int32_t sigma_rank;     /* angular rank of the factored scattering form (6 for
                              the 3D dipole, 2 for the slab's azimuth average; 0:

@@ -664,10 +664,16 @@ rt_status rt_problem_footprint(rt_problem p, int restart, rt_problem_info* info)
     info->n_rays = q->n_r;
     info->n_points = q->n_s;
     info->bytes_problem = q->bytes_problem;
+    // the scattering form's work buffer, allocated by the first FP64 (or
+    // FP32 factored) application of a solve
+    int64_t form_work = 0;
+    if (q->sigma_form == RT_SIGMA_OZAKI) form_work = (int64_t)ozaki_work_bytes(*q);
+    if (q->sigma_form == RT_SIGMA_FACTORED)
+      form_work = (int64_t)(factored_work_elems(*q) * sizeof(double));
     info->bytes_solve_fp64 = (int64_t)workspace_bytes(*q, restart, false, false) +
-                             (int64_t)(q->n * sizeof(double));
+                             (int64_t)(q->n * sizeof(double)) + form_work;
     info->bytes_solve_mixed = (int64_t)workspace_bytes(*q, restart, true, false) +
-                              (int64_t)(q->n * sizeof(double));
+                              (int64_t)(q->n * sizeof(double)) + form_work;
     info->sigma_rank = q->n_classes > 1 ? 0 : q->tab.frank;
     info->sigma_form = q->sigma_form;
   });
@@ -766,10 +772,21 @@ rt_status rt_problem_set_sigma(rt_problem p, int form) {
       if (!factored_fits(*q, sizeof(double)))
         fail(RT_E_INVALID, "too many frequencies for the factored scattering form");
     }
-    // the physical right-hand side is rebuilt in the new form
+    // the physical right-hand side is rebuilt in the new form; the other
+    // forms' work buffers are released
     RT_HIP(hipDeviceSynchronize());
     hipFree(q->d_rhs);
     q->d_rhs = nullptr;
+    if (form != RT_SIGMA_OZAKI && q->d_ozwork) {
+      hipFree(q->d_ozwork);
+      q->d_ozwork = nullptr;
+      q->ozwork_bytes = 0;
+    }
+    if (form != RT_SIGMA_FACTORED && q->d_fwork) {
+      hipFree(q->d_fwork);
+      q->d_fwork = nullptr;
+      q->fwork_bytes = 0;
+    }
     q->sigma_form = form;
   });
 }

@@ -41,7 +41,8 @@ constexpr int kBits = 51;
 
 typedef unsigned __int128 u128;
 
-// m_j^-1 mod m_l (j < l) for Garner's mixed-radix reconstruction
+// Tables of Garner's mixed-radix reconstruction, with P_l = m_0 ... m_{l-1}:
+// pmod[j][l] = P_j mod m_l (j < l) and pinv[l] = P_l^-1 mod m_l.
 constexpr int inv_mod(int a, int m) {
   a %= m;
   for (int t = 1; t < m; ++t)
@@ -49,10 +50,17 @@ constexpr int inv_mod(int a, int m) {
   return 0;
 }
 struct GarnerTable {
-  int inv[kMods][kMods];
-  constexpr GarnerTable() : inv{} {
-    for (int l = 0; l < kMods; ++l)
-      for (int j = 0; j < l; ++j) inv[j][l] = inv_mod(kMod[j], kMod[l]);
+  int pmod[kMods][kMods];
+  int pinv[kMods];
+  constexpr GarnerTable() : pmod{}, pinv{} {
+    for (int l = 0; l < kMods; ++l) {
+      int pl = 1 % kMod[l];                      // P_j mod m_l, j = 0, 1, ...
+      for (int j = 0; j < l; ++j) {
+        pmod[j][l] = pl;
+        pl = (pl * kMod[j]) % kMod[l];
+      }
+      pinv[l] = inv_mod(pl, kMod[l]);
+    }
   }
 };
 constexpr GarnerTable kGarner{};
@@ -74,14 +82,20 @@ __host__ __device__ __forceinline__ int sres(int64_t v, int m) {
   return r >= 128 ? r - m : r;
 }
 
-// The same for |v| < 2^52 in 32-bit arithmetic: v = hi 2^26 + lo with
-// 0 <= lo < 2^26, so v mod m = ((hi mod m) (2^26 mod m) + lo mod m) mod m.
+// The same for |v| <= 2^51 in 32-bit arithmetic: v = h 2^34 + c 2^17 + l with
+// 0 <= c, l < 2^17 and |h| <= 2^17, so v = h (2^34 mod m) + c (2^17 mod m) + l
+// (mod m), a sum below 2^26 in magnitude made non-negative by adding 2^18 m.
+struct Limbs {
+  int h, c, l;
+};
+__device__ __forceinline__ Limbs limbs_of(int64_t v) {
+  return Limbs{(int)(v >> 34), (int)((v >> 17) & 0x1ffff), (int)(v & 0x1ffff)};
+}
 template <int M>
-__device__ __forceinline__ int sres_split(int hi, int lo) {
-  constexpr int c = (1 << 26) % M;
-  int h = hi % M;
-  h += h < 0 ? M : 0;
-  int r = (h * c + lo % M) % M;
+__device__ __forceinline__ int sres_limbs(Limbs v) {
+  constexpr int c2 = (int)((1LL << 34) % M), c1 = (1 << 17) % M;
+  const uint32_t s = (uint32_t)(v.h * c2 + v.c * c1 + v.l + (M << 18));
+  const int r = (int)(s % (uint32_t)M);
   return r >= 128 ? r - M : r;
 }
 
@@ -117,18 +131,17 @@ __device__ __forceinline__ int col_shift(int pe) { return pe == kNoExp ? 0 : kBi
 // B'_l residues in the k4-virtual int8 layout: byte ((k / 8) Np + i) 8 + k % 8
 // of part l.  One thread per (group of 8 k, point i).
 template <int L0>
-__device__ __forceinline__ void store_residues(uint8_t* dst, int64_t part, const int (&hi)[8],
-                                               const int (&lo)[8]) {
+__device__ __forceinline__ void store_residues(uint8_t* dst, int64_t part, const Limbs (&b)[8]) {
   if constexpr (L0 < kMods) {
     constexpr int M = kMod[L0];
     uint32_t w0 = 0, w1 = 0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      w0 |= (uint32_t)(uint8_t)(int8_t)sres_split<M>(hi[kk], lo[kk]) << (8 * kk);
-      w1 |= (uint32_t)(uint8_t)(int8_t)sres_split<M>(hi[kk + 4], lo[kk + 4]) << (8 * kk);
+      w0 |= (uint32_t)(uint8_t)(int8_t)sres_limbs<M>(b[kk]) << (8 * kk);
+      w1 |= (uint32_t)(uint8_t)(int8_t)sres_limbs<M>(b[kk + 4]) << (8 * kk);
     }
     *reinterpret_cast<uint2*>(dst + (int64_t)L0 * part) = make_uint2(w0, w1);
-    store_residues<L0 + 1>(dst, part, hi, lo);
+    store_residues<L0 + 1>(dst, part, b);
   }
 }
 
@@ -142,59 +155,89 @@ __global__ __launch_bounds__(256) void oz_split_b(const double* __restrict__ L,
     const int g = (int)(e / n_s);
     const int64_t i = e - (int64_t)g * n_s;
     const int f = col_shift(pe[i]);
-    int hi[8], lo[8];
+    Limbs b[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       const int k = 8 * g + kk;
       const double v = k < n_r ? L[(int64_t)k * n_s + i] : 0.0;
-      const int64_t b = (int64_t)rint(ldexp(v, f));   // |b| <= 2^51
-      hi[kk] = (int)(b >> 26);                        // arithmetic shift: floor
-      lo[kk] = (int)(b & ((1 << 26) - 1));
+      b[kk] = limbs_of((int64_t)rint(ldexp(v, f)));   // |b| <= 2^51
     }
-    store_residues<0>(Bres + ((int64_t)g * Np + i) * 8, part, hi, lo);
+    store_residues<0>(Bres + ((int64_t)g * Np + i) * 8, part, b);
   }
 }
 
-// y = xs x + sign (1 - eps_i) 2^-(ea_k + fb_i) CRT(c_0 .. c_14), one thread per
-// element of the ray-major output.  Garner's algorithm: mixed-radix digits
-// v_l in [0, m_l) with A' B' mod M = v_0 + m_0 (v_1 + m_1 (v_2 + ...)), every
-// step in small integers, then the value by Horner in 128 bits (below M); the
-// centred representative (above M / 2 means negative) is A' B' itself.
+// y = xs x + sign (1 - eps_i) 2^-(ea_k + fb_i) CRT(c_0 .. c_14) for V
+// consecutive elements of one ray row per thread.  Garner's algorithm gives
+// mixed-radix digits v_l in [0, m_l) with A' B' mod M = sum_l v_l P_l:
+//   v_l = (c_l - sum_{j<l} v_j (P_j mod m_l)) P_l^-1 mod m_l,
+// the inner sum in plain 32-bit integers (below 2^20) and one reduction per
+// digit.  The value is then assembled as X_lo + P_8 X_hi from two 64-bit
+// Horner sums over digits 0..7 and 8..14; the centred representative (above
+// M / 2 means negative) is A' B' itself.
+template <int V>
+__device__ __forceinline__ void garner_digits(const uint8_t* __restrict__ Cres, int64_t part,
+                                              int64_t e, uint32_t (&v)[kMods][V]) {
+#pragma unroll
+  for (int l = 0; l < kMods; ++l) {
+    uint32_t c[V];
+    if constexpr (V == 4) {
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(Cres + (int64_t)l * part + e);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = (w >> (8 * u)) & 0xffu;
+    } else {
+      c[0] = Cres[(int64_t)l * part + e];
+    }
+    constexpr uint32_t bias = 8192u;   // 8192 m_l > 14 * 255^2 >= the inner sum
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int j = 0; j < l; ++j) sum += v[j][u] * (uint32_t)kGarner.pmod[j][l];
+      const uint32_t t = c[u] + bias * (uint32_t)kMod[l] - sum;
+      v[l][u] = (t * (uint32_t)kGarner.pinv[l]) % (uint32_t)kMod[l];
+    }
+  }
+}
+
+__device__ __forceinline__ double crt_value(const uint32_t (&d)[kMods], Crt c, uint64_t p8) {
+  uint64_t lo = d[7], hi = d[kMods - 1];
+#pragma unroll
+  for (int l = 6; l >= 0; --l) lo = lo * (uint64_t)kMod[l] + d[l];
+#pragma unroll
+  for (int l = kMods - 2; l >= 8; --l) hi = hi * (uint64_t)kMod[l] + d[l];
+  const u128 M = ((u128)c.m_hi << 64) | c.m_lo;
+  const u128 r = (u128)hi * p8 + lo;
+  const bool neg = r > (M >> 1);
+  const u128 mag = neg ? M - r : r;
+  const double val = ldexp((double)(uint64_t)(mag >> 64), 64) + (double)(uint64_t)mag;
+  return neg ? -val : val;
+}
+
+template <int V>
 __global__ __launch_bounds__(256) void oz_crt(const uint8_t* __restrict__ Cres, int64_t part,
                                               const int* __restrict__ ea,
                                               const int* __restrict__ fb,
                                               const double* __restrict__ albedo, const double* x,
                                               double* y, const double* __restrict__ xscale,
-                                              double sign, int n_r, int64_t n_s, Crt c) {
-  const int64_t n = (int64_t)n_r * n_s;
+                                              double sign, int64_t n_s, Crt c, uint64_t p8) {
+  const int64_t nv = part / V;
   const double xs = (x != nullptr && xscale != nullptr) ? *xscale : 1.0;
-  const u128 M = ((u128)c.m_hi << 64) | c.m_lo;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int v[kMods];
-#pragma unroll
-    for (int l = 0; l < kMods; ++l) {
-      int t = Cres[(int64_t)l * part + e];
-#pragma unroll
-      for (int j = 0; j < l; ++j) {
-        t -= v[j] % kMod[l];
-        t += t < 0 ? kMod[l] : 0;
-        t = (t * kGarner.inv[j][l]) % kMod[l];
-      }
-      v[l] = t;
-    }
-    u128 r = (u128)v[kMods - 1];
-#pragma unroll
-    for (int l = kMods - 2; l >= 0; --l) r = r * (u128)kMod[l] + (u128)v[l];
-    const bool neg = r > (M >> 1);
-    const u128 mag = neg ? M - r : r;
-    double val = ldexp((double)(uint64_t)(mag >> 64), 64) + (double)(uint64_t)mag;
-    if (neg) val = -val;
+  for (int64_t ev = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ev < nv;
+       ev += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = ev * V;
+    uint32_t v[kMods][V];
+    garner_digits<V>(Cres, part, e, v);
     const int k = (int)(e / n_s);
-    const int64_t i = e - (int64_t)k * n_s;
-    val = ldexp(val, -(ea[k] + col_shift(fb[i])));
-    const double t = sign * albedo[i] * val;
-    y[e] = x ? xs * x[e] + t : t;
+    const int64_t i = e - (int64_t)k * n_s;    // V points of ray k
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      uint32_t d[kMods];
+#pragma unroll
+      for (int l = 0; l < kMods; ++l) d[l] = v[l][u];
+      const double val = ldexp(crt_value(d, c, p8), -(ea[k] + col_shift(fb[i + u])));
+      const double t = sign * albedo[i + u] * val;
+      y[e + u] = x ? xs * x[e + u] + t : t;
+    }
   }
 }
 
@@ -293,8 +336,17 @@ void launch_sigma_ozaki(const Problem& p, const double* L, const double* x, doub
                        p.d_oz_a + l * apart, p.mp16,
                        reinterpret_cast<const uint16_t*>(Bres + l * bpart), (int)Np, Kv / 4,
                        Cres + l * cpart, n_r, (int)n_s, kMod[l]);
-  hipLaunchKernelGGL(oz_crt, dim3(grid_of(cpart)), dim3(256), 0, st, Cres, cpart, p.d_oz_ea, fb,
-                     p.d_albedo, x, y, xscale, sign, n_r, n_s, crt);
+  static const uint64_t p8 = [] {
+    uint64_t q = 1;
+    for (int l = 0; l < 8; ++l) q *= (uint64_t)kMod[l];
+    return q;
+  }();
+  if (n_s % 4 == 0)
+    hipLaunchKernelGGL((oz_crt<4>), dim3(grid_of(cpart / 4)), dim3(256), 0, st, Cres, cpart,
+                       p.d_oz_ea, fb, p.d_albedo, x, y, xscale, sign, n_s, crt, p8);
+  else
+    hipLaunchKernelGGL((oz_crt<1>), dim3(grid_of(cpart)), dim3(256), 0, st, Cres, cpart,
+                       p.d_oz_ea, fb, p.d_albedo, x, y, xscale, sign, n_s, crt, p8);
   RT_HIP(hipGetLastError());
 }
 
