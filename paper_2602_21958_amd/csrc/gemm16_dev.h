@@ -98,11 +98,12 @@ template <> struct MmaI8<true> {
 };
 
 // Tile configuration: BM x BN output tile, WGM x WGN waves, K stage BK,
-// BIG = 32x32x16 instructions (else 16x16x32).
-template <int BM_, int BN_, int WGM_, int WGN_, int BK_, bool BIG_>
+// BIG = 32x32x16 instructions (else 16x16x32), PP = ping-pong schedule
+// (tile_pp; eight waves in two groups).
+template <int BM_, int BN_, int WGM_, int WGN_, int BK_, bool BIG_, bool PP_ = false>
 struct Cfg {
   static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_, BK = BK_;
-  static constexpr bool BIG = BIG_;
+  static constexpr bool BIG = BIG_, PP = PP_;
   static constexpr int NW = WGM * WGN, NT = 64 * NW;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
   static constexpr int MI = BIG ? 32 : 16;           // instruction tile
@@ -121,6 +122,136 @@ struct Cfg {
     return 2 * (MODE == MODE_SPLIT ? 2 : 1) * (ASB + BSB);
   }
 };
+
+// Global loads of one K stage (k4 groups kg4 .. kg4 + BK/4 - 1) into
+// registers: wave w loads the 1 KB blocks w, w + NW, ... of A and of B.
+template <typename C, int NP>
+__device__ __forceinline__ void stage_gload(u32x4_t (&ra)[NP][C::AU], u32x4_t (&rb)[NP][C::BU],
+                                            const uint16_t* const (&Ap)[2],
+                                            const uint16_t* const (&Bp)[2], int Mp, int Np,
+                                            int m0, int n0, int kg4, int wave, int lane) {
+  const int kg8 = kg4 >> 1;
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+#pragma unroll
+    for (int u = 0; u < C::AU; ++u) {
+      const int b = wave + C::NW * u;
+      const int g8 = b / C::RB, rbk = b % C::RB;
+      ra[s][u] = *reinterpret_cast<const u32x4_t*>(
+          Ap[s] + ((size_t)(kg8 + g8) * Mp + m0 + rbk * 64 + lane) * 8);
+    }
+#pragma unroll
+    for (int u = 0; u < C::BU; ++u) {
+      const int b = wave + C::NW * u;
+      const int g4 = b / C::HB, hb = b % C::HB;
+      rb[s][u] = *reinterpret_cast<const u32x4_t*>(
+          Bp[s] + ((size_t)(kg4 + g4) * Np + n0 + hb * 128 + 2 * lane) * 4);
+    }
+  }
+}
+
+// The same blocks stored into one LDS stage buffer (parts hi, lo one after
+// the other); the two k4 groups of a B block row sit one LDS block apart.
+template <typename C, int NP>
+__device__ __forceinline__ void stage_lstore(const u32x4_t (&ra)[NP][C::AU],
+                                             const u32x4_t (&rb)[NP][C::BU], uint8_t* st_lds,
+                                             int wave, int lane) {
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    uint8_t* As = st_lds + s * (C::ASB + C::BSB);
+    uint8_t* Bs = As + C::ASB;
+#pragma unroll
+    for (int u = 0; u < C::AU; ++u) {
+      const int b = wave + C::NW * u;
+      *reinterpret_cast<u32x4_t*>(As + b * C::BLKA + 16 * lane) = ra[s][u];
+    }
+#pragma unroll
+    for (int u = 0; u < C::BU; ++u) {
+      const int b = wave + C::NW * u;
+      const int g4 = b / C::HB, hb = b % C::HB;
+      *reinterpret_cast<u32x4_t*>(
+          Bs + ((g4 >> 1) * 2 * C::HB + hb * 2 + (g4 & 1)) * C::BLKB + 16 * lane) = rb[s][u];
+    }
+  }
+}
+
+// Operand fragments of instruction step h of a stage for wave (wm, wn):
+// lane roles 16x16x32 -> 4 groups of 16 lanes (k8 chunk kgrp, row/col rc);
+// 32x32x16 -> 2 groups of 32 lanes.
+template <typename C, int NP>
+__device__ __forceinline__ void stage_frags(const uint8_t* st_lds, int h, int kgrp, int rc, int wm,
+                                            int wn, u32x4_t (&bf)[NP][C::TJ],
+                                            u32x4_t (&af)[NP][C::TI]) {
+  constexpr int KCH = (C::BIG ? 16 : 32) / 8;    // k8 chunks per instruction
+  const int c8 = KCH * h + kgrp;                 // k8 chunk of this lane within the stage
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    const uint8_t* As = st_lds + s * (C::ASB + C::BSB);
+    const uint8_t* Bs = As + C::ASB;
+#pragma unroll
+    for (int j = 0; j < C::TJ; ++j) {
+      const int n = wn * C::WN + C::MI * j + rc;
+      const uint8_t* p0 = Bs + (c8 * 2 * C::HB + (n >> 7) * 2) * C::BLKB + (n & 127) * 8;
+      const uint2 lo = *reinterpret_cast<const uint2*>(p0);
+      const uint2 hi = *reinterpret_cast<const uint2*>(p0 + C::BLKB);
+      bf[s][j] = u32x4_t{lo.x, lo.y, hi.x, hi.y};
+    }
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i) {
+      const int m = wm * C::WM + C::MI * i + rc;
+      af[s][i] = *reinterpret_cast<const u32x4_t*>(As + (c8 * C::RB + (m >> 6)) * C::BLKA +
+                                                  (m & 63) * 16);
+    }
+  }
+}
+
+// Epilogue of one wave's WM x WN part of an output tile.  Float modes:
+// Y = ymul (xs X + sign albedo[col] colmul rowscale[row] acc), with the stored
+// values left in acc (zero outside M x N) for fused dots.  MODE_I8: the exact
+// integer products reduced to [0, imod), stored as bytes.
+template <int MODE, typename C, typename TY, typename ACC>
+__device__ __forceinline__ void write_tile(ACC (&acc)[C::TI][C::TJ], int lane, int wm, int wn,
+                                           const TY* X, TY* Y,
+                                           const double* __restrict__ albedo,
+                                           const float* __restrict__ rowscale, float colmul,
+                                           float xs, float sign, int M, int N, int m0, int n0,
+                                           float ymul, int imod) {
+  constexpr int NR = C::BIG ? 16 : 4;
+  const int kgrp = C::BIG ? (lane >> 5) : (lane >> 4);
+  const int rc = C::BIG ? (lane & 31) : (lane & 15);
+#pragma unroll
+  for (int j = 0; j < C::TJ; ++j) {
+    const int col = n0 + wn * C::WN + C::MI * j + rc;
+    float cf = 0.f;
+    if constexpr (MODE != MODE_I8) cf = col < N ? sign * (float)albedo[col] * colmul : 0.f;
+#pragma unroll
+    for (int i = 0; i < C::TI; ++i) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int row = m0 + wm * C::WM + C::MI * i +
+                        (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
+        if constexpr (MODE == MODE_I8) {
+          if (row < M && col < N) {
+            int v = acc[i][j][r] % imod;
+            v += v < 0 ? imod : 0;
+            Y[(size_t)row * N + col] = (TY)v;
+          }
+        } else {
+          if (row < M && col < N) {
+            const size_t idx = (size_t)row * N + col;
+            float v = cf * (rowscale ? rowscale[row] : 1.f) * acc[i][j][r];
+            if (X != nullptr) v += xs * (float)X[idx];
+            const TY t = (TY)(ymul * v);
+            Y[idx] = t;
+            acc[i][j][r] = (float)t;
+          } else {
+            acc[i][j][r] = 0.f;
+          }
+        }
+      }
+    }
+  }
+}
 
 // One output tile at (m0, n0).  lds: Cfg::lds_bytes<MODE>() bytes, 16-byte
 // aligned.  Caller guarantees m0 + BM <= Mp, n0 + BN <= Np, K4p % (BK/4) == 0.
@@ -150,48 +281,12 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
   const int wm = wave / C::WGN, wn = wave % C::WGN;
 
   u32x4_t ra[NP][C::AU], rb[NP][C::BU];
-  const uint16_t* Ap[2] = {Ahi, Alo};
-  const uint16_t* Bp[2] = {Bhi, Blo};
-
+  const uint16_t* const Ap[2] = {Ahi, Alo};
+  const uint16_t* const Bp[2] = {Bhi, Blo};
   auto gload = [&](int kg4) {
-    const int kg8 = kg4 >> 1;
-#pragma unroll
-    for (int s = 0; s < NP; ++s) {
-#pragma unroll
-      for (int u = 0; u < C::AU; ++u) {
-        const int b = wave + C::NW * u;
-        const int g8 = b / C::RB, rbk = b % C::RB;
-        ra[s][u] = *reinterpret_cast<const u32x4_t*>(
-            Ap[s] + ((size_t)(kg8 + g8) * Mp + m0 + rbk * 64 + lane) * 8);
-      }
-#pragma unroll
-      for (int u = 0; u < C::BU; ++u) {
-        const int b = wave + C::NW * u;
-        const int g4 = b / C::HB, hb = b % C::HB;
-        rb[s][u] = *reinterpret_cast<const u32x4_t*>(
-            Bp[s] + ((size_t)(kg4 + g4) * Np + n0 + hb * 128 + 2 * lane) * 4);
-      }
-    }
+    stage_gload<C, NP>(ra, rb, Ap, Bp, Mp, Np, m0, n0, kg4, wave, lane);
   };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int s = 0; s < NP; ++s) {
-      uint8_t* As = lds + buf * STAGE + s * (C::ASB + C::BSB);
-      uint8_t* Bs = As + C::ASB;
-#pragma unroll
-      for (int u = 0; u < C::AU; ++u) {
-        const int b = wave + C::NW * u;
-        *reinterpret_cast<u32x4_t*>(As + b * C::BLKA + 16 * lane) = ra[s][u];
-      }
-#pragma unroll
-      for (int u = 0; u < C::BU; ++u) {
-        const int b = wave + C::NW * u;
-        const int g4 = b / C::HB, hb = b % C::HB;
-        *reinterpret_cast<u32x4_t*>(
-            Bs + ((g4 >> 1) * 2 * C::HB + hb * 2 + (g4 & 1)) * C::BLKB + 16 * lane) = rb[s][u];
-      }
-    }
-  };
+  auto lstore = [&](int buf) { stage_lstore<C, NP>(ra, rb, lds + buf * STAGE, wave, lane); };
 
   acc_t acc[C::TI][C::TJ];
 #pragma unroll
@@ -201,12 +296,9 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
 #pragma unroll
       for (int r = 0; r < NR; ++r) acc[i][j][r] = 0;
 
-  // lane roles: 16x16x32 -> 4 groups of 16 lanes (k8 chunk q, row/col r16);
-  // 32x32x16 -> 2 groups of 32 lanes (k8 chunk p, row/col r32)
   const int kgrp = C::BIG ? (lane >> 5) : (lane >> 4);
   const int rc = C::BIG ? (lane & 31) : (lane & 15);
   constexpr int KSTEP = C::BIG ? 16 : 32;      // k per instruction
-  constexpr int KCH = KSTEP / 8;               // k8 chunks per instruction
 
   const int nst = K4p / (C::BK / 4);
   __syncthreads();   // lds may still be read by a previous tile of this workgroup
@@ -223,26 +315,7 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
     constexpr int H = C::BK / KSTEP;
     u32x4_t bfr[2][NP][C::TJ], afr[2][NP][C::TI];
     auto read_frags = [&](int h, u32x4_t (&bf)[NP][C::TJ], u32x4_t (&af)[NP][C::TI]) {
-      const int c8 = KCH * h + kgrp;             // k8 chunk of this lane within the stage
-#pragma unroll
-      for (int s = 0; s < NP; ++s) {
-        const uint8_t* As = lds + buf * STAGE + s * (C::ASB + C::BSB);
-        const uint8_t* Bs = As + C::ASB;
-#pragma unroll
-        for (int j = 0; j < C::TJ; ++j) {
-          const int n = wn * C::WN + C::MI * j + rc;
-          const uint8_t* p0 = Bs + (c8 * 2 * C::HB + (n >> 7) * 2) * C::BLKB + (n & 127) * 8;
-          const uint2 lo = *reinterpret_cast<const uint2*>(p0);
-          const uint2 hi = *reinterpret_cast<const uint2*>(p0 + C::BLKB);
-          bf[s][j] = u32x4_t{lo.x, lo.y, hi.x, hi.y};
-        }
-#pragma unroll
-        for (int i = 0; i < C::TI; ++i) {
-          const int m = wm * C::WM + C::MI * i + rc;
-          af[s][i] = *reinterpret_cast<const u32x4_t*>(As + (c8 * C::RB + (m >> 6)) * C::BLKA +
-                                                      (m & 63) * 16);
-        }
-      }
+      stage_frags<C, NP>(lds + buf * STAGE, h, kgrp, rc, wm, wn, bf, af);
     };
     read_frags(0, bfr[0], afr[0]);
 #pragma unroll
@@ -267,51 +340,9 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
     __syncthreads();
   }
 
-  if constexpr (MODE == MODE_I8) {
-    // residues of the exact integer products
-#pragma unroll
-    for (int j = 0; j < C::TJ; ++j) {
-      const int col = n0 + wn * C::WN + C::MI * j + rc;
-#pragma unroll
-      for (int i = 0; i < C::TI; ++i) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const int row = m0 + wm * C::WM + C::MI * i +
-                          (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
-          if (row < M && col < N) {
-            int v = acc[i][j][r] % imod;
-            v += v < 0 ? imod : 0;
-            Y[(size_t)row * N + col] = (TY)v;
-          }
-        }
-      }
-    }
-    return;
-  } else {
-  // epilogue (the final values stay in acc for the fused dots; zero outside)
-#pragma unroll
-  for (int j = 0; j < C::TJ; ++j) {
-    const int col = n0 + wn * C::WN + C::MI * j + rc;
-    const float cf = col < N ? sign * (float)albedo[col] * colmul : 0.f;
-#pragma unroll
-    for (int i = 0; i < C::TI; ++i) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int row = m0 + wm * C::WM + C::MI * i +
-                        (C::BIG ? 8 * (r >> 2) + 4 * kgrp + (r & 3) : 4 * kgrp + r);
-        if (row < M && col < N) {
-          const size_t idx = (size_t)row * N + col;
-          float v = cf * (rowscale ? rowscale[row] : 1.f) * acc[i][j][r];
-          if (X != nullptr) v += xs * (float)X[idx];
-          const TY t = (TY)(ymul * v);
-          Y[idx] = t;
-          acc[i][j][r] = (float)t;
-        } else {
-          acc[i][j][r] = 0.f;
-        }
-      }
-    }
-  }
+  write_tile<MODE, C, TY>(acc, lane, wm, wn, X, Y, albedo, rowscale, colmul, xs, sign, M, N, m0,
+                          n0, ymul, imod);
+  if constexpr (MODE != MODE_I8) {
   if constexpr (DOTS) {
     // LDS is free: the K loop ended with a barrier after its last reads
     double* red = reinterpret_cast<double*>(lds);
@@ -346,6 +377,107 @@ __device__ __forceinline__ void tile(const uint16_t* __restrict__ Ahi,
     }
   }
   }
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight.  The scheduling fences keep every instruction on
+// its side of the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// The tile of `tile` (same operands, layouts, epilogue and k order per
+// output) with a ping-pong schedule for eight waves, two per SIMD.  Waves
+// 0-3 (rows 0 .. BM/2 - 1) and 4-7 (the other half) form two groups that
+// run the same K loop one phase apart, every phase ended by a workgroup
+// barrier, so that on each SIMD one wave issues only matrix instructions on
+// fragments already in its registers while the other moves data:
+//   M(s): read all fragments of stage s from LDS buffer s & 1; store the
+//         registers loaded in M(s - 2) (this wave's share of stage s + 1)
+//         into buffer (s + 1) & 1; load its share of stage s + 3 from global
+//         memory into those registers;
+//   C(s): the MFMAs of stage s, at raised wave priority.
+// Group 0 runs M(s) in phase 2s and C(s) in phase 2s + 1, group 1 one phase
+// later.  Stage s + 1 is written in phases 2s and 2s + 1 (half by each
+// group) and first read in phase 2s + 2; buffer s & 1 is read in phases 2s
+// and 2s + 1 and rewritten from phase 2s + 2 on.  Not for the split mode or
+// fused dots.
+template <int MODE, typename C, typename TY = float>
+__device__ __forceinline__ void tile_pp(const uint16_t* __restrict__ A, int Mp,
+                                        const uint16_t* __restrict__ B, int Np, int K4p,
+                                        const TY* X, TY* Y, const double* __restrict__ albedo,
+                                        const float* __restrict__ rowscale, float colmul,
+                                        float xs, float sign, int M, int N, int m0, int n0,
+                                        uint8_t* lds, float ymul = 1.f, int imod = 0) {
+  static_assert(C::PP && C::NW == 8 && C::WGM == 2 && MODE != MODE_SPLIT,
+                "ping-pong: two groups of four waves, one per row half");
+  using MM = typename std::conditional<MODE == MODE_I8, MmaI8<C::BIG>,
+                                       Mma<MODE != MODE_FP16, C::BIG>>::type;
+  using acc_t = typename MM::acc_t;
+  constexpr int NR = C::BIG ? 16 : 4;
+  constexpr int STAGE = C::ASB + C::BSB;
+  constexpr int KSTEP = C::BIG ? 16 : 32;
+  constexpr int H = C::BK / KSTEP;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave / C::WGN, wn = wave % C::WGN;
+  const int grp = wm;
+  const int kgrp = C::BIG ? (lane >> 5) : (lane >> 4);
+  const int rc = C::BIG ? (lane & 31) : (lane & 15);
+  const uint16_t* const Ap[2] = {A, nullptr};
+  const uint16_t* const Bp[2] = {B, nullptr};
+
+  // two register sets for the global loads: the set stored in M(s) holds
+  // stage s + 1 and is reloaded with stage s + 3, so loads have two phase
+  // pairs to arrive
+  u32x4_t ra[2][1][C::AU], rb[2][1][C::BU];
+  u32x4_t af[H][1][C::TI], bf[H][1][C::TJ];
+  acc_t acc[C::TI][C::TJ];
+#pragma unroll
+  for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TJ; ++j)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[i][j][r] = 0;
+
+  const int nst = K4p / (C::BK / 4);
+  constexpr int KG = C::BK / 4;
+  lds_barrier();   // lds may still be read by a previous tile of this workgroup
+  stage_gload<C, 1>(ra[0], rb[0], Ap, Bp, Mp, Np, m0, n0, 0, wave, lane);
+  stage_lstore<C, 1>(ra[0], rb[0], lds, wave, lane);
+  if (nst > 1) stage_gload<C, 1>(ra[0], rb[0], Ap, Bp, Mp, Np, m0, n0, KG, wave, lane);
+  if (nst > 2) stage_gload<C, 1>(ra[1], rb[1], Ap, Bp, Mp, Np, m0, n0, 2 * KG, wave, lane);
+  lds_barrier();
+  if (grp == 1) lds_barrier();
+  auto stage = [&](int s, u32x4_t (&rA)[1][C::AU], u32x4_t (&rB)[1][C::BU]) {
+    const uint8_t* cur = lds + (s & 1) * STAGE;
+#pragma unroll
+    for (int h = 0; h < H; ++h) stage_frags<C, 1>(cur, h, kgrp, rc, wm, wn, bf[h], af[h]);
+    if (s + 1 < nst) stage_lstore<C, 1>(rA, rB, lds + ((s + 1) & 1) * STAGE, wave, lane);
+    if (s + 3 < nst) stage_gload<C, 1>(rA, rB, Ap, Bp, Mp, Np, m0, n0, (s + 3) * KG, wave, lane);
+    lds_barrier();
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < C::TI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TJ; ++j) acc[i][j] = MM::run(af[h][0][i], bf[h][0][j], acc[i][j]);
+    __builtin_amdgcn_s_setprio(0);
+    lds_barrier();
+  };
+  for (int s = 0; s < nst; s += 2) {
+    stage(s, ra[0], rb[0]);
+    if (s + 1 < nst) stage(s + 1, ra[1], rb[1]);
+  }
+  if (grp == 0) lds_barrier();
+  write_tile<MODE, C, TY>(acc, lane, wm, wn, X, Y, albedo, rowscale, colmul, xs, sign, M, N, m0,
+                          n0, ymul, imod);
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin: give each XCD a contiguous

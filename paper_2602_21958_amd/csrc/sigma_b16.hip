@@ -42,8 +42,15 @@ __global__ __launch_bounds__(C::NT) __attribute__((amdgpu_waves_per_eu(1, OCC)))
   int tm, tn;
   if (!tile_of(blockIdx.x, Mt, (N + C::BN - 1) / C::BN, GM, tm, tn)) return;
   const float xs = (X != nullptr && xscale != nullptr) ? (float)*xscale : 1.f;
-  tile<MODE, C, DOTS, TY>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs,
-                          sign, M, N, tm * C::BM, tn * C::BN, lds, dots, tn * Mt + tm, ymul);
+  if constexpr (C::PP) {
+    static_assert(!DOTS, "the ping-pong tile has no fused dots");
+    tile_pp<MODE, C, TY>(Ahi, Mp, Bhi, (int)Np, K4p, X, Y, albedo, rowscale, colmul, xs, sign, M,
+                         N, tm * C::BM, tn * C::BN, lds, ymul);
+  } else {
+    tile<MODE, C, DOTS, TY>(Ahi, Alo, Mp, Bhi, Blo, (int)Np, K4p, X, Y, albedo, rowscale, colmul,
+                            xs, sign, M, N, tm * C::BM, tn * C::BN, lds, dots, tn * Mt + tm,
+                            ymul);
+  }
 }
 
 // Candidate tile shapes (BM x BN, waves, K stage, instruction) and the
@@ -54,9 +61,13 @@ using C0s = Cfg<256, 256, 2, 4, 32, true>;
 using C1 = Cfg<256, 128, 2, 2, 32, false>;
 using C2 = Cfg<128, 128, 2, 2, 32, true>;
 using C3 = Cfg<128, 128, 2, 2, 64, false>;
-constexpr int kNumCfg = 4;
+using C4 = Cfg<256, 256, 2, 4, 32, true, true>;   // ping-pong (not split, no fused dots)
+constexpr int kNumCfg = 5;
 const char* const kCfgName[kNumCfg] = {"256x256 32x32x16 K64", "256x128 16x16x32 K32",
-                                       "128x128 32x32x16 K32", "128x128 16x16x32 K64"};
+                                       "128x128 32x32x16 K32", "128x128 16x16x32 K64",
+                                       "256x256 32x32x16 K32 ping-pong"};
+// candidates a mode can run (the ping-pong tile has one operand part)
+bool cfg_allowed(int mode, int cfg) { return cfg != 4 || mode != MODE_SPLIT; }
 
 struct Args {
   const uint16_t *ahi, *alo;
@@ -94,11 +105,15 @@ void launch_cfg(const Args& a, hipStream_t st) {
                        a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, gemm::TileDots{},
                        a.ymul);
   } else if (a.dots) {
-    if (a.dots->ldp < T) fail(RT_E_INVALID, "fused dots: too few partial slots");
-    a.dots->ldp = T;   // one slot per tile, all written
-    hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, true, float>), dim3(grid), dim3(C::NT), 0,
-                       st, a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, xf, yf, a.albedo,
-                       a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, *a.dots, a.ymul);
+    if constexpr (C::PP) {
+      fail(RT_E_INVALID, "fused dots: not with the ping-pong tile");
+    } else {
+      if (a.dots->ldp < T) fail(RT_E_INVALID, "fused dots: too few partial slots");
+      a.dots->ldp = T;   // one slot per tile, all written
+      hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, true, float>), dim3(grid), dim3(C::NT),
+                         0, st, a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, xf, yf, a.albedo,
+                         a.rowscale, a.colmul, a.xscale, a.sign, a.M, a.N, 8, *a.dots, a.ymul);
+    }
   } else {
     hipLaunchKernelGGL((sigma16_kernel<MODE, C, OCC, false, float>), dim3(grid), dim3(C::NT), 0,
                        st, a.ahi, a.alo, a.Mp, a.bhi, a.blo, a.Np, a.K4p, xf, yf, a.albedo,
@@ -116,7 +131,14 @@ void launch_index(int cfg, const Args& a, hipStream_t st) {
       break;
     case 1: launch_cfg<MODE, C1, 2>(a, st); break;
     case 2: launch_cfg<MODE, C2, 4>(a, st); break;
-    default: launch_cfg<MODE, C3, 2>(a, st); break;
+    case 3: launch_cfg<MODE, C3, 2>(a, st); break;
+    default:
+      // the ping-pong tile: not for the split mode, and fused dots take the
+      // 128 x 128 tile
+      if constexpr (MODE == MODE_SPLIT) launch_cfg<MODE, C0s, 2>(a, st);
+      else if (a.dots) launch_cfg<MODE, C2, 4>(a, st);
+      else launch_cfg<MODE, C4, 2>(a, st);
+      break;
   }
 }
 
@@ -177,7 +199,7 @@ void cache_store(const std::string& key, int cfg) {
 int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   if (const char* e = std::getenv("RTSN_GEMM16_CFG")) {
     const int c = std::atoi(e);
-    if (c >= 0 && c < kNumCfg) return c;
+    if (c >= 0 && c < kNumCfg && cfg_allowed(mode, c)) return c;
   }
   const std::string key = cache_key(p.device, mode, full.M, full.N);
   if (const int c = cache_lookup(key); c >= 0) return c;
@@ -209,6 +231,7 @@ int autotune(const Problem& p, int mode, const Args& full, hipStream_t st) {
   int best = 2;
   float best_ms = 1e30f;
   for (int c = 0; c < kNumCfg; ++c) {
+    if (!cfg_allowed(mode, c)) continue;
     launch_mode(mode, c, a, st);   // warm-up
     float ms = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {

@@ -550,7 +550,7 @@ def test_sigma_16bit_within_rounding_bound(name, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16x3"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 def test_sigma_16bit_every_tile_shape(cfg, prec, monkeypatch):
     """Every candidate tile shape of the 16-bit GEMM (forced instead of tuned)
     on a ragged problem: 288 rays (not a multiple of the 64-wide K stage or
