@@ -24,6 +24,10 @@ independently, in plain NumPy float64, following the paper:
                        eq. RT_sys_algebraic; Sec. 3.5) and dense assembly.
 * ``krylov``         - restarted GMRES (Saad-Schultz, modified Gram-Schmidt,
                        Givens rotations) and BiCGStab (van der Vorst).
+* ``precond``        - the physics-based preconditioner of Sec. 6's remark:
+                       the plane-local part of Lambda, averaged over
+                       directions, with every point's scattering block, and
+                       right-preconditioned GMRES.
 
 Parity status per function is listed in each module header.
 """
