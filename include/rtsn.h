@@ -309,7 +309,21 @@ typedef struct {
                              (default 1; 0: one step per pass).  Same Krylov
                              spaces and iterates in exact arithmetic.  Ignored
                              in BiCGStab.                                         */
+  int precond;            /* RT_PRECOND_NONE (default: the unpreconditioned solve
+                             the paper analyses) or RT_PRECOND_LOCAL: GMRES on
+                             A P^-1 with the physics-based preconditioner of
+                             rt_apply_precond (Sec. 6 remark on physics-based
+                             preconditioning), FP64 or on the FP32 basis of the
+                             mixed inner cycles; right preconditioning, so the
+                             residual and stopping test are those of A x = b.
+                             Dipole x PRD kernels with one kernel for all points;
+                             not with BiCGStab or an fp16 basis (RT_E_INVALID).
+                             The first preconditioned solve in a precision builds
+                             the preconditioner's tables (see rt_apply_precond)
+                             and synchronises the device.                       */
 } rt_solver_opts;
+
+enum { RT_PRECOND_NONE = 0, RT_PRECOND_LOCAL = 1 };
 
 typedef struct {
   int iters;              /* total Krylov iterations (inner iterations if mixed)    */
@@ -324,6 +338,30 @@ typedef struct {
 
 /* Fill opts with defaults (GMRES(30), rtol 1e-8, FP64).                     */
 void rt_solver_opts_default(rt_solver_opts* opts);
+
+/* Physics-based preconditioner (Sec. 6 remarks that physics-based
+ * preconditioning can still cut iteration counts; Sec. 3.3 eq. Sigma for the
+ * scattering block): y = P^-1 x with P block diagonal over points,
+ *   P_i = Id - (1 - eps_i) Mhat diag_k(Dbar[nu(k)][i]),
+ *   Dbar[nu][i] = sum_o w_o (Lambda_0 1_z)[(o, nu), i] / sum_o w_o,
+ * where 1_z is a unit source on the plane z of point i (the slab: the depth
+ * point), so Lambda_0 1_z restricted to that plane is the local part of the
+ * formal solution (its diagonal with linear short characteristics or
+ * implicit Euler).  For the dipole x PRD kernel P_i^-1 is applied through the
+ * nonzero eigenvalues of the angular block (6 in 3D, 2 in the slab) as that
+ * many N_nu x N_nu blocks per point.  x, y: device vectors of n_unknowns
+ * FP64 (precision RT_PREC_FP64) or FP32 (RT_PREC_FP32), ray-major; y must not
+ * alias x.  The first call in a precision builds the tables: one FP64 formal
+ * solution per plane for Dbar, then the blocks (6 N_nu^2 n_points values of
+ * the precision) and two work vectors; they stay with the problem.  Errors:
+ * RT_E_INVALID (other precisions, null or aliased vectors, an explicit kernel
+ * or per-point classes, more frequencies than the in-LDS inversion holds,
+ * about 140), RT_E_NOMEM.                                                    */
+rt_status rt_apply_precond(rt_problem p, int precision, const void* x, void* y, void* stream);
+
+/* Dbar of rt_apply_precond (host array of n_frequencies x n_points doubles,
+ * frequency-major), built if missing.  Synchronises the device.            */
+rt_status rt_precond_local(rt_problem p, double* dbar);
 
 /* Solve A s = b (restarted GMRES, Sec. 5 and Sec. 5.3; or BiCGStab).
  * b: device FP64 or NULL (then the physical right-hand side rt_rhs is used).
@@ -411,7 +449,8 @@ rt_status rt_batch_destroy(rt_batch b);
  * that class afterwards.  Process-wide, internally synchronised.
  * ------------------------------------------------------------------------- */
 enum { RT_KCLASS_LAMBDA = 0, RT_KCLASS_SIGMA = 1, RT_KCLASS_ARNOLDI = 2,
-       RT_KCLASS_LAMBDA_LO = 3, RT_KCLASS_SIGMA_LO = 4, RT_KCLASS_COUNT = 5 };
+       RT_KCLASS_LAMBDA_LO = 3, RT_KCLASS_SIGMA_LO = 4, RT_KCLASS_PRECOND = 5,
+       RT_KCLASS_COUNT = 6 };
 
 rt_status rt_profile_enable(int on);
 rt_status rt_profile_read(int kclass, int64_t* launches, double* total_ms, int reset);

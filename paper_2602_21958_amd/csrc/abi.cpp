@@ -63,6 +63,14 @@ Problem::~Problem() {
   hipFree(d_oz_a);
   hipFree(d_oz_ea);
   hipFree(d_ozwork);
+  hipFree(d_prec_dbar);
+  hipFree(d_prec_F64);
+  hipFree(d_prec_G64);
+  hipFree(d_prec_T64);
+  hipFree(d_prec_F32);
+  hipFree(d_prec_G32);
+  hipFree(d_prec_T32);
+  hipFree(d_prec_work);
 }
 
 size_t lambda_elem_bytes(int precision) {
@@ -545,6 +553,40 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y, const d
   }
 }
 
+void operator_apply_kx(Problem& p, int precision, const void* u, const void* nd, void* y,
+                       const double* xscale, hipStream_t st) {
+  const size_t n = (size_t)p.n;
+  switch (precision) {
+    case RT_PREC_FP64: {
+      double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
+      launch_lambda<double, double>(p, static_cast<const double*>(u), L, false, xscale, st);
+      apply_sigma_f64(p, L, static_cast<const double*>(nd), static_cast<double*>(y), xscale,
+                      +1.0, st, nullptr);
+      break;
+    }
+    case RT_PREC_FP32: {
+      float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
+      launch_lambda<float, float>(p, static_cast<const float*>(u), L, false, xscale, st);
+      apply_sigma_f32(p, L, static_cast<const float*>(nd), static_cast<float*>(y), xscale, +1.0,
+                      st, nullptr);
+      break;
+    }
+    case RT_PREC_BF16:
+    case RT_PREC_FP16:
+    case RT_PREC_BF16X3: {
+      require_one_kernel(p, "a 16-bit operator");
+      uint16_t* L = problem_l16(p, st);
+      uint16_t* Llo = precision == RT_PREC_BF16X3 ? L + l16_part_elems(p) : nullptr;
+      launch_lambda_k4(p, precision, static_cast<const float*>(u), L, Llo, xscale, st);
+      launch_sigma_b16(p, precision, L, Llo, static_cast<const float*>(nd),
+                       static_cast<float*>(y), xscale, +1.0, st, nullptr);
+      break;
+    }
+    default:
+      fail(RT_E_INVALID, "unknown precision");
+  }
+}
+
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st, bool kform) {
   if (precision != RT_PREC_BF16 && precision != RT_PREC_FP16 && precision != RT_PREC_BF16X3)
@@ -810,6 +852,35 @@ rt_status rt_intensity(rt_problem p, const double* s, double* I, void* stream) {
   });
 }
 
+rt_status rt_apply_precond(rt_problem p, int precision, const void* x, void* y, void* stream) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    if (precision != RT_PREC_FP64 && precision != RT_PREC_FP32)
+      fail(RT_E_INVALID, "the preconditioner applies to FP64 or FP32 vectors");
+    if (!x || !y) fail(RT_E_INVALID, "null vector");
+    if (x == y) fail(RT_E_INVALID, "y must not alias x");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    precond_prepare(*q, precision == RT_PREC_FP64 ? 8 : 4, st);
+    if (precision == RT_PREC_FP64) {
+      double* nd = precond_nd<double>(*q);
+      precond_apply<double>(*q, static_cast<const double*>(x), static_cast<double*>(y), nd, st);
+    } else {
+      float* nd = precond_nd<float>(*q);
+      precond_apply<float>(*q, static_cast<const float*>(x), static_cast<float*>(y), nd, st);
+    }
+  });
+}
+
+rt_status rt_precond_local(rt_problem p, double* dbar) {
+  return guarded([&] {
+    Problem* q = as_problem(p);
+    if (!dbar) fail(RT_E_INVALID, "null output");
+    precond_prepare_local(*q, nullptr);
+    RT_HIP(hipMemcpy(dbar, q->d_prec_dbar, (size_t)q->n_nu * q->n_s * sizeof(double),
+                     hipMemcpyDeviceToHost));
+  });
+}
+
 void rt_solver_opts_default(rt_solver_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -846,6 +917,10 @@ rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, do
       fail(RT_E_INVALID, "basis_fp16 needs a 16-bit operator precision");
     if (o.basis_fp16 && q->scatter_inf > 2.0)
       fail(RT_E_INVALID, "basis_fp16 needs max row sum of |(1-eps) Mhat| <= 2");
+    if (o.precond != RT_PRECOND_NONE && o.precond != RT_PRECOND_LOCAL)
+      fail(RT_E_INVALID, "unknown preconditioner");
+    if (o.precond && (o.krylov != RT_KRYLOV_GMRES || o.basis_fp16))
+      fail(RT_E_INVALID, "the preconditioner is a GMRES option on FP64 or FP32 bases");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double* bb = b ? b : physical_rhs(*q, st);
     status = solve(*q, o, bb, x, x_is_guess, stats, st);

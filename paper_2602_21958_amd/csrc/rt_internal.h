@@ -137,6 +137,19 @@ struct Problem {
   int* d_oz_ea = nullptr;
   void* d_ozwork = nullptr;
   size_t ozwork_bytes = 0;
+  // physics-based preconditioner (precond.hip), built by precond_prepare:
+  // the kept angular modes (prec_rq <= 6 eigenvalues of the angular block,
+  // F and G n_omega x prec_rq), the direction-averaged plane response Dbar
+  // (n_nu x n_s, FP64), the per-point blocks T (prec_rq x n_s blocks of
+  // n_nu x n_nu, FP64 and / or FP32) and the apply's work (r, z and the
+  // u, nd vectors)
+  int prec_rq = 0;
+  std::vector<double> prec_lam, prec_F, prec_G;
+  double* d_prec_dbar = nullptr;
+  double *d_prec_F64 = nullptr, *d_prec_G64 = nullptr, *d_prec_T64 = nullptr;
+  float *d_prec_F32 = nullptr, *d_prec_G32 = nullptr, *d_prec_T32 = nullptr;
+  void* d_prec_work = nullptr;
+  size_t prec_work_bytes = 0;
   Workspace* ws = nullptr;
   int64_t bytes_problem = 0;
   std::vector<double> history;
@@ -238,6 +251,23 @@ void launch_sigma_classes_f64(const Problem& p, const double* L, const double* x
 void launch_sigma_classes_f32(const Problem& p, const float* L, const float* x, float* y,
                               float* work, const double* xscale, double sign, hipStream_t st);
 size_t classes_work_elems(const Problem& p);
+// Physics-based preconditioner (precond.hip).  precond_prepare builds the
+// tables for vectors of elem_bytes (8 FP64, 4 FP32) if missing (RT_E_INVALID
+// without the dipole x PRD kernel for all points); precond_apply writes
+// u = P^-1 x and nd = x - u; precond_apply_add adds P^-1 d to y.
+// precond_u / precond_nd: two n-vectors of the apply's work for callers.
+void precond_prepare(Problem& p, int elem_bytes, hipStream_t st);
+// the angular modes and Dbar only
+void precond_prepare_local(Problem& p, hipStream_t st);
+size_t precond_table_bytes(const Problem& p, int elem_bytes);
+template <typename T> void precond_apply(Problem& p, const T* x, T* u, T* nd, hipStream_t st);
+template <typename T> void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st);
+template <typename T> T* precond_u(Problem& p);
+template <typename T> T* precond_nd(Problem& p);
+// y = xs * nd + K (xs * u): the preconditioned step operator K' = I - A P^-1
+// applied to v with u = P^-1 v and nd = v - u (see solver.cpp)
+void operator_apply_kx(Problem& p, int precision, const void* u, const void* nd, void* y,
+                       const double* xscale, hipStream_t st);
 // Emulated FP64 scattering (sigma_ozaki.hip): ozaki_prepare builds the Mhat
 // residues once; launch_sigma_ozaki computes y = xs x + sign (1 - eps) Mhat L
 // with work of ozaki_work_bytes(p) bytes.

@@ -189,18 +189,35 @@ struct CoreResult {
 // With single_cycle the solve stops after one restart cycle and skips the
 // true-residual recomputation (inner solves of iterative refinement, whose
 // low-precision operator is not exactly linear).
+// With pre (right preconditioning, A P^-1 y = b, x = P^-1 y) the Arnoldi
+// operator is K' = I - A P^-1 instead of K = I - A, so the Hessenberg
+// bookkeeping is unchanged: with u = P^-1 v and P = Id - (1 - eps) Mhat Dbar,
+// K' v = v - A u = K u - (u - v), formed as one operator application on u
+// whose epilogue adds nd = v - u (operator_apply_kx).  The cycle end adds
+// P^-1 (V y) to x.
 template <typename TV>
 rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int m, double rtol,
                      int max_iters, double bnorm, Workspace& ws, TV* tmp, hipStream_t st,
                      std::vector<double>* hist, CoreResult& res, bool single_cycle = false,
-                     bool two = false) {
+                     bool two = false, bool pre = false) {
   const int64_t n = p.n;
   TV* V = static_cast<TV*>(ws.V);
   GmresState* gs = ws.gs;
   // the fused dots live in the dense GEMM's epilogue
   const bool fuse_dots =
-      fuse_dots_env() && (p.sigma_form == RT_SIGMA_DENSE ||
-                          (prec != RT_PREC_FP64 && prec != RT_PREC_FP32));
+      !pre && fuse_dots_env() &&
+      (p.sigma_form == RT_SIGMA_DENSE || (prec != RT_PREC_FP64 && prec != RT_PREC_FP32));
+  // y = K (xs v) or K' (xs v)
+  auto step_op = [&](const TV* v, TV* y, const double* xs) {
+    if (pre) {
+      TV* u = precond_u<TV>(p);
+      TV* nd = precond_nd<TV>(p);
+      precond_apply<TV>(p, v, u, nd, st);
+      operator_apply_kx(p, prec, u, nd, y, xs, st);
+    } else {
+      operator_apply_k(p, prec, v, y, xs, st);
+    }
+  };
   if (x_zero) {
     RT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(TV), st));
     RT_HIP(hipMemcpyAsync(V, b, (size_t)n * sizeof(TV), hipMemcpyDeviceToDevice, st));
@@ -227,8 +244,8 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
         // steps j and j + 1: u1 = K v_j, u2 = K u1, one dots and one update pass
         TV* u1 = V + (size_t)(j + 1) * n;
         TV* u2 = V + (size_t)(j + 2) * n;
-        operator_apply_k(p, prec, vj, u1, gs->vscale + j, st);
-        operator_apply_k(p, prec, u1, u2, nullptr, st);
+        step_op(vj, u1, gs->vscale + j);
+        step_op(u1, u2, nullptr);
         k_mdot2<TV>(V, n, j + 2, u1, u2, ws.partial, st);
         k_pair_coef(ws.partial, n, j, gs->vscale, ws.pair, st);
         k_update2<TV>(V, n, j + 1, ws.pair, u1, u2, ws.partial, st);
@@ -252,7 +269,7 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
         operator_apply_k(p, prec, vj, w, gs->vscale + j, st, &d);   // sets d.ldp
         k_reduce_rows_nb(ws.partial, d.ldp, j + 1, gs->vscale, gs->h, st);
       } else {
-        operator_apply_k(p, prec, vj, w, gs->vscale + j, st);
+        step_op(vj, w, gs->vscale + j);
         k_mdot<TV>(V, n, j + 1, w, ws.partial, st);
         k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
       }
@@ -267,7 +284,14 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
       if (r.stop || res.iters >= max_iters) break;
     }
     k_solve_r(gs, k, st);
-    k_combine<TV, TV>(V, n, k, gs->coef, x, st);
+    if (pre) {
+      TV* d = precond_nd<TV>(p);
+      RT_HIP(hipMemsetAsync(d, 0, (size_t)n * sizeof(TV), st));
+      k_combine<TV, TV>(V, n, k, gs->coef, d, st);
+      precond_apply_add<TV>(p, d, x, st);
+    } else {
+      k_combine<TV, TV>(V, n, k, gs->coef, x, st);
+    }
     if (single_cycle) {
       res.beta = ws.host->resid;
       return res.beta <= rtol * bnorm ? RT_OK : RT_NOT_CONVERGED;
@@ -490,6 +514,8 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
   auto t0 = std::chrono::steady_clock::now();
   const bool mixed = o.precision != RT_PREC_FP64;
   const bool bicg = o.krylov == RT_KRYLOV_BICGSTAB;
+  const bool pre = o.precond == RT_PRECOND_LOCAL;
+  if (pre) precond_prepare(p, mixed ? 4 : 8, st);
   Workspace& ws = ensure_workspace(p, o.restart, mixed, bicg,
                                    !mixed ? 8 : (o.basis_fp16 ? 2 : 4));
   const int64_t n = p.n;
@@ -508,7 +534,7 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
   } else if (!mixed && !bicg) {
     status = gmres_core<double>(p, RT_PREC_FP64, b, x, !x_is_guess, o.restart, o.rtol,
                                 o.max_iters, bnorm, ws, ws.ax64, st, hist, res, false,
-                                o.two_step != 0);
+                                o.two_step != 0, pre);
     outer = res.cycles;
   } else if (!mixed && bicg) {
     status = bicgstab_fp64(p, b, x, !x_is_guess, o.rtol, o.max_iters, bnorm, ws, st, hist, res);
@@ -549,11 +575,13 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
         // 16-bit operators' fp16 Lambda scale assumes entries of at most
         // about one, which |(1 - eps) Mhat|_inf <= 2 keeps (the physical
         // kernels give about 1); above that the steps go one at a time
+        // (preconditioned: P^-1 amplifies some directions, so with a 16-bit
+        // operator the steps go one at a time too)
         const bool pairs = o.two_step != 0 &&
-                           (o.precision == RT_PREC_FP32 || p.scatter_inf <= 2.0);
+                           (o.precision == RT_PREC_FP32 || (p.scatter_inf <= 2.0 && !pre));
         CoreResult ir;
         gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
-                          nullptr, st, nullptr, ir, /*single_cycle=*/true, pairs);
+                          nullptr, st, nullptr, ir, /*single_cycle=*/true, pairs, pre);
         total_inner += ir.iters;
       }
       RT_HIP(hipMemcpyAsync(ws.scal + 1, &rn, sizeof(double), hipMemcpyHostToDevice, st));

@@ -33,6 +33,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 RT_BATCH_BASIS_FP16 = 1
 KRYLOV = {"gmres": 0, "bicgstab": 1}
 SIGMA_FORM = {"dense": 0, "factored": 1, "ozaki": 2}
+PRECOND = {"none": 0, "local": 1}
 
 STATUS_NAMES = {0: "RT_OK", 1: "RT_NOT_CONVERGED", -1: "RT_E_INVALID", -2: "RT_E_NOMEM",
                 -3: "RT_E_DEVICE", -4: "RT_E_BREAKDOWN", -5: "RT_E_NONFINITE",
@@ -69,7 +70,7 @@ class SolverOpts(C.Structure):
     _fields_ = [("krylov", C.c_int), ("restart", C.c_int), ("max_iters", C.c_int),
                 ("rtol", C.c_double), ("precision", C.c_int), ("inner_rtol", C.c_double),
                 ("max_outer", C.c_int), ("record_history", C.c_int), ("basis_fp16", C.c_int),
-                ("two_step", C.c_int)]
+                ("two_step", C.c_int), ("precond", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -89,6 +90,8 @@ _sig = {
     "rt_apply_operator": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "rt_apply_operator_noalloc": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "rt_problem_set_sigma": (C.c_int, [_vp, C.c_int]),
+    "rt_apply_precond": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "rt_precond_local": (C.c_int, [_vp, C.POINTER(C.c_double)]),
     "rt_rhs": (C.c_int, [_vp, _vp, _vp]),
     "rt_intensity": (C.c_int, [_vp, _vp, _vp, _vp]),
     "rt_solver_opts_default": (None, [C.POINTER(SolverOpts)]),
@@ -234,6 +237,7 @@ class Problem:
         self.n = int(info.n_unknowns)
         self.n_r = int(info.n_rays)
         self.n_s = int(info.n_points)
+        self.n_nu = int(spec.n_nu)
 
     # ------------------------------------------------------------------ info
     def footprint(self, restart: int = 30) -> ProblemInfo:
@@ -283,6 +287,22 @@ class Problem:
                                               _stream(stream)), "rt_apply_operator_noalloc")
         return y
 
+    def apply_precond(self, x, y, precision: str = "fp64", stream=None):
+        """y = P^-1 x with the physics-based preconditioner (FP64 or FP32
+        device vectors)."""
+        _check(_lib.rt_apply_precond(self.handle, PREC[precision], _ptr(x), _ptr(y),
+                                     _stream(stream)), "rt_apply_precond")
+        return y
+
+    def precond_local(self):
+        """The preconditioner's direction-averaged plane response Dbar
+        (n_nu x n_s, numpy)."""
+        import numpy as np
+        out = np.empty((self.n_nu, self.n_s), dtype=np.float64)
+        _check(_lib.rt_precond_local(self.handle, out.ctypes.data_as(C.POINTER(C.c_double))),
+               "rt_precond_local")
+        return out
+
     def set_sigma(self, form: str):
         """Scattering form of FP64 / FP32 applications: 'dense' (GEMM),
         'factored' (dipole x PRD kernels) or 'ozaki' (FP64 GEMM emulated
@@ -301,7 +321,7 @@ class Problem:
     def solve(self, x, b=None, x_is_guess: bool = False, stream=None, **opts):
         """Solve A s = b (b None: physical rhs).  opts: krylov, restart,
         max_iters, rtol, precision, inner_rtol, max_outer, record_history,
-        basis_fp16, two_step.
+        basis_fp16, two_step, precond ('none' or 'local').
         Returns a dict of solve statistics; raises on errors other than
         RT_NOT_CONVERGED."""
         o = default_opts()
@@ -310,6 +330,8 @@ class Problem:
                 v = PREC[v] if isinstance(v, str) else v
             if k == "krylov":
                 v = KRYLOV[v] if isinstance(v, str) else v
+            if k == "precond":
+                v = PRECOND[v] if isinstance(v, str) else v
             setattr(o, k, v)
         st = SolveStats()
         code = _lib.rt_solve(self.handle, C.byref(o), _ptr(b), _ptr(x), int(bool(x_is_guess)),
@@ -416,7 +438,8 @@ class Batch:
 # kernel classes of rt_profile_read: the formal solver and the GEMM in FP64
 # arithmetic, the Arnoldi kernels, and the formal solver and the GEMM in the
 # lower precisions (FP32 sweeps, FP32 and 16-bit GEMMs)
-KCLASS = {"lambda": 0, "sigma": 1, "arnoldi": 2, "lambda_lo": 3, "sigma_lo": 4}
+KCLASS = {"lambda": 0, "sigma": 1, "arnoldi": 2, "lambda_lo": 3, "sigma_lo": 4,
+          "precond": 5}
 
 
 def profile_enable(on: bool = True) -> None:
