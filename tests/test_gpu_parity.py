@@ -501,6 +501,7 @@ def test_profile_counts_launches():
         y = torch.empty_like(x)
         x32 = x.float()
         y32 = torch.empty_like(x32)
+        p.apply_precond(x, y)        # builds the preconditioner before timing
         rt.profile_enable(True)
         for k in rt.KCLASS:
             rt.profile_read(k)
@@ -508,11 +509,14 @@ def test_profile_counts_launches():
             p.apply(x, y)
         for prec in ("fp32", "fp16"):
             p.apply(x32, y32, precision=prec)
+        p.apply_precond(x, y)
         rt.profile_enable(False)
         got = {k: rt.profile_read(k) for k in rt.KCLASS}
-    # FP64 arithmetic and the lower precisions are counted apart
+    # FP64 arithmetic, the lower precisions and the preconditioner are
+    # counted apart
     assert got["lambda"][0] == 3 and got["sigma"][0] == 3
     assert got["lambda_lo"][0] == 2 and got["sigma_lo"][0] == 2
+    assert got["precond"][0] == 1
     assert all(ms > 0 for k, (n, ms) in got.items() if k != "arnoldi")
 
 
