@@ -574,11 +574,12 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
         // a pair's second application takes u1 = K v_j unnormalised; the
         // 16-bit operators' fp16 Lambda scale assumes entries of at most
         // about one, which |(1 - eps) Mhat|_inf <= 2 keeps (the physical
-        // kernels give about 1); above that the steps go one at a time
-        // (preconditioned: P^-1 amplifies some directions, so with a 16-bit
-        // operator the steps go one at a time too)
+        // kernels give about 1); above that the steps go one at a time.
+        // Preconditioned, both steps feed P^-1 of a vector of about unit
+        // size to Lambda, as a single step does (an fp16 overflow would stop
+        // the solve with RT_E_NONFINITE).
         const bool pairs = o.two_step != 0 &&
-                           (o.precision == RT_PREC_FP32 || (p.scatter_inf <= 2.0 && !pre));
+                           (o.precision == RT_PREC_FP32 || p.scatter_inf <= 2.0);
         CoreResult ir;
         gmres_core<float>(p, o.precision, r32, ws.d32, true, o.restart, itol, cap, 1.0, ws,
                           nullptr, st, nullptr, ir, /*single_cycle=*/true, pairs, pre);
