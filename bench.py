@@ -458,10 +458,11 @@ def bench_batch512(args):
     n_tot = sum(p.n for p in probs)
     xs = [torch.empty(p.n, dtype=torch.float64, device="cuda:0") for p in probs]
 
-    def run(precision, profile=False, basis_fp16=False):
+    def run(precision, profile=False, basis_fp16=False, precond="none"):
         eng = rt.Batch(precision=precision, hbm_budget=64 << 30, max_slots=512,
                        basis_fp16=basis_fp16)
-        tk = [eng.submit(p, x, restart=30, rtol=1e-8, max_iters=4000, max_outer=200)
+        tk = [eng.submit(p, x, restart=30, rtol=1e-8, max_iters=4000, max_outer=200,
+                         precond=precond)
               for p, x in zip(probs, xs)]
         if profile:
             rt.profile_enable(True)
@@ -506,6 +507,15 @@ def bench_batch512(args):
                            "converged": sum(1 for s in st2 if s["converged"]),
                            "iters_median": float(np.median([s["iters"] for s in st2])),
                            "steps": s2}
+    # the physics-based preconditioner on every slab (its tables are built
+    # on each problem at its first admission: an untimed run first)
+    for v in (prec, "fp64"):
+        run(v, precond="local")
+        e2, s2, st2, _ = run(v, precond="local")
+        variants[v + "/precond"] = {
+            "solves_per_s": 512 / e2, "converged": sum(1 for s in st2 if s["converged"]),
+            "iters_median": float(np.median([s["iters"] for s in st2])),
+            "iters_max": int(max(s["iters"] for s in st2)), "steps": s2}
     # per-slab FP64 loop through the single-problem solver on a sample
     sample = list(range(0, 512, 16))
     t0 = time.perf_counter()

@@ -413,7 +413,14 @@ rt_status rt_batch_create_ex(int device, int precision, int64_t hbm_budget,
  * Non-blocking; *ticket identifies the request.  RT_E_BUSY if the queue is
  * full; RT_E_INVALID if the problem can never fit the budget or if
  * opts->basis_fp16 differs from the engine's basis (set iff it was created
- * with RT_BATCH_BASIS_FP16).                                                */
+ * with RT_BATCH_BASIS_FP16).  opts->precond = RT_PRECOND_LOCAL runs the
+ * solve preconditioned (see rt_solver_opts) on FP64 or FP32 bases (not in
+ * an fp16-basis engine; RT_E_INVALID also where rt_apply_precond would
+ * refuse the problem); its tables are built on the problem at admission
+ * (once per problem and precision, synchronising the engine's stream) and
+ * held by the problem outside the engine's budget, which holds the
+ * preconditioner's four work vectors (2 n_unknowns and 2 * 6 n_frequencies
+ * n_points elements of the basis type).                                     */
 rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts,
                           double* x_out, uint64_t* ticket);
 

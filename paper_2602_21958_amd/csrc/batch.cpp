@@ -146,7 +146,7 @@ struct Engine {
   int64_t steps = 0;
 
   ~Engine();
-  size_t footprint(const Problem& p, int restart) const;
+  size_t footprint(const Problem& p, int restart, bool pre = false) const;
   void tune_gemm16();
   void admit();
   bool setup_slot(Request* r, int s);
@@ -200,7 +200,9 @@ Engine::~Engine() {
   if (stream) hipStreamDestroy(stream);
 }
 
-size_t Engine::footprint(const Problem& p, int restart) const {
+// Arena bytes of one solve; pre adds the preconditioner's vectors (u, nd and
+// the reduced r, z; its tables live with the Problem).
+size_t Engine::footprint(const Problem& p, int restart, bool pre) const {
   const size_t n = (size_t)p.n;
   const size_t tv = fp64 ? sizeof(double) : (basis16 ? 2 : sizeof(float));
   size_t b = 0;
@@ -210,13 +212,18 @@ size_t Engine::footprint(const Problem& p, int restart) const {
   b += 2 * align_up(n * sizeof(double));                      // b, r
   b += align_up((size_t)(restart + 2) * nchunks(p.n) * sizeof(double));  // partials
   b += align_up(sizeof(GmresState));
+  if (pre) {
+    const size_t rz = (size_t)std::max(1, p.tab.frank) * p.n_nu * p.n_s;
+    b += 2 * align_up(n * tv) + 2 * align_up(rz * tv);
+  }
   return b;
 }
 
 bool Engine::setup_slot(Request* r, int s) {
   Problem& p = *r->p;
   const int m = r->o.restart;
-  const size_t fp = footprint(p, m);
+  const bool pre = r->o.precond == RT_PRECOND_LOCAL;
+  const size_t fp = footprint(p, m, pre);
   size_t off = 0;
   if (!arena.alloc(fp, off)) return false;
   r->off = off;
@@ -263,7 +270,20 @@ bool Engine::setup_slot(Request* r, int s) {
   d.b = reinterpret_cast<double*>(q);           q += align_up(n * sizeof(double));
   d.r = reinterpret_cast<double*>(q);           q += align_up(n * sizeof(double));
   d.partial = reinterpret_cast<double*>(q);     q += align_up((size_t)(m + 2) * d.nch * 8);
-  d.gs = reinterpret_cast<GmresState*>(q);
+  d.gs = reinterpret_cast<GmresState*>(q);      q += align_up(sizeof(GmresState));
+  if (pre) {
+    // the Problem's tables in the basis type (built on its first use)
+    precond_prepare(p, (int)tv, stream);
+    d.prq = p.prec_rq;
+    d.pF = fp64 ? (const void*)p.d_prec_F64 : (const void*)p.d_prec_F32;
+    d.pG = fp64 ? (const void*)p.d_prec_G64 : (const void*)p.d_prec_G32;
+    d.pT = fp64 ? (const void*)p.d_prec_T64 : (const void*)p.d_prec_T32;
+    const size_t rz = (size_t)std::max(1, p.tab.frank) * p.n_nu * p.n_s;
+    d.pu = q;                                   q += align_up(n * tv);
+    d.pnd = q;                                  q += align_up(n * tv);
+    d.pr = q;                                   q += align_up(rz * tv);
+    d.pz = q;                                   q += align_up(rz * tv);
+  }
   d.x = r->x_out;
   // (only the fp16 k4 operand is scaled; plain outputs ignore l_scale)
   d.l_scale = precision == RT_PREC_FP16 ? fp16_lambda_scale(p.n) : 1.f;
@@ -388,6 +408,8 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   hc[4] = (int)slots.size();
   for (int i = 0; i < 5; ++i) wl.h_counts[i] = hc[i];
   RT_HIP(hipMemcpyAsync(wl.counts, hc, 5 * sizeof(int), hipMemcpyHostToDevice, stream));
+  wl.any_prec = false;
+  for (int s : set) wl.any_prec = wl.any_prec || h_slots[s].prq > 0;
   wl.box_pmax = pmax;
   wl.box_npt = pmax <= 256 ? 1 : (pmax <= 1024 ? 2 : 16);
   wl.box_f = bf;
@@ -451,7 +473,8 @@ void Engine::run_inner() {
   const uint64_t key = (uint64_t)(wl_iter.h_counts[0] > 0) |
                        ((uint64_t)(wl_iter.h_counts[1] > 0) << 1) |
                        ((uint64_t)wl_iter.box_npt << 2) | ((uint64_t)wl_iter.box_pmax << 8) |
-                       (wl_iter.gen << 24) | ((uint64_t)tune.cfg << 60);
+                       (wl_iter.gen << 24) | ((uint64_t)tune.cfg << 60) |
+                       ((uint64_t)wl_iter.any_prec << 62);
   auto direct = [&] {
     if (fp64)
       b_inner_iteration<double>(d_slots, d_stat, wl_iter, precision, stream);
@@ -708,9 +731,13 @@ rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts, 
       fail(RT_E_INVALID, "basis_fp16 differs from the engine's basis");
     if (e->basis16 && q->scatter_inf > 2.0)
       fail(RT_E_INVALID, "an fp16 basis needs max row sum of |(1-eps) Mhat| <= 2");
+    if (o.precond != RT_PRECOND_NONE && o.precond != RT_PRECOND_LOCAL)
+      fail(RT_E_INVALID, "unknown preconditioner");
+    if (o.precond && e->basis16) fail(RT_E_INVALID, "the preconditioner needs FP64 or FP32 bases");
+    if (o.precond) precond_check(*q);
     if (o.max_outer < 1) o.max_outer = 1;
     std::lock_guard<std::mutex> lk(e->mu);
-    if (e->footprint(*q, o.restart) > e->arena.size())
+    if (e->footprint(*q, o.restart, o.precond != 0) > e->arena.size())
       fail(RT_E_INVALID, "problem can never fit the engine's HBM budget");
     if ((int)e->queue.size() >= e->queue_cap) fail(RT_E_BUSY, "queue full");
     Request* r = new Request();

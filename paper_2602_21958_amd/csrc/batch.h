@@ -48,6 +48,19 @@ struct SlotDev {
   float l_scale;                // fp16 Lambda output scale
   float vs;                     // basis scale: fp16_basis_scale for an fp16 basis,
                                 // 1 otherwise
+  // physics-based preconditioner (prq > 0; FP64 or FP32 bases): the angular
+  // modes F, G (n_omega x prq) and the per-point blocks T (prq x n_s blocks
+  // of n_nu x n_nu) borrowed from the Problem in the basis type; in the
+  // arena u = P^-1 v_j and nd = v_j - u (n each; nd also holds V y at a
+  // cycle end) and the reduced vectors r, z (prq n_nu n_s each)
+  int prq;
+  const void* pF;
+  const void* pG;
+  const void* pT;
+  void* pu;
+  void* pnd;
+  void* pr;
+  void* pz;
 };
 
 // Mutable per-slot scalars, written by the kernels (and by the host when a
@@ -83,6 +96,7 @@ struct WorkLists {
   int box_pmax = 0;          // largest box plane among the listed slots
   int box_f = 1;             // frequencies per box item (1 or 4)
   int max_lds = 0;           // LDS bytes per workgroup of the device
+  bool any_prec = false;     // some listed slot is preconditioned
   uint64_t gen = 0;          // bumped whenever a list buffer is reallocated: a graph
                              // captured with the old addresses must not be replayed
 };

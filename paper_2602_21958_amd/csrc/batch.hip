@@ -90,8 +90,9 @@ __global__ __launch_bounds__(TB) void bk_lambda_slab(const SlotDev* __restrict__
       sc = C(1);
       om = 1.f;
     } else {
+      // preconditioned slots sweep u = P^-1 v_j (same scale)
       const int j = stat[w.slot].j;
-      src = static_cast<const VT*>(s.V) + (size_t)j * s.n;
+      src = s.prq ? static_cast<const VT*>(s.pu) : static_cast<const VT*>(s.V) + (size_t)j * s.n;
       sc = C(s.gs->vscale[j]);
       om = s.l_scale;
     }
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(NT) void bk_lambda_box(const SlotDev* __restrict__ 
       om = 1.f;
     } else {
       const int j = stat[w.slot].j;
-      src = static_cast<const VT*>(s.V) + (size_t)j * s.n;
+      src = s.prq ? static_cast<const VT*>(s.pu) : static_cast<const VT*>(s.V) + (size_t)j * s.n;
       sc = C(s.gs->vscale[j]);
       om = s.l_scale;
     }
@@ -172,11 +173,13 @@ __global__ __launch_bounds__(TB) void bk_gemm(const SlotDev* __restrict__ slots,
         A = reinterpret_cast<const T*>(s.mhat64);
       else
         A = reinterpret_cast<const T*>(s.mhat32);
-      X = nullptr;   // Arnoldi on K: the step reads no V_j
+      // Arnoldi on K: the step reads no V_j; preconditioned (K' = I - A
+      // P^-1) it adds nd = v_j - u
+      X = s.prq ? static_cast<const T*>(s.pnd) : nullptr;
       Y = static_cast<T*>(s.V) + (size_t)(j + 1) * s.n;
       xs = s.gs->vscale[j];
     }
-    // Arnoldi steps on K: y = +(1 - eps) Mhat L, no x term
+    // Arnoldi steps on K: y = +(1 - eps) Mhat L (+ xs nd)
     const double sign = OUTER ? -1.0 : 1.0;
     gemm::gemm_tile<T, 16>(A, s.lda_mhat, static_cast<const T*>(s.L), X, Y, s.albedo, xs,
                            s.n_r, (int)s.n_s, s.n_r, w.a, w.b, sign);
@@ -206,7 +209,8 @@ __global__ __launch_bounds__(C::NT) void bk_gemm16(const SlotDev* __restrict__ s
     TY* Y = static_cast<TY*>(s.V) + (size_t)(j + 1) * s.n;
     const uint16_t* ahi = MODE == g16::MODE_FP16 ? s.a8_f16 : s.a8_hi;
     const uint16_t* blo = MODE == g16::MODE_SPLIT ? s.l16 + (size_t)s.kp16 * s.np16 : nullptr;
-    g16::tile<MODE, C, false, TY>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, nullptr,
+    const TY* X = s.prq ? static_cast<const TY*>(s.pnd) : nullptr;
+    g16::tile<MODE, C, false, TY>(ahi, s.a8_lo, s.mp16, s.l16, blo, (int)s.np16, s.kp16 / 4, X,
                                   Y, s.albedo, MODE == g16::MODE_FP16 ? s.f16_rowscale : nullptr,
                                   1.f / s.l_scale, (float)s.gs->vscale[j],
                                   1.f, s.n_r,
@@ -460,12 +464,147 @@ __global__ __launch_bounds__(TB) void bk_combine(const SlotDev* __restrict__ slo
     const TV* V = static_cast<const TV*>(s.V);
     const int64_t e0 = (int64_t)w.a * kChunk;
     const int64_t e1 = e0 + kChunk < s.n ? e0 + kChunk : s.n;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
-      double v = s.x[e];
-      for (int i = 0; i < k; ++i) v += coef[i] * (double)V[(size_t)i * s.n + e];
-      s.x[e] = v;
+    if (s.prq) {
+      // preconditioned: d = V y into nd; x += P^-1 d follows (bk_prec_*)
+      TV* d = static_cast<TV*>(s.pnd);
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+        double v = 0.0;
+        for (int i = 0; i < k; ++i) v += coef[i] * (double)V[(size_t)i * s.n + e];
+        d[e] = (TV)v;
+      }
+    } else {
+      for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+        double v = s.x[e];
+        for (int i = 0; i < k; ++i) v += coef[i] * (double)V[(size_t)i * s.n + e];
+        s.x[e] = v;
+      }
     }
     __syncthreads();
+  }
+}
+
+// ----------------------------------------------- physics-based preconditioner
+// The three passes of P^-1 (see precond.hip) over the chunk lists, for the
+// slots with prq > 0: chunk c covers elements c kChunk .. (c + 1) kChunk - 1
+// of the reduced index space (m = n_nu n_s for reduce and expand, prq m
+// for the block products; both fit in n).  CYCLE selects the source: the
+// basis vector v_j inside an iteration, d = V y (in nd) at a cycle end.
+constexpr int kMaxPrecModes = 6;
+
+template <typename TV, bool CYCLE>
+__global__ __launch_bounds__(TB) void bk_prec_reduce(const SlotDev* __restrict__ slots,
+                                                     const SlotStat* __restrict__ stat,
+                                                     const Item* __restrict__ items,
+                                                     const int* __restrict__ counts) {
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    if (s.prq == 0) continue;
+    const int64_t m = (int64_t)s.n_nu * s.n_s;
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    if (e0 >= m) continue;
+    const int64_t e1 = e0 + kChunk < m ? e0 + kChunk : m;
+    const TV* src = CYCLE ? static_cast<const TV*>(s.pnd)
+                          : static_cast<const TV*>(s.V) + (size_t)stat[w.slot].j * s.n;
+    const TV* G = static_cast<const TV*>(s.pG);
+    TV* r = static_cast<TV*>(s.pr);
+    const int n_om = s.n_r / s.n_nu, rq = s.prq;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+      TV acc[kMaxPrecModes];
+#pragma unroll
+      for (int q = 0; q < kMaxPrecModes; ++q) acc[q] = TV(0);
+      for (int o = 0; o < n_om; ++o) {
+        const TV v = src[(int64_t)o * m + e];
+#pragma unroll
+        for (int q = 0; q < kMaxPrecModes; ++q)
+          if (q < rq) acc[q] += G[o * rq + q] * v;
+      }
+#pragma unroll
+      for (int q = 0; q < kMaxPrecModes; ++q)
+        if (q < rq) r[(int64_t)q * m + e] = acc[q];
+    }
+  }
+}
+
+// z[q][nu][i] = sum_k T[q][i][nu][k] r[q][k][i]: one wave per block (q, i),
+// lane k holding r[q][k][i] (and k + 64), each row of the block read by the
+// whole wave in one coalesced load and summed across the lanes.  Item c of a
+// slot takes the blocks 4 c + w, 4 c + w + 4 nch, ... (w the wave).
+template <typename TV>
+__global__ __launch_bounds__(TB) void bk_prec_mix(const SlotDev* __restrict__ slots,
+                                                  const Item* __restrict__ items,
+                                                  const int* __restrict__ counts) {
+  const int cnt = counts[3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    if (s.prq == 0) continue;
+    const int n = s.n_nu;
+    const int64_t m = (int64_t)n * s.n_s, nblk = (int64_t)s.prq * s.n_s;
+    const TV* T = static_cast<const TV*>(s.pT);
+    const TV* r = static_cast<const TV*>(s.pr);
+    TV* z = static_cast<TV*>(s.pz);
+    for (int64_t b = (int64_t)w.a * 4 + wave; b < nblk; b += (int64_t)s.nch * 4) {
+      const int q = (int)(b / s.n_s);
+      const int64_t i = b - (int64_t)q * s.n_s;
+      const TV* rq = r + (int64_t)q * m + i;
+      const double r0 = lane < n ? (double)rq[(int64_t)lane * s.n_s] : 0.0;
+      const double r1 = lane + 64 < n ? (double)rq[(int64_t)(lane + 64) * s.n_s] : 0.0;
+      const TV* blk = T + (size_t)b * n * n;
+      for (int nu = 0; nu < n; ++nu) {
+        const TV* row = blk + (size_t)nu * n;
+        double v = lane < n ? (double)row[lane] * r0 : 0.0;
+        if (lane + 64 < n) v += (double)row[lane + 64] * r1;
+        v = wsum(v);
+        if (lane == 0) z[(int64_t)q * m + (int64_t)nu * s.n_s + i] = (TV)v;
+      }
+    }
+  }
+}
+
+// Delta[(o, nu), i] = sum_q F[o][q] z[q][nu][i]; inside an iteration
+// u = v_j + Delta and nd = -Delta, at a cycle end x += d + Delta (FP64 x)
+template <typename TV, bool CYCLE>
+__global__ __launch_bounds__(TB) void bk_prec_expand(const SlotDev* __restrict__ slots,
+                                                     const SlotStat* __restrict__ stat,
+                                                     const Item* __restrict__ items,
+                                                     const int* __restrict__ counts) {
+  const int cnt = counts[3];
+  for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
+    const Item w = items[it];
+    const SlotDev& s = slots[w.slot];
+    if (s.prq == 0) continue;
+    const int64_t m = (int64_t)s.n_nu * s.n_s;
+    const int64_t e0 = (int64_t)w.a * kChunk;
+    if (e0 >= m) continue;
+    const int64_t e1 = e0 + kChunk < m ? e0 + kChunk : m;
+    const TV* src = CYCLE ? static_cast<const TV*>(s.pnd)
+                          : static_cast<const TV*>(s.V) + (size_t)stat[w.slot].j * s.n;
+    const TV* F = static_cast<const TV*>(s.pF);
+    const TV* z = static_cast<const TV*>(s.pz);
+    TV* u = static_cast<TV*>(s.pu);
+    TV* nd = static_cast<TV*>(s.pnd);
+    const int n_om = s.n_r / s.n_nu, rq = s.prq;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += TB) {
+      TV zv[kMaxPrecModes];
+#pragma unroll
+      for (int q = 0; q < kMaxPrecModes; ++q) zv[q] = q < rq ? z[(int64_t)q * m + e] : TV(0);
+      for (int o = 0; o < n_om; ++o) {
+        TV dlt = TV(0);
+#pragma unroll
+        for (int q = 0; q < kMaxPrecModes; ++q)
+          if (q < rq) dlt += F[o * rq + q] * zv[q];
+        const int64_t at = (int64_t)o * m + e;
+        if constexpr (CYCLE) {
+          s.x[at] += (double)(src[at] + dlt);
+        } else {
+          u[at] = src[at] + dlt;
+          nd[at] = -dlt;
+        }
+      }
+    }
   }
 }
 
@@ -641,10 +780,25 @@ void b_time_gemm16(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, in
   else gemm16<float>(slots, stat, wl, prec, st, tune);
 }
 
+// u = P^-1 v_j and nd = v_j - u (CYCLE = false), or x += P^-1 d with d in
+// nd (CYCLE = true), for the preconditioned slots of the lists
+template <typename TV, bool CYCLE>
+void b_precond(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st) {
+  if constexpr (sizeof(TV) == 2) {
+    fail(RT_E_INVALID, "the preconditioner needs FP64 or FP32 bases");
+  } else {
+    ProfScope prof(RT_KCLASS_PRECOND, st);
+    persist(bk_prec_reduce<TV, CYCLE>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+    persist(bk_prec_mix<TV>, TB, 0, st, slots, wl.chunks, wl.counts);
+    persist(bk_prec_expand<TV, CYCLE>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+  }
+}
+
 template <typename TV>
 void b_inner_iteration(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, int prec,
                        hipStream_t st, const BatchTune& tune) {
   using C = typename ComputeOf<TV>::type;
+  if (wl.any_prec) b_precond<TV, false>(slots, stat, wl, st);
   if constexpr (sizeof(TV) == 8) {
     if (prec != RT_PREC_FP64) fail(RT_E_INVALID, "FP64 vectors need the FP64 operator");
     launch_b_lambda<double, double, double, -1, false>(slots, stat, wl, st);
@@ -682,6 +836,7 @@ template <typename TV>
 void b_cycle_end(const SlotDev* slots, SlotStat* stat, const WorkLists& wl, hipStream_t st) {
   persist(bk_solve_r, 64, 0, st, slots, stat, wl.slots, wl.counts);
   persist(bk_combine<TV>, TB, 0, st, slots, stat, wl.chunks, wl.counts);
+  if (wl.any_prec) b_precond<TV, true>(slots, stat, wl, st);
   launch_b_lambda<double, double, double, -1, true>(slots, stat, wl, st);
   {
     ProfScope prof(RT_KCLASS_SIGMA, st);

@@ -435,7 +435,7 @@ size_t precond_table_bytes(const Problem& p, int elem_bytes) {
          (size_t)(2 * rq * (size_t)p.n_nu * p.n_s + 2 * (size_t)p.n) * elem_bytes;
 }
 
-void precond_prepare_local(Problem& p, hipStream_t st) {
+void precond_check(const Problem& p) {
   if (p.tab.frank == 0 || p.n_classes > 1)
     fail(RT_E_INVALID, "the preconditioner needs the dipole x PRD kernel, one for all points");
   int max_lds = 0;
@@ -443,6 +443,10 @@ void precond_prepare_local(Problem& p, hipStream_t st) {
   if ((size_t)p.n_nu * (p.n_nu + 1) * sizeof(double) + (size_t)p.n_nu * sizeof(int) + 16 >
       (size_t)max_lds)
     fail(RT_E_INVALID, "preconditioner: too many frequencies for the in-LDS block inversion");
+}
+
+void precond_prepare_local(Problem& p, hipStream_t st) {
+  precond_check(p);
   if (p.prec_rq == 0) {
     angular_modes(p);
     p.d_prec_F64 = dcopy<double>(p.prec_F);

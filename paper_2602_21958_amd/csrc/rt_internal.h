@@ -259,6 +259,8 @@ size_t classes_work_elems(const Problem& p);
 void precond_prepare(Problem& p, int elem_bytes, hipStream_t st);
 // the angular modes and Dbar only
 void precond_prepare_local(Problem& p, hipStream_t st);
+// RT_E_INVALID unless the problem can take the preconditioner
+void precond_check(const Problem& p);
 size_t precond_table_bytes(const Problem& p, int elem_bytes);
 template <typename T> void precond_apply(Problem& p, const T* x, T* u, T* nd, hipStream_t st);
 template <typename T> void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st);

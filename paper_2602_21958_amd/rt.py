@@ -382,6 +382,8 @@ class Batch:
         for k, v in opts.items():
             if k == "precision":
                 v = PREC[v] if isinstance(v, str) else v
+            if k == "precond":
+                v = PRECOND[v] if isinstance(v, str) else v
             setattr(o, k, v)
         t = C.c_uint64()
         _check(_lib.rt_batch_submit(self.handle, problem.handle, C.byref(o), _ptr(x_out),

@@ -49,8 +49,9 @@ def small_slabs(count, seed):
 
 
 def run_engine(specs, precision="fp64", order=None, graph=True, budget=1 << 30, max_slots=64,
-               late=None, restart=30, basis_fp16=False):
-    """Solve all specs in one engine; returns (solutions, stats)."""
+               late=None, restart=30, basis_fp16=False, precond=()):
+    """Solve all specs in one engine (the indices in precond preconditioned);
+    returns (solutions, stats)."""
     rt = _rt()
     probs = [rt.Problem(s) for s in specs]
     xs = [torch.empty(p.n, dtype=torch.float64, device="cuda:0") for p in probs]
@@ -61,13 +62,15 @@ def run_engine(specs, precision="fp64", order=None, graph=True, budget=1 << 30, 
     tickets = {}
     for i in order:
         if i not in late:
-            tickets[i] = eng.submit(probs[i], xs[i], restart=restart, rtol=1e-8)
+            tickets[i] = eng.submit(probs[i], xs[i], restart=restart, rtol=1e-8,
+                                    precond="local" if i in precond else "none")
     step = 0
     max_queued = 0
     while True:
         for i, at in late.items():
             if at == step and i not in tickets:
-                tickets[i] = eng.submit(probs[i], xs[i], restart=restart, rtol=1e-8)
+                tickets[i] = eng.submit(probs[i], xs[i], restart=restart, rtol=1e-8,
+                                        precond="local" if i in precond else "none")
         pending = eng.step()
         max_queued = max(max_queued, eng.info()["queued"])
         step += 1
@@ -281,3 +284,76 @@ def test_batch_lists_grow_after_graph_capture():
     for a, b, s1, s2 in zip(ref, got, rst, gst):
         assert s1["converged"] and s2["converged"]
         assert np.array_equal(a, b)
+
+
+def test_batch_preconditioned_matches_single_solver_and_oracle():
+    """Preconditioned solves in the engine (the physics-based preconditioner,
+    Sec. 6 remark) against the single-problem preconditioned solver and the
+    oracle: oracle-evaluated residual <= 1e-8, iteration counts within one
+    of the single solver's and fewer than the unpreconditioned engine's."""
+    rt = _rt()
+    specs = small_slabs(5, 11) + [W.small_box(8, 4, 8, 5)]
+    say("batch preconditioned fp64 vs single")
+    idx = set(range(len(specs)))
+    sols, stats, _ = run_engine(specs, precond=idx)
+    _, plain, _ = run_engine(specs)
+    for spec, s, st, pl in zip(specs, sols, stats, plain):
+        assert st["converged"], st
+        op = OProblem(spec)
+        res = op.residual_norm(s)
+        with rt.Problem(spec) as p:
+            x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+            ref = p.solve(x, rtol=1e-8, restart=30, precond="local")
+        say(f"   iters {st['iters']} (single {ref['iters']}, plain engine {pl['iters']}), "
+            f"oracle residual {res:.2e}")
+        assert res <= 1e-8
+        assert abs(ref["iters"] - st["iters"]) <= 1
+        assert st["iters"] < pl["iters"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16x3"])
+def test_batch_preconditioned_mixed_reaches_fp64_residual(precision):
+    specs = small_slabs(4, 12) + [W.small_box(8, 4, 8, 5)]
+    say(f"batch preconditioned {precision}")
+    sols, stats, _ = run_engine(specs, precision=precision, precond=set(range(len(specs))))
+    for spec, s, st in zip(specs, sols, stats):
+        res = OProblem(spec).residual_norm(s)
+        say(f"   iters {st['iters']} outer {st['outer_iters']}, oracle residual {res:.2e}")
+        assert st["converged"] and res <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_batch_preconditioned_alone_equals_in_mix_bitwise(precision):
+    """A mix of preconditioned and plain solves: each result is bitwise the
+    same alone and in the mix."""
+    specs = small_slabs(6, 13) + [W.small_box(8, 4, 8, 5)]
+    pre = {0, 2, 5, 6}
+    say(f"preconditioned alone vs mix {precision}")
+    mix, mstats, _ = run_engine(specs, precision=precision, order=[6, 3, 0, 5, 1, 4, 2],
+                                precond=pre)
+    for i in (0, 1, 6):
+        alone, astats, _ = run_engine([specs[i]], precision=precision,
+                                      precond={0} if i in pre else set())
+        assert astats[0]["converged"] and mstats[i]["converged"]
+        assert astats[0]["iters"] == mstats[i]["iters"]
+        assert np.array_equal(alone[0], mix[i]), i
+
+
+def test_batch_preconditioner_rejections():
+    rt = _rt()
+    spec = small_slabs(1, 14)[0]
+    with rt.Problem(spec) as p:
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        eng = rt.Batch(precision="fp16", basis_fp16=True)
+        with pytest.raises(RuntimeError):
+            eng.submit(p, x, precond="local")
+        eng.close()
+    n_r = OProblem(spec).n_r
+    spec.kernel = "explicit"
+    spec.kernel_matrix = W.random_symmetric_kernel(n_r, 5)
+    with rt.Problem(spec) as p:
+        x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
+        eng = rt.Batch(precision="fp64")
+        with pytest.raises(RuntimeError):
+            eng.submit(p, x, precond="local")
+        eng.close()
