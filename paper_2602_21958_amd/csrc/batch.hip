@@ -514,7 +514,18 @@ __global__ __launch_bounds__(TB) void bk_prec_reduce(const SlotDev* __restrict__
       TV acc[kMaxPrecModes];
 #pragma unroll
       for (int q = 0; q < kMaxPrecModes; ++q) acc[q] = TV(0);
-      for (int o = 0; o < n_om; ++o) {
+      int o = 0;
+      for (; o + 4 <= n_om; o += 4) {   // four loads in flight
+        TV v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[(int64_t)(o + u) * m + e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < kMaxPrecModes; ++q)
+            if (q < rq) acc[q] += G[(o + u) * rq + q] * v[u];
+      }
+      for (; o < n_om; ++o) {
         const TV v = src[(int64_t)o * m + e];
 #pragma unroll
         for (int q = 0; q < kMaxPrecModes; ++q)
@@ -527,16 +538,33 @@ __global__ __launch_bounds__(TB) void bk_prec_reduce(const SlotDev* __restrict__
   }
 }
 
-// z[q][nu][i] = sum_k T[q][i][nu][k] r[q][k][i]: one wave per block (q, i),
-// lane k holding r[q][k][i] (and k + 64), each row of the block read by the
-// whole wave in one coalesced load and summed across the lanes.  Item c of a
-// slot takes the blocks 4 c + w, 4 c + w + 4 nch, ... (w the wave).
+// z[q][nu][i] = sum_k T[q][i][nu][k] r[q][k][i]: one wave per block (q, i).
+// FP32 blocks of up to kMixLds rows go through LDS: the wave copies the block
+// with coalesced loads into its own region (rows padded to n + 1, so that
+// lanes reading one row each hit distinct banks) with r beside it, then lane
+// nu sums its row.  Larger and FP64 blocks read their rows from global
+// memory.  Item c of a slot takes the blocks 4 c + w, 4 c + w + 4 nch, ...
+// (w the wave); the waves of a workgroup never wait for each other.
+constexpr int kMixLds = 64;
+
+template <typename TV>
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 template <typename TV>
 __global__ __launch_bounds__(TB) void bk_prec_mix(const SlotDev* __restrict__ slots,
                                                   const Item* __restrict__ items,
                                                   const int* __restrict__ counts) {
+  // FP32 tables only: an FP64 region would leave one workgroup per CU,
+  // which measured slower than the global-memory rows
+  constexpr bool kLds = sizeof(TV) == 4;
+  __shared__ TV lds[kLds ? 4 : 1][kLds ? kMixLds * (kMixLds + 1) + kMixLds : 1];
   const int cnt = counts[3];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  TV* L = lds[kLds ? wave : 0];
   for (int it = blockIdx.x; it < cnt; it += gridDim.x) {
     const Item w = items[it];
     const SlotDev& s = slots[w.slot];
@@ -550,15 +578,29 @@ __global__ __launch_bounds__(TB) void bk_prec_mix(const SlotDev* __restrict__ sl
       const int q = (int)(b / s.n_s);
       const int64_t i = b - (int64_t)q * s.n_s;
       const TV* rq = r + (int64_t)q * m + i;
-      const double r0 = lane < n ? (double)rq[(int64_t)lane * s.n_s] : 0.0;
-      const double r1 = lane + 64 < n ? (double)rq[(int64_t)(lane + 64) * s.n_s] : 0.0;
       const TV* blk = T + (size_t)b * n * n;
-      for (int nu = 0; nu < n; ++nu) {
-        const TV* row = blk + (size_t)nu * n;
-        double v = lane < n ? (double)row[lane] * r0 : 0.0;
-        if (lane + 64 < n) v += (double)row[lane + 64] * r1;
-        v = wsum(v);
-        if (lane == 0) z[(int64_t)q * m + (int64_t)nu * s.n_s + i] = (TV)v;
+      TV* zq = z + (int64_t)q * m + i;
+      if (kLds && n <= kMixLds) {
+        TV* rl = L + n * (n + 1);
+        for (int e = lane; e < n * n; e += 64) {
+          const int row = e / n;
+          L[row * (n + 1) + (e - row * n)] = blk[e];
+        }
+        if (lane < n) rl[lane] = rq[(int64_t)lane * s.n_s];
+        wave_lds_sync<TV>();
+        if (lane < n) {
+          TV acc = TV(0);
+          const TV* row = L + lane * (n + 1);
+          for (int k = 0; k < n; ++k) acc += row[k] * rl[k];
+          zq[(int64_t)lane * s.n_s] = acc;
+        }
+        wave_lds_sync<TV>();   // the next block overwrites the region
+      } else {
+        for (int nu = lane; nu < n; nu += 64) {
+          TV acc = TV(0);
+          for (int k = 0; k < n; ++k) acc += blk[(size_t)nu * n + k] * rq[(int64_t)k * s.n_s];
+          zq[(int64_t)nu * s.n_s] = acc;
+        }
       }
     }
   }
@@ -591,7 +633,27 @@ __global__ __launch_bounds__(TB) void bk_prec_expand(const SlotDev* __restrict__
       TV zv[kMaxPrecModes];
 #pragma unroll
       for (int q = 0; q < kMaxPrecModes; ++q) zv[q] = q < rq ? z[(int64_t)q * m + e] : TV(0);
-      for (int o = 0; o < n_om; ++o) {
+      int o = 0;
+      for (; o + 4 <= n_om; o += 4) {   // four loads in flight
+        TV sv[4];
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) sv[uu] = src[(int64_t)(o + uu) * m + e];
+#pragma unroll
+        for (int uu = 0; uu < 4; ++uu) {
+          TV dlt = TV(0);
+#pragma unroll
+          for (int q = 0; q < kMaxPrecModes; ++q)
+            if (q < rq) dlt += F[(o + uu) * rq + q] * zv[q];
+          const int64_t at = (int64_t)(o + uu) * m + e;
+          if constexpr (CYCLE) {
+            s.x[at] += (double)(sv[uu] + dlt);
+          } else {
+            u[at] = sv[uu] + dlt;
+            nd[at] = -dlt;
+          }
+        }
+      }
+      for (; o < n_om; ++o) {
         TV dlt = TV(0);
 #pragma unroll
         for (int q = 0; q < kMaxPrecModes; ++q)
