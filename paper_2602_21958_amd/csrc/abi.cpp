@@ -472,6 +472,11 @@ void problem_build(Problem& p, const rt_problem_desc& d_in) {
       s.tx = sx - fx;
       s.ty = sy - fy;
       s.path = path;
+      s.w00 = (1.0 - s.ty) * (1.0 - s.tx);
+      s.w01 = (1.0 - s.ty) * s.tx;
+      s.w10 = s.ty * (1.0 - s.tx);
+      s.w11 = s.ty * s.tx;
+      s.hpath = 0.5 * path;
       s.up = mu > 0 ? 1 : 0;
       const double dx = p.tab.om_x[o] * path * p.nx;
       const double dy = p.tab.om_y[o] * path * p.ny;

@@ -341,13 +341,18 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   std::vector<Item> slab, box, tiles, chunks;
   std::vector<int> slots;
   int pmax = 0;
+  size_t phmax = 0;
   for (int s : set)
-    if (h_slots[s].geom != RT_GEOM_SLAB) pmax = std::max(pmax, h_slots[s].nx * h_slots[s].ny);
+    if (h_slots[s].geom != RT_GEOM_SLAB) {
+      pmax = std::max(pmax, h_slots[s].nx * h_slots[s].ny);
+      // LDS plane with its halo row and column
+      phmax = std::max(phmax, (size_t)(h_slots[s].nx + 1) * (h_slots[s].ny + 1));
+    }
   if (max_lds == 0)
     RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
   // frequencies per box work item: one list serves the FP64 (cycle end) and
   // the low-precision sweeps, so size it for FP64
-  const int bf = pmax > 0 ? std::max(1, box_chunk(pmax, (int)sizeof(double), max_lds)) : 1;
+  const int bf = pmax > 0 ? std::max(1, box_chunk(phmax, (int)sizeof(double), max_lds)) : 1;
   for (int s : set) {
     const SlotDev& d = h_slots[s];
     slots.push_back(s);
@@ -411,6 +416,7 @@ void Engine::build_lists(WorkLists& wl, const std::vector<int>& set) {
   wl.any_prec = false;
   for (int s : set) wl.any_prec = wl.any_prec || h_slots[s].prq > 0;
   wl.box_pmax = pmax;
+  wl.box_phmax = phmax;
   wl.box_npt = pmax <= 256 ? 1 : (pmax <= 1024 ? 2 : 16);
   wl.box_f = bf;
   wl.max_lds = max_lds;

@@ -94,6 +94,7 @@ struct WorkLists {
   int h_counts[5] = {0, 0, 0, 0, 0};
   int box_npt = 1;           // points per thread class for box rays (1, 2, 16)
   int box_pmax = 0;          // largest box plane among the listed slots
+  size_t box_phmax = 0;      // largest box plane with its LDS halo (lam::box_halo)
   int box_f = 1;             // frequencies per box item (1 or 4)
   int max_lds = 0;           // LDS bytes per workgroup of the device
   bool any_prec = false;     // some listed slot is preconditioned

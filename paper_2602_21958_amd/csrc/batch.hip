@@ -774,8 +774,9 @@ void launch_b_lambda(const SlotDev* slots, const SlotStat* stat, const WorkLists
   if (wl.h_counts[1] > 0) {
     // two alternating LDS sets where they fit (the kernel takes PP = true
     // only then; PP = false needs no more than lds either way)
-    const bool pp = box_pingpong(wl.box_f, wl.box_pmax, (int)sizeof(C), wl.max_lds);
-    const size_t lds = lam::box_lds_elems(wl.box_f, wl.box_pmax, pp) * sizeof(C);
+    const bool pp = box_pingpong(wl.box_f, wl.box_pmax, wl.box_phmax, (int)sizeof(C),
+                                 wl.max_lds);
+    const size_t lds = lam::box_lds_elems(wl.box_f, wl.box_phmax, pp) * sizeof(C);
 #define RT_BBOX1(FF, NPT, NT, PPV)                                                          \
   persist(bk_lambda_box<VT, LT, C, K4, FF, NPT, NT, PPV, OUTER>, NT, lds, st, slots, stat, \
           wl.lam_box, wl.counts)

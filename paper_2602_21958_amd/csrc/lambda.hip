@@ -119,18 +119,19 @@ template <> struct ComputeOf<_Float16> { using type = float; };
 // together shares the upwind stencil and opacity but needs 4x the per-thread
 // state, and at the occupancy that leaves it was measured slower on the 32^3
 // box (FP64 0.82 against 0.40 ms; FP32 0.22 against 0.19 ms).
-int box_chunk(int P, int elem_bytes, int max_lds) {
-  return (size_t)3 * P * elem_bytes <= (size_t)max_lds ? 1 : 0;
+int box_chunk(size_t PH, int elem_bytes, int max_lds) {
+  return 3 * PH * elem_bytes <= (size_t)max_lds ? 1 : 0;
 }
 
 // Measured with two sets against one on the 32^3 box: FP64 0.239 -> 0.226 ms
 // (72 against 92 VGPRs: three groups per CU instead of two), FP32 0.144 ->
-// 0.141 ms, fp16 input 0.153 -> 0.126 ms; on 64^2 planes (FP32, 1024
-// threads, one group per CU either way) 5.76 -> 5.86 ms, so larger planes
-// keep one set.
-bool box_pingpong(int F, int P, int elem_bytes, int max_lds) {
-  if (F != 1 || lam::box_lds_elems(F, P, true) * elem_bytes > (size_t)max_lds) return false;
-  return P <= 1024;
+// 0.141 ms, fp16 input 0.153 -> 0.126 ms.  On 64^2 planes (1024 threads,
+// one group per CU either way) the FP32 form gains too (fp16 operand
+// 4.10 -> 3.89 ms per box64 sweep, bf16x3 5.43 -> 5.13 ms), while the FP64
+// form's two sets would not fit in LDS.
+bool box_pingpong(int F, int P, size_t PH, int elem_bytes, int max_lds) {
+  if (F != 1 || lam::box_lds_elems(F, PH, true) * elem_bytes > (size_t)max_lds) return false;
+  return P <= 1024 || elem_bytes == 4;
 }
 
 template <typename VT, typename LT, int K4>
@@ -149,11 +150,12 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
     const int P = p.nx * p.ny;
     int max_lds = 0;
     RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p.device));
-    const int F = box_chunk(P, (int)sizeof(C), max_lds);
+    const size_t PH = lam::box_halo(p.nx, p.ny);
+    const int F = box_chunk(PH, (int)sizeof(C), max_lds);
     if (F == 0) fail(RT_E_INVALID, "box plane too large for LDS in this precision");
     // the kernel takes PP = true only where pp sized the LDS for two sets
-    const bool pp = box_pingpong(F, P, (int)sizeof(C), max_lds);
-    const size_t lds = lam::box_lds_elems(F, P, pp) * sizeof(C);
+    const bool pp = box_pingpong(F, P, PH, (int)sizeof(C), max_lds);
+    const size_t lds = lam::box_lds_elems(F, PH, pp) * sizeof(C);
     const int grid = p.n_omega * ((p.n_nu + F - 1) / F);
     // one ray per group (group index = ray index) into the k4 operand
     const int xcd = (K4 >= 0 && F == 1) ? 1 : 0;
@@ -169,13 +171,15 @@ void lambda_dispatch(const Problem& p, const VT* s, void* out0, void* out1, int6
   if (pp) { RT_BOX_LAUNCH1(FF, NPT, NT, true); } \
   else { RT_BOX_LAUNCH1(FF, NPT, NT, false); }
     // planes up to 256 points: 256 threads; up to 1024 points: 512 threads of
-    // 2 points each (FP64 with two LDS sets: 72 VGPRs, three groups per CU;
+    // 2 points each (FP64 with two LDS sets: 64 VGPRs, three groups per CU;
     // 256 threads of 4 points or 1024 threads of 1 point measured slower on
-    // the 32^3 box); up to 4096 points: 1024 threads of 4 points (FP64: 128
-    // VGPRs with a few spilled, 16 waves per CU, 10.6 ms on the 64^3 box
-    // against 11.7 ms for 512 threads of 8 points at 250 VGPRs)
+    // the 32^3 box); up to 4096 points: 1024 threads of 4 points (FP64: 101
+    // VGPRs, 16 waves per CU; 512 threads of 8 points took 250 VGPRs and
+    // more time); the FP32 form computes all its point slots, so planes of
+    // up to 2048 points take two
     if (P <= 256) { RT_BOX_LAUNCH(1, 1, 256); }
     else if (P <= 1024) { RT_BOX_LAUNCH(1, 2, 512); }
+    else if (P <= 2048) { RT_BOX_LAUNCH(1, 2, 1024); }
     else if (P <= 4096) { RT_BOX_LAUNCH(1, 4, 1024); }
     else {
       fail(RT_E_INVALID, "box plane larger than 4096 points");

@@ -216,6 +216,12 @@ struct PlainOuts {
   __device__ __forceinline__ void put(int f, size_t i, C v) const {
     o[(size_t)f * stride + i] = store_val<C, LT>(v);
   }
+  // element base + i: base the same for the whole wavefront, i per lane
+  template <typename C>
+  __device__ __forceinline__ void put(int f, size_t base, int i, C v) const {
+    LT* r = o + (size_t)f * stride + base;
+    r[(unsigned)i] = store_val<C, LT>(v);
+  }
 };
 
 template <int MODE>
@@ -230,6 +236,13 @@ struct K4Outs {
     const int k = k0 + f;
     const size_t off = ((size_t)(k >> 2) * Np) * 4 + (k & 3);
     K4Out<MODE>{hi + off, lo ? lo + off : nullptr}.put(i, v);
+  }
+  // element base + i: base the same for the whole wavefront, i per lane
+  template <typename C>
+  __device__ __forceinline__ void put(int f, size_t base, int i, C v) const {
+    const int k = k0 + f;
+    const size_t off = ((size_t)(k >> 2) * Np + base) * 4 + (k & 3);
+    K4Out<MODE>{hi + off, lo ? lo + off : nullptr}.put((unsigned)i, v);
   }
 };
 
@@ -325,19 +338,53 @@ __device__ __forceinline__ void slab_ray(const VT* __restrict__ sk, const OUT ou
 // stencil, the interpolated opacity and the step's optical depth up to the
 // frequency factor are computed once per point and used by all F rays; the
 // previous plane's intensities and sources (per ray) and opacity sit in LDS,
-// (2F + 1) P values of type C (box_lds_elems).  PP: two such sets, written
-// by alternate planes, so that a plane needs one barrier (its writes go to
-// the set the next plane reads, while the set it reads is not written);
-// otherwise one set and two barriers per plane.  The next plane's sources
-// and opacity are loaded a plane ahead and kept as loaded (no arithmetic on
-// them before they are used, so the loads stay in flight over a plane).
+// (2F + 1) values per point.  PP: two such sets, written by alternate planes,
+// so that a plane needs one barrier (its writes go to the set the next plane
+// reads, while the set it reads is not written); otherwise one set and two
+// barriers per plane.  The next plane's sources and opacity are loaded a
+// plane ahead and kept as loaded (no arithmetic on them before they are
+// used, so the loads stay in flight over a plane).  Every thread takes up to
+// kBoxMaxPts points of each plane (point threadIdx.x + j NT).
+//
+// Both forms keep each plane in LDS with one halo column and row (copies of
+// column 0 and row 0: box_halo), so that the four corners of every upwind
+// stencil are a, a + 1, a + W and a + W + 1 (W = nx + 1) with no wrap and
+// one index per point serves them all; the stencil indices are re-formed
+// inside the plane loop (an empty asm statement stops the compiler from
+// hoisting every derived address out of the loop, which spilled).  The sums
+// of products are explicit FMA chains, so that every launch shape rounds
+// alike (the compiler's own contraction may fuse a different product from
+// one instantiation to the next).
+//
+// Two forms, by compute type:
+// * FP32 (box_rays_halo): a slot past the plane computes on the plane's
+//   last point and is neither stored nor written to LDS, so no load sits
+//   under a branch.  Loads and stores to global memory share one wait
+//   counter, which is waited down to zero whenever both kinds are
+//   outstanding; so the intensities of plane t are stored at the start of
+//   plane t + 1, right after the wait for its sources and next to the loads
+//   of plane t + 2, and the wait of every plane finds both a plane old
+//   (quadratic sweeps, which read downwind values from global memory in
+//   mid-plane, store at the end of the plane).  A point's 2F + 1 values
+//   sit side by side, so that one address serves a stencil row (paired
+//   LDS reads).  64^2 planes: 5.2 -> 4.1 ms per box64 sweep (fp16 operand).
+// * FP64 (box_rays_sep): separate opacity, intensity and source planes, a
+//   uniform exit per slot, stores at the end of each plane, and bilinear
+//   weights formed on the host (scalar registers): 64 VGPRs at two points
+//   per thread (eight waves per SIMD on 32^2 planes) and 101 at four with no
+//   spill (10.5 -> 8.9 ms per box64 sweep).  The FP32 form's layout and
+//   deferred stores hold more FP64 registers: 0.243 against 0.215 ms per
+//   box32 sweep, 12.8 against 10.5 ms on box64.
 //
 // src(f): the ray's nz*P source values; fac[f]: phi_nu + r of ray f;
 // out.put(f, i, v) stores value i of ray f.
 constexpr int kBoxThreads = 256;
 
-// LDS elements of type C that box_rays needs.
-constexpr size_t box_lds_elems(int F, int P, bool pp) { return (size_t)(pp ? 2 : 1) * (2 * F + 1) * P; }
+// Points of an LDS plane with its halo row and column.
+constexpr size_t box_halo(int nx, int ny) { return (size_t)(nx + 1) * (ny + 1); }
+
+// LDS elements of type C that box_rays needs, for halo planes of PH values.
+constexpr size_t box_lds_elems(int F, size_t PH, bool pp) { return (size_t)(pp ? 2 : 1) * (2 * F + 1) * PH; }
 
 //
 // QUAD: quadratic short characteristics (qsc_weights): every plane but the
@@ -348,38 +395,225 @@ constexpr size_t box_lds_elems(int F, int P, bool pp) { return (size_t)(pp ? 2 :
 // L2 as the next plane's local values).
 template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads,
           bool PP = false, bool QUAD = false>
-__device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_stride, int nf,
+__device__ __forceinline__ void box_rays_halo(const VT* __restrict__ s0, size_t ray_stride, int nf,
                                          const OUT& out, const double* __restrict__ kline,
                                          const BoxStencil st, const C* fac, int nx, int ny,
                                          int nz, C i_in, C sc, float out_mul, C* smem) {
   const int P = nx * ny;
-  const size_t set = (size_t)(2 * F + 1) * P;   // one set: K [P], I [F][P], S [F][P]
+  constexpr int V = 2 * F + 1;           // values per LDS point: K, I [F], S [F]
+  const int W = nx + 1;                  // LDS points per row
+  const int WV = W * V;                  // LDS row pitch in elements
+  const size_t PH = box_halo(nx, ny);
+  const size_t set = (size_t)V * PH;
   const C hpath = C(0.5) * C(st.path);   // exact: (a / 2) path = a (path / 2)
   const C tx = C(st.tx), ty = C(st.ty);
   const size_t plane_stride = (size_t)P;
+  constexpr bool kDefer = !QUAD;
+
+  // slot j: point pc[j] (clamped to the plane); nb[j]: LDS element of its
+  // upwind stencil's first corner; hq[j]: its own LDS element, with bit 20
+  // set on column 0 and bit 21 on row 0 (the values the halo repeats)
+  int pc[kBoxMaxPts], nb[kBoxMaxPts], hq[kBoxMaxPts];
+  bool live[kBoxMaxPts];
+#pragma unroll
+  for (int j = 0; j < kBoxMaxPts; ++j) {
+    const int p = threadIdx.x + j * NT;
+    live[j] = p < P;
+    pc[j] = live[j] ? p : P - 1;
+    const int x = pc[j] % nx, y = pc[j] / nx;
+    int xa = x + st.i0; if (xa >= nx) xa -= nx;
+    int ya = y + st.j0; if (ya >= ny) ya -= ny;
+    nb[j] = (ya * W + xa) * V;
+    hq[j] = (y * W + x) * V | (x == 0 ? 1 << 20 : 0) | (y == 0 ? 1 << 21 : 0);
+  }
+  const C w00 = (C(1) - ty) * (C(1) - tx), w01 = (C(1) - ty) * tx;
+  const C w10 = ty * (C(1) - tx), w11 = ty * tx;
+  const C om = C(out_mul);
+  // downwind stencil (QUAD)
+  int d00[QUAD ? kBoxMaxPts : 1], d01[QUAD ? kBoxMaxPts : 1];
+  int d10[QUAD ? kBoxMaxPts : 1], d11[QUAD ? kBoxMaxPts : 1];
+  C v00 = C(0), v01 = C(0), v10 = C(0), v11 = C(0);
+  if constexpr (QUAD) {
+    const C dtx = C(st.dtx), dty = C(st.dty);
+    v00 = (C(1) - dty) * (C(1) - dtx);
+    v01 = (C(1) - dty) * dtx;
+    v10 = dty * (C(1) - dtx);
+    v11 = dty * dtx;
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      const int x = pc[j] % nx, y = pc[j] / nx;
+      int xa = x + st.di0; if (xa >= nx) xa -= nx;
+      int xb = xa + 1;     if (xb >= nx) xb -= nx;
+      int ya = y + st.dj0; if (ya >= ny) ya -= ny;
+      int yb = ya + 1;     if (yb >= ny) yb -= ny;
+      d00[j] = ya * nx + xa;
+      d01[j] = ya * nx + xb;
+      d10[j] = yb * nx + xa;
+      d11[j] = yb * nx + xb;
+    }
+  }
+  // source of ray slot f (slots past nf repeat the last ray and are not stored)
+  const VT* src[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) src[f] = s0 + (size_t)(f < nf ? f : nf - 1) * ray_stride;
+  auto plane_of = [&](int t) { return st.up ? t : nz - 1 - t; };
+
+  // sources and opacity of the next plane, loaded one plane ahead
+  VT Sn[F][kBoxMaxPts];
+  double Kn[kBoxMaxPts];
+  C Sv[F][kBoxMaxPts], Iv[F][kBoxMaxPts], Kv[kBoxMaxPts];
+  auto load_plane = [&](int t) {
+    const size_t oz = (size_t)plane_of(t) * plane_stride;
+    const double* kz = kline + oz;
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) Kn[j] = kz[(unsigned)pc[j]];
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      // unsigned lane offsets: one 32-bit offset register from a uniform base
+      const unsigned q = (unsigned)pc[j];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        const VT* sz = src[f] + oz;
+        Sn[f][j] = sz[q];
+      }
+    }
+  };
+  // the intensities of plane t, held in Iv
+  auto store_plane = [&](int t) {
+    const size_t oz = (size_t)plane_of(t) * plane_stride;
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      if (!live[j]) continue;
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+        if (f < nf) out.put(f, oz, pc[j], scaled_out<OUT>(Iv[f][j], om));
+    }
+  };
+  load_plane(0);
+  for (int t = 0; t < nz; ++t) {
+    const int z = plane_of(t);
+    // the set the previous plane wrote, and the one this plane writes
+    const C* rd = smem + (PP ? (size_t)((t + 1) & 1) * set : 0);
+    C* wr = smem + (PP ? (size_t)(t & 1) * set : 0);
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      Kv[j] = C(Kn[j]);
+#pragma unroll
+      for (int f = 0; f < F; ++f) Sv[f][j] = sc * C(Sn[f][j]);
+    }
+    if constexpr (kDefer) {
+      if (t > 0) store_plane(t - 1);
+    }
+    // the last plane loads itself again (in the L2), keeping the loads unconditional
+    load_plane(t + 1 < nz ? t + 1 : t);
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      C I[F];
+      if (t == 0) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) I[f] = i_in;
+      } else {
+        int a = nb[j];
+        asm volatile("" : "+v"(a));    // addresses from a are formed here, not kept live
+        const C* r0 = rd + a;          // stencil rows
+        const C* r1 = r0 + WV;
+        // value c of the four corners
+        auto interp = [&](int c) {
+          return fma(w11, r1[V + c], fma(w10, r1[c], fma(w01, r0[V + c], w00 * r0[c])));
+        };
+        const C ku = interp(0);
+        const C base = (ku + Kv[j]) * hpath;
+        if (QUAD && t + 1 < nz) {
+          const int zd = st.up ? z + 1 : z - 1;
+          const double* kd = kline + (size_t)zd * plane_stride;
+          const C kdn = fma(v11, C(kd[d11[j]]),
+                            fma(v10, C(kd[d10[j]]), fma(v01, C(kd[d01[j]]), v00 * C(kd[d00[j]]))));
+          const C based = (kdn + Kv[j]) * hpath;
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            const VT* sd = src[f] + (size_t)zd * plane_stride;
+            const C Iu = interp(1 + f);
+            const C Su = interp(1 + F + f);
+            const C Sd = sc * fma(v11, C(sd[d11[j]]),
+                                  fma(v10, C(sd[d10[j]]),
+                                      fma(v01, C(sd[d01[j]]), v00 * C(sd[d00[j]]))));
+            C e, pu, p0, pd;
+            qsc_weights<C>(base * fac[f], based * fac[f], e, pu, p0, pd);
+            I[f] = fma(pd, Sd, fma(p0, Sv[f][j], fma(pu, Su, e * Iu)));
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            const C Iu = interp(1 + f);
+            const C Su = interp(1 + F + f);
+            C e, a, c;
+            sc_weights<C, true>(base * fac[f], e, a, c);   // branch form
+            I[f] = fma(c, Sv[f][j], fma(a, Su, e * Iu));
+          }
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < F; ++f) Iv[f][j] = I[f];
+    }
+    if constexpr (!kDefer) store_plane(t);
+    if constexpr (!PP) __syncthreads();   // every read of the one set is done
+    auto put_lds = [&](int q, int j) {
+      C* w = wr + q;
+      w[0] = Kv[j];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        w[1 + f] = Iv[f][j];
+        w[1 + F + f] = Sv[f][j];
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < kBoxMaxPts; ++j) {
+      if (!live[j]) continue;
+      int h = hq[j];
+      asm volatile("" : "+v"(h));    // as for the reads
+      const int q = h & 0xfffff;
+      put_lds(q, j);
+      if (h & (1 << 20)) put_lds(q + nx * V, j);                // halo column
+      if (h & (1 << 21)) put_lds(q + ny * WV, j);               // halo row
+      if ((h >> 20) == 3) put_lds(q + ny * WV + nx * V, j);     // halo corner
+    }
+    __syncthreads();
+  }
+  if constexpr (kDefer) store_plane(nz - 1);
+}
+
+template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads,
+          bool PP = false, bool QUAD = false>
+__device__ __forceinline__ void box_rays_sep(const VT* __restrict__ s0, size_t ray_stride, int nf,
+                                         const OUT& out, const double* __restrict__ kline,
+                                         const BoxStencil st, const C* fac, int nx, int ny,
+                                         int nz, C i_in, C sc, float out_mul, C* smem) {
+  const int P = nx * ny;
+  const int W = nx + 1;                 // LDS points per row (halo column)
+  const size_t PH = box_halo(nx, ny);
+  const size_t set = (size_t)(2 * F + 1) * PH;   // one set: K [PH], I [F][PH], S [F][PH]
+  const C hpath = C(st.hpath);   // exact: (a / 2) path = a (path / 2)
+  const size_t plane_stride = (size_t)P;
 
   const int npt = (P + NT - 1) / NT;
-  int n00[kBoxMaxPts], n01[kBoxMaxPts], n10[kBoxMaxPts], n11[kBoxMaxPts];
+  // slot j: nb[j], the LDS index of its upwind stencil's first corner (the
+  // others at + 1, + W, + W + 1); hq[j], its own LDS index, with bit 20 set on
+  // column 0 and bit 21 on row 0 (the values the halo repeats)
+  int nb[kBoxMaxPts], hq[kBoxMaxPts];
 #pragma unroll
   for (int j = 0; j < kBoxMaxPts; ++j) {
     if (j >= npt) break;
     const int p = threadIdx.x + j * NT;
+    nb[j] = hq[j] = 0;
     if (p < P) {
       const int x = p % nx, y = p / nx;
       int xa = x + st.i0; if (xa >= nx) xa -= nx;
-      int xb = xa + 1;    if (xb >= nx) xb -= nx;
       int ya = y + st.j0; if (ya >= ny) ya -= ny;
-      int yb = ya + 1;    if (yb >= ny) yb -= ny;
-      n00[j] = ya * nx + xa;
-      n01[j] = ya * nx + xb;
-      n10[j] = yb * nx + xa;
-      n11[j] = yb * nx + xb;
-    } else {
-      n00[j] = n01[j] = n10[j] = n11[j] = 0;
+      nb[j] = ya * W + xa;
+      hq[j] = (y * W + x) | (x == 0 ? 1 << 20 : 0) | (y == 0 ? 1 << 21 : 0);
     }
   }
-  const C w00 = (C(1) - ty) * (C(1) - tx), w01 = (C(1) - ty) * tx;
-  const C w10 = ty * (C(1) - tx), w11 = ty * tx;
+  const C w00 = C(st.w00), w01 = C(st.w01), w10 = C(st.w10), w11 = C(st.w11);
   const C om = C(out_mul);
   // downwind stencil (QUAD)
   int d00[QUAD ? kBoxMaxPts : 1], d01[QUAD ? kBoxMaxPts : 1];
@@ -433,11 +667,11 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
     const size_t oz = (size_t)z * plane_stride;
     // the set the previous plane wrote, and the one this plane writes
     const C* rK = smem + (PP ? (size_t)((t + 1) & 1) * set : 0);
-    const C* rI = rK + P;
-    const C* rS = rI + F * P;
+    const C* rI = rK + PH;
+    const C* rS = rI + F * PH;
     C* wK = smem + (PP ? (size_t)(t & 1) * set : 0);
-    C* wI = wK + P;
-    C* wS = wI + F * P;
+    C* wI = wK + PH;
+    C* wS = wI + F * PH;
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
@@ -456,37 +690,39 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
 #pragma unroll
         for (int f = 0; f < F; ++f) I[f] = i_in;
       } else {
-        const C ku = w00 * rK[n00[j]] + w01 * rK[n01[j]] + w10 * rK[n10[j]] + w11 * rK[n11[j]];
+        int a = nb[j];
+        asm volatile("" : "+v"(a));    // addresses from a are formed here, not kept live
+        auto interp = [&](const C* v) {
+          return fma(w11, v[a + W + 1], fma(w10, v[a + W], fma(w01, v[a + 1], w00 * v[a])));
+        };
+        const C ku = interp(rK);
         const C base = (ku + Kv[j]) * hpath;
         if (QUAD && t + 1 < nz) {
           const int zd = st.up ? z + 1 : z - 1;
           const double* kd = kline + (size_t)zd * plane_stride;
-          const C kdn = v00 * C(kd[d00[j]]) + v01 * C(kd[d01[j]]) + v10 * C(kd[d10[j]]) +
-                        v11 * C(kd[d11[j]]);
+          const C kdn = fma(v11, C(kd[d11[j]]),
+                            fma(v10, C(kd[d10[j]]), fma(v01, C(kd[d01[j]]), v00 * C(kd[d00[j]]))));
           const C based = (kdn + Kv[j]) * hpath;
 #pragma unroll
           for (int f = 0; f < F; ++f) {
-            const C* If = rI + f * P;
-            const C* Sf = rS + f * P;
             const VT* sd = s0 + (size_t)f * ray_stride + (size_t)zd * plane_stride;
-            const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
-            const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
-            const C Sd = sc * (v00 * C(sd[d00[j]]) + v01 * C(sd[d01[j]]) + v10 * C(sd[d10[j]]) +
-                               v11 * C(sd[d11[j]]));
+            const C Iu = interp(rI + f * PH);
+            const C Su = interp(rS + f * PH);
+            const C Sd = sc * fma(v11, C(sd[d11[j]]),
+                                  fma(v10, C(sd[d10[j]]),
+                                      fma(v01, C(sd[d01[j]]), v00 * C(sd[d00[j]]))));
             C e, pu, p0, pd;
             qsc_weights<C>(base * fac[f], based * fac[f], e, pu, p0, pd);
-            I[f] = e * Iu + pu * Su + p0 * Sv[f][j] + pd * Sd;
+            I[f] = fma(pd, Sd, fma(p0, Sv[f][j], fma(pu, Su, e * Iu)));
           }
         } else {
 #pragma unroll
           for (int f = 0; f < F; ++f) {
-            const C* If = rI + f * P;
-            const C* Sf = rS + f * P;
-            const C Iu = w00 * If[n00[j]] + w01 * If[n01[j]] + w10 * If[n10[j]] + w11 * If[n11[j]];
-            const C Su = w00 * Sf[n00[j]] + w01 * Sf[n01[j]] + w10 * Sf[n10[j]] + w11 * Sf[n11[j]];
+            const C Iu = interp(rI + f * PH);
+            const C Su = interp(rS + f * PH);
             C e, a, c;
             sc_weights<C, true>(base * fac[f], e, a, c);   // branch form
-            I[f] = e * Iu + a * Su + c * Sv[f][j];
+            I[f] = fma(c, Sv[f][j], fma(a, Su, e * Iu));
           }
         }
       }
@@ -497,20 +733,45 @@ __device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_s
       for (int f = 0; f < F; ++f) Iv[f][j] = I[f];
     }
     if constexpr (!PP) __syncthreads();   // every read of the one set is done
+    auto put_lds = [&](int q, int j) {
+      wK[q] = Kv[j];
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        wI[f * PH + q] = Iv[f][j];
+        wS[f * PH + q] = Sv[f][j];
+      }
+    };
 #pragma unroll
     for (int j = 0; j < kBoxMaxPts; ++j) {
       if (j >= npt) break;
       const int p = threadIdx.x + j * NT;
       if (p >= P) break;
-      wK[p] = Kv[j];
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        wI[f * P + p] = Iv[f][j];
-        wS[f * P + p] = Sv[f][j];
-      }
+      int h = hq[j];
+      asm volatile("" : "+v"(h));    // as for the reads
+      const int q = h & 0xfffff;
+      put_lds(q, j);
+      if (h & (1 << 20)) put_lds(q + nx, j);                // halo column
+      if (h & (1 << 21)) put_lds(q + ny * W, j);            // halo row
+      if ((h >> 20) == 3) put_lds(q + ny * W + nx, j);      // halo corner
     }
     __syncthreads();
   }
+}
+
+
+// The box sweep in the form for its compute type (see above).
+template <typename VT, typename OUT, typename C, int F, int kBoxMaxPts, int NT = kBoxThreads,
+          bool PP = false, bool QUAD = false>
+__device__ __forceinline__ void box_rays(const VT* __restrict__ s0, size_t ray_stride, int nf,
+                                         const OUT& out, const double* __restrict__ kline,
+                                         const BoxStencil st, const C* fac, int nx, int ny,
+                                         int nz, C i_in, C sc, float out_mul, C* smem) {
+  if constexpr (sizeof(C) == 8)
+    box_rays_sep<VT, OUT, C, F, kBoxMaxPts, NT, PP, QUAD>(s0, ray_stride, nf, out, kline, st, fac,
+                                                          nx, ny, nz, i_in, sc, out_mul, smem);
+  else
+    box_rays_halo<VT, OUT, C, F, kBoxMaxPts, NT, PP, QUAD>(s0, ray_stride, nf, out, kline, st,
+                                                           fac, nx, ny, nz, i_in, sc, out_mul, smem);
 }
 
 }  // namespace lam

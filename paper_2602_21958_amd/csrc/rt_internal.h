@@ -61,6 +61,10 @@ struct BoxStencil {
   // displacement on the next plane downstream
   int di0, dj0;
   double dtx, dty;
+  // FP64 forms of the bilinear weights (1-ty)(1-tx), (1-ty)tx, ty(1-tx), ty tx
+  // and of path / 2, formed once here so that an FP64 sweep reads them from
+  // scalar registers instead of holding them in vector ones
+  double w00, w01, w10, w11, hpath;
 };
 
 // --------------------------------------------------------------------------
@@ -177,12 +181,14 @@ void launch_lambda_k4(const Problem& p, int precision, const _Float16* s, uint16
 float fp16_lambda_scale(int64_t n);
 // Power-of-two scale of an fp16 Krylov basis of vectors of n entries.
 float fp16_basis_scale(int64_t n);
-// Frequencies swept together by one box workgroup for planes of P points.
-int box_chunk(int P, int elem_bytes, int max_lds);
-// Whether box sweeps of F frequencies per group on planes of P points keep two
-// alternating LDS sets (one barrier per plane): F == 1, P <= 1024 and
-// 2 (2F + 1) P elements within max_lds bytes.
-bool box_pingpong(int F, int P, int elem_bytes, int max_lds);
+// Frequencies swept together by one box workgroup for planes of PH values in
+// LDS (the plane with its halo row and column).
+int box_chunk(size_t PH, int elem_bytes, int max_lds);
+// Whether box sweeps of F frequencies per group on planes of P points (PH in
+// LDS) keep two alternating LDS sets (one barrier per plane): F == 1,
+// P <= 1024 or 4-byte values, and 2 (2F + 1) PH elements within max_lds
+// bytes.
+bool box_pingpong(int F, int P, size_t PH, int elem_bytes, int max_lds);
 // Size in elements of one part of the k4 operand; allocation of the
 // problem's (zeroed) two-part buffer.
 int64_t l16_part_elems(const Problem& p);
