@@ -729,7 +729,8 @@ BOX64_DEFAULT = [("fp16/basis16/m30", "fp16", 30, 1, "dense"),
                  ("bf16/basis16/m30", "bf16", 30, 1, "dense"),
                  ("fp16/basis16/m30/factored-outer", "fp16", 30, 1, "factored"),
                  ("fp16/m20/precond", "fp16", 20, 0, "dense", "local"),
-                 ("fp16/m20/precond/factored-outer", "fp16", 20, 0, "factored", "local")]
+                 ("fp16/m20/precond/factored-outer", "fp16", 20, 0, "factored", "local"),
+                 ("fp32/factored/m20/precond", "fp32", 20, 0, "factored", "local")]
 BOX64_MORE = [("fp32/factored/m20", "fp32", 20, 0, "factored"),
               ("bf16/m20/precond/factored-outer", "bf16", 20, 0, "factored", "local"),
               ("fp16/m20", "fp16", 20, 0, "dense"), ("bf16/m20", "bf16", 20, 0, "dense"),

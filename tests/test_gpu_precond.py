@@ -15,7 +15,8 @@ Bars:
   unpreconditioned solution to 1e-10 (as the plain solves do); iteration
   counts within 2 of the oracle's preconditioned GMRES and at most half of
   the plain solve's.
-* Preconditioned mixed solves: oracle-evaluated FP64 residual <= 1e-8.
+* Preconditioned mixed solves (dense or factored scattering): oracle-evaluated
+  FP64 residual <= 1e-8.
 """
 import sys
 
@@ -159,6 +160,30 @@ def test_preconditioned_mixed_solve(name, prec):
     say(f"precond mixed {prec} {name}")
     op = OProblem(spec)
     with rt.Problem(spec) as p:
+        x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
+        plain = p.solve(x, rtol=1e-8, precision=prec, max_outer=40)
+        st = p.solve(x, rtol=1e-8, precision=prec, precond="local", max_outer=40)
+        s = host(x)
+    res = op.residual_norm(s)
+    say(f"   inner {st['iters']} / outer {st['outer_iters']} (plain {plain['iters']} / "
+        f"{plain['outer_iters']}), oracle residual {res:.2e}")
+    assert st["converged"] and res <= 1e-8
+    assert st["iters"] < plain["iters"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("name", ["box8", "box_12x10x9"])
+def test_preconditioned_factored_solve(name, prec):
+    """The preconditioner with the factored scattering form: FP64 outer
+    residuals in factored form, the inner operator the factored FP32 form
+    (fp32) or the dense 16-bit GEMM (fp16); oracle-evaluated FP64 residual
+    <= 1e-8 in fewer inner iterations than the plain factored solve."""
+    rt = _rt()
+    spec = SPECS[name]()
+    say(f"precond factored {prec} {name}")
+    op = OProblem(spec)
+    with rt.Problem(spec) as p:
+        p.set_sigma("factored")
         x = torch.empty(op.n, dtype=torch.float64, device="cuda:0")
         plain = p.solve(x, rtol=1e-8, precision=prec, max_outer=40)
         st = p.solve(x, rtol=1e-8, precision=prec, precond="local", max_outer=40)
