@@ -154,23 +154,65 @@ __global__ __launch_bounds__(64) void build_blocks(const double* __restrict__ fb
   }
 }
 
-// r[q][nu][i] = sum_o G[o][q] x[(o n_nu + nu) n_s + i]
-template <typename T, int RQ>
+// W consecutive values of T moved as one access: 16 bytes (4 floats or 2
+// doubles) in the streaming kernels below, or one value where the arrays do
+// not allow it (m not a multiple of the width, or a vector not 16-byte
+// aligned).
+template <typename T> constexpr int kVec16 = 16 / (int)sizeof(T);
+
+template <typename T, int W>
+__device__ __forceinline__ void vload(const T* p, T (&v)[W]) {
+  if constexpr (W == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  } else if constexpr (W == 2) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    v[0] = t.x; v[1] = t.y;
+  } else {
+    v[0] = *p;
+  }
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void vstore(T* p, const T (&v)[W]) {
+  if constexpr (W == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (W == 2) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  } else {
+    *p = v[0];
+  }
+}
+
+// r[q][nu][i] = sum_o G[o][q] x[(o n_nu + nu) n_s + i]: each thread takes W
+// consecutive entries (m a multiple of W), eight ordinates' loads issued
+// together.
+template <typename T, int RQ, int W>
 __global__ __launch_bounds__(256) void prec_reduce(const T* __restrict__ x,
                                                    const T* __restrict__ G, T* __restrict__ r,
                                                    int n_om, int64_t m) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    T acc[RQ];
+  const int64_t mv = m / W;
+  for (int64_t ev = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ev < mv;
+       ev += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = ev * W;
+    T acc[RQ][W];
 #pragma unroll
-    for (int q = 0; q < RQ; ++q) acc[q] = T(0);
+    for (int q = 0; q < RQ; ++q)
+#pragma unroll
+      for (int w = 0; w < W; ++w) acc[q][w] = T(0);
+#pragma unroll 8
     for (int o = 0; o < n_om; ++o) {
-      const T v = x[(int64_t)o * m + e];
+      T v[W];
+      vload<T, W>(x + (int64_t)o * m + e, v);
 #pragma unroll
-      for (int q = 0; q < RQ; ++q) acc[q] += G[o * RQ + q] * v;
+      for (int q = 0; q < RQ; ++q) {
+        const T g = G[o * RQ + q];
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[q][w] += g * v[w];
+      }
     }
 #pragma unroll
-    for (int q = 0; q < RQ; ++q) r[(int64_t)q * m + e] = acc[q];
+    for (int q = 0; q < RQ; ++q) vstore<T, W>(r + (int64_t)q * m + e, acc[q]);
   }
 }
 
@@ -205,28 +247,121 @@ __global__ __launch_bounds__(256) void prec_mix(const T* __restrict__ Tb,
   }
 }
 
+// LDS accesses of one wavefront ordered around a wave barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// The same product, one wavefront per block (q, i): the block's n x n
+// values (contiguous) are read by all 64 lanes in 16-byte vectors, VPL per
+// lane, all issued before the first is used and none under a branch (a lane
+// past the block reloads its last vector; n a multiple of the vector width,
+// so that a vector lies in one row), into LDS rows padded to n + 1
+// (conflict-free column walks); then lane nu forms row nu against
+// r[q][.][i] (broadcast from LDS).  Four wavefronts per group, each with its
+// own LDS region of n (n + 1) + n values.  Wavefront k of a pass takes block
+// mix_order(k): groups are dealt to the 8 XCDs in turn, each with its own L2,
+// and the order puts the 32 consecutive points whose r and z values share a
+// 128-byte line on the waves of one XCD, so each line is fetched and
+// written back whole by one L2 (in launch order, by eight).
+__device__ __forceinline__ int64_t mix_order(int64_t k, int64_t nfull) {
+  if (k >= nfull) return k;
+  const int64_t base = k & ~(int64_t)255;
+  const int g = (int)((k >> 2) & 63), w = (int)(k & 3);   // group in the chunk, wave
+  return base + 32 * (g & 7) + 4 * (g >> 3) + w;
+}
+
+template <typename T, int VPL>
+__global__ __launch_bounds__(256) void prec_mix_wave(const T* __restrict__ Tb,
+                                                     const T* __restrict__ r, T* __restrict__ z,
+                                                     int n, int64_t n_s, int64_t nblk) {
+  constexpr int W = kVec16<T>;
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T* L = reinterpret_cast<T*>(smem_raw) + (size_t)wave * (n * (n + 1) + n);
+  T* rl = L + n * (n + 1);
+  const int64_t m = (int64_t)n * n_s;
+  const int nvr = n / W, nv = n * nvr;   // vectors per row, per block
+  // row of vector ev: (ev + 1/2) / nvr rounded down, exact in FP32 here
+  // (ev < 1024, nvr <= 16: the quotient stays 1/32 away from an integer)
+  const float inv_nvr = 1.0f / (float)nvr;
+  const int64_t nfull = nblk & ~(int64_t)255;
+  for (int64_t k = (int64_t)blockIdx.x * 4 + wave; k < nblk; k += (int64_t)gridDim.x * 4) {
+    const int64_t b = mix_order(k, nfull);
+    const int q = (int)(b / n_s);
+    const int64_t i = b - (int64_t)q * n_s;
+    const T* blk = Tb + (size_t)b * n * n;
+    T v[VPL][W];
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) vload<T, W>(blk + (size_t)min(lane + 64 * t, nv - 1) * W, v[t]);
+    const T rv = r[(int64_t)q * m + (int64_t)min(lane, n - 1) * n_s + i];
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) {
+      const int ev = lane + 64 * t;
+      if (ev < nv) {
+        const int row = (int)(((float)ev + 0.5f) * inv_nvr);
+        T* dst = L + row * (n + 1) + (ev - row * nvr) * W;
+#pragma unroll
+        for (int w = 0; w < W; ++w) dst[w] = v[t][w];
+      }
+    }
+    if (lane < n) rl[lane] = rv;
+    wave_lds_sync();
+    if (lane < n) {
+      const T* row = L + lane * (n + 1);
+      T acc = T(0);
+      for (int k = 0; k < n; ++k) acc += row[k] * rl[k];
+      z[(int64_t)q * m + (int64_t)lane * n_s + i] = acc;
+    }
+    wave_lds_sync();   // the next block overwrites the region
+  }
+}
+
 // Delta[(o, nu), i] = sum_q F[o][q] z[q][nu][i];
 //   ACC = false: u = x + Delta and nd = -Delta (u = P^-1 x, nd = x - u);
 //   ACC = true:  u += x + Delta (accumulate P^-1 x into u).
-template <typename T, int RQ, bool ACC>
+// W consecutive entries per thread, as in prec_reduce.
+template <typename T, int RQ, bool ACC, int W>
 __global__ __launch_bounds__(256) void prec_expand(const T* __restrict__ z,
                                                    const T* __restrict__ F, const T* x, T* u,
                                                    T* nd, int n_om, int64_t m) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    T zv[RQ];
+  const int64_t mv = m / W;
+  for (int64_t ev = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ev < mv;
+       ev += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = ev * W;
+    T zv[RQ][W];
 #pragma unroll
-    for (int q = 0; q < RQ; ++q) zv[q] = z[(int64_t)q * m + e];
+    for (int q = 0; q < RQ; ++q) vload<T, W>(z + (int64_t)q * m + e, zv[q]);
+#pragma unroll 4
     for (int o = 0; o < n_om; ++o) {
-      T d = T(0);
+      T d[W];
 #pragma unroll
-      for (int q = 0; q < RQ; ++q) d += F[o * RQ + q] * zv[q];
+      for (int w = 0; w < W; ++w) d[w] = T(0);
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const T f = F[o * RQ + q];
+#pragma unroll
+        for (int w = 0; w < W; ++w) d[w] += f * zv[q][w];
+      }
       const int64_t at = (int64_t)o * m + e;
+      T xv[W], uv[W];
+      vload<T, W>(x + at, xv);
       if constexpr (ACC) {
-        u[at] += x[at] + d;
+        vload<T, W>(u + at, uv);
+#pragma unroll
+        for (int w = 0; w < W; ++w) uv[w] += xv[w] + d[w];
+        vstore<T, W>(u + at, uv);
       } else {
-        u[at] = x[at] + d;
-        nd[at] = -d;
+        T nv[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          uv[w] = xv[w] + d[w];
+          nv[w] = -d[w];
+        }
+        vstore<T, W>(u + at, uv);
+        vstore<T, W>(nd + at, nv);
       }
     }
   }
@@ -399,24 +534,55 @@ void apply_impl(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
   T* r = work_rz<T>(p);
   T* z = r + (size_t)rq * m;
   ProfScope prof(RT_KCLASS_PRECOND, st);
-  const int g = grid_for(m);
-#define RT_PREC_RQ(RR)                                                                        \
-  case RR:                                                                                    \
-    hipLaunchKernelGGL((prec_reduce<T, RR>), dim3(g), dim3(256), 0, st, x, PP::G(p), r, n_om, \
-                       m);                                                                    \
+  // 16-byte accesses where every vector allows them
+  constexpr int WV = kVec16<T>;
+  auto al = [](const void* q) { return q == nullptr || ((uintptr_t)q & 15) == 0; };
+  const bool vec = m % WV == 0 && al(x) && al(u) && al(nd) && al(r);
+  const int g = grid_for(vec ? m / WV : m);
+  // the expansion runs one value per thread: 16-byte accesses measured
+  // slower there (box64, FP32: 3.89 against 3.75 ms)
+  const int ge = grid_for(m);
+#define RT_PREC_RQ(RR)                                                                           \
+  case RR:                                                                                       \
+    if (vec)                                                                                     \
+      hipLaunchKernelGGL((prec_reduce<T, RR, WV>), dim3(g), dim3(256), 0, st, x, PP::G(p), r,    \
+                         n_om, m);                                                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((prec_reduce<T, RR, 1>), dim3(g), dim3(256), 0, st, x, PP::G(p), r,     \
+                         n_om, m);                                                               \
     break;
   switch (rq) {
     RT_PREC_RQ(1) RT_PREC_RQ(2) RT_PREC_RQ(3) RT_PREC_RQ(4) RT_PREC_RQ(5) RT_PREC_RQ(6)
     default: fail(RT_E_INVALID, "preconditioner: mode count");
   }
 #undef RT_PREC_RQ
-  const int64_t tiles = (n_s + kMixPts - 1) / kMixPts;
-  hipLaunchKernelGGL((prec_mix<T>), dim3((unsigned)(rq * tiles)), dim3(256),
-                     (size_t)n_nu * kMixPts * sizeof(T), st, PP::T(p), r, z, n_nu, n_s, tiles);
-#define RT_PREC_RQ(RR)                                                                    \
-  case RR:                                                                                \
-    hipLaunchKernelGGL((prec_expand<T, RR, ACC>), dim3(g), dim3(256), 0, st, z, PP::F(p), \
-                       x, u, nd, n_om, m);                                                \
+  const size_t wave_lds = 4 * ((size_t)n_nu * (n_nu + 1) + n_nu) * sizeof(T);
+  // vectors per lane of the wavefront product: 4, 9 or 16
+  const int vpl = (int)(((int64_t)n_nu * n_nu / kVec16<T> + 63) / 64);
+  // FP32 tables only (FP64 on the 32^3 box: 22.4 against 20.8 ms of
+  // preconditioner per solve with the point-tile product)
+  const bool wave_mix = sizeof(T) == 4 && n_nu <= 64 && n_nu % kVec16<T> == 0 && vpl <= 16 &&
+                        wave_lds <= 65536;
+  if (wave_mix) {
+    const int64_t nblk = (int64_t)rq * n_s;
+    // a multiple of 64 groups keeps every pass on whole 256-wave chunks
+    const int grid = (int)std::min<int64_t>((nblk + 3) / 4, 4096);
+#define RT_MIX(V)                                                                            \
+  hipLaunchKernelGGL((prec_mix_wave<T, V>), dim3(grid), dim3(256), wave_lds, st, PP::T(p), r, \
+                     z, n_nu, n_s, nblk)
+    if (vpl <= 4) RT_MIX(4);
+    else if (vpl <= 9) RT_MIX(9);
+    else RT_MIX(16);
+#undef RT_MIX
+  } else {
+    const int64_t tiles = (n_s + kMixPts - 1) / kMixPts;
+    hipLaunchKernelGGL((prec_mix<T>), dim3((unsigned)(rq * tiles)), dim3(256),
+                       (size_t)n_nu * kMixPts * sizeof(T), st, PP::T(p), r, z, n_nu, n_s, tiles);
+  }
+#define RT_PREC_RQ(RR)                                                                       \
+  case RR:                                                                                   \
+    hipLaunchKernelGGL((prec_expand<T, RR, ACC, 1>), dim3(ge), dim3(256), 0, st, z, PP::F(p), \
+                       x, u, nd, n_om, m);                                                    \
     break;
   switch (rq) {
     RT_PREC_RQ(1) RT_PREC_RQ(2) RT_PREC_RQ(3) RT_PREC_RQ(4) RT_PREC_RQ(5) RT_PREC_RQ(6)
