@@ -392,12 +392,17 @@ def main():
 
     # the same system with the physics-based preconditioner (right
     # preconditioning: the same residual and tolerance), in FP64 and in the
-    # mixed precision; the first solve builds the preconditioner's tables
+    # mixed precision, with the dense and the factored scattering form (FP64
+    # outer residuals and, for fp32, the inner operator); the first solve
+    # builds the preconditioner's tables
     print("box32: preconditioned legs", file=sys.stderr, flush=True)
     out["preconditioned"] = {}
     xp = torch.empty_like(x)
-    for label, kw in (("fp64", {}),
-                      (args.mixed_precision, {"precision": args.mixed_precision})):
+    for label, form, kw in (("fp64", "dense", {}),
+                            (args.mixed_precision, "dense", {"precision": args.mixed_precision}),
+                            ("fp64/factored", "factored", {}),
+                            ("fp32/factored", "factored", {"precision": "fp32"})):
+        p.set_sigma(form)
         tp0 = time.perf_counter()
         p.solve(xp, rtol=1e-8, restart=30, precond="local", stream=stream, **kw)
         torch.cuda.synchronize()
@@ -421,6 +426,7 @@ def main():
                 (torch.linalg.vector_norm(xp - x) / torch.linalg.vector_norm(x)).item(),
             "first_solve_s_incl_setup": t_first,
             "kernel_ms_per_solve": {k: v["total_ms"] / args.steps for k, v in pprof.items()}}
+    p.set_sigma("dense")
     del xp
 
     if not args.no_cpu_baseline:

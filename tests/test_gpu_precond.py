@@ -125,6 +125,30 @@ def test_apply_precond_matches_oracle(name, prec):
     assert np.all(back <= 64 * u * cond)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_apply_precond_unaligned_vectors(prec):
+    """Vectors that are not 16-byte aligned take the one-value-per-thread
+    reduction: the same sums in the same order, so the same bits as the
+    16-byte path on aligned copies of the same vectors."""
+    rt = _rt()
+    spec = SPECS["box_12x10x9"]()
+    op = OProblem(spec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x = W.random_field(op.n, 43)
+    with rt.Problem(spec) as p:
+        xa = dev(x, dt)
+        ya = torch.empty_like(xa)
+        p.apply_precond(xa, ya, precision=prec)
+        xb_buf = torch.zeros(op.n + 1, dtype=dt, device="cuda:0")
+        yb_buf = torch.zeros_like(xb_buf)
+        xb, yb = xb_buf[1:], yb_buf[1:]   # offset by one value: not 16-byte aligned
+        xb.copy_(xa)
+        p.apply_precond(xb, yb, precision=prec)
+        torch.cuda.synchronize()
+        assert xb.data_ptr() % 16 != 0
+        assert torch.equal(ya, yb)
+
+
 @pytest.mark.parametrize("two_step", [1, 0])
 @pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
 def test_preconditioned_fp64_solve(name, two_step):
