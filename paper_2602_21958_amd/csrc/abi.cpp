@@ -561,19 +561,33 @@ void operator_apply_k(Problem& p, int precision, const void* x, void* y, const d
 void operator_apply_kx(Problem& p, int precision, const void* u, const void* nd, void* y,
                        const double* xscale, hipStream_t st) {
   const size_t n = (size_t)p.n;
+  const bool fused = precond_fused(p, precision);
+  if (!fused && !nd) fail(RT_E_INVALID, "operator_apply_kx: v - u missing");
   switch (precision) {
     case RT_PREC_FP64: {
       double* L = static_cast<double*>(problem_lbuf(p, n * sizeof(double)));
       launch_lambda<double, double>(p, static_cast<const double*>(u), L, false, xscale, st);
-      apply_sigma_f64(p, L, static_cast<const double*>(nd), static_cast<double*>(y), xscale,
-                      +1.0, st, nullptr);
+      if (fused)
+        launch_sigma_factored_pre_f64(
+            p, L, precond_modes_F<double>(p), precond_modes_z<double>(p), p.prec_rq,
+            static_cast<double*>(y), static_cast<double*>(problem_fwork(p, sizeof(double))),
+            xscale, st);
+      else
+        apply_sigma_f64(p, L, static_cast<const double*>(nd), static_cast<double*>(y), xscale,
+                        +1.0, st, nullptr);
       break;
     }
     case RT_PREC_FP32: {
       float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
       launch_lambda<float, float>(p, static_cast<const float*>(u), L, false, xscale, st);
-      apply_sigma_f32(p, L, static_cast<const float*>(nd), static_cast<float*>(y), xscale, +1.0,
-                      st, nullptr);
+      if (fused)
+        launch_sigma_factored_pre_f32(
+            p, L, precond_modes_F<float>(p), precond_modes_z<float>(p), p.prec_rq,
+            static_cast<float*>(y), static_cast<float*>(problem_fwork(p, sizeof(float))), xscale,
+            st);
+      else
+        apply_sigma_f32(p, L, static_cast<const float*>(nd), static_cast<float*>(y), xscale,
+                        +1.0, st, nullptr);
       break;
     }
     case RT_PREC_BF16:

@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void prec_expand(const T* __restrict__ z,
           nv[w] = -d[w];
         }
         vstore<T, W>(u + at, uv);
-        vstore<T, W>(nd + at, nv);
+        if (nd) vstore<T, W>(nd + at, nv);   // null: the caller forms v - u itself
       }
     }
   }
@@ -537,7 +537,7 @@ void apply_impl(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
   // 16-byte accesses where every vector allows them
   constexpr int WV = kVec16<T>;
   auto al = [](const void* q) { return q == nullptr || ((uintptr_t)q & 15) == 0; };
-  const bool vec = m % WV == 0 && al(x) && al(u) && al(nd) && al(r);
+  const bool vec = m % WV == 0 && al(x) && al(u) && al(r);
   const int g = grid_for(vec ? m / WV : m);
   // the expansion runs one value per thread: 16-byte accesses measured
   // slower there (box64, FP32: 3.89 against 3.75 ms)
@@ -653,6 +653,24 @@ template <typename T>
 void precond_apply(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
   apply_impl<T, false>(p, x, u, nd, st);
 }
+
+bool precond_fused(const Problem& p, int precision) {
+  return (precision == RT_PREC_FP64 || precision == RT_PREC_FP32) &&
+         p.sigma_form == RT_SIGMA_FACTORED && p.n_classes <= 1;
+}
+
+template <typename T>
+const T* precond_modes_F(Problem& p) {
+  return PrecPtrs<T>::F(p);
+}
+template <typename T>
+const T* precond_modes_z(Problem& p) {
+  return work_rz<T>(p) + (size_t)p.prec_rq * p.n_nu * p.n_s;
+}
+template const double* precond_modes_F<double>(Problem&);
+template const float* precond_modes_F<float>(Problem&);
+template const double* precond_modes_z<double>(Problem&);
+template const float* precond_modes_z<float>(Problem&);
 
 template <typename T>
 void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st) {

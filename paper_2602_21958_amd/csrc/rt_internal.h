@@ -248,6 +248,15 @@ void launch_sigma_factored_f64(const Problem& p, const double* L, const double* 
                                double* work, const double* xscale, double sign, hipStream_t st);
 void launch_sigma_factored_f32(const Problem& p, const float* L, const float* x, float* y,
                                float* work, const double* xscale, double sign, hipStream_t st);
+// The same with the preconditioner's correction as the x term: y = xs (-Delta)
+// + (1 - eps) Mhat L with Delta = sum_q Fp[o][q] zp[q][nu][i] (rp modes), i.e.
+// the preconditioned step's v - u formed in the expansion (precond_fused).
+void launch_sigma_factored_pre_f64(const Problem& p, const double* L, const double* Fp,
+                                   const double* zp, int rp, double* y, double* work,
+                                   const double* xscale, hipStream_t st);
+void launch_sigma_factored_pre_f32(const Problem& p, const float* L, const float* Fp,
+                                   const float* zp, int rp, float* y, float* work,
+                                   const double* xscale, hipStream_t st);
 // Scattering with per-point classes (sigma_classes.hip): for each class,
 // gather its points' columns of L, one GEMM with the class's Mhat and
 // albedo, and scatter y = xs x + sign (result) to the class's columns.
@@ -272,8 +281,19 @@ template <typename T> void precond_apply(Problem& p, const T* x, T* u, T* nd, hi
 template <typename T> void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st);
 template <typename T> T* precond_u(Problem& p);
 template <typename T> T* precond_nd(Problem& p);
+// Whether the preconditioned step operator in this precision forms v - u in
+// the scattering expansion (factored form in FP64 / FP32, one kernel for all
+// points); then precond_apply may take nd = nullptr, and operator_apply_kx
+// reads the last application's modes (precond_modes) instead of nd.
+bool precond_fused(const Problem& p, int precision);
+// the angular mode matrix F (n_omega x prec_rq) and the last application's
+// mode values z (prec_rq x n_nu x n_s) of the tables in T
+template <typename T> const T* precond_modes_F(Problem& p);
+template <typename T> const T* precond_modes_z(Problem& p);
 // y = xs * nd + K (xs * u): the preconditioned step operator K' = I - A P^-1
-// applied to v with u = P^-1 v and nd = v - u (see solver.cpp)
+// applied to v with u = P^-1 v and nd = v - u (see solver.cpp); with
+// precond_fused, nd is not read (may be null) and v - u comes from the
+// preconditioner's modes
 void operator_apply_kx(Problem& p, int precision, const void* u, const void* nd, void* y,
                        const double* xscale, hipStream_t st);
 // Emulated FP64 scattering (sigma_ozaki.hip): ozaki_prepare builds the Mhat

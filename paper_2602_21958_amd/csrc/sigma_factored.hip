@@ -105,20 +105,27 @@ __global__ __launch_bounds__(256) void fsig_mix(const T* __restrict__ W, const T
 }
 
 // y = xs x + sign (1 - eps_i) fq Z, one thread per (nu, V points), looping
-// over the ordinates (fq wave-uniform).
-template <typename T, int R, int V>
+// over the ordinates (fq wave-uniform).  RP > 0: the x term is instead
+// xs (-Delta) with Delta = sum_q Fp[o][q] zp[q][nu][i], the preconditioner's
+// correction (its RP angular modes, the same sum in the same order as the
+// preconditioner's expansion, so the same values as reading its v - u = -Delta
+// back from memory).
+template <typename T, int R, int V, int RP>
 __global__ __launch_bounds__(256) void fsig_expand(const T* __restrict__ Z,
                                                    const T* __restrict__ fq,
                                                    const double* __restrict__ albedo,
                                                    const T* x, T* y,
                                                    const double* __restrict__ xscale, T sign,
-                                                   int n_om, int n_nu, int64_t n_s) {
+                                                   int n_om, int n_nu, int64_t n_s,
+                                                   const T* __restrict__ Fp,
+                                                   const T* __restrict__ zp) {
   using VT = typename VecOf<T, V>::type;
   const int64_t m = (int64_t)n_nu * n_s;
   const int64_t mv = m / V;
-  const T xs = (x != nullptr && xscale != nullptr) ? T(*xscale) : T(1);
+  const T xs = ((x != nullptr || RP > 0) && xscale != nullptr) ? T(*xscale) : T(1);
   const VT* Zv = reinterpret_cast<const VT*>(Z);
   const VT* xv = reinterpret_cast<const VT*>(x);
+  const VT* zpv = reinterpret_cast<const VT*>(zp);
   VT* yv = reinterpret_cast<VT*>(y);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mv;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -133,12 +140,24 @@ __global__ __launch_bounds__(256) void fsig_expand(const T* __restrict__ Z,
     VT z[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) z[q] = a * Zv[(int64_t)q * mv + e];
+    VT zc[RP > 0 ? RP : 1];
+    if constexpr (RP > 0) {
+#pragma unroll
+      for (int q = 0; q < RP; ++q) zc[q] = zpv[(int64_t)q * mv + e];
+    }
     for (int o = 0; o < n_om; ++o) {
       VT s = VT(0);
 #pragma unroll
       for (int q = 0; q < R; ++q) s += fq[o * R + q] * z[q];
       const int64_t at = (int64_t)o * mv + e;
-      yv[at] = x ? xs * xv[at] + s : s;
+      if constexpr (RP > 0) {
+        VT d = VT(0);
+#pragma unroll
+        for (int q = 0; q < RP; ++q) d += Fp[o * RP + q] * zc[q];
+        yv[at] = xs * (-d) + s;
+      } else {
+        yv[at] = x ? xs * xv[at] + s : s;
+      }
     }
   }
 }
@@ -151,7 +170,7 @@ int stream_grid(int64_t m) {
 template <typename T>
 void launch_factored(const Problem& p, const T* fq, const T* fg, const T* fb, const T* L,
                      const T* x, T* y, T* work, const double* xscale, double sign,
-                     hipStream_t st) {
+                     hipStream_t st, const T* Fp = nullptr, const T* zp = nullptr, int rp = 0) {
   const int R = p.tab.frank;
   const int n_om = p.n_omega, n_nu = p.n_nu;
   const int64_t n_s = p.n_s, m = (int64_t)n_nu * n_s;
@@ -175,11 +194,31 @@ void launch_factored(const Problem& p, const T* fq, const T* fg, const T* fb, co
   const size_t lds = ((size_t)n_nu * kMixTile + (size_t)n_nu * n_nu) * sizeof(T);
   hipLaunchKernelGGL((fsig_mix<T>), dim3((unsigned)(R * tiles)), dim3(256), lds, st, W, fb, Z,
                      n_nu, n_s, tiles);
-  if (R == 6) {
-    RT_FSIG(fsig_expand, 6, Z, fq, p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s);
-  } else {
-    RT_FSIG(fsig_expand, 2, Z, fq, p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s);
+#define RT_FSIG_X(RR, PP)                                                                     \
+  if (vec)                                                                                    \
+    hipLaunchKernelGGL((fsig_expand<T, RR, VV, PP>), dim3(g), dim3(256), 0, st, Z, fq,        \
+                       p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s, Fp, zp);           \
+  else                                                                                        \
+    hipLaunchKernelGGL((fsig_expand<T, RR, 1, PP>), dim3(g), dim3(256), 0, st, Z, fq,         \
+                       p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s, Fp, zp)
+#define RT_FSIG_R(RR)                                   \
+  switch (rp) {                                         \
+    case 0: RT_FSIG_X(RR, 0); break;                    \
+    case 1: RT_FSIG_X(RR, 1); break;                    \
+    case 2: RT_FSIG_X(RR, 2); break;                    \
+    case 3: RT_FSIG_X(RR, 3); break;                    \
+    case 4: RT_FSIG_X(RR, 4); break;                    \
+    case 5: RT_FSIG_X(RR, 5); break;                    \
+    case 6: RT_FSIG_X(RR, 6); break;                    \
+    default: fail(RT_E_INVALID, "preconditioner: mode count"); \
   }
+  if (R == 6) {
+    RT_FSIG_R(6);
+  } else {
+    RT_FSIG_R(2);
+  }
+#undef RT_FSIG_R
+#undef RT_FSIG_X
 #undef RT_FSIG
   RT_HIP(hipGetLastError());
 }
@@ -208,6 +247,20 @@ void launch_sigma_factored_f64(const Problem& p, const double* L, const double* 
 void launch_sigma_factored_f32(const Problem& p, const float* L, const float* x, float* y,
                                float* work, const double* xscale, double sign, hipStream_t st) {
   launch_factored<float>(p, p.d_fq32, p.d_fg32, p.d_fb32, L, x, y, work, xscale, sign, st);
+}
+
+void launch_sigma_factored_pre_f64(const Problem& p, const double* L, const double* Fp,
+                                   const double* zp, int rp, double* y, double* work,
+                                   const double* xscale, hipStream_t st) {
+  launch_factored<double>(p, p.d_fq64, p.d_fg64, p.d_fb64, L, nullptr, y, work, xscale, +1.0, st,
+                          Fp, zp, rp);
+}
+
+void launch_sigma_factored_pre_f32(const Problem& p, const float* L, const float* Fp,
+                                   const float* zp, int rp, float* y, float* work,
+                                   const double* xscale, hipStream_t st) {
+  launch_factored<float>(p, p.d_fq32, p.d_fg32, p.d_fb32, L, nullptr, y, work, xscale, +1.0, st,
+                         Fp, zp, rp);
 }
 
 }  // namespace rtsn

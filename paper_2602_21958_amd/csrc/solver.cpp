@@ -211,7 +211,8 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
   auto step_op = [&](const TV* v, TV* y, const double* xs) {
     if (pre) {
       TV* u = precond_u<TV>(p);
-      TV* nd = precond_nd<TV>(p);
+      // the factored expansion forms v - u from the preconditioner's modes
+      TV* nd = precond_fused(p, prec) ? nullptr : precond_nd<TV>(p);
       precond_apply<TV>(p, v, u, nd, st);
       operator_apply_kx(p, prec, u, nd, y, xs, st);
     } else {

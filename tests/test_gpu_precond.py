@@ -195,13 +195,15 @@ def test_preconditioned_mixed_solve(name, prec):
     assert st["iters"] < plain["iters"]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 @pytest.mark.parametrize("name", ["box8", "box_12x10x9"])
 def test_preconditioned_factored_solve(name, prec):
-    """The preconditioner with the factored scattering form: FP64 outer
-    residuals in factored form, the inner operator the factored FP32 form
-    (fp32) or the dense 16-bit GEMM (fp16); oracle-evaluated FP64 residual
-    <= 1e-8 in fewer inner iterations than the plain factored solve."""
+    """The preconditioner with the factored scattering form: FP64 GMRES on
+    the factored FP64 operator (fp64), or FP64 outer residuals in factored
+    form with the inner operator the factored FP32 form (fp32) or the dense
+    16-bit GEMM (fp16).  In FP64 and FP32 the step's v - u is formed in the
+    factored expansion from the preconditioner's modes.  Oracle-evaluated
+    FP64 residual <= 1e-8 in fewer iterations than the plain factored solve."""
     rt = _rt()
     spec = SPECS[name]()
     say(f"precond factored {prec} {name}")
