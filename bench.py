@@ -736,7 +736,8 @@ BOX64_DEFAULT = [("fp16/basis16/m30", "fp16", 30, 1, "dense"),
                  ("fp16/basis16/m30/factored-outer", "fp16", 30, 1, "factored"),
                  ("fp16/m20/precond", "fp16", 20, 0, "dense", "local"),
                  ("fp16/m20/precond/factored-outer", "fp16", 20, 0, "factored", "local"),
-                 ("fp32/factored/m20/precond", "fp32", 20, 0, "factored", "local")]
+                 ("fp32/factored/m20/precond", "fp32", 20, 0, "factored", "local"),
+                 ("fp32/factored/basis16/m20/precond", "fp32", 20, 1, "factored", "local")]
 BOX64_MORE = [("fp32/factored/m20", "fp32", 20, 0, "factored"),
               ("bf16/m20/precond/factored-outer", "bf16", 20, 0, "factored", "local"),
               ("fp16/m20", "fp16", 20, 0, "dense"), ("bf16/m20", "bf16", 20, 0, "dense"),
@@ -1044,7 +1045,7 @@ def bench_solve(args):
     p.set_sigma(args.sigma_form)
     x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
     kw = dict(rtol=1e-8, restart=args.restart, precision=prec, precond=args.precond,
-              max_outer=40, record_history=0)
+              max_outer=40, record_history=0, basis_fp16=1 if args.basis16 else 0)
     t0 = time.perf_counter()
     for _ in range(max(1, args.warmup)):
         p.solve(x, **kw)
@@ -1065,7 +1066,8 @@ def bench_solve(args):
            "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": prec, "data": "synthetic",
            "config": {"workload": f"solve: {args.problem}, {prec}, {args.sigma_form} Sigma, "
-                                  f"preconditioner {args.precond}, GMRES({args.restart})",
+                                  f"preconditioner {args.precond}, GMRES({args.restart}), "
+                                  f"{'fp16' if args.basis16 else 'working-precision'} basis",
                       "n_unknowns": p.n},
            "iters": st["iters"], "outer_iters": st["outer_iters"], "relres": st["relres"],
            "converged": st["converged"], "warmup_s": t_warm,

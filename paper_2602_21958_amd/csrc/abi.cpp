@@ -606,6 +606,18 @@ void operator_apply_kx(Problem& p, int precision, const void* u, const void* nd,
   }
 }
 
+void operator_apply_kxh(Problem& p, const float* u, _Float16* y, const double* xscale,
+                        float ymul, hipStream_t st) {
+  if (!precond_fused(p, RT_PREC_FP32))
+    fail(RT_E_INVALID, "an fp16 basis with FP32 operators needs the factored scattering");
+  const size_t n = (size_t)p.n;
+  float* L = static_cast<float*>(problem_lbuf(p, n * sizeof(float)));
+  launch_lambda<float, float>(p, u, L, false, xscale, st);
+  launch_sigma_factored_pre_h(p, L, precond_modes_F<float>(p), precond_modes_z<float>(p),
+                              p.prec_rq, y, ymul,
+                              static_cast<float*>(problem_fwork(p, sizeof(float))), xscale, st);
+}
+
 void operator_apply_h(Problem& p, int precision, const _Float16* x, _Float16* y,
                       const double* xscale, float ymul, hipStream_t st, bool kform) {
   if (precision != RT_PREC_BF16 && precision != RT_PREC_FP16 && precision != RT_PREC_BF16X3)
@@ -931,15 +943,24 @@ rt_status rt_solve(rt_problem p, const rt_solver_opts* opts, const double* b, do
     if (o.precision != RT_PREC_FP64 && !(o.inner_rtol > 0 && o.inner_rtol < 1))
       fail(RT_E_INVALID, "inner_rtol must be in (0, 1)");
     if (o.max_outer < 1) o.max_outer = 1;
-    if (o.basis_fp16 && o.precision != RT_PREC_BF16 && o.precision != RT_PREC_FP16 &&
-        o.precision != RT_PREC_BF16X3)
-      fail(RT_E_INVALID, "basis_fp16 needs a 16-bit operator precision");
-    if (o.basis_fp16 && q->scatter_inf > 2.0)
-      fail(RT_E_INVALID, "basis_fp16 needs max row sum of |(1-eps) Mhat| <= 2");
     if (o.precond != RT_PRECOND_NONE && o.precond != RT_PRECOND_LOCAL)
       fail(RT_E_INVALID, "unknown preconditioner");
-    if (o.precond && (o.krylov != RT_KRYLOV_GMRES || o.basis_fp16))
-      fail(RT_E_INVALID, "the preconditioner is a GMRES option on FP64 or FP32 bases");
+    // an fp16 basis: 16-bit operators without the preconditioner, or the
+    // preconditioned FP32 operator with factored scattering
+    const bool b16_pre = o.precision == RT_PREC_FP32 && o.precond == RT_PRECOND_LOCAL &&
+                         precond_fused(*q, RT_PREC_FP32);
+    if (o.basis_fp16 && o.precision != RT_PREC_BF16 && o.precision != RT_PREC_FP16 &&
+        o.precision != RT_PREC_BF16X3 && !b16_pre)
+      fail(RT_E_INVALID,
+           "basis_fp16 needs a 16-bit operator precision, or FP32 with the preconditioner and "
+           "factored scattering");
+    if (o.basis_fp16 && q->scatter_inf > 2.0)
+      fail(RT_E_INVALID, "basis_fp16 needs max row sum of |(1-eps) Mhat| <= 2");
+    if (o.precond && o.krylov != RT_KRYLOV_GMRES)
+      fail(RT_E_INVALID, "the preconditioner is a GMRES option");
+    if (o.precond && o.basis_fp16 && !b16_pre)
+      fail(RT_E_INVALID,
+           "the preconditioner on an fp16 basis needs FP32 operators with factored scattering");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double* bb = b ? b : physical_rhs(*q, st);
     status = solve(*q, o, bb, x, x_is_guess, stats, st);

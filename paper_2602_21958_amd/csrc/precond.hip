@@ -25,6 +25,7 @@
 // eigen-solve of S on the host, and one in-LDS Gauss-Jordan inversion with
 // partial pivoting per (point, mode).
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -187,10 +188,12 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[W]) {
 // r[q][nu][i] = sum_o G[o][q] x[(o n_nu + nu) n_s + i]: each thread takes W
 // consecutive entries (m a multiple of W), eight ordinates' loads issued
 // together.
-template <typename T, int RQ, int W>
-__global__ __launch_bounds__(256) void prec_reduce(const T* __restrict__ x,
+// XT: type of x (T, or fp16 basis vectors read one value per thread).
+template <typename T, int RQ, int W, typename XT = T>
+__global__ __launch_bounds__(256) void prec_reduce(const XT* __restrict__ x,
                                                    const T* __restrict__ G, T* __restrict__ r,
                                                    int n_om, int64_t m) {
+  static_assert(std::is_same<XT, T>::value || W == 1, "converted input: one value per thread");
   const int64_t mv = m / W;
   for (int64_t ev = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ev < mv;
        ev += (int64_t)gridDim.x * blockDim.x) {
@@ -203,7 +206,8 @@ __global__ __launch_bounds__(256) void prec_reduce(const T* __restrict__ x,
 #pragma unroll 8
     for (int o = 0; o < n_om; ++o) {
       T v[W];
-      vload<T, W>(x + (int64_t)o * m + e, v);
+      if constexpr (std::is_same<XT, T>::value) vload<T, W>(x + (int64_t)o * m + e, v);
+      else v[0] = T(x[(int64_t)o * m + e]);
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
         const T g = G[o * RQ + q];
@@ -323,10 +327,11 @@ __global__ __launch_bounds__(256) void prec_mix_wave(const T* __restrict__ Tb,
 //   ACC = false: u = x + Delta and nd = -Delta (u = P^-1 x, nd = x - u);
 //   ACC = true:  u += x + Delta (accumulate P^-1 x into u).
 // W consecutive entries per thread, as in prec_reduce.
-template <typename T, int RQ, bool ACC, int W>
+template <typename T, int RQ, bool ACC, int W, typename XT = T>
 __global__ __launch_bounds__(256) void prec_expand(const T* __restrict__ z,
-                                                   const T* __restrict__ F, const T* x, T* u,
+                                                   const T* __restrict__ F, const XT* x, T* u,
                                                    T* nd, int n_om, int64_t m) {
+  static_assert(std::is_same<XT, T>::value || W == 1, "converted input: one value per thread");
   const int64_t mv = m / W;
   for (int64_t ev = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ev < mv;
        ev += (int64_t)gridDim.x * blockDim.x) {
@@ -347,7 +352,8 @@ __global__ __launch_bounds__(256) void prec_expand(const T* __restrict__ z,
       }
       const int64_t at = (int64_t)o * m + e;
       T xv[W], uv[W];
-      vload<T, W>(x + at, xv);
+      if constexpr (std::is_same<XT, T>::value) vload<T, W>(x + at, xv);
+      else xv[0] = T(x[at]);
       if constexpr (ACC) {
         vload<T, W>(u + at, uv);
 #pragma unroll
@@ -525,8 +531,8 @@ T* work_rz(Problem& p) {
   return static_cast<T*>(p.d_prec_work);
 }
 
-template <typename T, bool ACC>
-void apply_impl(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
+template <typename T, bool ACC, typename XT = T>
+void apply_impl(Problem& p, const XT* x, T* u, T* nd, hipStream_t st) {
   using PP = PrecPtrs<T>;
   if (!PP::T(p)) fail(RT_E_INVALID, "preconditioner not prepared in this precision");
   const int rq = p.prec_rq, n_om = p.n_omega, n_nu = p.n_nu;
@@ -537,7 +543,7 @@ void apply_impl(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
   // 16-byte accesses where every vector allows them
   constexpr int WV = kVec16<T>;
   auto al = [](const void* q) { return q == nullptr || ((uintptr_t)q & 15) == 0; };
-  const bool vec = m % WV == 0 && al(x) && al(u) && al(r);
+  const bool vec = std::is_same<XT, T>::value && m % WV == 0 && al(x) && al(u) && al(r);
   const int g = grid_for(vec ? m / WV : m);
   // the expansion runs one value per thread: 16-byte accesses measured
   // slower there (box64, FP32: 3.89 against 3.75 ms)
@@ -545,10 +551,10 @@ void apply_impl(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
 #define RT_PREC_RQ(RR)                                                                           \
   case RR:                                                                                       \
     if (vec)                                                                                     \
-      hipLaunchKernelGGL((prec_reduce<T, RR, WV>), dim3(g), dim3(256), 0, st, x, PP::G(p), r,    \
-                         n_om, m);                                                               \
+      hipLaunchKernelGGL((prec_reduce<T, RR, std::is_same<XT, T>::value ? WV : 1, XT>), dim3(g), \
+                         dim3(256), 0, st, x, PP::G(p), r, n_om, m);                             \
     else                                                                                         \
-      hipLaunchKernelGGL((prec_reduce<T, RR, 1>), dim3(g), dim3(256), 0, st, x, PP::G(p), r,     \
+      hipLaunchKernelGGL((prec_reduce<T, RR, 1, XT>), dim3(g), dim3(256), 0, st, x, PP::G(p), r, \
                          n_om, m);                                                               \
     break;
   switch (rq) {
@@ -581,8 +587,8 @@ void apply_impl(Problem& p, const T* x, T* u, T* nd, hipStream_t st) {
   }
 #define RT_PREC_RQ(RR)                                                                       \
   case RR:                                                                                   \
-    hipLaunchKernelGGL((prec_expand<T, RR, ACC, 1>), dim3(ge), dim3(256), 0, st, z, PP::F(p), \
-                       x, u, nd, n_om, m);                                                    \
+    hipLaunchKernelGGL((prec_expand<T, RR, ACC, 1, XT>), dim3(ge), dim3(256), 0, st, z,      \
+                       PP::F(p), x, u, nd, n_om, m);                                          \
     break;
   switch (rq) {
     RT_PREC_RQ(1) RT_PREC_RQ(2) RT_PREC_RQ(3) RT_PREC_RQ(4) RT_PREC_RQ(5) RT_PREC_RQ(6)
@@ -675,6 +681,10 @@ template const float* precond_modes_z<float>(Problem&);
 template <typename T>
 void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st) {
   apply_impl<T, true>(p, d, y, nullptr, st);
+}
+
+void precond_apply_h(Problem& p, const _Float16* x, float* u, hipStream_t st) {
+  apply_impl<float, false, _Float16>(p, x, u, nullptr, st);
 }
 
 template double* precond_u<double>(Problem&);

@@ -257,6 +257,16 @@ void launch_sigma_factored_pre_f64(const Problem& p, const double* L, const doub
 void launch_sigma_factored_pre_f32(const Problem& p, const float* L, const float* Fp,
                                    const float* zp, int rp, float* y, float* work,
                                    const double* xscale, hipStream_t st);
+// ... into an fp16 basis vector: y = ymul (xs (-Delta) + (1 - eps) Mhat L),
+// rounded to fp16
+void launch_sigma_factored_pre_h(const Problem& p, const float* L, const float* Fp,
+                                 const float* zp, int rp, _Float16* y, float ymul, float* work,
+                                 const double* xscale, hipStream_t st);
+// y = ymul K' (xs v) into an fp16 basis vector for the preconditioned step
+// with FP32 factored scattering: u = P^-1 v (FP32) already formed, v - u from
+// the preconditioner's modes
+void operator_apply_kxh(Problem& p, const float* u, _Float16* y, const double* xscale,
+                        float ymul, hipStream_t st);
 // Scattering with per-point classes (sigma_classes.hip): for each class,
 // gather its points' columns of L, one GEMM with the class's Mhat and
 // albedo, and scatter y = xs x + sign (result) to the class's columns.
@@ -279,6 +289,9 @@ void precond_check(const Problem& p);
 size_t precond_table_bytes(const Problem& p, int elem_bytes);
 template <typename T> void precond_apply(Problem& p, const T* x, T* u, T* nd, hipStream_t st);
 template <typename T> void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st);
+// u = P^-1 x for an fp16 basis vector x (FP32 tables and u; v - u is left to
+// the factored expansion, as with precond_fused)
+void precond_apply_h(Problem& p, const _Float16* x, float* u, hipStream_t st);
 template <typename T> T* precond_u(Problem& p);
 template <typename T> T* precond_nd(Problem& p);
 // Whether the preconditioned step operator in this precision forms v - u in

@@ -16,6 +16,8 @@
 // Work per unknown is 2 R (reduce) + 2 R (expand) flops plus 2 R N_nu / N_omega
 // (mix), so the passes are bound by HBM: reduce reads L, expand reads x and
 // writes y; W and Z hold R / N_omega of a vector each.
+#include <type_traits>
+
 #include "rt_internal.h"
 
 namespace rtsn {
@@ -110,23 +112,39 @@ __global__ __launch_bounds__(256) void fsig_mix(const T* __restrict__ W, const T
 // correction (its RP angular modes, the same sum in the same order as the
 // preconditioner's expansion, so the same values as reading its v - u = -Delta
 // back from memory).
-template <typename T, int R, int V, int RP>
+// YT = _Float16 (FP32 only): y is an fp16 basis vector, written as
+// ymul times the value, rounded to nearest.
+template <typename T, int V>
+__device__ __forceinline__ void put_h(_Float16* y, const typename VecOf<T, V>::type& v, T ymul) {
+  if constexpr (V == 1) {
+    *y = (_Float16)(ymul * v);
+  } else {
+    typedef _Float16 __attribute__((ext_vector_type(V))) HV;
+    HV h;
+#pragma unroll
+    for (int u = 0; u < V; ++u) h[u] = (_Float16)(ymul * v[u]);
+    *reinterpret_cast<HV*>(y) = h;
+  }
+}
+
+template <typename T, int R, int V, int RP, typename YT = T>
 __global__ __launch_bounds__(256) void fsig_expand(const T* __restrict__ Z,
                                                    const T* __restrict__ fq,
                                                    const double* __restrict__ albedo,
-                                                   const T* x, T* y,
+                                                   const T* x, YT* y,
                                                    const double* __restrict__ xscale, T sign,
                                                    int n_om, int n_nu, int64_t n_s,
                                                    const T* __restrict__ Fp,
-                                                   const T* __restrict__ zp) {
+                                                   const T* __restrict__ zp, T ymul = T(1)) {
   using VT = typename VecOf<T, V>::type;
+  constexpr bool kHalf = !std::is_same<YT, T>::value;
   const int64_t m = (int64_t)n_nu * n_s;
   const int64_t mv = m / V;
   const T xs = ((x != nullptr || RP > 0) && xscale != nullptr) ? T(*xscale) : T(1);
   const VT* Zv = reinterpret_cast<const VT*>(Z);
   const VT* xv = reinterpret_cast<const VT*>(x);
   const VT* zpv = reinterpret_cast<const VT*>(zp);
-  VT* yv = reinterpret_cast<VT*>(y);
+  VT* yv = reinterpret_cast<VT*>(y);   // YT = T only
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mv;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i0 = (e * V) % n_s;     // V points of one ray row
@@ -154,9 +172,13 @@ __global__ __launch_bounds__(256) void fsig_expand(const T* __restrict__ Z,
         VT d = VT(0);
 #pragma unroll
         for (int q = 0; q < RP; ++q) d += Fp[o * RP + q] * zc[q];
-        yv[at] = xs * (-d) + s;
+        const VT val = xs * (-d) + s;
+        if constexpr (kHalf) put_h<T, V>(y + at * V, val, ymul);
+        else yv[at] = val;
       } else {
-        yv[at] = x ? xs * xv[at] + s : s;
+        const VT val = x ? xs * xv[at] + s : s;
+        if constexpr (kHalf) put_h<T, V>(y + at * V, val, ymul);
+        else yv[at] = val;
       }
     }
   }
@@ -167,10 +189,11 @@ int stream_grid(int64_t m) {
   return (int)std::min<int64_t>(blocks, 8192);
 }
 
-template <typename T>
+template <typename T, typename YT = T>
 void launch_factored(const Problem& p, const T* fq, const T* fg, const T* fb, const T* L,
-                     const T* x, T* y, T* work, const double* xscale, double sign,
-                     hipStream_t st, const T* Fp = nullptr, const T* zp = nullptr, int rp = 0) {
+                     const T* x, YT* y, T* work, const double* xscale, double sign,
+                     hipStream_t st, const T* Fp = nullptr, const T* zp = nullptr, int rp = 0,
+                     T ymul = T(1)) {
   const int R = p.tab.frank;
   const int n_om = p.n_omega, n_nu = p.n_nu;
   const int64_t n_s = p.n_s, m = (int64_t)n_nu * n_s;
@@ -196,11 +219,11 @@ void launch_factored(const Problem& p, const T* fq, const T* fg, const T* fb, co
                      n_nu, n_s, tiles);
 #define RT_FSIG_X(RR, PP)                                                                     \
   if (vec)                                                                                    \
-    hipLaunchKernelGGL((fsig_expand<T, RR, VV, PP>), dim3(g), dim3(256), 0, st, Z, fq,        \
-                       p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s, Fp, zp);           \
+    hipLaunchKernelGGL((fsig_expand<T, RR, VV, PP, YT>), dim3(g), dim3(256), 0, st, Z, fq,    \
+                       p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s, Fp, zp, ymul);     \
   else                                                                                        \
-    hipLaunchKernelGGL((fsig_expand<T, RR, 1, PP>), dim3(g), dim3(256), 0, st, Z, fq,         \
-                       p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s, Fp, zp)
+    hipLaunchKernelGGL((fsig_expand<T, RR, 1, PP, YT>), dim3(g), dim3(256), 0, st, Z, fq,     \
+                       p.d_albedo, x, y, xscale, T(sign), n_om, n_nu, n_s, Fp, zp, ymul)
 #define RT_FSIG_R(RR)                                   \
   switch (rp) {                                         \
     case 0: RT_FSIG_X(RR, 0); break;                    \
@@ -261,6 +284,13 @@ void launch_sigma_factored_pre_f32(const Problem& p, const float* L, const float
                                    const double* xscale, hipStream_t st) {
   launch_factored<float>(p, p.d_fq32, p.d_fg32, p.d_fb32, L, nullptr, y, work, xscale, +1.0, st,
                          Fp, zp, rp);
+}
+
+void launch_sigma_factored_pre_h(const Problem& p, const float* L, const float* Fp,
+                                 const float* zp, int rp, _Float16* y, float ymul, float* work,
+                                 const double* xscale, hipStream_t st) {
+  launch_factored<float, _Float16>(p, p.d_fq32, p.d_fg32, p.d_fb32, L, nullptr, y, work, xscale,
+                                   +1.0, st, Fp, zp, rp, ymul);
 }
 
 }  // namespace rtsn

@@ -315,8 +315,13 @@ rt_status gmres_core(Problem& p, int prec, const TV* b, TV* x, bool x_zero, int 
 // right-hand side S r / ||r||, whose Hessenberg matrix is S times A's and
 // whose least-squares solution y, and hence d = sum y_i v_i, is the unscaled
 // one.  Returns the inner iteration count.
+//
+// pre: the preconditioned FP32 operator with factored scattering (u = P^-1 v
+// in FP32, v - u formed in the factored expansion, the result rounded into
+// the fp16 basis at S times its value); the cycle end adds P^-1 (V y).
 int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* d, int m,
-                     double itol, int cap, Workspace& ws, hipStream_t st, bool two) {
+                     double itol, int cap, Workspace& ws, hipStream_t st, bool two,
+                     bool pre) {
   const int64_t n = p.n;
   _Float16* V = static_cast<_Float16*>(ws.V);   // the FP32 basis's memory, half used
   GmresState* gs = ws.gs;
@@ -335,6 +340,16 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
   int k = 0, logged = 0;
   const int steps = std::min(m, cap), every = status_every(n);
   const bool pairs = two;
+  // w = S K v (K' v preconditioned) with v scaled by xs
+  auto op_h = [&](const _Float16* v, _Float16* w, const double* xs) {
+    if (pre) {
+      float* u = precond_u<float>(p);
+      precond_apply_h(p, v, u, st);
+      operator_apply_kxh(p, u, w, xs, S, st);
+    } else {
+      operator_apply_h(p, prec, v, w, xs, S, st, true);
+    }
+  };
   for (int j = 0; j < steps; ++j) {
     _Float16* w = V + (size_t)(j + 1) * n;
     if (pairs && j + 1 < steps) {
@@ -344,8 +359,8 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
       // formed as S K (u1 / S): the 16-bit Lambda output's scale assumes an
       // input of unit size, which u1 / S has and u1 does not.
       _Float16* u2 = V + (size_t)(j + 2) * n;
-      operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, true);
-      operator_apply_h(p, prec, w, u2, ws.pair + kPairUser, S, st, true);
+      op_h(V + (size_t)j * n, w, gs->vscale + j);
+      op_h(w, u2, ws.pair + kPairUser);
       k_mdot2<_Float16>(V, n, j + 2, w, u2, ws.partial, st);
       k_pair_coef(ws.partial, n, j, gs->vscale, ws.pair, st);
       k_update2<_Float16>(V, n, j + 1, ws.pair, w, u2, ws.partial, st);
@@ -360,7 +375,7 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
       continue;
     }
     // Arnoldi on S K: S A = S I - S K
-    operator_apply_h(p, prec, V + (size_t)j * n, w, gs->vscale + j, S, st, true);
+    op_h(V + (size_t)j * n, w, gs->vscale + j);
     k_mdot<_Float16>(V, n, j + 1, w, ws.partial, st);
     k_reduce_rows(ws.partial, n, j + 1, gs->vscale, gs->h, st);
     k_update<_Float16>(V, n, j + 1, gs->h, gs->vscale, w, ws.partial, st);
@@ -372,7 +387,14 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
     if (r.stop) break;
   }
   k_solve_r(gs, k, st);
-  k_combine<_Float16, float>(V, n, k, gs->coef, d, st);
+  if (pre) {
+    float* t = precond_nd<float>(p);   // free: the fused step writes no v - u
+    RT_HIP(hipMemsetAsync(t, 0, (size_t)n * sizeof(float), st));
+    k_combine<_Float16, float>(V, n, k, gs->coef, t, st);
+    precond_apply_add<float>(p, t, d, st);
+  } else {
+    k_combine<_Float16, float>(V, n, k, gs->coef, d, st);
+  }
   return k;
 }
 
@@ -570,7 +592,7 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
         total_inner += bicgstab_inner_f32(p, o.precision, r32, ws.d32, itol, cap, ws, st);
       } else if (o.basis_fp16) {
         total_inner += inner_cycle_fp16(p, o.precision, ws.r64, rn, ws.d32, o.restart, itol, cap,
-                                        ws, st, o.two_step != 0);
+                                        ws, st, o.two_step != 0, pre);
       } else {
         // a pair's second application takes u1 = K v_j unnormalised; the
         // 16-bit operators' fp16 Lambda scale assumes entries of at most
