@@ -288,13 +288,16 @@ typedef struct {
   int max_outer;          /* mixed: outer refinement cap (default 50)               */
   int record_history;     /* keep the per-iteration residual estimates              */
   int basis_fp16;         /* mixed with a 16-bit operator precision (RT_PREC_BF16,
-                             RT_PREC_FP16, RT_PREC_BF16X3): keep the inner Krylov
-                             basis in fp16, stored times 2^11, which halves the
-                             bytes of every Arnoldi pass (default 0: FP32
-                             basis).  An inner cycle then gains at most about
-                             kappa(A) 2^-11: on ill-conditioned problems the
-                             refinement takes more outer steps.  RT_E_INVALID
-                             with any other precision, or when a row of
+                             RT_PREC_FP16, RT_PREC_BF16X3), or with RT_PREC_FP32
+                             preconditioned (precond = RT_PRECOND_LOCAL) on the
+                             factored scattering form (rt_problem_set_sigma):
+                             keep the inner Krylov basis in fp16, stored times
+                             2^11, which halves the bytes of every Arnoldi pass
+                             (default 0: FP32 basis).  An inner cycle then gains
+                             at most about kappa 2^-11: on ill-conditioned
+                             problems the refinement takes more outer steps.
+                             RT_E_INVALID with any other combination, or when a
+                             row of
                              (1 - eps) |Mhat| sums to more than 2 (possible
                              only with an explicit kernel; the physical kernels
                              give about 1), which the basis scale assumes.      */
@@ -314,10 +317,13 @@ typedef struct {
                              A P^-1 with the physics-based preconditioner of
                              rt_apply_precond (Sec. 6 remark on physics-based
                              preconditioning), FP64 or on the FP32 basis of the
-                             mixed inner cycles; right preconditioning, so the
+                             mixed inner cycles, or on an fp16 basis with FP32
+                             operators on the factored scattering form (see
+                             basis_fp16); right preconditioning, so the
                              residual and stopping test are those of A x = b.
                              Dipole x PRD kernels with one kernel for all points;
-                             not with BiCGStab or an fp16 basis (RT_E_INVALID).
+                             not with BiCGStab or an fp16 basis of 16-bit
+                             operators (RT_E_INVALID).
                              The first preconditioned solve in a precision builds
                              the preconditioner's tables (see rt_apply_precond)
                              and synchronises the device.                       */
