@@ -401,7 +401,9 @@ def main():
     for label, form, kw in (("fp64", "dense", {}),
                             (args.mixed_precision, "dense", {"precision": args.mixed_precision}),
                             ("fp64/factored", "factored", {}),
-                            ("fp32/factored", "factored", {"precision": "fp32"})):
+                            ("fp32/factored", "factored", {"precision": "fp32"}),
+                            ("fp32/factored/basis16", "factored",
+                             {"precision": "fp32", "basis_fp16": 1})):
         p.set_sigma(form)
         tp0 = time.perf_counter()
         p.solve(xp, rtol=1e-8, restart=30, precond="local", stream=stream, **kw)
