@@ -70,6 +70,7 @@ Problem::~Problem() {
   hipFree(d_prec_F32);
   hipFree(d_prec_G32);
   hipFree(d_prec_T32);
+  hipFree(d_prec_T16);
   hipFree(d_prec_work);
 }
 

@@ -174,6 +174,15 @@ __device__ __forceinline__ void vload(const T* p, T (&v)[W]) {
   }
 }
 
+// 8 fp16 values (16 bytes) widened to T
+template <typename T>
+__device__ __forceinline__ void vload_h8(const _Float16* p, T (&v)[8]) {
+  typedef _Float16 __attribute__((ext_vector_type(8))) H8;
+  const H8 t = *reinterpret_cast<const H8*>(p);
+#pragma unroll
+  for (int w = 0; w < 8; ++w) v[w] = T(t[w]);
+}
+
 template <typename T, int W>
 __device__ __forceinline__ void vstore(T* p, const T (&v)[W]) {
   if constexpr (W == 4) {
@@ -277,11 +286,12 @@ __device__ __forceinline__ int64_t mix_order(int64_t k, int64_t nfull) {
   return base + 32 * (g & 7) + 4 * (g >> 3) + w;
 }
 
-template <typename T, int VPL>
-__global__ __launch_bounds__(256) void prec_mix_wave(const T* __restrict__ Tb,
+// TT: type of the stored blocks (T, or fp16 widened to T as it is staged).
+template <typename T, int VPL, typename TT = T>
+__global__ __launch_bounds__(256) void prec_mix_wave(const TT* __restrict__ Tb,
                                                      const T* __restrict__ r, T* __restrict__ z,
                                                      int n, int64_t n_s, int64_t nblk) {
-  constexpr int W = kVec16<T>;
+  constexpr int W = 16 / (int)sizeof(TT);
   extern __shared__ unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T* L = reinterpret_cast<T*>(smem_raw) + (size_t)wave * (n * (n + 1) + n);
@@ -296,10 +306,14 @@ __global__ __launch_bounds__(256) void prec_mix_wave(const T* __restrict__ Tb,
     const int64_t b = mix_order(k, nfull);
     const int q = (int)(b / n_s);
     const int64_t i = b - (int64_t)q * n_s;
-    const T* blk = Tb + (size_t)b * n * n;
+    const TT* blk = Tb + (size_t)b * n * n;
     T v[VPL][W];
 #pragma unroll
-    for (int t = 0; t < VPL; ++t) vload<T, W>(blk + (size_t)min(lane + 64 * t, nv - 1) * W, v[t]);
+    for (int t = 0; t < VPL; ++t) {
+      const TT* src = blk + (size_t)min(lane + 64 * t, nv - 1) * W;
+      if constexpr (std::is_same<TT, T>::value) vload<T, W>(src, v[t]);
+      else vload_h8<T>(src, v[t]);
+    }
     const T rv = r[(int64_t)q * m + (int64_t)min(lane, n - 1) * n_s + i];
 #pragma unroll
     for (int t = 0; t < VPL; ++t) {
@@ -531,8 +545,10 @@ T* work_rz(Problem& p) {
   return static_cast<T*>(p.d_prec_work);
 }
 
+// half: take the fp16 copy of the FP32 blocks where it exists (the solves
+// on fp16 bases)
 template <typename T, bool ACC, typename XT = T>
-void apply_impl(Problem& p, const XT* x, T* u, T* nd, hipStream_t st) {
+void apply_impl(Problem& p, const XT* x, T* u, T* nd, hipStream_t st, bool half = false) {
   using PP = PrecPtrs<T>;
   if (!PP::T(p)) fail(RT_E_INVALID, "preconditioner not prepared in this precision");
   const int rq = p.prec_rq, n_om = p.n_omega, n_nu = p.n_nu;
@@ -569,7 +585,21 @@ void apply_impl(Problem& p, const XT* x, T* u, T* nd, hipStream_t st) {
   // preconditioner per solve with the point-tile product)
   const bool wave_mix = sizeof(T) == 4 && n_nu <= 64 && n_nu % kVec16<T> == 0 && vpl <= 16 &&
                         wave_lds <= 65536;
-  if (wave_mix) {
+  // the fp16 blocks: 8 values per 16-byte vector, so n_nu a multiple of 8
+  const bool h16 = half && sizeof(T) == 4 && p.d_prec_T16 && n_nu % 8 == 0 && n_nu <= 64 &&
+                   wave_lds <= 65536;
+  if (h16) {
+    const int64_t nblk = (int64_t)rq * n_s;
+    const int grid = (int)std::min<int64_t>((nblk + 3) / 4, 4096);
+    const int vph = (int)(((int64_t)n_nu * n_nu / 8 + 63) / 64);   // 2, 5 or 8 at 32, 48, 64
+#define RT_MIXH(V)                                                                            \
+  hipLaunchKernelGGL((prec_mix_wave<T, V, _Float16>), dim3(grid), dim3(256), wave_lds, st,    \
+                     p.d_prec_T16, r, z, n_nu, n_s, nblk)
+    if (vph <= 2) RT_MIXH(2);
+    else if (vph <= 5) RT_MIXH(5);
+    else RT_MIXH(8);
+#undef RT_MIXH
+  } else if (wave_mix) {
     const int64_t nblk = (int64_t)rq * n_s;
     // a multiple of 64 groups keeps every pass on whole 256-wave chunks
     const int grid = (int)std::min<int64_t>((nblk + 3) / 4, 4096);
@@ -684,7 +714,45 @@ void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st) {
 }
 
 void precond_apply_h(Problem& p, const _Float16* x, float* u, hipStream_t st) {
-  apply_impl<float, false, _Float16>(p, x, u, nullptr, st);
+  apply_impl<float, false, _Float16>(p, x, u, nullptr, st, true);
+}
+
+void precond_apply_add_h(Problem& p, const float* d, float* y, hipStream_t st) {
+  apply_impl<float, true>(p, d, y, nullptr, st, true);
+}
+
+__global__ __launch_bounds__(256) void t16_convert(const float* __restrict__ a,
+                                                   _Float16* __restrict__ h, int64_t count,
+                                                   unsigned* __restrict__ bad) {
+  unsigned any = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const float v = a[e];
+    any |= !(fabsf(v) <= 65504.0f);   // out of fp16's range, or not finite
+    h[e] = (_Float16)v;
+  }
+  if (any) atomicOr(bad, 1u);
+}
+
+void precond_prepare_h(Problem& p, hipStream_t st) {
+  precond_prepare(p, 4, st);
+  if (p.d_prec_T16 || p.prec_t16_tried) return;
+  p.prec_t16_tried = true;
+  const int64_t count = (int64_t)p.prec_rq * p.n_s * p.n_nu * p.n_nu;
+  _Float16* h = nullptr;
+  unsigned* bad = nullptr;
+  RT_HIP(hipMalloc(&h, (size_t)count * sizeof(_Float16)));
+  RT_HIP(hipMalloc(&bad, sizeof(unsigned)));
+  RT_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned), st));
+  hipLaunchKernelGGL(t16_convert, dim3(grid_for(count)), dim3(256), 0, st, p.d_prec_T32, h,
+                     count, bad);
+  RT_HIP(hipGetLastError());
+  unsigned hb = 0;
+  RT_HIP(hipMemcpyAsync(&hb, bad, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  RT_HIP(hipStreamSynchronize(st));
+  hipFree(bad);
+  if (hb) hipFree(h);   // an entry outside fp16: keep the FP32 blocks
+  else p.d_prec_T16 = h;
 }
 
 template double* precond_u<double>(Problem&);

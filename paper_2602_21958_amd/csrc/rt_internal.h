@@ -152,6 +152,10 @@ struct Problem {
   double* d_prec_dbar = nullptr;
   double *d_prec_F64 = nullptr, *d_prec_G64 = nullptr, *d_prec_T64 = nullptr;
   float *d_prec_F32 = nullptr, *d_prec_G32 = nullptr, *d_prec_T32 = nullptr;
+  // fp16 copy of the FP32 blocks for the solves on fp16 bases (null when an
+  // entry falls outside fp16's range; prec_t16_tried then stops a retry)
+  _Float16* d_prec_T16 = nullptr;
+  bool prec_t16_tried = false;
   void* d_prec_work = nullptr;
   size_t prec_work_bytes = 0;
   Workspace* ws = nullptr;
@@ -289,9 +293,15 @@ void precond_check(const Problem& p);
 size_t precond_table_bytes(const Problem& p, int elem_bytes);
 template <typename T> void precond_apply(Problem& p, const T* x, T* u, T* nd, hipStream_t st);
 template <typename T> void precond_apply_add(Problem& p, const T* d, T* y, hipStream_t st);
-// u = P^-1 x for an fp16 basis vector x (FP32 tables and u; v - u is left to
-// the factored expansion, as with precond_fused)
+// The solves on fp16 bases: precond_prepare_h adds an fp16 copy of the FP32
+// blocks (where every entry fits); precond_apply_h forms u = P^-1 x for an
+// fp16 basis vector x (FP32 u; v - u is left to the factored expansion, as
+// with precond_fused) and precond_apply_add_h adds P^-1 d to y, both with the
+// fp16 blocks where they exist, so that the steps and the cycle end apply
+// the same preconditioner.
+void precond_prepare_h(Problem& p, hipStream_t st);
 void precond_apply_h(Problem& p, const _Float16* x, float* u, hipStream_t st);
+void precond_apply_add_h(Problem& p, const float* d, float* y, hipStream_t st);
 template <typename T> T* precond_u(Problem& p);
 template <typename T> T* precond_nd(Problem& p);
 // Whether the preconditioned step operator in this precision forms v - u in

@@ -391,7 +391,7 @@ int inner_cycle_fp16(Problem& p, int prec, const double* r64, double rn, float* 
     float* t = precond_nd<float>(p);   // free: the fused step writes no v - u
     RT_HIP(hipMemsetAsync(t, 0, (size_t)n * sizeof(float), st));
     k_combine<_Float16, float>(V, n, k, gs->coef, t, st);
-    precond_apply_add<float>(p, t, d, st);
+    precond_apply_add_h(p, t, d, st);
   } else {
     k_combine<_Float16, float>(V, n, k, gs->coef, d, st);
   }
@@ -538,7 +538,10 @@ rt_status solve(Problem& p, const rt_solver_opts& o, const double* b_in, double*
   const bool mixed = o.precision != RT_PREC_FP64;
   const bool bicg = o.krylov == RT_KRYLOV_BICGSTAB;
   const bool pre = o.precond == RT_PRECOND_LOCAL;
-  if (pre) precond_prepare(p, mixed ? 4 : 8, st);
+  if (pre) {
+    if (o.basis_fp16) precond_prepare_h(p, st);
+    else precond_prepare(p, mixed ? 4 : 8, st);
+  }
   Workspace& ws = ensure_workspace(p, o.restart, mixed, bicg,
                                    !mixed ? 8 : (o.basis_fp16 ? 2 : 4));
   const int64_t n = p.n;

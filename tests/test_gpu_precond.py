@@ -73,6 +73,8 @@ SPECS = {
     "box_qsc": qbox,
     # one inclination per hemisphere: four angular modes, not six
     "box_mu2": lambda: W.small_box(6, 2, 8, 6, nz=5),
+    # frequencies a multiple of 8: the fp16-basis solves take fp16 blocks
+    "box_nu16": lambda: W.small_box(8, 4, 4, 16, nz=6),
 }
 
 
@@ -222,12 +224,13 @@ def test_preconditioned_factored_solve(name, prec):
 
 
 @pytest.mark.parametrize("two_step", [1, 0])
-@pytest.mark.parametrize("name", ["box8", "box_12x10x9"])
+@pytest.mark.parametrize("name", ["box8", "box_12x10x9", "box_nu16"])
 def test_preconditioned_factored_fp16_basis(name, two_step):
     """The preconditioned FP32 operator with factored scattering on an fp16
     Krylov basis (u = P^-1 v in FP32, the step's result rounded into the
-    basis at the basis scale): oracle-evaluated FP64 residual <= 1e-8, in
-    fewer inner iterations than the unpreconditioned fp16-basis solve."""
+    basis at the basis scale; with 16 frequencies the preconditioner's blocks
+    are taken from their fp16 copy): oracle-evaluated FP64 residual <= 1e-8,
+    in fewer inner iterations than the unpreconditioned fp16-basis solve."""
     rt = _rt()
     spec = SPECS[name]()
     say(f"precond factored fp16 basis {name} two_step={two_step}")
