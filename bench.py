@@ -49,8 +49,8 @@ PEAK_BF16_TFLOPS = 2500.0
 # figure is stale and the bench reports null.
 TRAFFIC = {
     "sigma_f64_box32": {"files": ("gemm_dev.h", "sigma_gemm.hip", "solver.cpp", "abi.cpp"),
-                        "sha": "876965cee2199233",
-                        "fetch_kib": 1.340e6, "write_kib": 5.243e5,
+                        "sha": "8bad2c284fd50c9e",
+                        "fetch_kib": 1.341e6, "write_kib": 5.243e5,
                         "fetch_scale": 2.000, "write_scale": 1.000,
                         "profile": "profiles/sigma_gemm_f64_box32_counters.md"},
 }
