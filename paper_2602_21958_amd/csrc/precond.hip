@@ -345,7 +345,6 @@ template <typename T, int RQ, bool ACC, int W, typename XT = T>
 __global__ __launch_bounds__(256) void prec_expand(const T* __restrict__ z,
                                                    const T* __restrict__ F, const XT* x, T* u,
                                                    T* nd, int n_om, int64_t m) {
-  static_assert(std::is_same<XT, T>::value || W == 1, "converted input: one value per thread");
   const int64_t mv = m / W;
   for (int64_t ev = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ev < mv;
        ev += (int64_t)gridDim.x * blockDim.x) {
@@ -366,8 +365,16 @@ __global__ __launch_bounds__(256) void prec_expand(const T* __restrict__ z,
       }
       const int64_t at = (int64_t)o * m + e;
       T xv[W], uv[W];
-      if constexpr (std::is_same<XT, T>::value) vload<T, W>(x + at, xv);
-      else xv[0] = T(x[at]);
+      if constexpr (std::is_same<XT, T>::value) {
+        vload<T, W>(x + at, xv);
+      } else if constexpr (W == 1) {
+        xv[0] = T(x[at]);
+      } else {
+        typedef XT __attribute__((ext_vector_type(W))) XV;
+        const XV t = *reinterpret_cast<const XV*>(x + at);
+#pragma unroll
+        for (int w = 0; w < W; ++w) xv[w] = T(t[w]);
+      }
       if constexpr (ACC) {
         vload<T, W>(u + at, uv);
 #pragma unroll
@@ -615,10 +622,20 @@ void apply_impl(Problem& p, const XT* x, T* u, T* nd, hipStream_t st, bool half 
     hipLaunchKernelGGL((prec_mix<T>), dim3((unsigned)(rq * tiles)), dim3(256),
                        (size_t)n_nu * kMixPts * sizeof(T), st, PP::T(p), r, z, n_nu, n_s, tiles);
   }
+  // fp16 input: 4 values per thread (8-byte loads, 16-byte stores of u),
+  // where x and u allow it
+  constexpr bool kHalfIn = !std::is_same<XT, T>::value && sizeof(T) == 4;
+  const bool vh = kHalfIn && !ACC && nd == nullptr && m % 4 == 0 &&
+                  ((uintptr_t)x & 7) == 0 && ((uintptr_t)u & 15) == 0;
 #define RT_PREC_RQ(RR)                                                                       \
   case RR:                                                                                   \
-    hipLaunchKernelGGL((prec_expand<T, RR, ACC, 1, XT>), dim3(ge), dim3(256), 0, st, z,      \
-                       PP::F(p), x, u, nd, n_om, m);                                          \
+    if (vh)                                                                                  \
+      hipLaunchKernelGGL((prec_expand<T, RR, ACC, kHalfIn ? 4 : 1, XT>),                     \
+                         dim3(grid_for(m / 4)), dim3(256), 0, st, z, PP::F(p), x, u, nd,     \
+                         n_om, m);                                                           \
+    else                                                                                     \
+      hipLaunchKernelGGL((prec_expand<T, RR, ACC, 1, XT>), dim3(ge), dim3(256), 0, st, z,    \
+                         PP::F(p), x, u, nd, n_om, m);                                       \
     break;
   switch (rq) {
     RT_PREC_RQ(1) RT_PREC_RQ(2) RT_PREC_RQ(3) RT_PREC_RQ(4) RT_PREC_RQ(5) RT_PREC_RQ(6)
