@@ -302,19 +302,41 @@ __global__ __launch_bounds__(256) void prec_mix_wave(const TT* __restrict__ Tb,
   // (ev < 1024, nvr <= 16: the quotient stays 1/32 away from an integer)
   const float inv_nvr = 1.0f / (float)nvr;
   const int64_t nfull = nblk & ~(int64_t)255;
-  for (int64_t k = (int64_t)blockIdx.x * 4 + wave; k < nblk; k += (int64_t)gridDim.x * 4) {
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  // software pipeline: the loads of the next block and the store of the
+  // previous block's row are issued together, after the wait for this
+  // block's loads, so that both have a whole block's work to complete (loads
+  // and stores share one wait counter, which is waited down to zero while
+  // both are outstanding)
+  typedef TT __attribute__((ext_vector_type(W))) RV;   // 16 bytes
+  RV raw[VPL];
+  T rv;
+  auto fetch = [&](int64_t kk) {
+    const int64_t bb = mix_order(kk, nfull);
+    const int qq = (int)(bb / n_s);
+    const int64_t ii = bb - (int64_t)qq * n_s;
+    const TT* blk = Tb + (size_t)bb * n * n;
+#pragma unroll
+    for (int t = 0; t < VPL; ++t)
+      raw[t] = *reinterpret_cast<const RV*>(blk + (size_t)min(lane + 64 * t, nv - 1) * W);
+    rv = r[(int64_t)qq * m + (int64_t)min(lane, n - 1) * n_s + ii];
+  };
+  int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  if (k >= nblk) return;   // the whole wavefront
+  fetch(k);
+  int64_t zat = -1;        // where the previous block's row goes
+  T zval = T(0);
+  for (; k < nblk; k += stride) {
+    RV cur[VPL];
+#pragma unroll
+    for (int t = 0; t < VPL; ++t) cur[t] = raw[t];
+    const T rcur = rv;
+    if (zat >= 0 && lane < n) z[zat] = zval;
+    // the last block reloads itself, which keeps the loads unconditional
+    fetch(k + stride < nblk ? k + stride : k);
     const int64_t b = mix_order(k, nfull);
     const int q = (int)(b / n_s);
     const int64_t i = b - (int64_t)q * n_s;
-    const TT* blk = Tb + (size_t)b * n * n;
-    T v[VPL][W];
-#pragma unroll
-    for (int t = 0; t < VPL; ++t) {
-      const TT* src = blk + (size_t)min(lane + 64 * t, nv - 1) * W;
-      if constexpr (std::is_same<TT, T>::value) vload<T, W>(src, v[t]);
-      else vload_h8<T>(src, v[t]);
-    }
-    const T rv = r[(int64_t)q * m + (int64_t)min(lane, n - 1) * n_s + i];
 #pragma unroll
     for (int t = 0; t < VPL; ++t) {
       const int ev = lane + 64 * t;
@@ -322,19 +344,21 @@ __global__ __launch_bounds__(256) void prec_mix_wave(const TT* __restrict__ Tb,
         const int row = (int)(((float)ev + 0.5f) * inv_nvr);
         T* dst = L + row * (n + 1) + (ev - row * nvr) * W;
 #pragma unroll
-        for (int w = 0; w < W; ++w) dst[w] = v[t][w];
+        for (int w = 0; w < W; ++w) dst[w] = T(cur[t][w]);
       }
     }
-    if (lane < n) rl[lane] = rv;
+    if (lane < n) rl[lane] = rcur;
     wave_lds_sync();
     if (lane < n) {
       const T* row = L + lane * (n + 1);
       T acc = T(0);
-      for (int k = 0; k < n; ++k) acc += row[k] * rl[k];
-      z[(int64_t)q * m + (int64_t)lane * n_s + i] = acc;
+      for (int kk = 0; kk < n; ++kk) acc += row[kk] * rl[kk];
+      zval = acc;
+      zat = (int64_t)q * m + (int64_t)lane * n_s + i;
     }
     wave_lds_sync();   // the next block overwrites the region
   }
+  if (zat >= 0 && lane < n) z[zat] = zval;
 }
 
 // Delta[(o, nu), i] = sum_q F[o][q] z[q][nu][i];
