@@ -148,7 +148,12 @@ typedef struct {
                                 with the restart passed to rt_problem_footprint,
                                 including the work buffer of the problem's
                                 current scattering form (rt_problem_set_sigma) */
-  int64_t bytes_solve_mixed; /* same for a mixed-precision (FP32 basis) solve      */
+  int64_t bytes_solve_mixed; /* same for a mixed-precision (FP32 basis) solve.
+                                Neither counts the preconditioner's tables
+                                (rt_apply_precond: R' n_frequencies^2 n_points
+                                values of the solve's precision, plus an fp16
+                                copy for solves on an fp16 basis) nor its two
+                                work vectors.                                   */
   int32_t sigma_rank;     /* angular rank of the factored scattering form (6 for
                              the 3D dipole, 2 for the slab's azimuth average; 0:
                              no factored form, explicit kernel)                  */
