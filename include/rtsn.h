@@ -431,7 +431,9 @@ rt_status rt_batch_create_ex(int device, int precision, int64_t hbm_budget,
  * (once per problem and precision, synchronising the engine's stream) and
  * held by the problem outside the engine's budget, which holds the
  * preconditioner's four work vectors (2 n_unknowns and 2 * 6 n_frequencies
- * n_points elements of the basis type).                                     */
+ * n_points elements of the basis type).  The engine applies the scattering
+ * as the dense GEMM whatever form rt_problem_set_sigma chose for p (the same
+ * operator; the factored and emulated forms are single-problem options).   */
 rt_status rt_batch_submit(rt_batch b, rt_problem p, const rt_solver_opts* opts,
                           double* x_out, uint64_t* ticket);
 
