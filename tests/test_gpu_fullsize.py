@@ -184,14 +184,22 @@ def _box32_oracle():
     return _BOX32_ORACLE["op"], _BOX32_ORACLE["b"]
 
 
-@pytest.mark.parametrize("prec,basis16", [("fp64", 0), ("fp16", 0), ("fp16", 1)])
-def test_box32_full_size_solve_oracle_residual(prec, basis16):
+@pytest.mark.parametrize("prec,basis16,pre", [("fp64", 0, ""), ("fp16", 0, ""), ("fp16", 1, ""),
+                                              ("fp64", 0, "local"), ("fp32", 1, "local")])
+def test_box32_full_size_solve_oracle_residual(prec, basis16, pre):
+    """Full-size box32 solves, the oracle's FP64 residual of the solution:
+    FP64, fp16 refinement on FP32 / fp16 bases, and preconditioned (FP64 with
+    the dense scattering; FP32 operators with factored scattering on an fp16
+    basis, the fastest mixed combination)."""
     rt = _rt()
-    say(f"box32 full-size solve {prec} basis_fp16={basis16}")
+    say(f"box32 full-size solve {prec} basis_fp16={basis16} precond={pre or 'none'}")
     op, b = _box32_oracle()
     with rt.Problem(W.box32()) as p:
+        if pre and prec == "fp32":
+            p.set_sigma("factored")
         x = torch.empty(p.n, dtype=torch.float64, device="cuda:0")
-        st = p.solve(x, rtol=1e-8, restart=30, precision=prec, basis_fp16=basis16)
+        st = p.solve(x, rtol=1e-8, restart=30, precision=prec, basis_fp16=basis16,
+                     precond=pre or "none")
         s = x.cpu().numpy()
         del x
     res = op.residual_norm(s, b)
