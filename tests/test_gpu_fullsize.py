@@ -17,8 +17,9 @@ unknowns in a test) and through the oracle on sampled problems.
   the stratified atmosphere with x = 1, sampled points checked against the
   closed-form Lambda and the oracle's Mhat in FP64.
 * 32^3 box (the benchmark workload) solved in FP64, in mixed precision with
-  an fp16 Sigma and with an fp16 Krylov basis: the oracle's FP64 residual of
-  each solution meets 1e-8.
+  an fp16 Sigma and with an fp16 Krylov basis, and preconditioned (FP64; FP32
+  operators with factored scattering on an fp16 basis): the oracle's FP64
+  residual of each solution meets 1e-8.
 * batch512 (512 slabs of the batch recipe) in one engine: every 32nd slab's
   solution checked against the oracle's FP64 residual.
 """
