@@ -118,7 +118,10 @@ template <> struct ComputeOf<_Float16> { using type = float; };
 // three LDS planes do not fit.  Sweeping four frequencies of an ordinate
 // together shares the upwind stencil and opacity but needs 4x the per-thread
 // state, and at the occupancy that leaves it was measured slower on the 32^3
-// box (FP64 0.82 against 0.40 ms; FP32 0.22 against 0.19 ms).
+// box (FP64 0.82 against 0.40 ms; FP32 0.22 against 0.19 ms); two
+// frequencies per group on 64^2 planes (FP32 form, 1024 threads of 4
+// points) need more than the 128 registers a thread has there (172 bytes
+// spilled).
 int box_chunk(size_t PH, int elem_bytes, int max_lds) {
   return 3 * PH * elem_bytes <= (size_t)max_lds ? 1 : 0;
 }
