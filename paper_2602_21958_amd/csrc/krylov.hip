@@ -658,10 +658,32 @@ __global__ __launch_bounds__(kThreads) void pair_fix_kernel(const TV* __restrict
   const double rho = pair[1];
   double nz = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-    const TV v = (TV)((double)z[e] - rho * (double)p1[e]);
-    z[e] = v;
-    nz += (double)v * (double)v;
+  bool done = false;
+  if constexpr (sizeof(TV) == 2) {
+    // fp16 basis: 8 values per 16-byte access (basis vectors are n values
+    // apart, so 16-byte aligned when n is a multiple of 8)
+    using VT = typename Vec16<TV>::type;
+    done = n % 8 == 0;
+    const VT* pv = reinterpret_cast<const VT*>(p1);
+    VT* zv = reinterpret_cast<VT*>(z);
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; done && e < n / 8;
+         e += stride) {
+      const VT a = pv[e];
+      VT b = zv[e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        b[q] = (TV)((double)b[q] - rho * (double)a[q]);
+        nz += (double)b[q] * (double)b[q];
+      }
+      zv[e] = b;
+    }
+  }
+  if (!done) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
+      const TV v = (TV)((double)z[e] - rho * (double)p1[e]);
+      z[e] = v;
+      nz += (double)v * (double)v;
+    }
   }
   double acc[1] = {nz};
   block_reduce_store<1>(acc, partial + gridDim.x + blockIdx.x, 1, 1);
