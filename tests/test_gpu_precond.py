@@ -5,7 +5,9 @@ oracle's (oracle/precond.py; Sec. 6 remark on physics-based preconditioning).
 Bars:
 * Dbar (FP64 formal solutions of plane sources, direction averaged): within
   1e-13 of the oracle's (values in [0, 1) for the linear schemes).
-* P^-1 x: the per-point blocks are ill-conditioned where eps is small
+* P^-1 x (16 frequencies: the FP32 tables take the one-wavefront-per-block
+  product; the other cases the point-tile one): the per-point blocks are
+  ill-conditioned where eps is small
   (P_i approaches the singular Id - Mhat Dbar in optically thick points), so
   the forward error is bounded by a small multiple of cond(P_i) times the
   rounding unit of the precision, per point, and so is the backward error
@@ -96,7 +98,8 @@ def test_precond_local_matches_oracle(name):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9", "box_mu2", "box_qsc"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9", "box_mu2", "box_qsc",
+                                  "box_nu16"])
 def test_apply_precond_matches_oracle(name, prec):
     rt = _rt()
     spec = SPECS[name]()
@@ -179,7 +182,7 @@ def test_preconditioned_fp64_solve(name, two_step):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16", "bf16x3"])
-@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9", "box_nu16"])
 def test_preconditioned_mixed_solve(name, prec):
     rt = _rt()
     spec = SPECS[name]()
