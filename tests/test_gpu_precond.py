@@ -201,7 +201,7 @@ def test_preconditioned_mixed_solve(name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
-@pytest.mark.parametrize("name", ["box8", "box_12x10x9"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9"])
 def test_preconditioned_factored_solve(name, prec):
     """The preconditioner with the factored scattering form: FP64 GMRES on
     the factored FP64 operator (fp64), or FP64 outer residuals in factored
@@ -227,7 +227,7 @@ def test_preconditioned_factored_solve(name, prec):
 
 
 @pytest.mark.parametrize("two_step", [1, 0])
-@pytest.mark.parametrize("name", ["box8", "box_12x10x9", "box_nu16"])
+@pytest.mark.parametrize("name", ["slab64", "box8", "box_12x10x9", "box_nu16"])
 def test_preconditioned_factored_fp16_basis(name, two_step):
     """The preconditioned FP32 operator with factored scattering on an fp16
     Krylov basis (u = P^-1 v in FP32, the step's result rounded into the
